@@ -1,0 +1,207 @@
+"""Stream segment tree with Alg. "append", Alg. "insert" and Alg. "recall".
+
+Sec. 4.2 defines leaf (L), intermediate (M) and placeholder (P) nodes; Sec.
+6.2 gives the append/insert procedures; Sec. 5.1 gives the pruned hit set.
+
+Readings:
+  * leaves hold blocks of ``leaf_len`` slices (the paper's leaf is one slice,
+    leaf_len = 1); the tree algorithms run on block indices and node ranges
+    are reported in slices.  Only whole blocks are committed, so queries need
+    te <= T_c = leaf_len * (number of complete blocks);
+  * a leaf reached by Recall is accepted even below the threshold (it has no
+    children) and is trimmed like a partial hit;
+  * theta = num/den and the test |[ts,te) & [s,t)| >= theta |[s,t)| is done
+    in integers as den * overlap >= num * length;
+  * node ids are the 1-based creation order, which reproduces the numbering of
+    the paper's example (Fig. "illust");
+  * the new root made by Alg. "append" is a placeholder whose range is
+    [0, 2 tau_r) and whose left child is the old root (the prose has typos);
+  * a range equal to one node returns that node's stored decomposition;
+    every other query goes through Alg. "stitch".
+"""
+
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import stitch as stitch_mod
+from .tucker import canonical_signs, effective_ranks, hooi
+
+
+class Node:
+    __slots__ = ("id", "lo", "hi", "kind", "left", "right", "H", "V", "info")
+
+    def __init__(self, nid: int, lo: int, hi: int):
+        self.id = nid          # creation order, 1-based
+        self.lo = lo           # range in blocks [lo, hi)
+        self.hi = hi
+        self.kind = "P"
+        self.left: Optional["Node"] = None
+        self.right: Optional["Node"] = None
+        self.H = None
+        self.V = None
+        self.info = None
+
+
+class StreamSegmentTree:
+    """Literal pointer-based stream segment tree over blocks of slices.
+
+    ``append(block)`` takes a leaf_len x D_2 x ... x D_p array (or None for a
+    structure-only tree, which skips every decomposition).
+    """
+
+    def __init__(self, dims: Sequence[int], ranks: Sequence[int], leaf_len: int = 1,
+                 theta: Tuple[int, int] = (7, 10), max_iter: int = 20, tol: float = 0.01):
+        self.dims = tuple(int(d) for d in dims)
+        self.ranks = tuple(int(r) for r in ranks)
+        self.leaf_len = int(leaf_len)
+        self.theta = (int(theta[0]), int(theta[1]))
+        self.max_iter = int(max_iter)
+        self.tol = float(tol)
+        self.root: Optional[Node] = None
+        self.T_b = 0                 # committed blocks
+        self.next_id = 1
+        self.nodes: List[Node] = []  # in creation order
+        self.merges_last = 0         # stitches run by the last append
+        self.merges_total = 0
+
+    # -- helpers ------------------------------------------------------------
+    @property
+    def T(self) -> int:
+        """Committed timespan in slices."""
+        return self.T_b * self.leaf_len
+
+    def sigma(self, v: Node) -> int:
+        return v.lo * self.leaf_len
+
+    def tau(self, v: Node) -> int:
+        return v.hi * self.leaf_len
+
+    def _new(self, lo: int, hi: int) -> Node:
+        v = Node(self.next_id, lo, hi)
+        self.next_id += 1
+        self.nodes.append(v)
+        return v
+
+    def height(self) -> int:
+        def h(v):
+            if v is None:
+                return 0
+            return 1 + max(h(v.left), h(v.right))
+        return h(self.root)
+
+    # -- Alg. "append" ---------------------------------------------------------
+    def append(self, block: Optional[np.ndarray]) -> None:
+        T = self.T_b
+        if T == 0:
+            self.root = self._new(0, 1)
+        elif T == self.root.hi:
+            r = self._new(0, 2 * self.root.hi)
+            r.left = self.root
+            self.root = r
+        self.merges_last = 0
+        self._insert(self.root, T, block)
+        self.T_b += 1
+        self.merges_total += self.merges_last
+
+    # -- Alg. "insert" ---------------------------------------------------------
+    def _insert(self, v: Node, T: int, block) -> None:
+        if v.lo == T and v.hi == T + 1:
+            v.kind = "L"
+            if block is not None:
+                X = np.asarray(block, dtype=np.float64)
+                r = effective_ranks(self.leaf_len, self.dims, self.ranks)
+                G, U, info = hooi(X, r, self.max_iter, self.tol)
+                v.H, v.V = canonical_signs(G, U)
+                v.info = info
+            return
+        mu = (v.lo + v.hi) // 2
+        if T < mu:
+            if v.left is None:
+                v.left = self._new(v.lo, mu)
+            self._insert(v.left, T, block)
+        else:
+            if v.right is None:
+                v.right = self._new(mu, v.hi)
+            self._insert(v.right, T, block)
+            if v.hi == T + 1:
+                v.kind = "M"
+                self.merges_last += 1
+                if block is not None:
+                    u1, u2 = v.left, v.right
+                    r = effective_ranks((v.hi - v.lo) * self.leaf_len, self.dims, self.ranks)
+                    pieces = [stitch_mod.Piece(u1.H, u1.V), stitch_mod.Piece(u2.H, u2.V)]
+                    G, U, info = stitch_mod.stitch(pieces, r, self.max_iter, self.tol)
+                    v.H, v.V, v.info = G, U, info
+
+    # -- Alg. "recall" ---------------------------------------------------------
+    def _accept(self, v: Node, ts: int, te: int) -> bool:
+        inter = max(0, min(te, self.tau(v)) - max(ts, self.sigma(v)))
+        num, den = self.theta
+        return den * inter >= num * (self.tau(v) - self.sigma(v))
+
+    def recall(self, ts: int, te: int, _visited: Optional[list] = None) -> List[Tuple[Node, int, int]]:
+        """Pruned hit set of [ts, te) in time order: (node, lo, hi) with the
+        clipped range [lo, hi) in slices."""
+        if not (0 <= ts < te <= self.T):
+            raise ValueError("range [%d,%d) not inside [0,%d)" % (ts, te, self.T))
+        out: List[Node] = []
+
+        def rec(v: Node):
+            if _visited is not None:
+                _visited.append(v)
+            if v.kind in ("L", "M") and self._accept(v, ts, te):
+                out.append(v)
+                return
+            if v.kind == "L":          # terminal leaf below the threshold
+                out.append(v)
+                return
+            u1, u2 = v.left, v.right
+            if te <= self.tau(u1):
+                rec(u1)
+            elif u2 is not None and ts >= self.sigma(u2):
+                rec(u2)
+            else:
+                assert u2 is not None, "placeholder without right child inside the range"
+                rec(u1)
+                rec(u2)
+
+        rec(self.root)
+        return [(v, max(ts, self.sigma(v)), min(te, self.tau(v))) for v in out]
+
+    # -- Sec. 6.1 query ----------------------------------------------------------
+    def query(self, ts: int, te: int, max_iter: Optional[int] = None,
+              tol: Optional[float] = None):
+        """Tucker decomposition of X[ts:te): Recall, trims, Stitch.
+        Returns (G, [U^(1)..U^(p)], info)."""
+        max_iter = self.max_iter if max_iter is None else max_iter
+        tol = self.tol if tol is None else tol
+        hits = self.recall(ts, te)
+        if len(hits) == 1 and hits[0][1] == self.sigma(hits[0][0]) and hits[0][2] == self.tau(hits[0][0]):
+            v = hits[0][0]
+            return v.H.copy(), [U.copy() for U in v.V], {
+                "sweeps": 0, "fits": [], "converged": True, "hits": hits,
+                "err_model": None, "norm_ytilde": None}
+        pieces = []
+        for v, lo, hi in hits:
+            if lo == self.sigma(v) and hi == self.tau(v):
+                pieces.append(stitch_mod.Piece(v.H, list(v.V)))
+            else:
+                pieces.append(stitch_mod.trim(v.H, v.V, lo - self.sigma(v), hi - lo))
+        r = effective_ranks(te - ts, self.dims, self.ranks)
+        G, U, info = stitch_mod.stitch(pieces, r, max_iter, tol)
+        info["hits"] = hits
+        return G, U, info
+
+    def pieces(self, ts: int, te: int):
+        """The pieces Y~_i of a query (after trims), for the checks."""
+        out = []
+        for v, lo, hi in self.recall(ts, te):
+            if lo == self.sigma(v) and hi == self.tau(v):
+                out.append(stitch_mod.Piece(v.H, list(v.V)))
+            else:
+                out.append(stitch_mod.trim(v.H, v.V, lo - self.sigma(v), hi - lo))
+        return out
+
+    def complete_nodes(self) -> List[Node]:
+        return [v for v in self.nodes if v.kind in ("L", "M")]

@@ -1,0 +1,188 @@
+/*
+ * tucket.h -- C ABI of the MI355X TUCKET range-query engine.
+ *
+ * Operations follow the paper's problem statement (Qiu et al., PVLDB 17(13),
+ * 2024, Sec. 3): a tensor stream X in R^{* x D_2 x ... x D_p} whose first mode
+ * is time receives slices X_T (stream update), and a range query [t_s, t_e)
+ * returns a Tucker decomposition of X[t_s:t_e): a core G of size
+ * r_1 x ... x r_p and factors U^(1) ((t_e - t_s) x r_1), U^(n) (D_n x r_n).
+ * The data structure is the stream segment tree of Sec. 4.2 (built by
+ * Alg. "append"/"insert", Sec. 6.2); queries run Alg. "recall" (Sec. 5.1)
+ * and Alg. "stitch" (Sec. 5.2) on the device.
+ *
+ * Conventions
+ *   - Tensors are C-order (row-major), time first (App. A: vec is C-order,
+ *     mat_n rows run over mode n).  Factors are [rows][columns] row-major.
+ *   - Modes are numbered 0..p-1 in arrays; index 0 is the temporal mode.
+ *   - Every floating-point buffer crossing the ABI is IEEE binary32.
+ *   - "device" pointers are HIP device allocations on the device that was
+ *     current when the tree was created; "host" pointers are ordinary memory.
+ *   - Leaves hold blocks of leaf_len slices; only whole blocks are committed,
+ *     so a query needs 0 <= t_s < t_e <= T_c = leaf_len * floor(T / leaf_len).
+ *   - Output ranks are the effective ranks of the range: r_1 <= length,
+ *     r_n <= D_n, and r_n <= prod_{m != n} r_m (tk_query_shape reports them).
+ *
+ * Errors: every call returns a tk_status and never aborts.  Argument checks
+ * happen before any device work.  A failed device call returns TK_EDEVICE
+ * and poisons the tree (later calls return TK_EDEVICE); tk_last_error()
+ * gives the message.
+ */
+#ifndef TUCKET_H
+#define TUCKET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TK_MAX_MODES 8
+
+typedef enum {
+  TK_OK = 0,
+  TK_EINVAL = 1,  /* bad argument (dims, ranks, null pointer, ...)          */
+  TK_ERANGE = 2,  /* query range outside [0, T_c), or t_s >= t_e              */
+  TK_ENOMEM = 3,  /* capacity or memory budget exceeded                      */
+  TK_EDEVICE = 4, /* a HIP call failed; the tree is poisoned                 */
+  TK_EBUSY = 5    /* serving queue full                                       */
+} tk_status;
+
+typedef enum {
+  TK_F32 = 1,  /* contractions and Grams in FP32                             */
+  TK_BF16 = 2  /* BF16 operands, FP32 accumulation                           */
+} tk_prec;
+
+typedef struct tk_tree tk_tree;
+
+/* Tree configuration.  Hyperparameter defaults of Sec. 8.1: max_iter 20,
+ * tol 0.01, theta 0.7. */
+typedef struct {
+  int32_t p;                      /* number of modes, 2..6 (time included)   */
+  int64_t dims[TK_MAX_MODES];     /* dims[1..p-1] = D_2..D_p; dims[0] unused */
+  int32_t ranks[TK_MAX_MODES];    /* target ranks r_1..r_p                   */
+  int32_t leaf_len;               /* slices per leaf block, >= 1             */
+  int32_t theta_num, theta_den;   /* pruning threshold theta = num/den       */
+  int32_t max_iter;               /* ALS sweep cap (>= 1)                    */
+  double tol;                     /* stop when |fit_k - fit_{k-1}| < tol     */
+  int32_t prec;                   /* tk_prec                                 */
+  int64_t capacity_T;             /* maximum number of slices                */
+  int64_t mem_budget_bytes;       /* device bytes the tree may use; 0 = any  */
+} tk_config;
+
+/* One member of a pruned hit set (Alg. "recall"). */
+typedef struct {
+  int32_t level;     /* node covers leaf blocks [index 2^level, (index+1) 2^level) */
+  int32_t partial;   /* 1 if the node is only partly inside the query           */
+  int64_t index;
+  int64_t node_id;   /* 1-based creation order (numbering of Fig. "illust")     */
+  int64_t sigma;     /* node range [sigma, tau) in slices                       */
+  int64_t tau;
+  int64_t lo;        /* clipped range [lo, hi) = [t_s, t_e) & [sigma, tau)      */
+  int64_t hi;
+} tk_hit;
+
+/* Shape of a query's output. */
+typedef struct {
+  int32_t ranks_eff[TK_MAX_MODES]; /* effective output ranks                   */
+  int64_t L;                       /* t_e - t_s                                */
+  int64_t core_elems;              /* prod of ranks_eff                        */
+  int64_t factor_elems[TK_MAX_MODES]; /* [0] = L r_1; [n] = D_n r_n            */
+  int32_t n_hits;
+} tk_shape;
+
+/* A query result.  core and factor[0..p-1] are caller-owned DEVICE buffers of
+ * at least the sizes tk_query_shape reports (float elements); the call
+ * fills the other fields. */
+typedef struct {
+  float* core;
+  float* factor[TK_MAX_MODES];
+  int32_t ranks_eff[TK_MAX_MODES];
+  int32_t sweeps;      /* ALS sweeps run (0: the range is one stored node)     */
+  int32_t converged;   /* 1 if the fit-change rule stopped the loop            */
+  int32_t n_hits;
+  double fit;          /* 1 - |Y~ - Y^| / |Y~|                                 */
+  double err_model;    /* |Y~ - Y^| / |Y~|, Y~ = concatenated hit pieces       */
+  double norm_ytilde;  /* |Y~|_F                                               */
+} tk_result;
+
+typedef struct {
+  int64_t T;             /* slices appended                                   */
+  int64_t T_committed;   /* slices in complete leaf blocks (queryable)        */
+  int64_t blocks;        /* complete leaf blocks                              */
+  int64_t nodes;         /* nodes created, placeholders included              */
+  int64_t merges_total;  /* stitches run by appends                           */
+  int64_t merges_last;   /* stitches run by the last completed block          */
+  int64_t store_bytes;   /* device bytes held by the node store               */
+  int32_t height;        /* tree height (Thm. "height-T")                     */
+} tk_stats;
+
+/* Create an empty tree.  hip_stream: a hipStream_t (NULL = default stream);
+ * all device work of the tree is ordered on it.  The node store for
+ * capacity_T slices is allocated here.  *out is owned by the caller and
+ * released with tk_destroy. */
+tk_status tk_create(const tk_config* cfg, void* hip_stream, tk_tree** out);
+void tk_destroy(tk_tree* t);
+const char* tk_last_error(const tk_tree* t);
+
+/* Stream update (Sec. 3; Alg. "append"): one slice of D_2 x ... x D_p FP32
+ * values, on the host (copied before return) or on the device (read in
+ * stream order).  When a leaf block completes, the leaf Tucker decomposition
+ * (Tucker-ALS, Sec. 2) and the stitches of Alg. "insert" run on the device. */
+tk_status tk_append(tk_tree* t, const float* slice, int on_device);
+
+/* T successive appends of X (T x D_2 x ... x D_p, C-order), executed level
+ * by level: all leaves in one launch, then each tree level's merges. */
+tk_status tk_build(tk_tree* t, const float* X, int64_t T, int on_device);
+
+/* Pruned hit set of [t_s, t_e) in time order (host-side, bit-exact
+ * integer Alg. "recall").  Writes at most cap hits; *n = hits needed. */
+tk_status tk_hitset(const tk_tree* t, int64_t ts, int64_t te, tk_hit* out,
+                    int32_t cap, int32_t* n);
+
+tk_status tk_query_shape(const tk_tree* t, int64_t ts, int64_t te, tk_shape* out);
+
+/* Range query (Sec. 6.1): Recall, partial-hit trims (Eq. "partial-tucker")
+ * and Stitch, one device launch.  Blocks until the result is written. */
+tk_status tk_query(tk_tree* t, int64_t ts, int64_t te, tk_result* res);
+
+/* n range queries stitched in one device launch (one workgroup per query).
+ * Each query's result is identical to what tk_query returns for it. */
+tk_status tk_query_batch(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* te,
+                         tk_result* res);
+
+/* Override the ALS sweep cap and tolerance for later queries (not merges). */
+tk_status tk_set_query_iters(tk_tree* t, int32_t max_iter, double tol);
+
+tk_status tk_stats_get(const tk_tree* t, tk_stats* out);
+
+/* Node store access (checkpoint/restore and tests).  A node (level, index)
+ * is complete once (index+1) 2^level <= blocks.  Buffers are HOST float
+ * arrays: core of prod(r_eff(level)) elements, factor[0] of
+ * (leaf_len 2^level) x r_1 elements, factor[n] of D_n x r_n elements, with
+ * r_eff the effective ranks of a range of length leaf_len 2^level. */
+tk_status tk_node_ranks(const tk_tree* t, int32_t level, int32_t* ranks_eff);
+tk_status tk_read_node(tk_tree* t, int32_t level, int64_t index, float* core,
+                       float* const* factor);
+/* Set the committed horizon to T slices without computing anything, then
+ * load complete nodes with tk_load_node.  Queries are valid once every node
+ * they touch is loaded. */
+tk_status tk_restore_begin(tk_tree* t, int64_t T);
+tk_status tk_load_node(tk_tree* t, int32_t level, int64_t index, const float* core,
+                       const float* const* factor);
+
+/* Host-only planning helpers (no tree, no device): the pruned hit set of
+ * [t_s, t_e) in a tree of committed horizon T built with cfg's leaf_len and
+ * theta, and the effective ranks of a range of the given length. */
+tk_status tk_hitset_plan(const tk_config* cfg, int64_t T, int64_t ts, int64_t te, tk_hit* out,
+                         int32_t cap, int32_t* n);
+tk_status tk_effective_ranks(const tk_config* cfg, int64_t length, int32_t* ranks_eff);
+
+/* Library version, "major.minor.patch". */
+const char* tk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TUCKET_H */

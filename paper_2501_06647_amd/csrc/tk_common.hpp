@@ -1,0 +1,378 @@
+// Shared host/device definitions: dyadic tree topology, Recall, effective
+// ranks, device views of the node store and job descriptors, and the
+// workspace layout of a stitch job.  Everything here is compiled once for the
+// host and once for the device from the same source, so the host-side hit
+// sets and workspace sizes are bit-identical to what the kernels use.
+#pragma once
+
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#define TK_HD __host__ __device__ inline
+
+namespace tk {
+
+constexpr int MAXP = 6;      // modes handled by the kernels (time included)
+constexpr int MAXLEV = 48;   // tree levels (2^47 leaf blocks)
+constexpr int MAXHITS = 96;  // hits per query: <= 2(h-1), h <= MAXLEV
+
+// ---------------------------------------------------------------------------
+// Topology.  The stream segment tree built by Alg. "append"/"insert" (Sec.
+// 6.2) is the dyadic segment tree over leaf blocks, created lazily: node
+// (k, j) covers blocks [j 2^k, (j+1) 2^k), exists once its first block has
+// arrived, and is complete (a leaf or intermediate node) once its last block
+// has.  The root after T_b blocks sits at level ceil(log2 T_b) (Thm.
+// "alg-log-height": height ceil(log2 T) + 1).
+// ---------------------------------------------------------------------------
+
+TK_HD int root_level(int64_t Tb) {
+  int k = 0;
+  while ((int64_t(1) << k) < Tb) ++k;
+  return k;
+}
+
+TK_HD bool node_complete(int k, int64_t j, int64_t Tb) { return ((j + 1) << k) <= Tb; }
+
+TK_HD int popcount64(uint64_t x) {
+  int c = 0;
+  while (x) {
+    x &= x - 1;
+    ++c;
+  }
+  return c;
+}
+
+TK_HD int bitlen64(uint64_t x) {
+  int c = 0;
+  while (x) {
+    x >>= 1;
+    ++c;
+  }
+  return c;
+}
+
+// 1-based creation order of node (k, j) under Alg. "append"/"insert": the
+// node is created when block c arrives, c = 2^(k-1) for a new root (j = 0,
+// k >= 1) and c = j 2^k otherwise; blocks before c created
+// [c>=1] + [c>=2](2(c-1) - popcount(c-1) + bitlen(c-1)) nodes; at block c the
+// new root (if c is a power of two) comes first, then levels nu_2(c) .. 0.
+TK_HD int64_t node_id(int k, int64_t j) {
+  const int64_t c = (j == 0 && k >= 1) ? (int64_t(1) << (k - 1)) : (j << k);
+  int64_t before = 0;
+  if (c == 1) {
+    before = 1;
+  } else if (c >= 2) {
+    const uint64_t m = uint64_t(c - 1);
+    before = 1 + 2 * int64_t(m) - popcount64(m) + bitlen64(m);
+  }
+  int64_t pos = 0;
+  if (c > 0) {
+    const bool pow2 = (c & (c - 1)) == 0;
+    if (j == 0 && k >= 1) {
+      pos = 0;  // the new root
+    } else {
+      const int nu = bitlen64(uint64_t(c & -c)) - 1;
+      pos = (pow2 ? 1 : 0) + (nu - k);
+    }
+  }
+  return before + 1 + pos;
+}
+
+struct Hit {
+  int32_t level;
+  int32_t partial;
+  int64_t index;
+  int64_t a;  // clipped start inside the node, in slices
+  int64_t l;  // clipped length
+};
+
+// Alg. "recall" (Sec. 5.1) on the dyadic tree, iteratively with an explicit
+// stack.  A complete node v is taken when den |[ts,te) & v| >= num |v|
+// (theta = num/den, exact integer test); a leaf that is reached is taken even
+// below the threshold (it has no children).  Hits come out in time order.
+// Returns the number of hits (writes at most cap of them), or -1 if the range
+// is outside [0, Tb ell) or empty.
+TK_HD int recall(int64_t ts, int64_t te, int64_t Tb, int64_t ell, int64_t num, int64_t den,
+                 Hit* out, int cap) {
+  if (!(ts >= 0 && ts < te && te <= Tb * ell)) return -1;
+  int64_t sk[2 * MAXLEV + 4];
+  int sp = 0;
+  const int K = root_level(Tb);
+  sk[sp++] = (int64_t(K) << 56) | 0;  // (level << 56) | index
+  int n = 0;
+  while (sp > 0) {
+    const int64_t e = sk[--sp];
+    const int k = int(e >> 56);
+    const int64_t j = e & ((int64_t(1) << 56) - 1);
+    const int64_t sig = (j << k) * ell;
+    const int64_t tau = ((j + 1) << k) * ell;
+    const int64_t lo = ts > sig ? ts : sig;
+    const int64_t hi = te < tau ? te : tau;
+    if (node_complete(k, j, Tb) && (k == 0 || den * (hi - lo) >= num * (tau - sig))) {
+      if (n < cap) {
+        out[n].level = k;
+        out[n].index = j;
+        out[n].a = lo - sig;
+        out[n].l = hi - lo;
+        out[n].partial = (lo != sig || hi != tau) ? 1 : 0;
+      }
+      ++n;
+      continue;
+    }
+    const int64_t mid = sig + (tau - sig) / 2;
+    const int64_t left = (int64_t(k - 1) << 56) | (2 * j);
+    const int64_t right = (int64_t(k - 1) << 56) | (2 * j + 1);
+    if (te <= mid) {
+      sk[sp++] = left;
+    } else if (ts >= mid) {
+      sk[sp++] = right;
+    } else {
+      sk[sp++] = right;  // popped after the left subtree: time order
+      sk[sp++] = left;
+    }
+  }
+  return n;
+}
+
+// Effective ranks of a len x D_1 x ... x D_{p-1} range: r_0 <= len,
+// r_n <= D_n, and r_n <= prod_{m != n} r_m, iterated to a fixed point (a mode
+// rank cannot exceed the product of the others).
+TK_HD void effective_ranks(int p, int64_t len, const int64_t* D, const int32_t* r, int32_t* out) {
+  out[0] = int32_t(r[0] < len ? r[0] : len);
+  for (int n = 1; n < p; ++n) out[n] = int32_t(r[n] < D[n] ? r[n] : D[n]);
+  bool changed = true;
+  while (changed) {
+    changed = false;
+    for (int n = 0; n < p; ++n) {
+      int64_t other = 1;
+      for (int m = 0; m < p; ++m)
+        if (m != n) other *= out[m];
+      if (out[n] > other) {
+        out[n] = int32_t(other);
+        changed = true;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Device view of the node store.  Level k holds n_k node slots; node (k, j)
+// has a dense core of prod(rk[k]) floats, factors D_n x rk[k][n] for n >= 1,
+// and owns rows [j ell 2^k, (j+1) ell 2^k) of the level's temporal plane
+// (row width rk[k][0]).  Addresses are arithmetic; nodes never move.
+// ---------------------------------------------------------------------------
+struct StoreView {
+  int32_t p;
+  int32_t nlev;
+  int64_t ell;
+  int64_t D[MAXP];  // D[0] unused
+  int32_t rk[MAXLEV][MAXP];
+  int64_t core_elems[MAXLEV];
+  float* core[MAXLEV];
+  float* fac[MAXLEV][MAXP];
+  float* plane[MAXLEV];
+};
+
+TK_HD int64_t fac_elems(const StoreView& st, int k, int n) { return st.D[n] * st.rk[k][n]; }
+
+// A stitch job: a range query or the merge of two children (Alg. "insert").
+struct Job {
+  int32_t kind;  // 0 query, 1 merge
+  int32_t s;     // hits
+  int32_t hit0;  // first hit in the launch's hit array
+  int32_t pad0;
+  int64_t L;
+  int32_t rq[MAXP];          // output effective ranks
+  float* out_core;           // prod(rq) floats
+  float* out_fac[MAXP];      // [0]: L x rq[0] rows; [n]: D_n x rq[n]
+  double* stats;             // 8 doubles (see STAT_*)
+  int64_t ws_off;            // byte offset of the job's workspace
+};
+
+// A leaf job: Tucker-ALS of one raw block.
+struct LeafJob {
+  const float* X;     // ell x D_1 x ... x D_{p-1}
+  int64_t block;      // leaf index
+  double* stats;
+  int64_t ws_off;
+};
+
+enum { STAT_FIT = 0, STAT_ERR = 1, STAT_NORM = 2, STAT_SWEEPS = 3, STAT_CONV = 4, STAT_HITS = 5 };
+
+// ---------------------------------------------------------------------------
+// Workspace layout of a stitch job (bump allocation, 256-byte aligned), used
+// by the host to size the workspace and by the kernel to find its buffers.
+// ---------------------------------------------------------------------------
+struct StitchLayout {
+  int64_t Ht[MAXHITS];        // float k_i x R_i, partial hits only
+  int64_t F[MAXHITS];         // double k_i x k_i, partial hits only
+  int64_t A[MAXHITS];         // float sum_{n>=1} rq_n x r_i^(n), modes in order
+  int64_t F0[MAXHITS];        // double k_i x rq_0
+  int64_t C[MAXP];            // float D_n x sr_n (q_n x sr_n used)
+  int64_t C64[MAXP];          // double, same
+  int64_t A64[MAXHITS];       // double, same shape as A
+  int64_t Fn[MAXP];           // double sr_n x sr_n (basis route only)
+  int64_t Pd[MAXP];           // double D_n x rq_n  ([0]: sk x rq_0)
+  int64_t Pf[MAXP];           // float  same
+  int64_t Fh[MAXP];           // double sr_n x rq_n
+  int64_t M;                  // float sk x Rhat_0
+  int64_t K;                  // float max_n qmax_n Rhat_n
+  int64_t T1, T2;             // float tmax
+  int64_t D1, D2;             // double tmax (final FP64 core)
+  int64_t G;                  // float prod(rq)
+  int64_t G64;                // double prod(rq)
+  int64_t EIG;                // double neig^2 + 4 neig (only when neig > n_lds)
+  int64_t total;
+  int32_t sr[MAXP];           // sum over hits of r_i^(n)
+  int32_t qmax[MAXP];
+  int32_t sk;                 // sum over hits of k_i
+  int32_t neig;               // largest eigenproblem
+  int64_t tmax;
+};
+
+TK_HD int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+// Doubles needed by the eigensolver for an n x n problem: the matrix, then
+// column norms, ranks, Gram-Schmidt coefficients and eigenvalues.
+TK_HD int64_t eig_doubles(int64_t n) { return n * n + 4 * n; }
+
+TK_HD void stitch_layout(const StoreView& st, const Hit* hits, int s, const int32_t* rq,
+                         int n_lds, StitchLayout* Lo) {
+  const int p = st.p;
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t o = off;
+    off = align256(off + (bytes > 0 ? bytes : 0));
+    return o;
+  };
+  int64_t Rhat[MAXP];
+  for (int n = 0; n < p; ++n) {
+    int64_t pr = 1;
+    for (int m = 0; m < p; ++m)
+      if (m != n) pr *= rq[m];
+    Rhat[n] = pr;
+  }
+  Lo->sk = 0;
+  for (int n = 0; n < p; ++n) Lo->sr[n] = 0;
+  Lo->tmax = 1;
+  int maxk = 0;
+  for (int i = 0; i < s; ++i) {
+    const int lev = hits[i].level;
+    const int k = st.rk[lev][0];
+    int64_t R = 1;
+    for (int n = 1; n < p; ++n) R *= st.rk[lev][n];
+    Lo->Ht[i] = hits[i].partial ? take(int64_t(k) * R * 4) : -1;
+    Lo->F[i] = hits[i].partial ? take(int64_t(k) * k * 8) : -1;
+    int64_t asz = 0;
+    for (int n = 1; n < p; ++n) asz += int64_t(rq[n]) * st.rk[lev][n];
+    Lo->A[i] = take(asz * 4);
+    Lo->A64[i] = take(asz * 8);
+    Lo->F0[i] = take(int64_t(k) * rq[0] * 8);
+    Lo->sk += k;
+    if (k > maxk) maxk = k;
+    for (int n = 1; n < p; ++n) Lo->sr[n] += st.rk[lev][n];
+    int64_t t = (k > rq[0] ? k : rq[0]);
+    for (int n = 1; n < p; ++n) t *= (st.rk[lev][n] > rq[n] ? st.rk[lev][n] : rq[n]);
+    if (t > Lo->tmax) Lo->tmax = t;
+    if (int64_t(k) * k > Lo->tmax) Lo->tmax = int64_t(k) * k;  // R~ of a trim
+  }
+  int neig = maxk > Lo->sk ? maxk : Lo->sk;
+  int64_t kmax = 0;
+  for (int n = 1; n < p; ++n) {
+    // reduced coordinates: q_n <= sr_n on the basis route, q_n = D_n otherwise
+    Lo->qmax[n] = int32_t(st.D[n]);
+    Lo->C[n] = take(int64_t(Lo->qmax[n]) * Lo->sr[n] * 4);
+    Lo->C64[n] = take(int64_t(Lo->qmax[n]) * Lo->sr[n] * 8);
+    Lo->Fn[n] = take(st.D[n] > Lo->sr[n] ? int64_t(Lo->sr[n]) * Lo->sr[n] * 8 : 0);
+    Lo->Pd[n] = take(int64_t(Lo->qmax[n]) * rq[n] * 8);
+    Lo->Pf[n] = take(int64_t(Lo->qmax[n]) * rq[n] * 4);
+    Lo->Fh[n] = take(int64_t(Lo->sr[n]) * rq[n] * 8);
+    if (Lo->sr[n] > neig) neig = Lo->sr[n];
+    if (Lo->qmax[n] > neig) neig = Lo->qmax[n];
+    const int64_t kn = int64_t(Lo->qmax[n]) * Rhat[n];
+    if (kn > kmax) kmax = kn;
+  }
+  Lo->qmax[0] = Lo->sk;
+  Lo->sr[0] = Lo->sk;
+  Lo->Pd[0] = take(int64_t(Lo->sk) * rq[0] * 8);
+  Lo->Pf[0] = take(int64_t(Lo->sk) * rq[0] * 4);
+  Lo->M = take(int64_t(Lo->sk) * Rhat[0] * 4);
+  Lo->K = take(kmax * 4);
+  // the HOSVD init keeps C_i S_i (q x r) in T1
+  int64_t tq = 0;
+  for (int n = 1; n < p; ++n) {
+    int64_t rmax = 0;
+    for (int i = 0; i < s; ++i)
+      if (st.rk[hits[i].level][n] > rmax) rmax = st.rk[hits[i].level][n];
+    if (int64_t(Lo->qmax[n]) * rmax > tq) tq = int64_t(Lo->qmax[n]) * rmax;
+  }
+  if (tq > Lo->tmax) Lo->tmax = tq;
+  Lo->T1 = take(Lo->tmax * 4);
+  Lo->T2 = take(Lo->tmax * 4);
+  Lo->D1 = take(Lo->tmax * 8);
+  Lo->D2 = take(Lo->tmax * 8);
+  int64_t gel = 1;
+  for (int n = 0; n < p; ++n) gel *= rq[n];
+  Lo->G = take(gel * 4);
+  Lo->G64 = take(gel * 8);
+  Lo->neig = neig;
+  Lo->EIG = neig > n_lds ? take(eig_doubles(neig) * 8) : -1;
+  Lo->total = off;
+}
+
+// Workspace of a leaf job.
+struct LeafLayout {
+  int64_t Ud[MAXP];  // double D_n x rq_n (D_0 = ell)
+  int64_t Uf[MAXP];  // float
+  int64_t T1, T2;    // float, size of the raw block
+  int64_t V;         // double N x rq (other-side route)
+  int64_t G;         // float prod(rq)
+  int64_t EIG;       // double eig_doubles(neig) when neig > n_lds
+  int64_t total;
+  int32_t neig;
+};
+
+TK_HD void leaf_layout(const StoreView& st, int n_lds, LeafLayout* Lo) {
+  const int p = st.p;
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t o = off;
+    off = align256(off + (bytes > 0 ? bytes : 0));
+    return o;
+  };
+  int64_t Dm[MAXP];
+  Dm[0] = st.ell;
+  for (int n = 1; n < p; ++n) Dm[n] = st.D[n];
+  int64_t size = 1;
+  for (int n = 0; n < p; ++n) size *= Dm[n];
+  const int32_t* rq = st.rk[0];
+  int neig = 0;
+  int64_t vmax = 0;
+  for (int n = 0; n < p; ++n) {
+    Lo->Ud[n] = take(Dm[n] * rq[n] * 8);
+    Lo->Uf[n] = take(Dm[n] * rq[n] * 4);
+    // HOSVD: mat_n(X) is D_n x size/D_n; sweeps: D_n x prod_{m != n} rq_m
+    int64_t other = 1;
+    for (int m = 0; m < p; ++m)
+      if (m != n) other *= rq[m];
+    const int64_t other0 = size / Dm[n];
+    const int64_t e1 = Dm[n] < other0 ? Dm[n] : other0;
+    const int64_t e2 = Dm[n] < other ? Dm[n] : other;
+    if (e1 > neig) neig = int(e1);
+    if (e2 > neig) neig = int(e2);
+    if (Dm[n] > other0 && other0 * rq[n] > vmax) vmax = other0 * rq[n];
+    if (Dm[n] > other && other * rq[n] > vmax) vmax = other * rq[n];
+  }
+  Lo->T1 = take(size * 4);
+  Lo->T2 = take(size * 4);
+  Lo->V = take(vmax * 8);
+  int64_t gel = 1;
+  for (int n = 0; n < p; ++n) gel *= rq[n];
+  Lo->G = take(gel * 4);
+  Lo->neig = neig;
+  Lo->EIG = neig > n_lds ? take(eig_doubles(neig) * 8) : -1;
+  Lo->total = off;
+}
+
+}  // namespace tk

@@ -1,0 +1,137 @@
+"""CPU-only checks of libtucket: exports, host-side integer logic, argument errors.
+
+No compute call reaches a GPU here: tk_hitset_plan and tk_effective_ranks are
+host-only, and invalid configurations are rejected before any device call.
+"""
+
+import ctypes
+import itertools
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.tree import StreamSegmentTree
+from oracle.tucker import effective_ranks as orc_ranks
+from paper_2501_06647_amd import tucket as tk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(tk_[a-z_]+)\s*\(", src))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = tk.lib()
+    declared = _declared_symbols()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(L, name), name
+    assert declared == {n for n, _, _ in tk.SIGNATURES}
+    assert tk.lib().tk_version().decode().count(".") == 2
+
+
+@pytest.mark.parametrize("leaf_len,theta", [(1, (7, 10)), (1, (1, 2)), (3, (7, 10)), (4, (9, 10)),
+                                            (2, (1, 1))])
+def test_host_recall_bit_exact_vs_oracle(leaf_len, theta):
+    cfg = tk.make_config((2, 2), (1, 1, 1), leaf_len=leaf_len, theta=theta, capacity_T=1 << 20)
+    for T_b in list(range(1, 20)) + [33, 64, 65]:
+        orc = StreamSegmentTree((2, 2), (1, 1, 1), leaf_len, theta)
+        for _ in range(T_b):
+            orc.append(None)
+        T = orc.T
+        ranges = [(a, b) for a in range(T) for b in range(a + 1, T + 1)]
+        if len(ranges) > 3000:
+            rng = np.random.default_rng(T_b)
+            ranges = [ranges[i] for i in rng.choice(len(ranges), 3000, replace=False)]
+        for ts, te in ranges:
+            got = tk.hitset_plan(cfg, T, ts, te)
+            exp = orc.recall(ts, te)
+            assert len(got) == len(exp)
+            for g, (v, lo, hi) in zip(got, exp):
+                assert (g["node_id"], g["sigma"], g["tau"], g["lo"], g["hi"]) == \
+                    (v.id, orc.sigma(v), orc.tau(v), lo, hi)
+                assert g["partial"] == (not (lo == orc.sigma(v) and hi == orc.tau(v)))
+                k = g["level"]
+                assert (v.hi - v.lo) == 1 << k and v.lo == g["index"] << k
+
+
+def test_host_recall_large_trees_sampled():
+    """Bit-exact on the full-size workloads' trees (sampled ranges)."""
+    for T, ell in [(4096, 8), (16384, 16), (32768, 1), (65536, 1)]:
+        cfg = tk.make_config((2, 2), (1, 1, 1), leaf_len=ell, capacity_T=T)
+        orc = StreamSegmentTree((2, 2), (1, 1, 1), ell)
+        for _ in range(T // ell):
+            orc.append(None)
+        rng = np.random.default_rng(T)
+        for _ in range(400):
+            L = int(np.exp(rng.uniform(0, np.log(T))))
+            ts = int(rng.integers(0, T - L + 1))
+            got = tk.hitset_plan(cfg, T, ts, ts + L)
+            exp = orc.recall(ts, ts + L)
+            assert [(g["node_id"], g["lo"], g["hi"]) for g in got] == [(v.id, lo, hi) for v, lo, hi in exp]
+
+
+def test_paper_example_through_the_abi():
+    cfg = tk.make_config((2, 2), (1, 1, 1), leaf_len=1, theta=(7, 10), capacity_T=16)
+    got = tk.hitset_plan(cfg, 9, 1, 6)
+    assert [(g["node_id"], g["lo"], g["hi"], g["partial"]) for g in got] == \
+        [(4, 1, 4, True), (10, 4, 6, False)]
+
+
+def test_host_recall_rejects_bad_ranges():
+    cfg = tk.make_config((2, 2), (1, 1, 1), leaf_len=4, capacity_T=64)
+    for ts, te in [(0, 0), (5, 3), (-1, 2), (0, 33)]:
+        with pytest.raises(tk.TuckerError) as e:
+            tk.hitset_plan(cfg, 34, ts, te)       # T_c = 32 with leaf_len 4
+        assert e.value.status == tk.TK_ERANGE
+
+
+def test_effective_ranks_match_oracle():
+    rng = np.random.default_rng(0)
+    for _ in range(500):
+        p = int(rng.integers(2, 6))
+        dims = tuple(int(x) for x in rng.integers(1, 40, size=p - 1))
+        ranks = tuple(int(x) for x in rng.integers(1, 33, size=p))
+        length = int(rng.integers(1, 100))
+        cfg = tk.make_config(dims, ranks, capacity_T=1 << 10)
+        assert tk.effective_ranks(cfg, length) == orc_ranks(length, dims, ranks)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dims=(), ranks=(4,)),                              # p = 1
+    dict(dims=(3, 3), ranks=(4, 0, 4)),                     # zero rank
+    dict(dims=(3, 3), ranks=(4, 40, 4)),                    # rank above the kernel limit
+    dict(dims=(3, 3), ranks=(4, 4, 4), leaf_len=0),
+    dict(dims=(3, 3), ranks=(4, 4, 4), theta=(8, 7)),       # theta > 1
+    dict(dims=(3, 3), ranks=(4, 4, 4), theta=(0, 7)),
+    dict(dims=(3, 3), ranks=(4, 4, 4), max_iter=0),
+    dict(dims=(3, 3), ranks=(4, 4, 4), tol=-1.0),
+    dict(dims=(3, 3), ranks=(4, 4, 4), capacity_T=0),
+    dict(dims=(3, 3), ranks=(4, 4, 4), prec=7),
+])
+def test_create_rejects_bad_config_before_device_work(bad):
+    kw = dict(leaf_len=1, theta=(7, 10), max_iter=20, tol=0.01, capacity_T=64)
+    kw.update({k: v for k, v in bad.items() if k not in ("dims", "ranks")})
+    cfg = tk.make_config(bad["dims"], bad["ranks"], **kw)
+    h = ctypes.c_void_p(0)
+    st = tk.lib().tk_create(ctypes.byref(cfg), None, ctypes.byref(h))
+    assert st == tk.TK_EINVAL
+    assert not h.value
+    assert tk.lib().tk_last_error(None)
+
+
+def test_create_respects_memory_budget():
+    cfg = tk.make_config((128, 128), (16, 16, 16), leaf_len=1, capacity_T=65536,
+                         mem_budget_bytes=1 << 20)
+    h = ctypes.c_void_p(0)
+    assert tk.lib().tk_create(ctypes.byref(cfg), None, ctypes.byref(h)) == tk.TK_ENOMEM
+    assert b"mem_budget" in tk.lib().tk_last_error(None)

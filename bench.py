@@ -1,0 +1,232 @@
+#!/usr/bin/env python
+"""Range queries/s of the TUCKET stitch engine on one MI355X.
+
+A step answers every query of the workload's query list in one batched
+device launch (Recall, partial-hit trims and Stitch for each query, one
+workgroup per query), with the node store already built and resident in
+HBM.  Beside it the same queries run one per launch (the plain GPU path),
+giving per-query latencies (p50/p99), and the FP64 CPU oracle is timed on a
+bounded sample on the host cores.
+
+Prints one JSON line (see the keys below).
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3     # MI355X dense FP32 (MFMA and packed vector)
+HBM_TBPS = 8.0
+
+
+def stitch_flops(p, D, rq, hits, node_ranks, sweeps, L):
+    """Algorithmic FLOPs of one query (Alg. "stitch" on its hit set), counted
+    from the shapes: per sweep, per hit the projections U^(m)T V~^(m), the
+    temporal-mode TTM chain and the mode-n chains with their x_n V~ products;
+    per query the Gram of each unfolding (smaller side) and the core update;
+    once, the temporal factor rows and the partial-hit QRs."""
+    if sweeps == 0:
+        return 0.0
+    r = list(rq)
+    R = [math.prod(r[m] for m in range(p) if m != n) for n in range(p)]
+    F = 0.0
+    ksum = 0
+    kbar = 0.0
+    for h in hits:
+        nr = node_ranks[h["level"]]
+        k = nr[0]
+        ksum += k
+        kbar += k * (h["hi"] - h["lo"])
+        f = sum(2.0 * D[m] * r[m] * nr[m] for m in range(1, p))
+        f += sum(2.0 * k * R[0] * r[m] for m in range(1, p))
+        for n in range(1, p):
+            f += 2.0 * r[0] * k * R[0]
+            f += sum(2.0 * r[0] * R[0] * r[m] for m in range(1, p) if m != n)
+            f += 2.0 * D[n] * nr[n] * R[n]
+        F += f
+    Fq = 2.0 * min(ksum * ksum * R[0], R[0] * R[0] * ksum)
+    Fq += sum(2.0 * min(D[n] * D[n] * R[n], R[n] * R[n] * D[n]) for n in range(1, p))
+    Fq += 2.0 * r[p - 1] * D[p - 1] * R[p - 1]
+    Ffin = 2.0 * L * r[0] * (kbar / max(L, 1))
+    Ffin += sum(4.0 * (h["hi"] - h["lo"]) * node_ranks[h["level"]][0] ** 2 for h in hits if h["partial"])
+    return sweeps * (F + Fq) + Ffin
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        n = [d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"]
+        return max(n) if n else 1
+    except Exception:
+        return 1
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="plain")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(queries are independent; see DESIGN.md on sharding)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2501_06647_amd import Tree
+
+    wl = synth.get(args.workload)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    X = synth.series(wl)
+    Xd = torch.from_numpy(X.astype(np.float32)).to(dev)
+    tree = Tree(wl.dims, wl.node_ranks, wl.leaf_len, wl.theta, wl.max_iter, wl.tol, capacity_T=wl.T)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tree.build(Xd)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    print("[bench] built %s tree: %d slices in %.3f s" % (wl.name, wl.T, build_s), file=sys.stderr, flush=True)
+
+    ts, te = synth.queries(wl)
+    nq = len(ts)
+    batch = tree.prepare_batch(ts, te)
+    for _ in range(args.warmup):
+        batch.run()
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.run()
+        kms.append(tree.last_kernel_ms())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1000.0 * wall / args.steps
+    qps = nq * args.steps / wall
+    print("[bench] batched: %.3f ms/step, kernel %.3f ms" % (ms_per_step, float(np.mean(kms))),
+          file=sys.stderr, flush=True)
+
+    results = batch.results()
+    D = [0] + list(wl.dims)
+    node_ranks = {k: tree.node_ranks(k) for k in range(40) if (wl.leaf_len << k) <= wl.T}
+    flops = 0.0
+    sweeps = []
+    hit_counts = []
+    for i in range(nq):
+        hits = tree.hitset(int(ts[i]), int(te[i]))
+        res = results[i]
+        flops += stitch_flops(tree.p, D, res.ranks, hits, node_ranks, res.sweeps, int(te[i] - ts[i]))
+        sweeps.append(res.sweeps)
+        hit_counts.append(len(hits))
+    kernel_s = float(np.mean(kms)) / 1000.0
+    achieved = flops / kernel_s / 1e12
+    prof = [tree.last_profile(i) for i in range(nq)]
+    phase_mean = {k: float(np.mean([pr[k] for pr in prof])) for k in tree.PHASES}
+    tot = np.array([sum(pr[k] for k in tree.PHASES) for pr in prof])
+    counters = {k: float(np.mean([pr[k] for pr in prof])) for k in tree.COUNTERS}
+    print("[bench] eigensolver per query: %s" % json.dumps({k: round(v, 1) for k, v in counters.items()}),
+          file=sys.stderr, flush=True)
+    slow = int(np.argmax(tot))
+    print("[bench] phase mean us: %s" % json.dumps({k: round(v, 1) for k, v in phase_mean.items()}),
+          file=sys.stderr, flush=True)
+    print("[bench] per-query device us: mean %.1f p50 %.1f max %.1f (query %d, %d hits, L=%d)"
+          % (tot.mean(), np.median(tot), tot.max(), slow, hit_counts[slow], int(te[slow] - ts[slow])),
+          file=sys.stderr, flush=True)
+
+    plain = None
+    if not args.no_plain:
+        lat = []
+        for i in range(nq):
+            t1 = time.perf_counter()
+            batch.run_one(i)
+            lat.append(time.perf_counter() - t1)
+        lat = np.array(lat)
+        plain = {"queries_per_s": float(nq / lat.sum()), "p50_ms": float(1000 * np.percentile(lat, 50)),
+                 "p99_ms": float(1000 * np.percentile(lat, 99)), "launches": nq}
+        print("[bench] plain: %.1f q/s p50 %.3f ms p99 %.3f ms" % (plain["queries_per_s"], plain["p50_ms"],
+                                                                 plain["p99_ms"]), file=sys.stderr, flush=True)
+
+    cpu = None
+    accuracy = None
+    if not args.no_cpu:
+        from oracle.evaluate import relative_error
+        from oracle.tree import StreamSegmentTree
+        t0 = time.perf_counter()
+        orc = StreamSegmentTree(wl.dims, wl.node_ranks, wl.leaf_len, wl.theta, wl.max_iter, wl.tol)
+        for b in range(wl.T // wl.leaf_len):
+            orc.append(X[b * wl.leaf_len:(b + 1) * wl.leaf_len])
+        orc_build_s = time.perf_counter() - t0
+        done, qt, deltas, errs = 0, 0.0, [], []
+        while done < nq and qt < args.cpu_seconds:
+            a, b = int(ts[done]), int(te[done])
+            t1 = time.perf_counter()
+            Go, Uo, _ = orc.query(a, b)
+            qt += time.perf_counter() - t1
+            r = results[done]
+            e_g = relative_error(X[a:b], r.core.double().cpu().numpy(), [u.double().cpu().numpy() for u in r.factors])
+            e_o = relative_error(X[a:b], Go, Uo)
+            deltas.append(abs(e_g / e_o - 1.0) if e_o > 0 else e_g)
+            errs.append(e_g)
+            done += 1
+        cpu = {"value": done / qt, "unit": "queries/s", "cores": blas_threads(), "kind": "oracle",
+               "sample": "FP64 NumPy oracle: tree built over all %d slices (%.1f s, %.0f slices/s), then "
+                         "queries 0..%d of the same query list (Recall, QR trims, Stitch with Z^(1) "
+                         "materialised), %.1f s of query time" % (wl.T, orc_build_s, wl.T / orc_build_s,
+                                                                 done - 1, qt)}
+        accuracy = {"n_checked": done, "max_err_ratio_delta": float(max(deltas)),
+                    "median_rel_err": float(np.median(errs)), "gate": 1e-5}
+
+    out = {
+        "metric": "range queries/sec at fixed rel. error; p50/p99 query latency vs plain GPU path",
+        "value": qps,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%s: %s x T=%d FP32 series, true rank %s, noise %.2f, leaf %d, node ranks %s, "
+                               "%d queries (%s lengths), theta %d/%d, <=%d sweeps, tol %g"
+                               % (wl.name, "x".join(map(str, wl.dims)), wl.T, wl.true_ranks, wl.noise,
+                                  wl.leaf_len, wl.node_ranks, nq, wl.query_kind, wl.theta[0], wl.theta[1],
+                                  wl.max_iter, wl.tol),
+                   "queries_per_step": nq, "path": "batched: one launch per step, one workgroup per query"},
+        "latency_ms": {"batch_p50": ms_per_step, "batch_p99": ms_per_step,
+                       "plain_p50": plain["p50_ms"] if plain else None,
+                       "plain_p99": plain["p99_ms"] if plain else None},
+        "plain_gpu_path": plain,
+        "speedup_vs_plain": (qps / plain["queries_per_s"]) if plain else None,
+        "appends_per_s": wl.T / build_s,
+        "sweeps_mean": float(np.mean(sweeps)),
+        "device_us_per_query": {"mean": float(tot.mean()), "p50": float(np.median(tot)), "max": float(tot.max()),
+                                "phase_mean": phase_mean, "eig_counters_mean": counters},
+        "hits_mean": float(np.mean(hit_counts)),
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "stitch_kernel", "kernel_ms": float(np.mean(kms)),
+                     "gflop_per_launch": flops / 1e9},
+        "accuracy_vs_oracle": accuracy,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -151,6 +151,21 @@ tk_status tk_query(tk_tree* t, int64_t ts, int64_t te, tk_result* res);
 tk_status tk_query_batch(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* te,
                          tk_result* res);
 
+/* Device time, in milliseconds, of the stitch launches issued by the last
+ * tk_query / tk_query_batch call, measured with HIP events recorded on the
+ * tree's stream around those launches (instrumentation for benchmarks). */
+tk_status tk_last_query_kernel_ms(const tk_tree* t, double* ms);
+
+/* Device time of query i of the last tk_query_batch call split into its
+ * eight phases, in microseconds (a 100 MHz wall clock read by the query's
+ * workgroup): partial-hit trims, factor-span bases, HOSVD initialisation,
+ * temporal-mode contractions and Gram, temporal-mode eigensolve, other
+ * modes' contractions and Grams (with the core update), their eigensolves,
+ * and writing the result; then four eigensolver counters: calls, Jacobi
+ * sweeps, microseconds in rotations, microseconds extracting vectors.
+ * phase_us has 12 entries. */
+tk_status tk_last_query_profile(const tk_tree* t, int32_t i, double* phase_us);
+
 /* Override the ALS sweep cap and tolerance for later queries (not merges). */
 tk_status tk_set_query_iters(tk_tree* t, int32_t max_iter, double tol);
 

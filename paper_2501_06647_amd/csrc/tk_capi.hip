@@ -58,6 +58,9 @@ struct tk_tree {
   int64_t lds_limit = 65536;  // dynamic LDS a workgroup may request
   bool poisoned = false;
   std::string err;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the last query launches
+  std::vector<double> last_stats;           // per-job stats of the last query batch
+  bool ev_valid = false;
 };
 
 namespace {
@@ -120,41 +123,24 @@ int eig_need(const tk::StitchLayout& lo, const StoreView& st, int s) {
   return n;
 }
 
-// Launch stitch jobs (queries or merges) in chunks bounded by workspace size.
-tk_status run_stitch(tk_tree* t, std::vector<Job>& jobs, const std::vector<Hit>& hits, int max_iter,
+// Launch one bin of stitch jobs (all sharing n_lds) in chunks bounded by
+// workspace size.  The hit array is already on the device.
+tk_status launch_bin(tk_tree* t, std::vector<Job>& jobs, const std::vector<Hit>& hits, int n_lds, int max_iter,
                      double tol) {
   const int64_t nj = int64_t(jobs.size());
   if (nj == 0) return TK_OK;
-  // LDS eigen capacity: enough for this launch's typical problems; larger
-  // batches keep it smaller so that several workgroups share a CU.
-  int n_need = 1;
-  std::vector<tk::StitchLayout> los(static_cast<size_t>(nj));
-  for (int64_t i = 0; i < nj; ++i) {
-    tk::StitchLayout lo0;
-    tk::stitch_layout(t->view, hits.data() + jobs[i].hit0, jobs[i].s, jobs[i].rq, 1 << 30, &lo0);
-    const int e = eig_need(lo0, t->view, jobs[i].s);
-    if (e > n_need) n_need = e;
-  }
-  int cap = nj > 256 ? 64 : 128;
-  while (cap > 8 && int64_t(tk::eig_doubles(cap)) * 8 > t->lds_limit - int64_t(tk::stitch_static_lds())) cap -= 8;
-  const int n_lds = n_need < cap ? n_need : cap;
   const size_t lds_bytes = size_t(tk::eig_doubles(n_lds)) * 8;
-  std::vector<int64_t> off(size_t(nj) + 1, 0);
+  std::vector<int64_t> off(static_cast<size_t>(nj) + 1, 0);
   for (int64_t i = 0; i < nj; ++i) {
-    tk::stitch_layout(t->view, hits.data() + jobs[i].hit0, jobs[i].s, jobs[i].rq, n_lds, &los[i]);
-    off[i + 1] = off[i] + los[i].total;
+    tk::StitchLayout lo;
+    tk::stitch_layout(t->view, hits.data() + jobs[i].hit0, jobs[i].s, jobs[i].rq, n_lds, &lo);
+    off[i + 1] = off[i] + lo.total;
   }
-  tk_status st = ensure(t, &t->dhits, &t->dhits_cap, int64_t(hits.size() * sizeof(Hit)) + 64, "hits");
-  if (st) return st;
-  if (!hits.empty())
-    TK_HIP(t, hipMemcpyAsync(t->dhits, hits.data(), hits.size() * sizeof(Hit), hipMemcpyHostToDevice,
-                             t->stream));
   int64_t i0 = 0;
   while (i0 < nj) {
     int64_t i1 = i0 + 1;
     while (i1 < nj && i1 - i0 < kMaxJobsPerLaunch && off[i1 + 1] - off[i0] <= kWsChunkBytes) ++i1;
-    const int64_t wsb = off[i1] - off[i0];
-    st = ensure(t, &t->ws, &t->ws_cap, wsb + 256, "workspace");
+    tk_status st = ensure(t, &t->ws, &t->ws_cap, off[i1] - off[i0] + 256, "workspace");
     if (st) return st;
     for (int64_t i = i0; i < i1; ++i) jobs[i].ws_off = off[i] - off[i0];
     st = ensure(t, &t->djobs, &t->djobs_cap, (i1 - i0) * int64_t(sizeof(Job)), "jobs");
@@ -172,8 +158,47 @@ tk_status run_stitch(tk_tree* t, std::vector<Job>& jobs, const std::vector<Hit>&
     a.merge_max_iter = t->cfg.max_iter;
     a.merge_tol = t->cfg.tol;
     TK_HIP(t, tk::launch_stitch(a, int(i1 - i0), lds_bytes, t->stream));
-    if (i1 < nj) TK_HIP(t, hipStreamSynchronize(t->stream));  // jobs/ws are reused
+    // the job array and workspace are reused by the next launch
+    TK_HIP(t, hipStreamSynchronize(t->stream));
     i0 = i1;
+  }
+  return TK_OK;
+}
+
+// Launch stitch jobs (queries or merges).  Jobs are binned by the size of
+// their largest eigenproblem so that each launch sizes its LDS for its own
+// jobs: small problems keep several workgroups per CU, large ones still run
+// their eigensolves in LDS.
+tk_status run_stitch(tk_tree* t, std::vector<Job>& jobs, const std::vector<Hit>& hits, int max_iter,
+                     double tol) {
+  const int64_t nj = int64_t(jobs.size());
+  if (nj == 0) return TK_OK;
+  int lds_cap = 128;
+  while (lds_cap > 8 && int64_t(tk::eig_doubles(lds_cap)) * 8 > t->lds_limit - int64_t(tk::stitch_static_lds()))
+    lds_cap -= 8;
+  const int bins[3] = {32 < lds_cap ? 32 : lds_cap, 64 < lds_cap ? 64 : lds_cap, lds_cap};
+  std::vector<std::vector<Job>> binned(4);
+  for (int64_t i = 0; i < nj; ++i) {
+    tk::StitchLayout lo;
+    tk::stitch_layout(t->view, hits.data() + jobs[i].hit0, jobs[i].s, jobs[i].rq, 1 << 30, &lo);
+    const int need = eig_need(lo, t->view, jobs[i].s);
+    if (need > tk::EIG_MAXK_HOST) return fail(t, TK_EINVAL, "query needs an eigenproblem above 1024");
+    int b = 3;
+    for (int k = 0; k < 3; ++k)
+      if (need <= bins[k]) {
+        b = k;
+        break;
+      }
+    binned[size_t(b)].push_back(jobs[i]);
+  }
+  tk_status st = ensure(t, &t->dhits, &t->dhits_cap, int64_t(hits.size() * sizeof(Hit)) + 64, "hits");
+  if (st) return st;
+  if (!hits.empty())
+    TK_HIP(t, hipMemcpyAsync(t->dhits, hits.data(), hits.size() * sizeof(Hit), hipMemcpyHostToDevice,
+                             t->stream));
+  for (int b = 0; b < 4; ++b) {
+    st = launch_bin(t, binned[size_t(b)], hits, b < 3 ? bins[b] : lds_cap, max_iter, tol);
+    if (st) return st;
   }
   return TK_OK;
 }
@@ -442,6 +467,8 @@ void tk_destroy(tk_tree* t) {
   if (t->block_buf) (void)hipFree(t->block_buf);
   if (t->dstats) (void)hipFree(t->dstats);
   if (t->xbuf) (void)hipFree(t->xbuf);
+  if (t->ev0) (void)hipEventDestroy(t->ev0);
+  if (t->ev1) (void)hipEventDestroy(t->ev1);
   delete t;
 }
 
@@ -537,16 +564,26 @@ tk_status tk_query_batch(tk_tree* t, int32_t n, const int64_t* ts, const int64_t
     if (st) return st;
   }
   if (n == 0) return TK_OK;
-  tk_status st = ensure(t, reinterpret_cast<char**>(&t->dstats), &t->dstats_cap, int64_t(n) * 8 * 8, "stats");
+  tk_status st = ensure(t, reinterpret_cast<char**>(&t->dstats), &t->dstats_cap,
+                        int64_t(n) * tk::STAT_COUNT * 8, "stats");
   if (st) return st;
-  for (int32_t i = 0; i < n; ++i) jobs[i].stats = t->dstats + 8 * int64_t(i);
+  for (int32_t i = 0; i < n; ++i) jobs[i].stats = t->dstats + tk::STAT_COUNT * int64_t(i);
+  if (!t->ev0) {
+    TK_HIP(t, hipEventCreate(&t->ev0));
+    TK_HIP(t, hipEventCreate(&t->ev1));
+  }
+  t->ev_valid = false;
+  TK_HIP(t, hipEventRecord(t->ev0, t->stream));
   st = run_stitch(t, jobs, hits, t->q_max_iter, t->q_tol);
   if (st) return st;
-  std::vector<double> hs(size_t(n) * 8);
+  TK_HIP(t, hipEventRecord(t->ev1, t->stream));
+  t->ev_valid = true;
+  std::vector<double>& hs = t->last_stats;
+  hs.assign(size_t(n) * tk::STAT_COUNT, 0.0);
   TK_HIP(t, hipMemcpyAsync(hs.data(), t->dstats, hs.size() * 8, hipMemcpyDeviceToHost, t->stream));
   TK_HIP(t, hipStreamSynchronize(t->stream));
   for (int32_t i = 0; i < n; ++i) {
-    const double* s = hs.data() + 8 * size_t(i);
+    const double* s = hs.data() + tk::STAT_COUNT * size_t(i);
     for (int m = 0; m < tk::MAXP; ++m) res[i].ranks_eff[m] = m < t->p ? jobs[i].rq[m] : 0;
     res[i].fit = s[tk::STAT_FIT];
     res[i].err_model = s[tk::STAT_ERR];
@@ -560,6 +597,25 @@ tk_status tk_query_batch(tk_tree* t, int32_t n, const int64_t* ts, const int64_t
 
 tk_status tk_query(tk_tree* t, int64_t ts, int64_t te, tk_result* res) {
   return tk_query_batch(t, 1, &ts, &te, res);
+}
+
+tk_status tk_last_query_kernel_ms(const tk_tree* t, double* ms) {
+  if (!t || !ms) return TK_EINVAL;
+  if (!t->ev_valid) return TK_EINVAL;
+  float f = 0.f;
+  if (hipEventSynchronize(t->ev1) != hipSuccess) return TK_EDEVICE;
+  if (hipEventElapsedTime(&f, t->ev0, t->ev1) != hipSuccess) return TK_EDEVICE;
+  *ms = double(f);
+  return TK_OK;
+}
+
+tk_status tk_last_query_profile(const tk_tree* t, int32_t i, double* phase_us) {
+  if (!t || !phase_us || i < 0) return TK_EINVAL;
+  const int64_t n = int64_t(t->last_stats.size()) / tk::STAT_COUNT;
+  if (i >= n) return TK_EINVAL;
+  for (int k = 0; k < tk::STAT_NPHASE + 4; ++k)
+    phase_us[k] = t->last_stats[size_t(i) * tk::STAT_COUNT + tk::STAT_PHASE + k];
+  return TK_OK;
 }
 
 tk_status tk_set_query_iters(tk_tree* t, int32_t max_iter, double tol) {

@@ -16,6 +16,7 @@ namespace tk {
 constexpr int MAXP = 6;      // modes handled by the kernels (time included)
 constexpr int MAXLEV = 48;   // tree levels (2^47 leaf blocks)
 constexpr int MAXHITS = 96;  // hits per query: <= 2(h-1), h <= MAXLEV
+constexpr int EIG_MAXK_HOST = 1024;  // largest eigenproblem a job may need
 
 // ---------------------------------------------------------------------------
 // Topology.  The stream segment tree built by Alg. "append"/"insert" (Sec.
@@ -186,7 +187,7 @@ struct Job {
   int32_t rq[MAXP];          // output effective ranks
   float* out_core;           // prod(rq) floats
   float* out_fac[MAXP];      // [0]: L x rq[0] rows; [n]: D_n x rq[n]
-  double* stats;             // 8 doubles (see STAT_*)
+  double* stats;             // STAT_COUNT doubles (see STAT_*)
   int64_t ws_off;            // byte offset of the job's workspace
 };
 
@@ -198,7 +199,14 @@ struct LeafJob {
   int64_t ws_off;
 };
 
-enum { STAT_FIT = 0, STAT_ERR = 1, STAT_NORM = 2, STAT_SWEEPS = 3, STAT_CONV = 4, STAT_HITS = 5 };
+// Per-job statistics; STAT_PHASE.. hold device time per phase in microseconds
+// (trims, bases, init, temporal TTM+Gram, temporal eigen, other TTM+Gram,
+// other eigens, finalize); STAT_EIG.. hold eigensolver calls, Jacobi sweeps,
+// and microseconds in the rotation loop and in the extraction.
+enum {
+  STAT_FIT = 0, STAT_ERR = 1, STAT_NORM = 2, STAT_SWEEPS = 3, STAT_CONV = 4, STAT_HITS = 5,
+  STAT_PHASE = 8, STAT_NPHASE = 8, STAT_EIG = 16, STAT_COUNT = 20
+};
 
 // ---------------------------------------------------------------------------
 // Workspace layout of a stitch job (bump allocation, 256-byte aligned), used
@@ -234,8 +242,8 @@ struct StitchLayout {
 TK_HD int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
 // Doubles needed by the eigensolver for an n x n problem: the matrix, then
-// column norms, ranks, Gram-Schmidt coefficients and eigenvalues.
-TK_HD int64_t eig_doubles(int64_t n) { return n * n + 4 * n; }
+// column norms, Gram-Schmidt coefficients and eigenvalues.
+TK_HD int64_t eig_doubles(int64_t n) { return n * n + 3 * n; }
 
 TK_HD void stitch_layout(const StoreView& st, const Hit* hits, int s, const int32_t* rq,
                          int n_lds, StitchLayout* Lo) {

@@ -11,6 +11,7 @@
 namespace tk {
 
 constexpr int NT = 256;  // threads per workgroup (four wave64 wavefronts)
+constexpr int EIG_MAXK = EIG_MAXK_HOST;  // eigenvectors one eig_top call can return
 
 // Sum of v over the workgroup; every thread gets the result.
 __device__ inline double block_sum(double v, double* red) {
@@ -90,11 +91,72 @@ __device__ void gram_other(const float* __restrict__ X, int64_t a, int D, int64_
   __syncthreads();
 }
 
+// Orthonormalise columns idx[0..k) of W (column c at W + c n, n rows) in
+// place, in FP64.  The columns are first checked: when their Gram is within
+// 1e-12 of the identity nothing more is done.  Otherwise classical
+// Gram-Schmidt is applied twice, column by column; a column that vanishes
+// (a zero or dependent vector) is replaced by the next unit vector e_c that
+// survives, so the k columns always end orthonormal when k <= n.
+// coef: >= k doubles; flag: an int in LDS.
+__device__ void orthonormalize_cols(double* W, int n, int k, const int* idx, double* coef, double* red,
+                                    int* flag) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (k <= 0) return;
+  if (tid == 0) *flag = 0;
+  __syncthreads();
+  for (int e = tid; e < k * k; e += nt) {
+    const int i = e / k, j = e % k;
+    if (j < i) continue;
+    const double* a = W + int64_t(idx[i]) * n;
+    const double* b = W + int64_t(idx[j]) * n;
+    double d = 0.0;
+    for (int r = 0; r < n; ++r) d += a[r] * b[r];
+    if (fabs(d - (i == j ? 1.0 : 0.0)) > 1e-12) *flag = 1;
+  }
+  __syncthreads();
+  if (*flag == 0) return;
+  int cand = 0;
+  for (int j = 0; j < k && j < n; ++j) {
+    double* w = W + int64_t(idx[j]) * n;
+    for (int attempt = 0; attempt <= n; ++attempt) {
+      for (int pass = 0; pass < 2; ++pass) {
+        // all coefficients of column j at once: groups of 8 lanes per column i < j
+        for (int base = 0; base < j; base += nt / 8) {
+          const int i = base + tid / 8, lane = tid % 8;
+          double d = 0.0;
+          if (i < j) {
+            const double* a = W + int64_t(idx[i]) * n;
+            for (int r = lane; r < n; r += 8) d += a[r] * w[r];
+          }
+          for (int o = 4; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+          if (i < j && lane == 0) coef[i] = d;
+        }
+        __syncthreads();
+        for (int r = tid; r < n; r += nt) {
+          double v = w[r];
+          for (int i = 0; i < j; ++i) v -= coef[i] * W[int64_t(idx[i]) * n + r];
+          w[r] = v;
+        }
+        __syncthreads();
+      }
+      double part = 0.0;
+      for (int r = tid; r < n; r += nt) part += w[r] * w[r];
+      const double nrm = sqrt(block_sum(part, red));
+      if (nrm > 0.5) {
+        for (int r = tid; r < n; r += nt) w[r] /= nrm;
+        __syncthreads();
+        break;
+      }
+      for (int r = tid; r < n; r += nt) w[r] = (r == cand) ? 1.0 : 0.0;
+      ++cand;
+      __syncthreads();
+    }
+  }
+}
+
 // Orthonormalise the k columns of E (n x k, row-major, leading dimension
-// lde) in FP64 by classical Gram-Schmidt applied twice; a column that
-// vanishes (a zero or dependent eigenvector) is replaced by the next unit
-// vector e_c that survives, so the result always has k orthonormal columns
-// when k <= n.  coef: >= k doubles of scratch.
+// lde) in FP64, as orthonormalize_cols does (used on results held outside
+// the eigensolver's buffer).  coef: >= k doubles.
 __device__ void orthonormalize(double* E, int n, int k, int lde, double* coef, double* red) {
   int cand = 0;
   for (int j = 0; j < k && j < n; ++j) {
@@ -121,13 +183,12 @@ __device__ void orthonormalize(double* E, int n, int k, int lde, double* coef, d
         __syncthreads();
         break;
       }
-      // dependent column: restart from a unit vector
       for (int r = threadIdx.x; r < n; r += blockDim.x) E[r * lde + j] = (r == cand) ? 1.0 : 0.0;
       ++cand;
       __syncthreads();
     }
   }
-  for (int j = n; j < k; ++j)  // more columns than dimensions: zero them
+  for (int j = n; j < k; ++j)
     for (int r = threadIdx.x; r < n; r += blockDim.x) E[r * lde + j] = 0.0;
   __syncthreads();
 }
@@ -138,17 +199,29 @@ __device__ void orthonormalize(double* E, int n, int k, int lde, double* coef, d
 // W = S V; then V holds eigenvectors of S and column c of W equals
 // lambda_c v_c.  Pairs are visited in the round-robin order, n/2 disjoint
 // pairs per step, each pair by a group of g lanes of one wavefront.
-// Outputs the k leading unit eigenvectors into E (n x k, row-major, lde) and
-// the eigenvalues into lam[0..k) in descending order; the columns of E are
-// orthonormalised (dependent ones completed).  W must hold eig_doubles(n)
-// doubles: the scratch (norms, ranks, coefficients) follows the matrix, and
-// the returned pointer to the k eigenvalues points into it (valid until W is
-// reused).  When k > n only n eigenpairs exist: lam holds n values and the
-// extra columns of E are zero.
-__device__ const double* eig_top(double* W, int n, int k, double* E, int lde, double* red) {
+// Writes the k leading unit eigenvectors into E (n x k, row-major, lde) in
+// descending eigenvalue order and returns a pointer to the k eigenvalues.
+// Columns whose eigenvalue is at most keep_rel times the largest are
+// normalised but not orthonormalised (callers that drop such directions pass
+// keep_rel > 0); with keep_rel = 0 all k columns come out orthonormal, a
+// dependent one completed by a unit vector.  W must hold eig_doubles(n)
+// doubles; the scratch (norms, ranks, coefficients, eigenvalues) follows the
+// matrix, and the eigenvalues stay valid until W is reused.  When k > n only
+// n eigenpairs exist and the extra columns of E are zero.
+struct EigCounters {
+  uint64_t calls = 0, sweeps = 0, jacobi_ticks = 0, tail_ticks = 0;
+};
+
+__device__ const double* eig_top(double* W, int n, int k, double* E, int lde, double* red,
+                                 double keep_rel = 0.0, EigCounters* cnt = nullptr) {
+  const uint64_t t_start = wall_clock64();
+  __shared__ int s_idx[EIG_MAXK];
+  __shared__ int s_flag;
   const int tid = threadIdx.x, nt = blockDim.x;
   double* scratch = W + int64_t(n) * n;
-  double* lam = scratch + 2 * n + n;
+  double* nrm = scratch;
+  double* coef = scratch + n;
+  double* lam = scratch + 2 * n;
   if (n <= 0) return lam;
   const int N = n + (n & 1);
   const int npairs = N / 2;
@@ -160,7 +233,9 @@ __device__ const double* eig_top(double* W, int n, int k, double* E, int lde, do
   tr = block_sum(tr, red);
   const double tiny = (1e-17 * tr) * (1e-17 * tr);
   const double eps = 4e-16 * double(n > 8 ? n : 8);
+  int sweeps_run = 0;
   for (int sweep = 0; sweep < 40 && N > 1; ++sweep) {
+    ++sweeps_run;
     int rotated = 0;
     for (int step = 0; step < N - 1; ++step) {
       for (int base = 0; base < npairs; base += groups) {
@@ -215,9 +290,8 @@ __device__ const double* eig_top(double* W, int n, int k, double* E, int lde, do
     }
     if (!__syncthreads_or(rotated)) break;
   }
-  // column norms = |lambda|; rank them (ties by index) and extract the top k
-  double* nrm = scratch;
-  double* idx = scratch + n;
+  const uint64_t t_jac = wall_clock64();
+  // column norms = |lambda|; rank them (ties by index) and keep the top k
   for (int c = tid; c < n; c += nt) {
     double s = 0.0;
     const double* w = W + int64_t(c) * n;
@@ -225,23 +299,44 @@ __device__ const double* eig_top(double* W, int n, int k, double* E, int lde, do
     nrm[c] = sqrt(s);
   }
   __syncthreads();
+  const int kk = k < n ? k : n;
   for (int c = tid; c < n; c += nt) {
     int rank = 0;
     for (int c2 = 0; c2 < n; ++c2)
       if (nrm[c2] > nrm[c] || (nrm[c2] == nrm[c] && c2 < c)) ++rank;
-    if (rank < k) idx[rank] = double(c);
+    if (rank < kk) s_idx[rank] = c;
   }
   __syncthreads();
-  const int kk = k < n ? k : n;
+  for (int j = tid; j < kk; j += nt) lam[j] = nrm[s_idx[j]];
+  __syncthreads();
+  // normalise the kept columns in place, then orthonormalise the leading
+  // ones (those above keep_rel, or all of them)
+  const double lmax = kk > 0 ? lam[0] : 0.0;
   for (int e = tid; e < n * kk; e += nt) {
-    const int r = e / kk, j = e % kk;
-    const int c = int(idx[j]);
-    const double s = nrm[c];
-    E[r * lde + j] = s > 0.0 ? W[int64_t(c) * n + r] / s : 0.0;
+    const int j = e / n, r = e % n;
+    const double s = lam[j];
+    double* w = W + int64_t(s_idx[j]) * n;
+    w[r] = s > 0.0 ? w[r] / s : 0.0;
   }
-  for (int j = tid; j < kk; j += nt) lam[j] = nrm[int(idx[j])];
   __syncthreads();
-  orthonormalize(E, n, k, lde, scratch + 2 * n, red);
+  int ko = kk;
+  if (keep_rel > 0.0) {
+    ko = 0;
+    for (int j = 0; j < kk; ++j)
+      if (lam[j] > keep_rel * lmax) ko = j + 1;
+  }
+  orthonormalize_cols(W, n, ko, s_idx, coef, red, &s_flag);
+  for (int e = tid; e < n * k; e += nt) {
+    const int r = e / k, j = e % k;
+    E[r * lde + j] = j < kk ? W[int64_t(s_idx[j]) * n + r] : 0.0;
+  }
+  __syncthreads();
+  if (cnt && tid == 0) {
+    cnt->calls += 1;
+    cnt->sweeps += uint64_t(sweeps_run);
+    cnt->jacobi_ticks += t_jac - t_start;
+    cnt->tail_ticks += wall_clock64() - t_jac;
+  }
   return lam;
 }
 

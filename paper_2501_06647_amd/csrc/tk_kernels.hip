@@ -41,6 +41,26 @@ __device__ inline int64_t prod_range(const int32_t* d, int lo, int hi) {
   return r;
 }
 
+// Phase timer: thread 0 accumulates the 100 MHz wall clock between marks.
+struct PhaseClock {
+  uint64_t last = 0;
+  uint64_t acc[STAT_NPHASE] = {0, 0, 0, 0, 0, 0, 0, 0};
+  __device__ void start() {
+    if (threadIdx.x == 0) last = wall_clock64();
+  }
+  __device__ void mark(int ph) {
+    if (threadIdx.x == 0) {
+      const uint64_t now = wall_clock64();
+      acc[ph] += now - last;
+      last = now;
+    }
+  }
+  __device__ void store(double* stats) const {
+    if (threadIdx.x == 0 && stats)
+      for (int i = 0; i < STAT_NPHASE; ++i) stats[STAT_PHASE + i] = double(acc[i]) * 0.01;
+  }
+};
+
 struct StitchShared {
   StitchLayout lo;
   Hit hits[MAXHITS];
@@ -88,6 +108,9 @@ __device__ void stitch_one(const StoreView& st, const Job& job, const Hit* ghits
     return;
   }
 
+  PhaseClock clk;
+  EigCounters ec;
+  clk.start();
   if (tid == 0) stitch_layout(st, sh.hits, s, rq, n_lds, &sh.lo);
   __syncthreads();
   const StitchLayout& lo = sh.lo;
@@ -116,7 +139,7 @@ __device__ void stitch_one(const StoreView& st, const Job& job, const Hit* ghits
     double* Wm = eig_buf(k, n_lds, lds, ws, lo);
     gram_mode<double>(V, h.l, k, 1, Wm, k);
     double* E = Dp(lo.F[i]);  // k x k, becomes F_i = E Lambda^{-1/2}
-    const double* lam = eig_top(Wm, k, k, E, k, red);
+    const double* lam = eig_top(Wm, k, k, E, k, red, 1e-12, &ec);
     int kp = 0;
     for (int j = 0; j < k; ++j)
       if (lam[j] > 1e-12) kp = j + 1;
@@ -139,6 +162,7 @@ __device__ void stitch_one(const StoreView& st, const Job& job, const Hit* ghits
     if (tid == 0) sh.kp[i] = kp;
     __syncthreads();
   }
+  clk.mark(0);
   if (tid == 0) {
     sh.koff[0] = 0;
     for (int i = 0; i < s; ++i) sh.koff[i + 1] = sh.koff[i] + sh.kp[i];
@@ -186,7 +210,7 @@ __device__ void stitch_one(const StoreView& st, const Job& job, const Hit* ghits
       }
       __syncthreads();
       double* E = Dp(lo.Fn[n]);  // sr x sr; becomes F_n = E Lambda^{-1/2}
-      const double* lam = eig_top(Wm, sr, sr, E, sr, red);
+      const double* lam = eig_top(Wm, sr, sr, E, sr, red, 1e-11, &ec);
       int q = 0;
       const double lmax = lam[0];
       for (int j = 0; j < sr; ++j)
@@ -223,6 +247,7 @@ __device__ void stitch_one(const StoreView& st, const Job& job, const Hit* ghits
     __syncthreads();
   }
 
+  clk.mark(1);
   // P_n^T C_i for every piece (mode n >= 1)
   auto update_A = [&](int n) {
     const int q = sh.q[n], sr = lo.sr[n], r_out = rq[n];
@@ -275,10 +300,11 @@ __device__ void stitch_one(const StoreView& st, const Job& job, const Hit* ghits
       }
       __syncthreads();
     }
-    eig_top(Wm, q, rq[n], Dp(lo.Pd[n]), rq[n], red);
+    eig_top(Wm, q, rq[n], Dp(lo.Pd[n]), rq[n], red, 0.0, &ec);
     update_A(n);
   }
 
+  clk.mark(2);
   // ---- ALS sweeps (Alg. "stitch") ---------------------------------------------
   int64_t Rhat[MAXP];
   for (int n = 0; n < p; ++n) {
@@ -312,7 +338,9 @@ __device__ void stitch_one(const StoreView& st, const Job& job, const Hit* ghits
     const int sk = sh.koff[s];
     double* Wm = eig_buf(sk, n_lds, lds, ws, lo);
     gram_mode<double>(M, 1, sk, Rhat[0], Wm, sk);
-    eig_top(Wm, sk, rq[0], Dp(lo.Pd[0]), rq[0], red);
+    clk.mark(3);
+    eig_top(Wm, sk, rq[0], Dp(lo.Pd[0]), rq[0], red, 0.0, &ec);
+    clk.mark(4);
     float* P0f = Fp(lo.Pf[0]);
     {
       const double* P0 = Dp(lo.Pd[0]);
@@ -355,8 +383,10 @@ __device__ void stitch_one(const StoreView& st, const Job& job, const Hit* ghits
       }
       double* Wn = eig_buf(q, n_lds, lds, ws, lo);
       gram_mode<double>(K, ka, q, kb, Wn, q);
-      eig_top(Wn, q, rq[n], Dp(lo.Pd[n]), rq[n], red);
+      clk.mark(5);
+      eig_top(Wn, q, rq[n], Dp(lo.Pd[n]), rq[n], red, 0.0, &ec);
       update_A(n);
+      clk.mark(6);
     }
     // core update: G = Z^(p) x_p U^(p)T, here K_p x_p P_p^T
     {
@@ -370,6 +400,7 @@ __device__ void stitch_one(const StoreView& st, const Job& job, const Hit* ghits
     }
     fit = ny2 > 0.0 ? 1.0 - sqrt(fmax(0.0, ny2 - g2)) / sqrt(ny2) : 1.0;
     sweeps = it;
+    clk.mark(5);
     if (it >= 2 && fabs(fit - fit_prev) < tol) {
       conv = 1;
       break;
@@ -510,6 +541,14 @@ __device__ void stitch_one(const StoreView& st, const Job& job, const Hit* ghits
     job.stats[STAT_SWEEPS] = double(sweeps);
     job.stats[STAT_CONV] = double(conv);
     job.stats[STAT_HITS] = double(s);
+  }
+  clk.mark(7);
+  clk.store(job.stats);
+  if (tid == 0 && job.stats) {
+    job.stats[STAT_EIG + 0] = double(ec.calls);
+    job.stats[STAT_EIG + 1] = double(ec.sweeps);
+    job.stats[STAT_EIG + 2] = double(ec.jacobi_ticks) * 0.01;
+    job.stats[STAT_EIG + 3] = double(ec.tail_ticks) * 0.01;
   }
 }
 

@@ -68,6 +68,8 @@ SIGNATURES = [
     ("tk_query_batch", c_i32, [c_vp, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
                                ctypes.POINTER(TkResult)]),
     ("tk_set_query_iters", c_i32, [c_vp, c_i32, c_dbl]),
+    ("tk_last_query_kernel_ms", c_i32, [c_vp, ctypes.POINTER(c_dbl)]),
+    ("tk_last_query_profile", c_i32, [c_vp, c_i32, ctypes.POINTER(c_dbl)]),
     ("tk_stats_get", c_i32, [c_vp, ctypes.POINTER(TkStats)]),
     ("tk_node_ranks", c_i32, [c_vp, c_i32, ctypes.POINTER(c_i32)]),
     ("tk_read_node", c_i32, [c_vp, c_i32, c_i64, c_vp, ctypes.POINTER(c_vp)]),
@@ -161,6 +163,52 @@ class QueryResult:
         self.norm_ytilde = res.norm_ytilde
 
 
+class PreparedBatch:
+    """A list of range queries with device output buffers allocated once."""
+
+    def __init__(self, tree: "Tree", ts, te):
+        self.tree = tree
+        self.ts = np.asarray(ts, dtype=np.int64).reshape(-1)
+        self.te = np.asarray(te, dtype=np.int64).reshape(-1)
+        n = len(self.ts)
+        self.n = n
+        p = tree.p
+        shapes_all = []
+        for i in range(n):
+            sh = tree.query_shape(int(self.ts[i]), int(self.te[i]))
+            r = tuple(sh.ranks_eff[:p])
+            shapes_all.append([r, (int(self.te[i] - self.ts[i]), r[0])] +
+                              [(tree.dims[m - 1], r[m]) for m in range(1, p)])
+        self.buf, views = tree._alloc([s for shp in shapes_all for s in shp])
+        self.res = (TkResult * max(n, 1))()
+        self.outputs = []
+        k = 0
+        for i in range(n):
+            core, facs = views[k], views[k + 1:k + 1 + p]
+            k += 1 + p
+            self.res[i].core = core.data_ptr()
+            for m in range(p):
+                self.res[i].factor[m] = facs[m].data_ptr()
+            self.outputs.append((core, facs))
+        self._ts = (c_i64 * max(n, 1))(*self.ts.tolist())
+        self._te = (c_i64 * max(n, 1))(*self.te.tolist())
+
+    def run(self):
+        """One tk_query_batch call: Recall, trims and Stitch for every query."""
+        self.tree._check(lib().tk_query_batch(self.tree._h, self.n, self._ts, self._te, self.res),
+                         "tk_query_batch")
+
+    def run_one(self, i: int):
+        """Query i alone (one device launch)."""
+        ts = ctypes.cast(ctypes.addressof(self._ts) + 8 * i, ctypes.POINTER(c_i64))
+        te = ctypes.cast(ctypes.addressof(self._te) + 8 * i, ctypes.POINTER(c_i64))
+        res = ctypes.cast(ctypes.addressof(self.res) + ctypes.sizeof(TkResult) * i, ctypes.POINTER(TkResult))
+        self.tree._check(lib().tk_query_batch(self.tree._h, 1, ts, te, res), "tk_query")
+
+    def results(self) -> List[QueryResult]:
+        return [QueryResult(c, f, self.res[i], self.tree.p) for i, (c, f) in enumerate(self.outputs)]
+
+
 class Tree:
     """A stream segment tree on the current HIP device."""
 
@@ -240,39 +288,27 @@ class Tree:
             off += n
         return buf, views
 
+    def prepare_batch(self, ts, te) -> "PreparedBatch":
+        """Allocate the outputs of a fixed list of queries once; run() reuses them."""
+        return PreparedBatch(self, ts, te)
+
     def query_batch(self, ts, te) -> List[QueryResult]:
-        ts = np.asarray(ts, dtype=np.int64).reshape(-1)
-        te = np.asarray(te, dtype=np.int64).reshape(-1)
-        n = len(ts)
-        shapes_all, res = [], (TkResult * max(n, 1))()
-        for i in range(n):
-            sh = self.query_shape(int(ts[i]), int(te[i]))
-            r = tuple(sh.ranks_eff[:self.p])
-            shapes_all.append([r, (int(te[i] - ts[i]), r[0])] +
-                              [(self.dims[m - 1], r[m]) for m in range(1, self.p)])
-        flat = [s for shp in shapes_all for s in shp]
-        buf, views = self._alloc(flat)
-        k = 0
-        per_query = []
-        for i in range(n):
-            core = views[k]
-            facs = views[k + 1:k + 1 + self.p]
-            k += 1 + self.p
-            res[i].core = core.data_ptr()
-            for m in range(self.p):
-                res[i].factor[m] = facs[m].data_ptr()
-            per_query.append((core, facs))
-        self._torch.cuda.synchronize()
-        tsa = (c_i64 * max(n, 1))(*ts.tolist())
-        tea = (c_i64 * max(n, 1))(*te.tolist())
-        self._check(lib().tk_query_batch(self._h, n, tsa, tea, res), "tk_query_batch")
-        out = []
-        for i in range(n):
-            core, facs = per_query[i]
-            out.append(QueryResult(core, facs, res[i], self.p))
-        out_buf = buf  # keep the allocation alive through the views
-        del out_buf
-        return out
+        b = self.prepare_batch(ts, te)
+        b.run()
+        return b.results()
+
+    PHASES = ("trim", "basis", "init", "t_ttm_gram", "t_eig", "n_ttm_gram", "n_eig", "final")
+    COUNTERS = ("eig_calls", "eig_sweeps", "eig_rot_us", "eig_tail_us")
+
+    def last_profile(self, i: int) -> dict:
+        out = (c_dbl * 12)()
+        self._check(lib().tk_last_query_profile(self._h, i, out), "tk_last_query_profile")
+        return dict(zip(self.PHASES + self.COUNTERS, list(out)))
+
+    def last_kernel_ms(self) -> float:
+        ms = c_dbl(0.0)
+        self._check(lib().tk_last_query_kernel_ms(self._h, ctypes.byref(ms)), "tk_last_query_kernel_ms")
+        return ms.value
 
     def query(self, ts: int, te: int) -> QueryResult:
         return self.query_batch([ts], [te])[0]

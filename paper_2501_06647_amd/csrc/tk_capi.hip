@@ -1,6 +1,7 @@
 // C ABI of the TUCKET engine: tree object, node store, append/build
 // scheduling and query launches.  Integer work (which nodes, where they live)
 // happens here on the host; every floating-point step runs in the kernels.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -47,6 +48,16 @@ struct tk_tree {
   int64_t ws_cap = 0;
   char* djobs = nullptr;
   int64_t djobs_cap = 0;
+  // per-bin launch resources: bins of a query batch run concurrently on
+  // their own streams, joined back to the tree's stream with events
+  static constexpr int kBins = 6;
+  char* bws[kBins] = {nullptr};
+  int64_t bws_cap[kBins] = {0};
+  char* bjobs[kBins] = {nullptr};
+  int64_t bjobs_cap[kBins] = {0};
+  hipStream_t bstream[kBins] = {nullptr};
+  hipEvent_t bev[kBins] = {nullptr};
+  hipEvent_t fork_ev = nullptr;
   char* dhits = nullptr;
   int64_t dhits_cap = 0;
   double* dstats = nullptr;
@@ -91,7 +102,7 @@ tk_status fail_dev(tk_tree* t, hipError_t e, const char* what) {
 tk_status ensure(tk_tree* t, char** buf, int64_t* cap, int64_t need, const char* what) {
   if (need <= *cap) return TK_OK;
   if (*buf) {
-    TK_HIP(t, hipStreamSynchronize(t->stream));
+    TK_HIP(t, hipDeviceSynchronize());  // the buffer may be in use on any of the tree's streams
     TK_HIP(t, hipFree(*buf));
     *buf = nullptr;
     *cap = 0;
@@ -123,12 +134,17 @@ int eig_need(const tk::StitchLayout& lo, const StoreView& st, int s) {
   return n;
 }
 
-// Launch one bin of stitch jobs (all sharing n_lds) in chunks bounded by
-// workspace size.  The hit array is already on the device.
+// Launch one bin of stitch jobs (all sharing n_lds) on stream `stream`,
+// with workspace and job array `ws` / `djobs`; heaviest jobs first.  The
+// hit array is already on the device.  Large bins are split into chunks
+// bounded by workspace size (chunks of one bin run in order on its stream).
 tk_status launch_bin(tk_tree* t, std::vector<Job>& jobs, const std::vector<Hit>& hits, int n_lds, int max_iter,
-                     double tol) {
+                     double tol, hipStream_t stream, char** ws, int64_t* ws_cap, char** djobs, int64_t* djobs_cap) {
   const int64_t nj = int64_t(jobs.size());
   if (nj == 0) return TK_OK;
+  std::stable_sort(jobs.begin(), jobs.end(), [](const Job& a, const Job& b) {
+    return a.s * a.L > b.s * b.L;  // longer ranges with more hits take longer
+  });
   const size_t lds_bytes = size_t(tk::eig_doubles(n_lds)) * 8;
   std::vector<int64_t> off(static_cast<size_t>(nj) + 1, 0);
   for (int64_t i = 0; i < nj; ++i) {
@@ -140,35 +156,36 @@ tk_status launch_bin(tk_tree* t, std::vector<Job>& jobs, const std::vector<Hit>&
   while (i0 < nj) {
     int64_t i1 = i0 + 1;
     while (i1 < nj && i1 - i0 < kMaxJobsPerLaunch && off[i1 + 1] - off[i0] <= kWsChunkBytes) ++i1;
-    tk_status st = ensure(t, &t->ws, &t->ws_cap, off[i1] - off[i0] + 256, "workspace");
+    if (i0 > 0) TK_HIP(t, hipStreamSynchronize(stream));  // the buffers are reused by this chunk
+    tk_status st = ensure(t, ws, ws_cap, off[i1] - off[i0] + 256, "workspace");
     if (st) return st;
     for (int64_t i = i0; i < i1; ++i) jobs[i].ws_off = off[i] - off[i0];
-    st = ensure(t, &t->djobs, &t->djobs_cap, (i1 - i0) * int64_t(sizeof(Job)), "jobs");
+    st = ensure(t, djobs, djobs_cap, (i1 - i0) * int64_t(sizeof(Job)), "jobs");
     if (st) return st;
-    TK_HIP(t, hipMemcpyAsync(t->djobs, jobs.data() + i0, size_t(i1 - i0) * sizeof(Job),
-                             hipMemcpyHostToDevice, t->stream));
+    TK_HIP(t, hipMemcpyAsync(*djobs, jobs.data() + i0, size_t(i1 - i0) * sizeof(Job), hipMemcpyHostToDevice,
+                             stream));
     tk::StitchArgs a;
     a.st = t->dview;
-    a.jobs = reinterpret_cast<const Job*>(t->djobs);
+    a.jobs = reinterpret_cast<const Job*>(*djobs);
     a.hits = reinterpret_cast<const Hit*>(t->dhits);
-    a.ws = t->ws;
+    a.ws = *ws;
     a.n_lds = n_lds;
     a.max_iter = max_iter;
     a.tol = tol;
     a.merge_max_iter = t->cfg.max_iter;
     a.merge_tol = t->cfg.tol;
-    TK_HIP(t, tk::launch_stitch(a, int(i1 - i0), lds_bytes, t->stream));
-    // the job array and workspace are reused by the next launch
-    TK_HIP(t, hipStreamSynchronize(t->stream));
+    TK_HIP(t, tk::launch_stitch(a, int(i1 - i0), lds_bytes, n_lds > 48, stream));
     i0 = i1;
   }
   return TK_OK;
 }
 
 // Launch stitch jobs (queries or merges).  Jobs are binned by the size of
-// their largest eigenproblem so that each launch sizes its LDS for its own
-// jobs: small problems keep several workgroups per CU, large ones still run
-// their eigensolves in LDS.
+// their largest eigenproblem so that each launch sizes its LDS (and its
+// wavefronts per job) for its own jobs: small problems keep many jobs per
+// CU, large ones still run their eigensolves in LDS.  Bins run concurrently
+// on their own streams and are joined back to the tree's stream, so a batch
+// completes in about the time of its slowest bin.
 tk_status run_stitch(tk_tree* t, std::vector<Job>& jobs, const std::vector<Hit>& hits, int max_iter,
                      double tol) {
   const int64_t nj = int64_t(jobs.size());
@@ -176,15 +193,16 @@ tk_status run_stitch(tk_tree* t, std::vector<Job>& jobs, const std::vector<Hit>&
   int lds_cap = 128;
   while (lds_cap > 8 && int64_t(tk::eig_doubles(lds_cap)) * 8 > t->lds_limit - int64_t(tk::stitch_static_lds()))
     lds_cap -= 8;
-  const int bins[3] = {32 < lds_cap ? 32 : lds_cap, 64 < lds_cap ? 64 : lds_cap, lds_cap};
-  std::vector<std::vector<Job>> binned(4);
+  int bins[tk_tree::kBins - 1] = {24, 32, 48, 64, 96};
+  for (int& b : bins) b = b < lds_cap ? b : lds_cap;
+  std::vector<std::vector<Job>> binned(tk_tree::kBins);
   for (int64_t i = 0; i < nj; ++i) {
     tk::StitchLayout lo;
     tk::stitch_layout(t->view, hits.data() + jobs[i].hit0, jobs[i].s, jobs[i].rq, 1 << 30, &lo);
     const int need = eig_need(lo, t->view, jobs[i].s);
     if (need > tk::EIG_MAXK_HOST) return fail(t, TK_EINVAL, "query needs an eigenproblem above 1024");
-    int b = 3;
-    for (int k = 0; k < 3; ++k)
+    int b = tk_tree::kBins - 1;
+    for (int k = 0; k < tk_tree::kBins - 1; ++k)
       if (need <= bins[k]) {
         b = k;
         break;
@@ -196,9 +214,29 @@ tk_status run_stitch(tk_tree* t, std::vector<Job>& jobs, const std::vector<Hit>&
   if (!hits.empty())
     TK_HIP(t, hipMemcpyAsync(t->dhits, hits.data(), hits.size() * sizeof(Hit), hipMemcpyHostToDevice,
                              t->stream));
-  for (int b = 0; b < 4; ++b) {
-    st = launch_bin(t, binned[size_t(b)], hits, b < 3 ? bins[b] : lds_cap, max_iter, tol);
+  int nonempty = 0;
+  for (auto& b : binned) nonempty += b.empty() ? 0 : 1;
+  if (nonempty <= 1) {
+    for (int b = 0; b < tk_tree::kBins; ++b)
+      if (!binned[size_t(b)].empty())
+        return launch_bin(t, binned[size_t(b)], hits, b < tk_tree::kBins - 1 ? bins[b] : lds_cap, max_iter, tol,
+                          t->stream, &t->ws, &t->ws_cap, &t->djobs, &t->djobs_cap);
+    return TK_OK;
+  }
+  if (!t->fork_ev) TK_HIP(t, hipEventCreateWithFlags(&t->fork_ev, hipEventDisableTiming));
+  TK_HIP(t, hipEventRecord(t->fork_ev, t->stream));
+  for (int b = 0; b < tk_tree::kBins; ++b) {
+    if (binned[size_t(b)].empty()) continue;
+    if (!t->bstream[b]) {
+      TK_HIP(t, hipStreamCreateWithFlags(&t->bstream[b], hipStreamNonBlocking));
+      TK_HIP(t, hipEventCreateWithFlags(&t->bev[b], hipEventDisableTiming));
+    }
+    TK_HIP(t, hipStreamWaitEvent(t->bstream[b], t->fork_ev, 0));
+    st = launch_bin(t, binned[size_t(b)], hits, b < tk_tree::kBins - 1 ? bins[b] : lds_cap, max_iter, tol,
+                    t->bstream[b], &t->bws[b], &t->bws_cap[b], &t->bjobs[b], &t->bjobs_cap[b]);
     if (st) return st;
+    TK_HIP(t, hipEventRecord(t->bev[b], t->bstream[b]));
+    TK_HIP(t, hipStreamWaitEvent(t->stream, t->bev[b], 0));
   }
   return TK_OK;
 }
@@ -467,6 +505,14 @@ void tk_destroy(tk_tree* t) {
   if (t->block_buf) (void)hipFree(t->block_buf);
   if (t->dstats) (void)hipFree(t->dstats);
   if (t->xbuf) (void)hipFree(t->xbuf);
+  for (int b = 0; b < tk_tree::kBins; ++b) {
+    if (t->bstream[b]) (void)hipStreamSynchronize(t->bstream[b]);
+    if (t->bws[b]) (void)hipFree(t->bws[b]);
+    if (t->bjobs[b]) (void)hipFree(t->bjobs[b]);
+    if (t->bstream[b]) (void)hipStreamDestroy(t->bstream[b]);
+    if (t->bev[b]) (void)hipEventDestroy(t->bev[b]);
+  }
+  if (t->fork_ev) (void)hipEventDestroy(t->fork_ev);
   if (t->ev0) (void)hipEventDestroy(t->ev0);
   if (t->ev1) (void)hipEventDestroy(t->ev1);
   delete t;

@@ -15,7 +15,7 @@ namespace tk {
 
 constexpr int MAXP = 6;      // modes handled by the kernels (time included)
 constexpr int MAXLEV = 48;   // tree levels (2^47 leaf blocks)
-constexpr int MAXHITS = 96;  // hits per query: <= 2(h-1), h <= MAXLEV
+constexpr int MAXHITS = 64;  // hits per query: <= 2(h-1) for trees of height <= 33
 constexpr int EIG_MAXK_HOST = 1024;  // largest eigenproblem a job may need
 
 // ---------------------------------------------------------------------------
@@ -216,21 +216,24 @@ struct StitchLayout {
   int64_t Ht[MAXHITS];        // float k_i x R_i, partial hits only
   int64_t F[MAXHITS];         // double k_i x k_i, partial hits only
   int64_t A[MAXHITS];         // float sum_{n>=1} rq_n x r_i^(n), modes in order
+  int64_t A64[MAXHITS];       // double, same shape as A
   int64_t F0[MAXHITS];        // double k_i x rq_0
   int64_t C[MAXP];            // float D_n x sr_n (q_n x sr_n used)
   int64_t C64[MAXP];          // double, same
-  int64_t A64[MAXHITS];       // double, same shape as A
   int64_t Fn[MAXP];           // double sr_n x sr_n (basis route only)
   int64_t Pd[MAXP];           // double D_n x rq_n  ([0]: sk x rq_0)
   int64_t Pf[MAXP];           // float  same
   int64_t Fh[MAXP];           // double sr_n x rq_n
+  int64_t EF[MAXP];           // double eigenbasis kept for warm starts: [0] sk x sk, [n] D_n x D_n
   int64_t M;                  // float sk x Rhat_0
-  int64_t K;                  // float max_n qmax_n Rhat_n
+  int64_t K;                  // float max_n D_n Rhat_n
   int64_t T1, T2;             // float tmax
-  int64_t D1, D2;             // double tmax (final FP64 core)
+  int64_t D1, D2;             // double tmax (init and final FP64 core)
+  int64_t S;                  // double 32 x 32 (mode Gram of one core)
   int64_t G;                  // float prod(rq)
   int64_t G64;                // double prod(rq)
-  int64_t EIG;                // double neig^2 + 4 neig (only when neig > n_lds)
+  int64_t TMP;                // double neig^2 (eigensolver / Cholesky scratch)
+  int64_t EIG;                // double eig_doubles(neig) (only when neig > n_lds)
   int64_t total;
   int32_t sr[MAXP];           // sum over hits of r_i^(n)
   int32_t qmax[MAXP];
@@ -245,10 +248,11 @@ TK_HD int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 // column norms, Gram-Schmidt coefficients and eigenvalues.
 TK_HD int64_t eig_doubles(int64_t n) { return n * n + 3 * n; }
 
+// The layout record itself occupies the head of the job's workspace.
 TK_HD void stitch_layout(const StoreView& st, const Hit* hits, int s, const int32_t* rq,
                          int n_lds, StitchLayout* Lo) {
   const int p = st.p;
-  int64_t off = 0;
+  int64_t off = align256(int64_t(sizeof(StitchLayout)));
   auto take = [&](int64_t bytes) {
     const int64_t o = off;
     off = align256(off + (bytes > 0 ? bytes : 0));
@@ -296,6 +300,7 @@ TK_HD void stitch_layout(const StoreView& st, const Hit* hits, int s, const int3
     Lo->Pd[n] = take(int64_t(Lo->qmax[n]) * rq[n] * 8);
     Lo->Pf[n] = take(int64_t(Lo->qmax[n]) * rq[n] * 4);
     Lo->Fh[n] = take(int64_t(Lo->sr[n]) * rq[n] * 8);
+    Lo->EF[n] = take(int64_t(Lo->qmax[n]) * Lo->qmax[n] * 8);
     if (Lo->sr[n] > neig) neig = Lo->sr[n];
     if (Lo->qmax[n] > neig) neig = Lo->qmax[n];
     const int64_t kn = int64_t(Lo->qmax[n]) * Rhat[n];
@@ -305,9 +310,10 @@ TK_HD void stitch_layout(const StoreView& st, const Hit* hits, int s, const int3
   Lo->sr[0] = Lo->sk;
   Lo->Pd[0] = take(int64_t(Lo->sk) * rq[0] * 8);
   Lo->Pf[0] = take(int64_t(Lo->sk) * rq[0] * 4);
+  Lo->EF[0] = take(int64_t(Lo->sk) * Lo->sk * 8);
   Lo->M = take(int64_t(Lo->sk) * Rhat[0] * 4);
   Lo->K = take(kmax * 4);
-  // the HOSVD init keeps C_i S_i (q x r) in T1
+  // the HOSVD init keeps C_i S_i (q x r) in D1
   int64_t tq = 0;
   for (int n = 1; n < p; ++n) {
     int64_t rmax = 0;
@@ -316,15 +322,19 @@ TK_HD void stitch_layout(const StoreView& st, const Hit* hits, int s, const int3
     if (int64_t(Lo->qmax[n]) * rmax > tq) tq = int64_t(Lo->qmax[n]) * rmax;
   }
   if (tq > Lo->tmax) Lo->tmax = tq;
+  // partial Gram tiles of a trim (gram_rows): at most 64 x 16 doubles
+  if (Lo->tmax < 64 * 16) Lo->tmax = 64 * 16;
   Lo->T1 = take(Lo->tmax * 4);
   Lo->T2 = take(Lo->tmax * 4);
   Lo->D1 = take(Lo->tmax * 8);
   Lo->D2 = take(Lo->tmax * 8);
+  Lo->S = take(32 * 32 * 8);
   int64_t gel = 1;
   for (int n = 0; n < p; ++n) gel *= rq[n];
   Lo->G = take(gel * 4);
   Lo->G64 = take(gel * 8);
   Lo->neig = neig;
+  Lo->TMP = take(int64_t(neig) * neig * 8);
   Lo->EIG = neig > n_lds ? take(eig_doubles(neig) * 8) : -1;
   Lo->total = off;
 }
@@ -336,6 +346,7 @@ struct LeafLayout {
   int64_t T1, T2;    // float, size of the raw block
   int64_t V;         // double N x rq (other-side route)
   int64_t G;         // float prod(rq)
+  int64_t TMP;       // double neig^2 (eigensolver scratch)
   int64_t EIG;       // double eig_doubles(neig) when neig > n_lds
   int64_t total;
   int32_t neig;
@@ -379,6 +390,7 @@ TK_HD void leaf_layout(const StoreView& st, int n_lds, LeafLayout* Lo) {
   for (int n = 0; n < p; ++n) gel *= rq[n];
   Lo->G = take(gel * 4);
   Lo->neig = neig;
+  Lo->TMP = take(int64_t(neig) * neig * 8);
   Lo->EIG = neig > n_lds ? take(eig_doubles(neig) * 8) : -1;
   Lo->total = off;
 }

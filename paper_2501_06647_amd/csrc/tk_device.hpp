@@ -1,7 +1,9 @@
 // Workgroup-level building blocks for the stitch and leaf kernels.
 //
 // Every routine is called by all threads of a workgroup and ends with a
-// barrier, so its output is visible to the whole workgroup on return.
+// barrier, so its output is visible to the whole workgroup on return.  The
+// stitch kernel runs one wavefront per job, where these barriers reduce to
+// wavefront-local ordering; the leaf kernel runs four wavefronts.
 // Tensors are C-order; a mode-n view of a tensor is (a, r, b) with a the
 // product of the sizes before mode n and b the product after it.
 #pragma once
@@ -10,26 +12,118 @@
 
 namespace tk {
 
-constexpr int NT = 256;  // threads per workgroup (four wave64 wavefronts)
-constexpr int EIG_MAXK = EIG_MAXK_HOST;  // eigenvectors one eig_top call can return
+// ---------------------------------------------------------------------------
+// Reductions
+// ---------------------------------------------------------------------------
 
-// Sum of v over the workgroup; every thread gets the result.
-__device__ inline double block_sum(double v, double* red) {
+// Sum of v over the workgroup; every thread gets the result.  red: one
+// double per wavefront (unused for a single-wavefront workgroup).
+__device__ __forceinline__ double block_sum(double v, double* red) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (blockDim.x <= 64) return v;
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   double s = 0.0;
   for (int w = 0; w < int(blockDim.x >> 6); ++w) s += red[w];
+  __syncthreads();
   return s;
 }
 
+// Largest v over the workgroup with its index (smallest index on ties).
+__device__ __forceinline__ void block_argmax(double& v, int& idx, double* red, int* redi) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(v, o, 64);
+    const int oi = __shfl_xor(idx, o, 64);
+    if (ov > v || (ov == v && oi < idx)) {
+      v = ov;
+      idx = oi;
+    }
+  }
+  if (blockDim.x <= 64) return;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = v;
+    redi[threadIdx.x >> 6] = idx;
+  }
+  __syncthreads();
+  for (int w = 0; w < int(blockDim.x >> 6); ++w)
+    if (red[w] > v || (red[w] == v && redi[w] < idx)) {
+      v = red[w];
+      idx = redi[w];
+    }
+  __syncthreads();
+}
+
+// Exchange a double with the lane whose index differs in bit 0 (CTRL 0xB1)
+// or bit 1 (CTRL 0x4E) inside each group of four lanes (DPP quad_perm).
+template <int CTRL>
+__device__ __forceinline__ double quad_swap(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// 1/x and 1/sqrt(x) for finite x > 0: the hardware approximations refined by
+// two Newton steps each (quadratic convergence to FP64 rounding).
+__device__ __forceinline__ double fast_rcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+
+__device__ __forceinline__ double fast_rsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+
+// ---------------------------------------------------------------------------
+// Contractions
+// ---------------------------------------------------------------------------
+
 // Mode product (App. A): Y[x][i][y] (+)= sum_j A(i, j) X[x][j][y] with
-// A(i, j) = A[i as + j bs], i < m, j < r; accumulation in Acc.
+// A(i, j) = A[i as + j bs], i < m, j < r; accumulation in Acc.  Each thread
+// takes whole fibers X[x][:][y]: the fiber is loaded once into registers and
+// every output of that fiber is formed from it (A is read uniformly across
+// the wavefront).  Fibers longer than RMAX fall back to one output per
+// thread.
+template <typename TX, typename TA, typename TY, typename Acc, int RMAX>
+__device__ __forceinline__ void mode_product_fiber(const TX* __restrict__ X, int64_t a, int r, int64_t b,
+                                   const TA* __restrict__ A, int64_t as, int64_t bs, int m,
+                                   TY* __restrict__ Y, bool acc) {
+  const int64_t nf = a * b;
+  for (int64_t f = threadIdx.x; f < nf; f += blockDim.x) {
+    const int64_t x = f / b, y = f % b;
+    const TX* xp = X + x * r * b + y;
+    Acc v[RMAX];
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j) v[j] = j < r ? Acc(xp[j * b]) : Acc(0);
+    TY* yp = Y + x * int64_t(m) * b + y;
+    for (int i = 0; i < m; ++i) {
+      const TA* ap = A + i * as;
+      Acc s = 0;
+#pragma unroll
+      for (int j = 0; j < RMAX; ++j)
+        if (j < r) s += Acc(ap[j * bs]) * v[j];
+      yp[i * b] = acc ? TY(Acc(yp[i * b]) + s) : TY(s);
+    }
+  }
+  __syncthreads();
+}
+
 template <typename TX, typename TA, typename TY, typename Acc>
-__device__ void mode_product_t(const TX* __restrict__ X, int64_t a, int r, int64_t b,
+__device__ __forceinline__ void mode_product_t(const TX* __restrict__ X, int64_t a, int r, int64_t b,
                                const TA* __restrict__ A, int64_t as, int64_t bs, int m,
                                TY* __restrict__ Y, bool acc) {
+  // fibers live in registers: up to 32 FP32 or 16 FP64 values
+  constexpr int kMax = sizeof(Acc) == 4 ? 32 : 16;
+  if (r <= 8) return mode_product_fiber<TX, TA, TY, Acc, 8>(X, a, r, b, A, as, bs, m, Y, acc);
+  if (r <= 16) return mode_product_fiber<TX, TA, TY, Acc, 16>(X, a, r, b, A, as, bs, m, Y, acc);
+  if (kMax >= 32 && r <= 32) return mode_product_fiber<TX, TA, TY, Acc, kMax>(X, a, r, b, A, as, bs, m, Y, acc);
   const int64_t total = a * int64_t(m) * b;
   for (int64_t o = threadIdx.x; o < total; o += blockDim.x) {
     const int64_t y = o % b;
@@ -46,7 +140,7 @@ __device__ void mode_product_t(const TX* __restrict__ X, int64_t a, int r, int64
 }
 
 // FP32 operands with FP32 accumulation (the contractions of the ALS loop).
-__device__ inline void mode_product(const float* __restrict__ X, int64_t a, int r, int64_t b,
+__device__ __forceinline__ void mode_product(const float* __restrict__ X, int64_t a, int r, int64_t b,
                                     const float* __restrict__ A, int64_t as, int64_t bs, int m,
                                     float* __restrict__ Y, bool acc) {
   mode_product_t<float, float, float, float>(X, a, r, b, A, as, bs, m, Y, acc);
@@ -54,28 +148,119 @@ __device__ inline void mode_product(const float* __restrict__ X, int64_t a, int 
 
 // Mode Gram G = mat_n(X) mat_n(X)^T (q x q, written as FP64 with leading
 // dimension ld; symmetric) for X viewed as (a, q, b).  Acc is the
-// accumulation type.
+// accumulation type.  Each thread owns a 4 x 4 tile of the upper triangle
+// and streams the fibers through registers.
 template <typename Acc>
-__device__ void gram_mode(const float* __restrict__ X, int64_t a, int q, int64_t b,
+__device__ __forceinline__ void gram_mode(const float* __restrict__ X, int64_t a, int q, int64_t b,
                           double* __restrict__ G, int ld) {
-  for (int e = threadIdx.x; e < q * q; e += blockDim.x) {
-    const int i = e / q, j = e % q;
-    if (j < i) continue;
-    Acc s = 0;
-    for (int64_t x = 0; x < a; ++x) {
-      const float* pi = X + (x * q + i) * b;
-      const float* pj = X + (x * q + j) * b;
-      for (int64_t y = 0; y < b; ++y) s += Acc(pi[y]) * Acc(pj[y]);
+  const int nb = (q + 3) / 4;
+  const int ntiles = nb * (nb + 1) / 2;
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+    int bi = 0, rem = t;
+    while (rem >= nb - bi) {
+      rem -= nb - bi;
+      ++bi;
     }
-    G[i * ld + j] = double(s);
-    G[j * ld + i] = double(s);
+    const int bj = bi + rem;
+    Acc s[4][4];
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) s[ii][jj] = 0;
+    for (int64_t x = 0; x < a; ++x) {
+      const float* base = X + x * q * b;
+      for (int64_t y = 0; y < b; ++y) {
+        Acc u[4], w[4];
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const int i = bi * 4 + ii, j = bj * 4 + ii;
+          u[ii] = i < q ? Acc(base[i * b + y]) : Acc(0);
+          w[ii] = j < q ? Acc(base[j * b + y]) : Acc(0);
+        }
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) s[ii][jj] += u[ii] * w[jj];
+      }
+    }
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int i = bi * 4 + ii, j = bj * 4 + jj;
+        if (i < q && j < q) {
+          G[i * ld + j] = double(s[ii][jj]);
+          G[j * ld + i] = double(s[ii][jj]);
+        }
+      }
+  }
+  __syncthreads();
+}
+
+// Gram of the rows of a tall, narrow matrix: G = V^T V for V (l x k,
+// row-major), FP64 accumulation, k <= 32.  Threads split the rows; each owns
+// a 4 x 4 tile of G for its share of rows, and the partial tiles are summed
+// through part (ntiles x nsplit x 16 doubles of scratch).
+__device__ __forceinline__ void gram_rows(const float* __restrict__ V, int64_t l, int k, double* __restrict__ G,
+                                          int ld, double* __restrict__ part) {
+  const int nb = (k + 3) / 4;
+  const int ntiles = nb * (nb + 1) / 2;
+  const int nsplit = int(blockDim.x) / ntiles > 0 ? int(blockDim.x) / ntiles : 1;
+  for (int w = threadIdx.x; w < ntiles * nsplit; w += blockDim.x) {
+    const int t = w % ntiles, sp = w / ntiles;
+    int bi = 0, rem = t;
+    while (rem >= nb - bi) {
+      rem -= nb - bi;
+      ++bi;
+    }
+    const int bj = bi + rem;
+    double s[4][4];
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) s[ii][jj] = 0.0;
+    for (int64_t r = sp; r < l; r += nsplit) {
+      const float* row = V + r * k;
+      double u[4], v[4];
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        u[ii] = bi * 4 + ii < k ? double(row[bi * 4 + ii]) : 0.0;
+        v[ii] = bj * 4 + ii < k ? double(row[bj * 4 + ii]) : 0.0;
+      }
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) s[ii][jj] += u[ii] * v[jj];
+    }
+    double* pp = part + (int64_t(t) * nsplit + sp) * 16;
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) pp[ii * 4 + jj] = s[ii][jj];
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < ntiles * 16; w += blockDim.x) {
+    const int t = w / 16, e = w % 16;
+    int bi = 0, rem = t;
+    while (rem >= nb - bi) {
+      rem -= nb - bi;
+      ++bi;
+    }
+    const int bj = bi + rem;
+    double acc = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) acc += part[(int64_t(t) * nsplit + sp) * 16 + e];
+    const int i = bi * 4 + e / 4, j = bj * 4 + e % 4;
+    if (i < k && j < k) {
+      G[i * ld + j] = acc;
+      G[j * ld + i] = acc;
+    }
   }
   __syncthreads();
 }
 
 // Gram over the other side: G[c1][c2] = sum_d X[x1][d][y1] X[x2][d][y2] with
 // c = x b + y, N = a b; FP64 accumulation.
-__device__ void gram_other(const float* __restrict__ X, int64_t a, int D, int64_t b,
+__device__ __forceinline__ void gram_other(const float* __restrict__ X, int64_t a, int D, int64_t b,
                            double* __restrict__ G, int ld) {
   const int64_t N = a * b;
   for (int64_t e = threadIdx.x; e < N * N; e += blockDim.x) {
@@ -91,15 +276,19 @@ __device__ void gram_other(const float* __restrict__ X, int64_t a, int D, int64_
   __syncthreads();
 }
 
-// Orthonormalise columns idx[0..k) of W (column c at W + c n, n rows) in
-// place, in FP64.  The columns are first checked: when their Gram is within
-// 1e-12 of the identity nothing more is done.  Otherwise classical
-// Gram-Schmidt is applied twice, column by column; a column that vanishes
-// (a zero or dependent vector) is replaced by the next unit vector e_c that
-// survives, so the k columns always end orthonormal when k <= n.
-// coef: >= k doubles; flag: an int in LDS.
-__device__ void orthonormalize_cols(double* W, int n, int k, const int* idx, double* coef, double* red,
-                                    int* flag) {
+// ---------------------------------------------------------------------------
+// Orthonormalisation
+// ---------------------------------------------------------------------------
+
+// Orthonormalise the k columns of E (n rows; entry (r, j) at E[r rs + j cs];
+// FP64) in place: if their Gram is within 1e-12 of the identity nothing
+// changes; otherwise classical Gram-Schmidt is applied twice, column by
+// column, and a column that vanishes (a zero or dependent vector) is replaced
+// by the next unit vector that survives, so the k columns end orthonormal
+// when k <= n (columns beyond n are zeroed).  coef: >= k doubles; flag: an
+// int in LDS.
+__device__ __forceinline__ void orthonormalize(double* E, int n, int k, int64_t rs, int64_t cs, double* coef, double* red,
+                               int* flag) {
   const int tid = threadIdx.x, nt = blockDim.x;
   if (k <= 0) return;
   if (tid == 0) *flag = 0;
@@ -107,135 +296,225 @@ __device__ void orthonormalize_cols(double* W, int n, int k, const int* idx, dou
   for (int e = tid; e < k * k; e += nt) {
     const int i = e / k, j = e % k;
     if (j < i) continue;
-    const double* a = W + int64_t(idx[i]) * n;
-    const double* b = W + int64_t(idx[j]) * n;
     double d = 0.0;
-    for (int r = 0; r < n; ++r) d += a[r] * b[r];
+    for (int r = 0; r < n; ++r) d += E[r * rs + i * cs] * E[r * rs + j * cs];
     if (fabs(d - (i == j ? 1.0 : 0.0)) > 1e-12) *flag = 1;
   }
   __syncthreads();
   if (*flag == 0) return;
   int cand = 0;
   for (int j = 0; j < k && j < n; ++j) {
-    double* w = W + int64_t(idx[j]) * n;
     for (int attempt = 0; attempt <= n; ++attempt) {
       for (int pass = 0; pass < 2; ++pass) {
-        // all coefficients of column j at once: groups of 8 lanes per column i < j
-        for (int base = 0; base < j; base += nt / 8) {
-          const int i = base + tid / 8, lane = tid % 8;
+        for (int i = tid; i < j; i += nt) {
           double d = 0.0;
-          if (i < j) {
-            const double* a = W + int64_t(idx[i]) * n;
-            for (int r = lane; r < n; r += 8) d += a[r] * w[r];
-          }
-          for (int o = 4; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
-          if (i < j && lane == 0) coef[i] = d;
-        }
-        __syncthreads();
-        for (int r = tid; r < n; r += nt) {
-          double v = w[r];
-          for (int i = 0; i < j; ++i) v -= coef[i] * W[int64_t(idx[i]) * n + r];
-          w[r] = v;
-        }
-        __syncthreads();
-      }
-      double part = 0.0;
-      for (int r = tid; r < n; r += nt) part += w[r] * w[r];
-      const double nrm = sqrt(block_sum(part, red));
-      if (nrm > 0.5) {
-        for (int r = tid; r < n; r += nt) w[r] /= nrm;
-        __syncthreads();
-        break;
-      }
-      for (int r = tid; r < n; r += nt) w[r] = (r == cand) ? 1.0 : 0.0;
-      ++cand;
-      __syncthreads();
-    }
-  }
-}
-
-// Orthonormalise the k columns of E (n x k, row-major, leading dimension
-// lde) in FP64, as orthonormalize_cols does (used on results held outside
-// the eigensolver's buffer).  coef: >= k doubles.
-__device__ void orthonormalize(double* E, int n, int k, int lde, double* coef, double* red) {
-  int cand = 0;
-  for (int j = 0; j < k && j < n; ++j) {
-    for (int attempt = 0; attempt <= n; ++attempt) {
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int i = threadIdx.x; i < j; i += blockDim.x) {
-          double d = 0.0;
-          for (int r = 0; r < n; ++r) d += E[r * lde + i] * E[r * lde + j];
+          for (int r = 0; r < n; ++r) d += E[r * rs + i * cs] * E[r * rs + j * cs];
           coef[i] = d;
         }
         __syncthreads();
-        for (int r = threadIdx.x; r < n; r += blockDim.x) {
-          double v = E[r * lde + j];
-          for (int i = 0; i < j; ++i) v -= coef[i] * E[r * lde + i];
-          E[r * lde + j] = v;
+        for (int r = tid; r < n; r += nt) {
+          double v = E[r * rs + j * cs];
+          for (int i = 0; i < j; ++i) v -= coef[i] * E[r * rs + i * cs];
+          E[r * rs + j * cs] = v;
         }
         __syncthreads();
       }
       double part = 0.0;
-      for (int r = threadIdx.x; r < n; r += blockDim.x) part += E[r * lde + j] * E[r * lde + j];
+      for (int r = tid; r < n; r += nt) part += E[r * rs + j * cs] * E[r * rs + j * cs];
       const double nrm = sqrt(block_sum(part, red));
       if (nrm > 0.5) {
-        for (int r = threadIdx.x; r < n; r += blockDim.x) E[r * lde + j] /= nrm;
+        for (int r = tid; r < n; r += nt) E[r * rs + j * cs] /= nrm;
         __syncthreads();
         break;
       }
-      for (int r = threadIdx.x; r < n; r += blockDim.x) E[r * lde + j] = (r == cand) ? 1.0 : 0.0;
+      for (int r = tid; r < n; r += nt) E[r * rs + j * cs] = (r == cand) ? 1.0 : 0.0;
       ++cand;
       __syncthreads();
     }
   }
   for (int j = n; j < k; ++j)
-    for (int r = threadIdx.x; r < n; r += blockDim.x) E[r * lde + j] = 0.0;
+    for (int r = tid; r < n; r += nt) E[r * rs + j * cs] = 0.0;
   __syncthreads();
 }
 
-// Leading eigenpairs of a symmetric positive semi-definite n x n matrix S by
-// one-sided Jacobi (Hestenes 1958): W (holding S, column c at W + c n) is
-// rotated by plane rotations V until its columns are mutually orthogonal,
-// W = S V; then V holds eigenvectors of S and column c of W equals
-// lambda_c v_c.  Pairs are visited in the round-robin order, n/2 disjoint
-// pairs per step, each pair by a group of g lanes of one wavefront.
-// Writes the k leading unit eigenvectors into E (n x k, row-major, lde) in
-// descending eigenvalue order and returns a pointer to the k eigenvalues.
-// Columns whose eigenvalue is at most keep_rel times the largest are
-// normalised but not orthonormalised (callers that drop such directions pass
-// keep_rel > 0); with keep_rel = 0 all k columns come out orthonormal, a
-// dependent one completed by a unit vector.  W must hold eig_doubles(n)
-// doubles; the scratch (norms, ranks, coefficients, eigenvalues) follows the
-// matrix, and the eigenvalues stay valid until W is reused.  When k > n only
-// n eigenpairs exist and the extra columns of E are zero.
+// ---------------------------------------------------------------------------
+// Pivoted Cholesky
+// ---------------------------------------------------------------------------
+
+// Pivoted Cholesky of a symmetric positive semi-definite m x m matrix G
+// (row-major, leading dimension m): P^T G P = L L^T with the pivot taken as
+// the largest remaining diagonal (outer-product Cholesky with diagonal
+// pivoting, Golub & Van Loan); it stops when that diagonal is at most tau
+// times the largest initial one.  L: m x m row-major (row i belongs to pivot
+// position i; columns < q hold the factor).  piv: m ints; d: m doubles of
+// scratch.  Returns the rank q.
+__device__ __forceinline__ int pchol(const double* G, int m, double tau, double* L, int* piv, double* d, double* red,
+                     int* redi) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double dmax0 = 0.0;
+  for (int i = tid; i < m; i += nt) {
+    d[i] = G[int64_t(i) * m + i];
+    piv[i] = i;
+    dmax0 = fmax(dmax0, d[i]);
+  }
+  int dummy = 0;
+  block_argmax(dmax0, dummy, red, redi);
+  __syncthreads();
+  int q = m;
+  for (int j = 0; j < m; ++j) {
+    double bv = -1.0;
+    int bi = m;
+    for (int i = j + tid; i < m; i += nt) {
+      const double v = d[piv[i]];
+      if (v > bv || (v == bv && i < bi)) {
+        bv = v;
+        bi = i;
+      }
+    }
+    block_argmax(bv, bi, red, redi);
+    if (!(bv > tau * dmax0) || !(bv > 0.0)) {
+      q = j;
+      break;
+    }
+    // move pivot position bi to j, with the rows of L computed so far
+    for (int t = tid; t < j; t += nt) {
+      const double x = L[int64_t(j) * m + t];
+      L[int64_t(j) * m + t] = L[int64_t(bi) * m + t];
+      L[int64_t(bi) * m + t] = x;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const int x = piv[j];
+      piv[j] = piv[bi];
+      piv[bi] = x;
+      L[int64_t(j) * m + j] = sqrt(bv);
+    }
+    __syncthreads();
+    const double ljj = sqrt(bv);
+    const int pj = piv[j];
+    for (int i = j + 1 + tid; i < m; i += nt) {
+      const int pi = piv[i];
+      double s = G[int64_t(pi) * m + pj];
+      for (int t = 0; t < j; ++t) s -= L[int64_t(i) * m + t] * L[int64_t(j) * m + t];
+      const double l = s / ljj;
+      L[int64_t(i) * m + j] = l;
+      d[pi] -= l * l;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  return q;
+}
+
+// From a pivoted Cholesky factor (L, piv, rank q) of the Gram V^T V of a
+// matrix V with m columns, write the coordinates C (q x m, leading dimension
+// ldc) of V's columns in the orthonormal basis B = V P [L11^{-T}; 0], i.e.
+// C = B^T V = L^T P^T, and F (m x q, leading dimension ldf) with B = V F.
+// Tinv: q x q doubles of scratch (L11^{-1}).
+template <typename TC>
+__device__ __forceinline__ void pchol_basis(const double* L, const int* piv, int m, int q, TC* C, int ldc, double* F, int ldf,
+                            double* Tinv) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int e = tid; e < q * m; e += nt) {
+    const int j = e / m, c = e % m;
+    C[int64_t(j) * ldc + piv[c]] = TC(c >= j ? L[int64_t(c) * m + j] : 0.0);
+  }
+  // T = L11^{-1} (lower triangular), one column per thread
+  for (int c = tid; c < q; c += nt) {
+    for (int i = 0; i < q; ++i) Tinv[int64_t(i) * q + c] = 0.0;
+    Tinv[int64_t(c) * q + c] = 1.0 / L[int64_t(c) * m + c];
+    for (int i = c + 1; i < q; ++i) {
+      double s = 0.0;
+      for (int t = c; t < i; ++t) s += L[int64_t(i) * m + t] * Tinv[int64_t(t) * q + c];
+      Tinv[int64_t(i) * q + c] = -s / L[int64_t(i) * m + i];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < m * q; e += nt) {
+    const int c = e / q, j = e % q;
+    F[int64_t(piv[c]) * ldf + j] = c < q ? Tinv[int64_t(j) * q + c] : 0.0;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric eigenproblems
+// ---------------------------------------------------------------------------
+
 struct EigCounters {
   uint64_t calls = 0, sweeps = 0, jacobi_ticks = 0, tail_ticks = 0;
 };
 
-__device__ const double* eig_top(double* W, int n, int k, double* E, int lde, double* red,
-                                 double keep_rel = 0.0, EigCounters* cnt = nullptr) {
-  const uint64_t t_start = wall_clock64();
-  __shared__ int s_idx[EIG_MAXK];
+// Leading eigenpairs of a symmetric positive semi-definite n x n matrix S by
+// one-sided Jacobi (Hestenes 1958): W (holding S, column c at W + c n) is
+// rotated by plane rotations until its columns are mutually orthogonal,
+// W = S V; then V holds eigenvectors of S and column c of W equals
+// lambda_c v_c.  Pairs are visited in the round-robin order, n/2 disjoint
+// pairs per step, each pair by a group of g <= 16 adjacent lanes that add
+// their partial dot products through DPP quad exchanges (and shuffles beyond
+// four lanes); column norms are carried from rotation to rotation, so a step
+// computes one dot product per pair.
+//
+// Warm start: when warm is set, Ef (n x n, column c at Ef + c n) holds an
+// orthogonal matrix from a previous, nearby problem and the rotations start
+// from W = S Ef, which converges in a few sweeps when Ef is close to an
+// eigenbasis.  When Ef is given it receives all n unit eigenvectors in
+// descending eigenvalue order (orthonormalised, dependent ones completed)
+// for the next warm start.
+//
+// Writes the k leading unit eigenvectors into E (n x k, row-major, lde) in
+// descending eigenvalue order and returns a pointer to the k eigenvalues.
+// W must hold eig_doubles(n) doubles (the scratch follows the matrix; the
+// eigenvalues stay valid until W is reused); tmp: n x n doubles.  When k > n
+// only n eigenpairs exist and the extra columns of E are zero.
+__device__ __forceinline__ const double* eig_top(double* W, int n, int k, double* E, int lde, double* red, double* Ef,
+                                 double* tmp, bool warm, EigCounters* cnt) {
   __shared__ int s_flag;
+  const uint64_t t_start = wall_clock64();
   const int tid = threadIdx.x, nt = blockDim.x;
-  double* scratch = W + int64_t(n) * n;
-  double* nrm = scratch;
-  double* coef = scratch + n;
-  double* lam = scratch + 2 * n;
+  double* nrm = W + int64_t(n) * n;
+  double* coef = nrm + n;
+  double* lam = coef + n;
+  int* order = reinterpret_cast<int*>(coef);  // coef is free until the final orthonormalisation
   if (n <= 0) return lam;
+  double tr = 0.0;
+  for (int i = tid; i < n; i += nt) tr += fabs(W[int64_t(i) * n + i]);
+  tr = block_sum(tr, red);
+  if (warm && Ef) {
+    for (int64_t e = tid; e < int64_t(n) * n; e += nt) tmp[e] = W[e];
+    __syncthreads();
+    for (int64_t e = tid; e < int64_t(n) * n; e += nt) {
+      const int c = int(e / n), r = int(e % n);
+      const double* ec = Ef + int64_t(c) * n;
+      double s = 0.0;
+      for (int j = 0; j < n; ++j) s += tmp[int64_t(j) * n + r] * ec[j];
+      W[e] = s;
+    }
+    __syncthreads();
+  }
   const int N = n + (n & 1);
   const int npairs = N / 2;
-  int g = 64;
+  int g = 16;
   while (g > 1 && npairs * g > nt) g >>= 1;
   const int groups = nt / g;
-  double tr = 0.0;
-  for (int i = tid; i < n; i += nt) tr += fabs(W[i * n + i]);
-  tr = block_sum(tr, red);
   const double tiny = (1e-17 * tr) * (1e-17 * tr);
   const double eps = 4e-16 * double(n > 8 ? n : 8);
+  const double eps2 = eps * eps;
+  // squared column norms, refreshed every sweep and updated by each rotation
+  // (a rotation that zeroes w_p . w_q maps |w_p|^2 -> |w_p|^2 - t g and
+  // |w_q|^2 -> |w_q|^2 + t g), so a step needs only the one dot product
+  double* cn = nrm;
   int sweeps_run = 0;
   for (int sweep = 0; sweep < 40 && N > 1; ++sweep) {
     ++sweeps_run;
+    double maxc2 = 0.0;  // largest squared cosine rotated away in this sweep
+    for (int c = tid; c < n; c += nt) {
+      const double* w = W + int64_t(c) * n;
+      double s2 = 0.0;
+      for (int r = 0; r < n; ++r) s2 += w[r] * w[r];
+      cn[c] = s2;
+    }
+    __syncthreads();
     int rotated = 0;
     for (int step = 0; step < N - 1; ++step) {
       for (int base = 0; base < npairs; base += groups) {
@@ -247,51 +526,93 @@ __device__ const double* eig_top(double* W, int n, int k, double* E, int lde, do
             pp = N - 1;
             qq = step;
           } else {
-            pp = (step + pi) % (N - 1);
-            qq = (step - pi + (N - 1)) % (N - 1);
+            pp = step + pi;
+            if (pp >= N - 1) pp -= N - 1;
+            qq = step - pi;
+            if (qq < 0) qq += N - 1;
           }
         }
         const bool act = pp < n && qq < n;
-        double al = 0.0, be = 0.0, ga = 0.0;
+        constexpr int RPL = 8;  // rows per lane kept in registers
+        double xr[RPL], yr[RPL];
+        double ga = 0.0, ga2 = 0.0, al = 0.0, be = 0.0;
+        double* wp = W + int64_t(act ? pp : 0) * n;
+        double* wq = W + int64_t(act ? qq : 0) * n;
+        const bool inreg = (n + g - 1) / g <= RPL;
         if (act) {
-          const double* wp = W + int64_t(pp) * n;
-          const double* wq = W + int64_t(qq) * n;
-          for (int r = lane; r < n; r += g) {
-            const double x = wp[r], y = wq[r];
-            al += x * x;
-            be += y * y;
-            ga += x * y;
+          al = cn[pp];
+          be = cn[qq];
+          if (inreg) {
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) {
+              const int r = lane + t * g;
+              xr[t] = r < n ? wp[r] : 0.0;
+              yr[t] = r < n ? wq[r] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < RPL; t += 2) {
+              ga += xr[t] * yr[t];
+              ga2 += xr[t + 1] * yr[t + 1];
+            }
+            ga += ga2;
+          } else {
+            for (int r = lane; r < n; r += g) ga += wp[r] * wq[r];
           }
         }
-        for (int o = g >> 1; o > 0; o >>= 1) {
-          al += __shfl_xor(al, o, 64);
-          be += __shfl_xor(be, o, 64);
-          ga += __shfl_xor(ga, o, 64);
-        }
-        if (act) {
-          const double ab = sqrt(al * be);
-          if (ab > tiny && fabs(ga) > eps * ab) {
-            const double zeta = (be - al) / (2.0 * ga);
-            const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double c = 1.0 / sqrt(1.0 + t * t);
-            const double sn = c * t;
-            double* wp = W + int64_t(pp) * n;
-            double* wq = W + int64_t(qq) * n;
+        if (g >= 2) ga += quad_swap<0xB1>(ga);
+        if (g >= 4) ga += quad_swap<0x4E>(ga);
+        if (g >= 8) ga += __shfl_xor(ga, 4, 64);
+        if (g >= 16) ga += __shfl_xor(ga, 8, 64);
+        if (act && ga * ga > eps2 * al * be && al * be > tiny * tiny) {
+          maxc2 = fmax(maxc2, ga * ga / (al * be));
+          // t = tan of the rotation angle, the root of t^2 + 2 zeta t - 1 = 0
+          // of smaller magnitude, zeta = (be - al) / (2 ga)
+          const double tau = be - al, rho = 2.0 * ga;
+          const double h2 = tau * tau + rho * rho;
+          const double h = h2 * fast_rsqrt(h2);
+          const double t = (tau >= 0.0 ? rho : -rho) * fast_rcp(fabs(tau) + h);
+          const double c = fast_rsqrt(fma(t, t, 1.0));
+          const double sn = c * t;
+          if (inreg) {
+#pragma unroll
+            for (int tt = 0; tt < RPL; ++tt) {
+              const int r = lane + tt * g;
+              if (r < n) {
+                wp[r] = c * xr[tt] - sn * yr[tt];
+                wq[r] = sn * xr[tt] + c * yr[tt];
+              }
+            }
+          } else {
             for (int r = lane; r < n; r += g) {
               const double x = wp[r], y = wq[r];
               wp[r] = c * x - sn * y;
               wq[r] = sn * x + c * y;
             }
-            rotated = 1;
           }
+          if (lane == 0) {
+            cn[pp] = al - t * ga;
+            cn[qq] = be + t * ga;
+          }
+          rotated = 1;
         }
       }
       __syncthreads();
     }
     if (!__syncthreads_or(rotated)) break;
+    // quadratic convergence: once every rotated cosine is below sqrt(eps)
+    // the next sweep would leave them below eps, so stop without it
+    double mx = maxc2;
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if (nt > 64) {
+      if ((tid & 63) == 0) red[tid >> 6] = mx;
+      __syncthreads();
+      for (int w = 0; w < nt / 64; ++w) mx = fmax(mx, red[w]);
+      __syncthreads();
+    }
+    if (mx < eps) break;
   }
   const uint64_t t_jac = wall_clock64();
-  // column norms = |lambda|; rank them (ties by index) and keep the top k
+  // column norms = |lambda|; rank the columns (ties by index)
   for (int c = tid; c < n; c += nt) {
     double s = 0.0;
     const double* w = W + int64_t(c) * n;
@@ -299,36 +620,29 @@ __device__ const double* eig_top(double* W, int n, int k, double* E, int lde, do
     nrm[c] = sqrt(s);
   }
   __syncthreads();
-  const int kk = k < n ? k : n;
   for (int c = tid; c < n; c += nt) {
     int rank = 0;
     for (int c2 = 0; c2 < n; ++c2)
       if (nrm[c2] > nrm[c] || (nrm[c2] == nrm[c] && c2 < c)) ++rank;
-    if (rank < kk) s_idx[rank] = c;
+    order[rank] = c;
   }
   __syncthreads();
-  for (int j = tid; j < kk; j += nt) lam[j] = nrm[s_idx[j]];
-  __syncthreads();
-  // normalise the kept columns in place, then orthonormalise the leading
-  // ones (those above keep_rel, or all of them)
-  const double lmax = kk > 0 ? lam[0] : 0.0;
-  for (int e = tid; e < n * kk; e += nt) {
-    const int j = e / n, r = e % n;
-    const double s = lam[j];
-    double* w = W + int64_t(s_idx[j]) * n;
-    w[r] = s > 0.0 ? w[r] / s : 0.0;
+  const int kk = k < n ? k : n;
+  const int nkeep = Ef ? n : kk;
+  double* dst = Ef ? Ef : tmp;
+  for (int64_t e = tid; e < int64_t(n) * nkeep; e += nt) {
+    const int j = int(e / n), r = int(e % n);
+    const int c = order[j];
+    const double s = nrm[c];
+    dst[e] = s > 0.0 ? W[int64_t(c) * n + r] / s : 0.0;
   }
   __syncthreads();
-  int ko = kk;
-  if (keep_rel > 0.0) {
-    ko = 0;
-    for (int j = 0; j < kk; ++j)
-      if (lam[j] > keep_rel * lmax) ko = j + 1;
-  }
-  orthonormalize_cols(W, n, ko, s_idx, coef, red, &s_flag);
-  for (int e = tid; e < n * k; e += nt) {
-    const int r = e / k, j = e % k;
-    E[r * lde + j] = j < kk ? W[int64_t(s_idx[j]) * n + r] : 0.0;
+  for (int j = tid; j < kk; j += nt) lam[j] = nrm[order[j]];
+  __syncthreads();
+  orthonormalize(dst, n, nkeep, 1, n, coef, red, &s_flag);
+  for (int64_t e = tid; e < int64_t(n) * k; e += nt) {
+    const int r = int(e / k), j = int(e % k);
+    E[int64_t(r) * lde + j] = j < kk ? dst[int64_t(j) * n + r] : 0.0;
   }
   __syncthreads();
   if (cnt && tid == 0) {

@@ -5,6 +5,10 @@
 
 namespace tk {
 
+constexpr int NT_STITCH = 64;        // one wavefront per stitch job
+constexpr int NT_STITCH_WIDE = 256;  // four wavefronts for jobs with large eigenproblems
+constexpr int NT_LEAF = 256;    // four wavefronts per leaf job
+
 struct StitchArgs {
   const StoreView* st;
   const Job* jobs;
@@ -26,7 +30,7 @@ struct LeafArgs {
   double tol;
 };
 
-hipError_t launch_stitch(const StitchArgs& a, int n_jobs, size_t lds_bytes, hipStream_t stream);
+hipError_t launch_stitch(const StitchArgs& a, int n_jobs, size_t lds_bytes, bool wide, hipStream_t stream);
 hipError_t launch_leaf(const LeafArgs& a, int n_jobs, size_t lds_bytes, hipStream_t stream);
 hipError_t set_lds_limits(size_t stitch_bytes, size_t leaf_bytes);
 size_t stitch_static_lds();

@@ -69,6 +69,90 @@ def blas_threads():
         return 1
 
 
+def serve_main(args):
+    """Serving run: a prefix of the stream is built, then slices are appended
+    at a steady rate while range queries arrive as a Poisson process, each
+    over a log-uniform length inside the horizon committed so far; the
+    library's scheduler admits and batches them.  Reports queries/s and
+    p50/p99 latency (submission to completion, host clock)."""
+    import torch
+    import synth
+    from paper_2501_06647_amd import Tree
+
+    wl = synth.get(args.workload)
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(wl.query_seed + 77)
+    T0 = min(args.serve_prefix, wl.T)
+    n_app = min(int(args.aps * args.serve_seconds), wl.T - T0)
+    X = synth.series(wl, 0, T0 + n_app).astype(np.float32)
+    tree = Tree(wl.dims, wl.node_ranks, wl.leaf_len, wl.theta, wl.max_iter, wl.tol, capacity_T=wl.T)
+    tree.build(X[:T0])
+    torch.cuda.synchronize()
+    if not args.no_tune:
+        ts, te = synth.queries(wl, T=T0, n=512)
+        print("[serve] autotune: %s" % (tree.autotune(ts, te, reps=1),), file=sys.stderr, flush=True)
+    # arrival schedule
+    horizon = n_app / args.aps
+    q_times = np.cumsum(rng.exponential(1.0 / args.qps, size=int(args.qps * horizon * 1.2) + 16))
+    q_times = q_times[q_times < horizon]
+    a_times = np.arange(n_app) / args.aps
+    events = sorted([(t, 1, i) for i, t in enumerate(a_times)] + [(t, 0, i) for i, t in enumerate(q_times)])
+    print("[serve] prefix %d slices, %d appends at %g/s, %d queries at %g/s over %.1f s"
+          % (T0, n_app, args.aps, len(q_times), args.qps, horizon), file=sys.stderr, flush=True)
+    srv = tree.serve()
+    ell = wl.leaf_len
+    T = T0
+    qtickets = []
+    open_q = []
+    t_start = time.perf_counter()
+    last_print = t_start
+    for (tev, kind, i) in events:
+        while True:
+            now = time.perf_counter() - t_start
+            if now >= tev:
+                break
+            if tev - now > 2e-4:
+                time.sleep(min(tev - now - 1e-4, 1e-3))
+        if kind == 1:
+            srv.submit_append(X[T])
+            T += 1
+        else:
+            Tc = (T // ell) * ell
+            L = int(min(Tc, max(1, round(math.exp(rng.uniform(0.0, math.log(Tc)))))))
+            a = int(rng.integers(0, Tc - L + 1))
+            tk = srv.submit_query(a, a + L)
+            qtickets.append(tk)
+            open_q.append(tk)
+        # release finished outputs so device memory stays bounded
+        while open_q and srv.poll(open_q[0]):
+            srv.release(open_q.pop(0))
+        if time.perf_counter() - last_print > 5.0:
+            last_print = time.perf_counter()
+            print("[serve] t=%.1f s T=%d %s" % (last_print - t_start, T, srv.stats()), file=sys.stderr, flush=True)
+    srv.sync()
+    wall = time.perf_counter() - t_start
+    stats = srv.stats()
+    lat = np.array([srv.times(tk) for tk in qtickets])
+    srv.stop()
+    lat_ms = (lat[:, 2] - lat[:, 0]) / 1000.0
+    qps = len(qtickets) / wall
+    out = {
+        "metric": "serving: range queries/s with p50/p99 latency, appends interleaved",
+        "value": qps, "unit": "queries/s", "n_gpus": 1, "steps": len(qtickets), "warmup": 0,
+        "ms_per_step": 1000.0 * wall / max(1, len(qtickets)), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "%s: %s slices, T %d -> %d, node ranks %s, leaf %d; Poisson queries at %g/s "
+                               "(log-uniform lengths in [1, T_c]), appends at %g/s"
+                               % (wl.name, "x".join(map(str, wl.dims)), T0, T, wl.node_ranks, wl.leaf_len,
+                                  args.qps, args.aps)},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
+                       "max": float(lat_ms.max())},
+        "appends_per_s": n_app / wall,
+        "server": stats,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,11 +162,21 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="serving run instead of the batched benchmark")
+    ap.add_argument("--qps", type=float, default=2000.0)
+    ap.add_argument("--aps", type=float, default=1000.0)
+    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-prefix", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(queries are independent; see DESIGN.md on sharding)", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        if args.workload == "plain":
+            args.workload = "serving"
+        return serve_main(args)
 
     import torch
     import synth
@@ -103,6 +197,13 @@ def main():
 
     ts, te = synth.queries(wl)
     nq = len(ts)
+    tuning, tune_ms = None, None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        tuning, tune_ms = tree.autotune(ts, te, reps=2)
+        print("[bench] autotune: %s (%.3f ms per batch) in %.1f s" % (tuning, tune_ms, time.perf_counter() - t0),
+              file=sys.stderr, flush=True)
+    tuning = tree.tuning()
     batch = tree.prepare_batch(ts, te)
     for _ in range(args.warmup):
         batch.run()
@@ -111,13 +212,22 @@ def main():
     t0 = time.perf_counter()
     for _ in range(args.steps):
         batch.run()
-        kms.append(tree.last_kernel_ms())
+        kms.append(batch.kernel_ms())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = 1000.0 * wall / args.steps
     qps = nq * args.steps / wall
-    print("[bench] batched: %.3f ms/step, kernel %.3f ms" % (ms_per_step, float(np.mean(kms))),
+    print("[bench] batched (graph): %.3f ms/step, kernel %.3f ms" % (ms_per_step, float(np.mean(kms))),
           file=sys.stderr, flush=True)
+    # the same queries through tk_query_batch (host Recall and planning every call)
+    sync_steps = max(1, min(3, args.steps))
+    t1 = time.perf_counter()
+    for _ in range(sync_steps):
+        batch.run_sync()
+    torch.cuda.synchronize()
+    sync_ms = 1000.0 * (time.perf_counter() - t1) / sync_steps
+    print("[bench] batched (tk_query_batch): %.3f ms/step" % sync_ms, file=sys.stderr, flush=True)
+    batch.run()
 
     results = batch.results()
     D = [0] + list(wl.dims)
@@ -133,7 +243,7 @@ def main():
         hit_counts.append(len(hits))
     kernel_s = float(np.mean(kms)) / 1000.0
     achieved = flops / kernel_s / 1e12
-    prof = [tree.last_profile(i) for i in range(nq)]
+    prof = [batch.profile(i) for i in range(nq)]
     phase_mean = {k: float(np.mean([pr[k] for pr in prof])) for k in tree.PHASES}
     tot = np.array([sum(pr[k] for k in tree.PHASES) for pr in prof])
     counters = {k: float(np.mean([pr[k] for pr in prof])) for k in tree.COUNTERS}
@@ -207,7 +317,10 @@ def main():
                                % (wl.name, "x".join(map(str, wl.dims)), wl.T, wl.true_ranks, wl.noise,
                                   wl.leaf_len, wl.node_ranks, nq, wl.query_kind, wl.theta[0], wl.theta[1],
                                   wl.max_iter, wl.tol),
-                   "queries_per_step": nq, "path": "batched: one launch per step, one workgroup per query"},
+                   "queries_per_step": nq,
+                   "path": "prepared batch: one HIP graph per step, fused Recall+trims+Stitch kernel per LDS bin",
+                   "tuning": tuning},
+        "sync_batch_ms_per_step": sync_ms,
         "latency_ms": {"batch_p50": ms_per_step, "batch_p99": ms_per_step,
                        "plain_p50": plain["p50_ms"] if plain else None,
                        "plain_p99": plain["p99_ms"] if plain else None},

@@ -45,7 +45,7 @@ typedef enum {
   TK_ERANGE = 2,  /* query range outside [0, T_c), or t_s >= t_e              */
   TK_ENOMEM = 3,  /* capacity or memory budget exceeded                      */
   TK_EDEVICE = 4, /* a HIP call failed; the tree is poisoned                 */
-  TK_EBUSY = 5    /* serving queue full                                       */
+  TK_EBUSY = 5    /* serving: queue full, or a call that the server excludes  */
 } tk_status;
 
 typedef enum {
@@ -89,6 +89,7 @@ typedef struct {
   int64_t core_elems;              /* prod of ranks_eff                        */
   int64_t factor_elems[TK_MAX_MODES]; /* [0] = L r_1; [n] = D_n r_n            */
   int32_t n_hits;
+  int64_t ws_bytes;                /* device workspace of the query, at most   */
 } tk_shape;
 
 /* A query result.  core and factor[0..p-1] are caller-owned DEVICE buffers of
@@ -185,6 +186,114 @@ tk_status tk_read_node(tk_tree* t, int32_t level, int64_t index, float* core,
 tk_status tk_restore_begin(tk_tree* t, int64_t T);
 tk_status tk_load_node(tk_tree* t, int32_t level, int64_t index, const float* core,
                        const float* const* factor);
+
+/* ---------------------------------------------------------------------------
+ * Launch tuning, prepared batches and the autotuner.
+ *
+ * Stitch jobs are grouped into LDS bins by the size of their largest
+ * eigenproblem.  Jobs up to wide_threshold run one wavefront per workgroup;
+ * larger ones run wide_threads threads.  With persistent = 1 a launch has at
+ * most as many workgroups as the device holds at once and each workgroup
+ * takes jobs from a queue, heaviest first.  A job's result depends on the
+ * tuning only through wide_threshold and wide_threads (reduction orders).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t wide_threshold; /* 16..1024, default 48                              */
+  int32_t wide_threads;   /* 128 or 256, default 256                           */
+  int32_t persistent;     /* 0 or 1, default 0                                 */
+  int32_t graph;          /* 1: prepared batches replay a captured HIP graph   */
+} tk_tuning;
+
+tk_status tk_get_tuning(const tk_tree* t, tk_tuning* out);
+tk_status tk_set_tuning(tk_tree* t, const tk_tuning* in);   /* TK_EINVAL if out of range */
+
+/* A prepared batch: n range queries planned once at the current committed
+ * horizon T_c (the snapshot), job descriptors resident on the device, and
+ * (tuning.graph = 1) the launches captured in a HIP graph: per LDS bin one
+ * fused stitch kernel that runs Recall (Alg. "recall") on each query's range
+ * and snapshot, the partial-hit trims (Eq. "partial-tucker") and the Stitch
+ * (Alg. "stitch").  res[0..n-1] are caller-owned and must stay valid until
+ * tk_batch_destroy; their core/factor buffers are device buffers sized by
+ * tk_query_shape.  Results equal those of tk_query_batch under the same
+ * tuning.  Later appends do not change what a batch computes (completed
+ * nodes are immutable). */
+typedef struct tk_batch tk_batch;
+tk_status tk_batch_create(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* te,
+                          tk_result* res, tk_batch** out);
+/* Enqueue one execution on the tree's stream and return (no host wait). */
+tk_status tk_batch_run(tk_batch* b);
+/* Wait for the last execution and fill res[i]'s scalar fields. */
+tk_status tk_batch_wait(tk_batch* b);
+/* Device time of the last execution (HIP events on the tree's stream). */
+tk_status tk_batch_kernel_ms(const tk_batch* b, double* ms);
+/* Per-query phase times of the last execution (as tk_last_query_profile). */
+tk_status tk_batch_profile(const tk_batch* b, int32_t i, double* phase_us);
+/* The hit set query i's kernel computed on the device (after a run). */
+tk_status tk_batch_hits(const tk_batch* b, int32_t i, tk_hit* out, int32_t cap, int32_t* n);
+void tk_batch_destroy(tk_batch* b);
+
+/* Time every candidate tuning (wide_threshold in {32, 48, 64, 96} x
+ * wide_threads in {128, 256} x persistent in {0, 1}) on a prepared batch of
+ * the given queries (reps timed executions after one warm-up, results into
+ * scratch buffers), keep the fastest on the tree and report it. */
+tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* te, int32_t reps,
+                      tk_tuning* best, double* best_ms);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of range queries interleaved with appends.
+ *
+ * After tk_serve_start, queries and appends are submitted from any thread
+ * and return a ticket at once; a scheduler thread owned by the tree issues
+ * them.  A query sees every append submitted before it (its snapshot T_c),
+ * even if that append is still being committed: its launch waits for the
+ * commit.  Queries are grouped in three size classes with their own streams;
+ * a class admits waiting queries into its next batch, in arrival order,
+ * while the batch has job slots (max_batch) and workspace bytes (an equal
+ * share of ws_budget_bytes) left.  Appends are committed in groups of up to
+ * max_commit_blocks leaf blocks on a stream of their own, concurrently with
+ * the query batches.  A query's result is bit-identical to tk_query on a tree
+ * holding the same slices (same tuning).  While serving, the synchronous
+ * calls that read or change the tree return TK_EBUSY.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t max_batch;          /* queries per batch per class; 0: 256          */
+  int32_t max_commit_blocks;  /* leaf blocks per append commit; 0: 64         */
+  int64_t ws_budget_bytes;    /* query workspace on the device; 0: 1 GiB      */
+  int64_t max_queue;          /* unfinished requests before TK_EBUSY; 0: 2^20 */
+} tk_serve_config;
+
+typedef struct {
+  int64_t queries, appends;   /* accepted submissions                          */
+  int64_t completed;          /* finished requests                             */
+  int64_t rejected;           /* refused (queue full or over the budget)       */
+  int64_t batches, commits;   /* query launches and append commits issued      */
+  int64_t max_batch_seen;     /* largest query batch launched                  */
+  int64_t outstanding;        /* submitted, not finished                       */
+  int64_t T_submitted;        /* slices submitted                              */
+  int64_t T_committed;        /* slices in committed blocks                    */
+} tk_serve_stats;
+
+tk_status tk_serve_start(tk_tree* t, const tk_serve_config* cfg);  /* cfg may be NULL */
+/* Finish every submitted request, stop the scheduler; synchronous calls work
+ * again afterwards (tickets are forgotten). */
+tk_status tk_serve_stop(tk_tree* t);
+/* res: caller-owned, valid until the ticket is done.  TK_ERANGE if
+ * [ts, te) is not inside the snapshot; TK_ENOMEM if the query alone exceeds
+ * its class's workspace budget; TK_EBUSY if max_queue requests are open. */
+tk_status tk_submit_query(tk_tree* t, int64_t ts, int64_t te, tk_result* res, uint64_t* ticket);
+/* A host slice is copied before return; a device slice must stay valid
+ * until its ticket is done. */
+tk_status tk_submit_append(tk_tree* t, const float* slice, int on_device, uint64_t* ticket);
+tk_status tk_poll(tk_tree* t, uint64_t ticket, int32_t* done);  /* TK_EDEVICE if it failed */
+tk_status tk_wait(tk_tree* t, uint64_t ticket);
+/* Wait until every submitted request is done (without a server: the
+ * tree's stream). */
+tk_status tk_sync(tk_tree* t);
+/* Host times of a request in microseconds since tk_serve_start: submitted,
+ * launched (staged, for an append) and done (-1 while pending). */
+tk_status tk_ticket_times(tk_tree* t, uint64_t ticket, double* submit_us, double* launch_us,
+                          double* done_us);
+tk_status tk_serve_stats_get(tk_tree* t, tk_serve_stats* out);
 
 /* Host-only planning helpers (no tree, no device): the pruned hit set of
  * [t_s, t_e) in a tree of committed horizon T built with cfg's leaf_len and

@@ -5,7 +5,9 @@ include/tucket.h."""
 
 from .tucket import (  # noqa: F401
     LIB_PATH,
+    PreparedBatch,
     QueryResult,
+    Server,
     Tree,
     TuckerError,
     effective_ranks,

@@ -1,0 +1,328 @@
+// Prepared query batches and the launch autotuner.
+//
+// A prepared batch plans a fixed list of range queries once (Recall for the
+// workspace sizes, LDS bins, heaviest-first order), uploads the job
+// descriptors, and captures its launches in a HIP graph: one fused stitch
+// kernel per LDS bin, each running Recall, the partial-hit trims and the
+// Stitch of its queries, the bins forked onto their own streams and joined.
+// tk_batch_run replays the graph on the tree's stream.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "tk_host.hpp"
+
+using namespace tk;
+
+struct tk_batch {
+  tk_tree* t = nullptr;
+  int32_t n = 0;
+  tk_result* res = nullptr;
+  std::vector<Job> qjobs;  // in the caller's order (ranks, hit counts)
+  Plan plan;
+  DevBuf hits, stats, queue, ws[kMaxGroups], jobs[kMaxGroups];
+  hipStream_t cap_stream = nullptr;
+  hipStream_t gstream[kMaxGroups] = {};
+  hipEvent_t gev[kMaxGroups] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool ran = false;
+  std::vector<double> hstats;
+};
+
+namespace {
+
+void batch_free(tk_batch* b) {
+  if (!b) return;
+  tk_tree* t = b->t;
+  if (t && t->stream) (void)hipStreamSynchronize(t->stream);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  release(&b->hits);
+  release(&b->stats);
+  release(&b->queue);
+  for (int g = 0; g < kMaxGroups; ++g) {
+    release(&b->ws[g]);
+    release(&b->jobs[g]);
+    if (b->gstream[g]) (void)hipStreamDestroy(b->gstream[g]);
+    if (b->gev[g]) (void)hipEventDestroy(b->gev[g]);
+  }
+  if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+  delete b;
+}
+
+// Enqueue the batch's kernels on `stream` (captured or direct): every group
+// on its own stream, forked from and joined back to `stream`.
+tk_status issue(tk_batch* b, hipStream_t stream) {
+  tk_tree* t = b->t;
+  StitchArgs base = stitch_args(t, t->q_max_iter, t->q_tol);
+  base.hits = reinterpret_cast<Hit*>(b->hits.p);
+  const bool fork = b->plan.groups.size() > 1;
+  if (fork) TK_HIP(t, hipEventRecord(b->fork_ev, stream));
+  for (const Group& gr : b->plan.groups) {
+    const int g = gr.bin;
+    hipStream_t s = fork ? b->gstream[g] : stream;
+    if (fork) TK_HIP(t, hipStreamWaitEvent(s, b->fork_ev, 0));
+    const size_t lds_bytes = size_t(eig_doubles(gr.n_lds)) * 8;
+    StitchArgs a = base;
+    a.jobs = reinterpret_cast<const Job*>(b->jobs[g].p);
+    a.ws = b->ws[g].p;
+    a.n_jobs = int(gr.jobs.size());
+    a.n_lds = gr.n_lds;
+    int grid = a.n_jobs;
+    a.queue = nullptr;
+    if (t->tuning.persistent) {
+      const int64_t resident = int64_t(stitch_blocks_per_cu(gr.threads, lds_bytes)) * t->n_cu;
+      if (resident < grid) grid = int(resident);
+      a.queue = reinterpret_cast<int*>(b->queue.p) + g;
+      TK_HIP(t, launch_reset_queue(a.queue, 1, s));
+    }
+    TK_HIP(t, launch_stitch(a, grid, lds_bytes, gr.threads, s));
+    if (fork) {
+      TK_HIP(t, hipEventRecord(b->gev[g], s));
+      TK_HIP(t, hipStreamWaitEvent(stream, b->gev[g], 0));
+    }
+  }
+  return TK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tk_status tk_batch_create(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* te, tk_result* res,
+                          tk_batch** out) {
+  if (!t || !out || n < 1 || !ts || !te || !res) return fail(t, TK_EINVAL, "bad argument");
+  *out = nullptr;
+  if (t->server) return fail(t, TK_EBUSY, "the tree is serving; stop the server first");
+  if (t->poisoned) return TK_EDEVICE;
+  tk_batch* b = new tk_batch();
+  b->t = t;
+  b->n = n;
+  b->res = res;
+  std::vector<Hit> hits;
+  for (int32_t i = 0; i < n; ++i) {
+    tk_status st = make_query_job(t, ts[i], te[i], t->Tb, &res[i], true, b->qjobs, hits);
+    if (st) {
+      batch_free(b);
+      return st;
+    }
+  }
+  auto bail = [&](tk_status st) {
+    batch_free(b);
+    return st;
+  };
+  tk_status st = ensure(t, &b->stats, int64_t(n) * STAT_COUNT * 8, "stats");
+  if (st) return bail(st);
+  double* dstats = reinterpret_cast<double*>(b->stats.p);
+  std::vector<Job> jobs = b->qjobs;
+  for (int32_t i = 0; i < n; ++i) jobs[i].stats = dstats + STAT_COUNT * int64_t(i);
+  st = plan_stitch(t, jobs, hits, &b->plan);
+  if (st) return bail(st);
+  // the kernels run Recall themselves and write the hits; the slots start zeroed
+  st = ensure(t, &b->hits, int64_t(hits.size() * sizeof(Hit)) + 64, "hits");
+  if (st) return bail(st);
+  TK_HIP(t, hipMemset(b->hits.p, 0, size_t(b->hits.cap)));
+  st = ensure(t, &b->queue, kMaxGroups * 64, "queue");
+  if (st) return bail(st);
+  TK_HIP(t, hipMemset(b->queue.p, 0, size_t(b->queue.cap)));
+  TK_HIP(t, hipMemset(b->stats.p, 0, size_t(b->stats.cap)));
+  for (const Group& gr : b->plan.groups) {
+    if (int64_t(gr.jobs.size()) > (int64_t(1) << 24)) return bail(fail(t, TK_EINVAL, "batch too large"));
+    st = ensure(t, &b->ws[gr.bin], gr.ws_total + 256, "batch workspace");
+    if (st) return bail(st);
+    st = ensure(t, &b->jobs[gr.bin], int64_t(gr.jobs.size() * sizeof(Job)), "batch jobs");
+    if (st) return bail(st);
+    TK_HIP(t, hipMemcpy(b->jobs[gr.bin].p, gr.jobs.data(), gr.jobs.size() * sizeof(Job), hipMemcpyHostToDevice));
+    if (!b->gstream[gr.bin]) {
+      TK_HIP(t, hipStreamCreateWithFlags(&b->gstream[gr.bin], hipStreamNonBlocking));
+      TK_HIP(t, hipEventCreateWithFlags(&b->gev[gr.bin], hipEventDisableTiming));
+    }
+  }
+  TK_HIP(t, hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
+  TK_HIP(t, hipEventCreate(&b->ev0));
+  TK_HIP(t, hipEventCreate(&b->ev1));
+  if (t->tuning.graph) {
+    TK_HIP(t, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    TK_HIP(t, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    st = issue(b, b->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    if (st) {
+      if (g) (void)hipGraphDestroy(g);
+      return bail(st);
+    }
+    if (e != hipSuccess) return bail(fail_dev(t, e, "hipStreamEndCapture"));
+    b->graph = g;
+    TK_HIP(t, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  *out = b;
+  return TK_OK;
+}
+
+tk_status tk_batch_run(tk_batch* b) {
+  if (!b) return TK_EINVAL;
+  tk_tree* t = b->t;
+  if (t->server) return fail(t, TK_EBUSY, "the tree is serving; stop the server first");
+  if (t->poisoned) return TK_EDEVICE;
+  TK_HIP(t, hipEventRecord(b->ev0, t->stream));
+  if (b->exec) {
+    TK_HIP(t, hipGraphLaunch(b->exec, t->stream));
+  } else {
+    tk_status st = issue(b, t->stream);
+    if (st) return st;
+  }
+  TK_HIP(t, hipEventRecord(b->ev1, t->stream));
+  b->ran = true;
+  return TK_OK;
+}
+
+tk_status tk_batch_wait(tk_batch* b) {
+  if (!b) return TK_EINVAL;
+  tk_tree* t = b->t;
+  if (!b->ran) return fail(t, TK_EINVAL, "batch has not run");
+  TK_HIP(t, hipEventSynchronize(b->ev1));
+  b->hstats.assign(size_t(b->n) * STAT_COUNT, 0.0);
+  TK_HIP(t, hipMemcpy(b->hstats.data(), b->stats.p, b->hstats.size() * 8, hipMemcpyDeviceToHost));
+  for (int32_t i = 0; i < b->n; ++i) {
+    const double* s = b->hstats.data() + STAT_COUNT * size_t(i);
+    if (s[STAT_STATUS] != 0.0)
+      return fail(t, TK_EDEVICE, "stitch kernel: device Recall or workspace disagrees with the host plan");
+    tk_result& r = b->res[i];
+    for (int m = 0; m < TK_MAX_MODES; ++m) r.ranks_eff[m] = m < t->p ? b->qjobs[i].rq[m] : 0;
+    r.fit = s[STAT_FIT];
+    r.err_model = s[STAT_ERR];
+    r.norm_ytilde = s[STAT_NORM];
+    r.sweeps = int32_t(s[STAT_SWEEPS]);
+    r.converged = int32_t(s[STAT_CONV]);
+    r.n_hits = b->qjobs[i].s;
+  }
+  return TK_OK;
+}
+
+tk_status tk_batch_kernel_ms(const tk_batch* b, double* ms) {
+  if (!b || !ms || !b->ran) return TK_EINVAL;
+  float f = 0.f;
+  if (hipEventSynchronize(b->ev1) != hipSuccess) return TK_EDEVICE;
+  if (hipEventElapsedTime(&f, b->ev0, b->ev1) != hipSuccess) return TK_EDEVICE;
+  *ms = double(f);
+  return TK_OK;
+}
+
+tk_status tk_batch_profile(const tk_batch* b, int32_t i, double* phase_us) {
+  if (!b || !phase_us || i < 0 || i >= b->n) return TK_EINVAL;
+  if (b->hstats.size() != size_t(b->n) * STAT_COUNT) return TK_EINVAL;
+  for (int k = 0; k < STAT_NPHASE + 4; ++k) phase_us[k] = b->hstats[size_t(i) * STAT_COUNT + STAT_PHASE + k];
+  return TK_OK;
+}
+
+tk_status tk_batch_hits(const tk_batch* b, int32_t i, tk_hit* out, int32_t cap, int32_t* n) {
+  if (!b || !n || i < 0 || i >= b->n || (cap > 0 && !out)) return TK_EINVAL;
+  tk_tree* t = b->t;
+  const Job& jb = b->qjobs[i];
+  std::vector<Hit> h(static_cast<size_t>(jb.s));
+  if (hipMemcpy(h.data(), b->hits.p + size_t(jb.hit0) * sizeof(Hit), h.size() * sizeof(Hit),
+                hipMemcpyDeviceToHost) != hipSuccess)
+    return TK_EDEVICE;
+  *n = jb.s;
+  for (int k = 0; k < jb.s && k < cap; ++k) {
+    const int64_t sig = (h[k].index << h[k].level) * t->ell;
+    out[k].level = h[k].level;
+    out[k].index = h[k].index;
+    out[k].partial = h[k].partial;
+    out[k].node_id = node_id(h[k].level, h[k].index);
+    out[k].sigma = sig;
+    out[k].tau = sig + (t->ell << h[k].level);
+    out[k].lo = sig + h[k].a;
+    out[k].hi = sig + h[k].a + h[k].l;
+  }
+  return TK_OK;
+}
+
+void tk_batch_destroy(tk_batch* b) { batch_free(b); }
+
+tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* te, int32_t reps, tk_tuning* best,
+                      double* best_ms) {
+  if (!t || n < 1 || !ts || !te || reps < 1) return fail(t, TK_EINVAL, "bad argument");
+  if (t->server) return fail(t, TK_EBUSY, "the tree is serving; stop the server first");
+  if (t->poisoned) return TK_EDEVICE;
+  // scratch outputs for the sample
+  int64_t total = 0;
+  std::vector<int64_t> off(static_cast<size_t>(n) * (t->p + 1));
+  for (int32_t i = 0; i < n; ++i) {
+    if (!(ts[i] >= 0 && ts[i] < te[i] && te[i] <= t->Tb * t->ell)) return fail(t, TK_ERANGE, "query range");
+    int32_t r[MAXP];
+    effective_ranks(t->p, te[i] - ts[i], t->view.D, t->cfg.ranks, r);
+    int64_t ce = 1;
+    for (int m = 0; m < t->p; ++m) ce *= r[m];
+    off[size_t(i) * (t->p + 1)] = total;
+    total += ce;
+    off[size_t(i) * (t->p + 1) + 1] = total;
+    total += (te[i] - ts[i]) * r[0];
+    for (int m = 1; m < t->p; ++m) {
+      off[size_t(i) * (t->p + 1) + 1 + m] = total;
+      total += t->view.D[m] * r[m];
+    }
+  }
+  DevBuf outbuf;
+  tk_status st = ensure(t, &outbuf, total * 4 + 256, "autotune outputs");
+  if (st) return st;
+  float* base = reinterpret_cast<float*>(outbuf.p);
+  std::vector<tk_result> res(static_cast<size_t>(n));
+  for (int32_t i = 0; i < n; ++i) {
+    std::memset(&res[i], 0, sizeof(tk_result));
+    res[i].core = base + off[size_t(i) * (t->p + 1)];
+    for (int m = 0; m < t->p; ++m) res[i].factor[m] = base + off[size_t(i) * (t->p + 1) + 1 + m];
+  }
+  const Tuning saved = t->tuning;
+  Tuning bestt = saved;
+  double bms = 1e300;
+  const int thr[] = {32, 48, 64, 96};
+  const int wth[] = {128, 256};
+  for (int th : thr)
+    for (int wt : wth)
+      for (int pers = 0; pers < 2; ++pers) {
+        t->tuning = saved;
+        t->tuning.wide_threshold = th;
+        t->tuning.wide_threads = wt;
+        t->tuning.persistent = pers;
+        tk_batch* b = nullptr;
+        st = tk_batch_create(t, n, ts, te, res.data(), &b);
+        double sum = 0.0;
+        for (int r = 0; r <= reps && st == TK_OK; ++r) {
+          st = tk_batch_run(b);
+          if (st == TK_OK) st = tk_batch_wait(b);
+          double ms = 0.0;
+          if (st == TK_OK) st = tk_batch_kernel_ms(b, &ms);
+          if (r > 0) sum += ms;  // the first run warms up
+        }
+        tk_batch_destroy(b);
+        if (st) {
+          t->tuning = saved;
+          release(&outbuf);
+          return st;
+        }
+        const double ms = sum / reps;
+        if (ms < bms) {
+          bms = ms;
+          bestt = t->tuning;
+        }
+      }
+  t->tuning = bestt;
+  release(&outbuf);
+  if (best) {
+    best->wide_threshold = bestt.wide_threshold;
+    best->wide_threads = bestt.wide_threads;
+    best->persistent = bestt.persistent;
+    best->graph = bestt.graph;
+  }
+  if (best_ms) *best_ms = bms;
+  return TK_OK;
+}
+
+}  // extern "C"

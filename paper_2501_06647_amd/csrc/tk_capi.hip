@@ -8,8 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "tk_internal.hpp"
-#include "tucket.h"
+#include "tk_host.hpp"
 
 using tk::Hit;
 using tk::Job;
@@ -17,64 +16,10 @@ using tk::LeafJob;
 using tk::StoreView;
 
 namespace {
-
 thread_local std::string g_create_error;
-
-constexpr int kMaxRank = 32;
-constexpr int64_t kMaxJobsPerLaunch = 1 << 16;
-constexpr int64_t kWsChunkBytes = int64_t(4) << 30;  // workspace per launch chunk
-constexpr size_t kLdsBytes = 160 * 1024;              // LDS per CU on gfx950
-
 }  // namespace
 
-struct tk_tree {
-  tk_config cfg{};
-  hipStream_t stream = nullptr;
-  int p = 0;
-  int64_t ell = 1;
-  int64_t cap_blocks = 0;
-  int nlev = 0;
-  StoreView view{};
-  StoreView* dview = nullptr;
-  char* store = nullptr;
-  int64_t store_bytes = 0;
-  float* block_buf = nullptr;
-  int64_t slice_elems = 0;
-  int64_t T = 0;
-  int64_t Tb = 0;
-  int64_t merges_total = 0;
-  int64_t merges_last = 0;
-  char* ws = nullptr;
-  int64_t ws_cap = 0;
-  char* djobs = nullptr;
-  int64_t djobs_cap = 0;
-  // per-bin launch resources: bins of a query batch run concurrently on
-  // their own streams, joined back to the tree's stream with events
-  static constexpr int kBins = 6;
-  char* bws[kBins] = {nullptr};
-  int64_t bws_cap[kBins] = {0};
-  char* bjobs[kBins] = {nullptr};
-  int64_t bjobs_cap[kBins] = {0};
-  hipStream_t bstream[kBins] = {nullptr};
-  hipEvent_t bev[kBins] = {nullptr};
-  hipEvent_t fork_ev = nullptr;
-  char* dhits = nullptr;
-  int64_t dhits_cap = 0;
-  double* dstats = nullptr;
-  int64_t dstats_cap = 0;
-  float* xbuf = nullptr;
-  int64_t xbuf_cap = 0;
-  int q_max_iter = 20;
-  double q_tol = 0.01;
-  int64_t lds_limit = 65536;  // dynamic LDS a workgroup may request
-  bool poisoned = false;
-  std::string err;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the last query launches
-  std::vector<double> last_stats;           // per-job stats of the last query batch
-  bool ev_valid = false;
-};
-
-namespace {
+namespace tk {
 
 tk_status fail(tk_tree* t, tk_status st, const std::string& msg) {
   if (t) t->err = msg;
@@ -93,39 +38,54 @@ tk_status fail_dev(tk_tree* t, hipError_t e, const char* what) {
   return TK_EDEVICE;
 }
 
-#define TK_HIP(t, call)                                 \
-  do {                                                  \
-    hipError_t e_ = (call);                             \
-    if (e_ != hipSuccess) return fail_dev(t, e_, #call); \
-  } while (0)
-
-tk_status ensure(tk_tree* t, char** buf, int64_t* cap, int64_t need, const char* what) {
-  if (need <= *cap) return TK_OK;
-  if (*buf) {
+tk_status ensure(tk_tree* t, DevBuf* b, int64_t need, const char* what) {
+  if (need <= b->cap) return TK_OK;
+  if (b->p) {
     TK_HIP(t, hipDeviceSynchronize());  // the buffer may be in use on any of the tree's streams
-    TK_HIP(t, hipFree(*buf));
-    *buf = nullptr;
-    *cap = 0;
+    TK_HIP(t, hipFree(b->p));
+    b->p = nullptr;
+    b->cap = 0;
   }
   const int64_t sz = need + need / 4 + 4096;
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, size_t(sz));
   if (e != hipSuccess) return fail_dev(t, e, what);
-  *buf = static_cast<char*>(p);
-  *cap = sz;
+  b->p = static_cast<char*>(p);
+  b->cap = sz;
   return TK_OK;
 }
 
-int nu2_trailing_ones(int64_t b) {
-  int n = 0;
-  while (b & 1) {
-    ++n;
-    b >>= 1;
-  }
-  return n;
+void release(DevBuf* b) {
+  if (b->p) (void)hipFree(b->p);
+  b->p = nullptr;
+  b->cap = 0;
 }
 
-int eig_need(const tk::StitchLayout& lo, const StoreView& st, int s) {
+void lane_destroy(Lane* l) {
+  if (l->stream) (void)hipStreamSynchronize(l->stream);
+  for (int g = 0; g < kMaxGroups; ++g)
+    if (l->gstream[g]) (void)hipStreamSynchronize(l->gstream[g]);
+  release(&l->hits);
+  release(&l->stats);
+  release(&l->queue);
+  release(&l->leaf_ws);
+  release(&l->leaf_jobs);
+  release(&l->xbuf);
+  for (int g = 0; g < kMaxGroups; ++g) {
+    release(&l->ws[g]);
+    release(&l->jobs[g]);
+    if (l->gstream[g]) (void)hipStreamDestroy(l->gstream[g]);
+    if (l->gev[g]) (void)hipEventDestroy(l->gev[g]);
+    l->gstream[g] = nullptr;
+    l->gev[g] = nullptr;
+  }
+  if (l->fork_ev) (void)hipEventDestroy(l->fork_ev);
+  l->fork_ev = nullptr;
+  if (l->own_stream && l->stream) (void)hipStreamDestroy(l->stream);
+  l->stream = nullptr;
+}
+
+int eig_need(const StitchLayout& lo, const StoreView& st) {
   int n = lo.sk;
   for (int m = 1; m < st.p; ++m) {
     const int e = lo.sr[m] < st.D[m] ? lo.sr[m] : int(st.D[m]);
@@ -134,166 +94,64 @@ int eig_need(const tk::StitchLayout& lo, const StoreView& st, int s) {
   return n;
 }
 
-// Launch one bin of stitch jobs (all sharing n_lds) on stream `stream`,
-// with workspace and job array `ws` / `djobs`; heaviest jobs first.  The
-// hit array is already on the device.  Large bins are split into chunks
-// bounded by workspace size (chunks of one bin run in order on its stream).
-tk_status launch_bin(tk_tree* t, std::vector<Job>& jobs, const std::vector<Hit>& hits, int n_lds, int max_iter,
-                     double tol, hipStream_t stream, char** ws, int64_t* ws_cap, char** djobs, int64_t* djobs_cap) {
-  const int64_t nj = int64_t(jobs.size());
-  if (nj == 0) return TK_OK;
-  std::stable_sort(jobs.begin(), jobs.end(), [](const Job& a, const Job& b) {
-    return a.s * a.L > b.s * b.L;  // longer ranges with more hits take longer
-  });
-  const size_t lds_bytes = size_t(tk::eig_doubles(n_lds)) * 8;
-  std::vector<int64_t> off(static_cast<size_t>(nj) + 1, 0);
-  for (int64_t i = 0; i < nj; ++i) {
-    tk::StitchLayout lo;
-    tk::stitch_layout(t->view, hits.data() + jobs[i].hit0, jobs[i].s, jobs[i].rq, n_lds, &lo);
-    off[i + 1] = off[i] + lo.total;
-  }
-  int64_t i0 = 0;
-  while (i0 < nj) {
-    int64_t i1 = i0 + 1;
-    while (i1 < nj && i1 - i0 < kMaxJobsPerLaunch && off[i1 + 1] - off[i0] <= kWsChunkBytes) ++i1;
-    if (i0 > 0) TK_HIP(t, hipStreamSynchronize(stream));  // the buffers are reused by this chunk
-    tk_status st = ensure(t, ws, ws_cap, off[i1] - off[i0] + 256, "workspace");
-    if (st) return st;
-    for (int64_t i = i0; i < i1; ++i) jobs[i].ws_off = off[i] - off[i0];
-    st = ensure(t, djobs, djobs_cap, (i1 - i0) * int64_t(sizeof(Job)), "jobs");
-    if (st) return st;
-    TK_HIP(t, hipMemcpyAsync(*djobs, jobs.data() + i0, size_t(i1 - i0) * sizeof(Job), hipMemcpyHostToDevice,
-                             stream));
-    tk::StitchArgs a;
-    a.st = t->dview;
-    a.jobs = reinterpret_cast<const Job*>(*djobs);
-    a.hits = reinterpret_cast<const Hit*>(t->dhits);
-    a.ws = *ws;
-    a.n_lds = n_lds;
-    a.max_iter = max_iter;
-    a.tol = tol;
-    a.merge_max_iter = t->cfg.max_iter;
-    a.merge_tol = t->cfg.tol;
-    TK_HIP(t, tk::launch_stitch(a, int(i1 - i0), lds_bytes, n_lds > 48, stream));
-    i0 = i1;
-  }
-  return TK_OK;
-}
-
-// Launch stitch jobs (queries or merges).  Jobs are binned by the size of
-// their largest eigenproblem so that each launch sizes its LDS (and its
-// wavefronts per job) for its own jobs: small problems keep many jobs per
-// CU, large ones still run their eigensolves in LDS.  Bins run concurrently
-// on their own streams and are joined back to the tree's stream, so a batch
-// completes in about the time of its slowest bin.
-tk_status run_stitch(tk_tree* t, std::vector<Job>& jobs, const std::vector<Hit>& hits, int max_iter,
-                     double tol) {
-  const int64_t nj = int64_t(jobs.size());
-  if (nj == 0) return TK_OK;
-  int lds_cap = 128;
-  while (lds_cap > 8 && int64_t(tk::eig_doubles(lds_cap)) * 8 > t->lds_limit - int64_t(tk::stitch_static_lds()))
-    lds_cap -= 8;
-  int bins[tk_tree::kBins - 1] = {24, 32, 48, 64, 96};
-  for (int& b : bins) b = b < lds_cap ? b : lds_cap;
-  std::vector<std::vector<Job>> binned(tk_tree::kBins);
-  for (int64_t i = 0; i < nj; ++i) {
-    tk::StitchLayout lo;
-    tk::stitch_layout(t->view, hits.data() + jobs[i].hit0, jobs[i].s, jobs[i].rq, 1 << 30, &lo);
-    const int need = eig_need(lo, t->view, jobs[i].s);
-    if (need > tk::EIG_MAXK_HOST) return fail(t, TK_EINVAL, "query needs an eigenproblem above 1024");
-    int b = tk_tree::kBins - 1;
-    for (int k = 0; k < tk_tree::kBins - 1; ++k)
-      if (need <= bins[k]) {
-        b = k;
-        break;
-      }
-    binned[size_t(b)].push_back(jobs[i]);
-  }
-  tk_status st = ensure(t, &t->dhits, &t->dhits_cap, int64_t(hits.size() * sizeof(Hit)) + 64, "hits");
-  if (st) return st;
-  if (!hits.empty())
-    TK_HIP(t, hipMemcpyAsync(t->dhits, hits.data(), hits.size() * sizeof(Hit), hipMemcpyHostToDevice,
-                             t->stream));
-  int nonempty = 0;
-  for (auto& b : binned) nonempty += b.empty() ? 0 : 1;
-  if (nonempty <= 1) {
-    for (int b = 0; b < tk_tree::kBins; ++b)
-      if (!binned[size_t(b)].empty())
-        return launch_bin(t, binned[size_t(b)], hits, b < tk_tree::kBins - 1 ? bins[b] : lds_cap, max_iter, tol,
-                          t->stream, &t->ws, &t->ws_cap, &t->djobs, &t->djobs_cap);
-    return TK_OK;
-  }
-  if (!t->fork_ev) TK_HIP(t, hipEventCreateWithFlags(&t->fork_ev, hipEventDisableTiming));
-  TK_HIP(t, hipEventRecord(t->fork_ev, t->stream));
-  for (int b = 0; b < tk_tree::kBins; ++b) {
-    if (binned[size_t(b)].empty()) continue;
-    if (!t->bstream[b]) {
-      TK_HIP(t, hipStreamCreateWithFlags(&t->bstream[b], hipStreamNonBlocking));
-      TK_HIP(t, hipEventCreateWithFlags(&t->bev[b], hipEventDisableTiming));
-    }
-    TK_HIP(t, hipStreamWaitEvent(t->bstream[b], t->fork_ev, 0));
-    st = launch_bin(t, binned[size_t(b)], hits, b < tk_tree::kBins - 1 ? bins[b] : lds_cap, max_iter, tol,
-                    t->bstream[b], &t->bws[b], &t->bws_cap[b], &t->bjobs[b], &t->bjobs_cap[b]);
-    if (st) return st;
-    TK_HIP(t, hipEventRecord(t->bev[b], t->bstream[b]));
-    TK_HIP(t, hipStreamWaitEvent(t->stream, t->bev[b], 0));
-  }
-  return TK_OK;
-}
-
-tk_status run_leaves(tk_tree* t, int64_t first_block, int64_t nb, const float* X) {
-  if (nb <= 0) return TK_OK;
-  tk::LeafLayout lo;
-  tk::leaf_layout(t->view, 1 << 30, &lo);
+int lds_cap(const tk_tree* t) {
   int cap = 128;
-  while (cap > 8 && int64_t(tk::eig_doubles(cap)) * 8 > t->lds_limit - int64_t(tk::leaf_static_lds())) cap -= 8;
-  const int n_lds = lo.neig < cap ? lo.neig : cap;
-  tk::leaf_layout(t->view, n_lds, &lo);
-  const size_t lds_bytes = size_t(tk::eig_doubles(n_lds)) * 8;
-  const int64_t per = lo.total;
-  int64_t chunk = kWsChunkBytes / (per > 0 ? per : 1);
-  if (chunk < 1) chunk = 1;
-  if (chunk > kMaxJobsPerLaunch) chunk = kMaxJobsPerLaunch;
-  const int64_t block_elems = t->ell * t->slice_elems;
-  for (int64_t i0 = 0; i0 < nb; i0 += chunk) {
-    const int64_t n = (nb - i0) < chunk ? (nb - i0) : chunk;
-    tk_status st = ensure(t, &t->ws, &t->ws_cap, n * per + 256, "workspace");
-    if (st) return st;
-    std::vector<LeafJob> jobs(static_cast<size_t>(n));
-    for (int64_t i = 0; i < n; ++i) {
-      jobs[i].X = X + (i0 + i) * block_elems;
-      jobs[i].block = first_block + i0 + i;
-      jobs[i].stats = nullptr;
-      jobs[i].ws_off = i * per;
-    }
-    st = ensure(t, &t->djobs, &t->djobs_cap, n * int64_t(sizeof(LeafJob)), "jobs");
-    if (st) return st;
-    TK_HIP(t, hipMemcpyAsync(t->djobs, jobs.data(), size_t(n) * sizeof(LeafJob), hipMemcpyHostToDevice,
-                             t->stream));
-    tk::LeafArgs a;
-    a.st = t->dview;
-    a.jobs = reinterpret_cast<const LeafJob*>(t->djobs);
-    a.ws = t->ws;
-    a.n_lds = n_lds;
-    a.max_iter = t->cfg.max_iter;
-    a.tol = t->cfg.tol;
-    TK_HIP(t, tk::launch_leaf(a, int(n), lds_bytes, t->stream));
-    TK_HIP(t, hipStreamSynchronize(t->stream));  // jobs/ws are reused by the next chunk
+  while (cap > 8 && int64_t(eig_doubles(cap)) * 8 > t->lds_limit - int64_t(stitch_static_lds())) cap -= 8;
+  return cap;
+}
+
+StitchArgs stitch_args(tk_tree* t, int max_iter, double tol) {
+  StitchArgs a{};
+  a.st = t->dview;
+  a.max_iter = max_iter;
+  a.tol = tol;
+  a.merge_max_iter = t->cfg.max_iter;
+  a.merge_tol = t->cfg.tol;
+  a.theta_num = t->cfg.theta_num;
+  a.theta_den = t->cfg.theta_den;
+  return a;
+}
+
+tk_status make_query_job(tk_tree* t, int64_t ts, int64_t te, int64_t Tb, const tk_result* res, bool check_outputs,
+                         std::vector<Job>& jobs, std::vector<Hit>& hits) {
+  if (!(ts >= 0 && ts < te && te <= Tb * t->ell)) return fail(t, TK_ERANGE, "query range outside [0, T_c) or empty");
+  Hit buf[MAXHITS];
+  const int n = recall(ts, te, Tb, t->ell, t->cfg.theta_num, t->cfg.theta_den, buf, MAXHITS);
+  if (n < 1 || n > MAXHITS) return fail(t, TK_EINVAL, "hit set too large");
+  Job jb{};
+  jb.kind = 0;
+  jb.s = n;
+  jb.hit0 = int32_t(hits.size());
+  jb.L = te - ts;
+  jb.ts = ts;
+  jb.Tb = Tb;
+  effective_ranks(t->p, te - ts, t->view.D, t->cfg.ranks, jb.rq);
+  if (check_outputs) {
+    if (!res || !res->core) return fail(t, TK_EINVAL, "null core buffer");
+    for (int m = 0; m < t->p; ++m)
+      if (!res->factor[m]) return fail(t, TK_EINVAL, "null factor buffer");
   }
+  if (res) {
+    jb.out_core = res->core;
+    for (int m = 0; m < t->p; ++m) jb.out_fac[m] = res->factor[m];
+  }
+  for (int i = 0; i < n; ++i) hits.push_back(buf[i]);
+  jobs.push_back(jb);
   return TK_OK;
 }
 
-// Merge job for node (k, j): Stitch of its two children (Alg. "insert").
-void merge_job(tk_tree* t, int k, int64_t j, std::vector<Job>& jobs, std::vector<Hit>& hits) {
+void make_merge_job(tk_tree* t, int k, int64_t j, std::vector<Job>& jobs, std::vector<Hit>& hits) {
   const StoreView& v = t->view;
   Job jb{};
   jb.kind = 1;
   jb.s = 2;
   jb.hit0 = int32_t(hits.size());
   jb.L = t->ell << k;
+  jb.ts = (j << k) * t->ell;
+  jb.Tb = (j + 1) << k;
   for (int n = 0; n < t->p; ++n) jb.rq[n] = v.rk[k][n];
   jb.out_core = v.core[k] + j * v.core_elems[k];
-  for (int n = 1; n < t->p; ++n) jb.out_fac[n] = v.fac[k][n] + j * tk::fac_elems(v, k, n);
+  for (int n = 1; n < t->p; ++n) jb.out_fac[n] = v.fac[k][n] + j * fac_elems(v, k, n);
   jb.out_fac[0] = v.plane[k] + (j << k) * t->ell * v.rk[k][0];
   jb.stats = nullptr;
   const int64_t half = t->ell << (k - 1);
@@ -304,13 +162,203 @@ void merge_job(tk_tree* t, int k, int64_t j, std::vector<Job>& jobs, std::vector
   jobs.push_back(jb);
 }
 
-// Leaves for blocks [Tb, Tb + nb) from device data, then every merge they
-// complete, level by level.
-tk_status commit_blocks(tk_tree* t, int64_t nb, const float* Xdev) {
-  const int64_t b0 = t->Tb, b1 = t->Tb + nb;
-  tk_status st = run_leaves(t, b0, nb, Xdev);
+tk_status plan_stitch(tk_tree* t, std::vector<Job>& jobs, std::vector<Hit>& hits, Plan* plan) {
+  plan->groups.clear();
+  plan->n_jobs = int64_t(jobs.size());
+  const int cap = lds_cap(t);
+  const Tuning& tu = t->tuning;
+  // bin bounds: fixed sizes plus the wide threshold, capped by the LDS limit;
+  // the last bin takes everything above (eigenproblems beyond cap run in HBM)
+  std::vector<int> bounds = {24, 32, 48, 64, 96};
+  if (tu.wide_threshold < cap) bounds.push_back(tu.wide_threshold);
+  for (int& b : bounds) b = b < cap ? b : cap;
+  std::sort(bounds.begin(), bounds.end());
+  bounds.erase(std::unique(bounds.begin(), bounds.end()), bounds.end());
+  while (int(bounds.size()) > kMaxGroups - 1) bounds.erase(bounds.begin());
+  const int nb = int(bounds.size()) + 1;
+  std::vector<Group> g(static_cast<size_t>(nb));
+  for (int b = 0; b < nb; ++b) {
+    g[b].bin = b;
+    g[b].n_lds = b < nb - 1 ? bounds[b] : cap;
+    const int hi = b < nb - 1 ? bounds[b] : (1 << 30);
+    g[b].threads = hi <= tu.wide_threshold ? NT_STITCH : tu.wide_threads;
+  }
+  for (Job& jb : jobs) {
+    StitchLayout lo;
+    stitch_layout(t->view, hits.data() + jb.hit0, jb.s, jb.rq, 1 << 30, &lo);
+    const int need = eig_need(lo, t->view);
+    if (need > EIG_MAXK_HOST) return fail(t, TK_EINVAL, "query needs an eigenproblem above 1024");
+    int b = nb - 1;
+    for (int k = 0; k < nb - 1; ++k)
+      if (need <= bounds[k]) {
+        b = k;
+        break;
+      }
+    g[b].jobs.push_back(jb);
+  }
+  for (Group& gr : g) {
+    if (gr.jobs.empty()) continue;
+    std::stable_sort(gr.jobs.begin(), gr.jobs.end(), [](const Job& a, const Job& b) {
+      return a.s * a.L > b.s * b.L;  // longer ranges with more hits take longer
+    });
+    int64_t off = 0;
+    for (Job& jb : gr.jobs) {
+      StitchLayout lo;
+      stitch_layout(t->view, hits.data() + jb.hit0, jb.s, jb.rq, gr.n_lds, &lo);
+      jb.ws_off = off;
+      jb.ws_bytes = lo.total;
+      off += lo.total;
+    }
+    gr.ws_total = off;
+    plan->groups.push_back(std::move(gr));
+  }
+  plan->hits = hits;
+  return TK_OK;
+}
+
+namespace {
+
+// Launch one group (chunked by workspace size) on `stream`.
+tk_status launch_group(tk_tree* t, Lane* lane, Group& gr, const StitchArgs& base, hipStream_t stream) {
+  const int64_t nj = int64_t(gr.jobs.size());
+  if (nj == 0) return TK_OK;
+  const size_t lds_bytes = size_t(eig_doubles(gr.n_lds)) * 8;
+  const int per_cu = t->tuning.persistent ? stitch_blocks_per_cu(gr.threads, lds_bytes) : 0;
+  DevBuf* ws = &lane->ws[gr.bin];
+  DevBuf* djobs = &lane->jobs[gr.bin];
+  int64_t i0 = 0;
+  while (i0 < nj) {
+    const int64_t base_off = gr.jobs[size_t(i0)].ws_off;
+    int64_t i1 = i0 + 1;
+    while (i1 < nj && i1 - i0 < kMaxJobsPerLaunch &&
+           gr.jobs[size_t(i1)].ws_off + gr.jobs[size_t(i1)].ws_bytes - base_off <= kWsChunkBytes)
+      ++i1;
+    if (i0 > 0) TK_HIP(t, hipStreamSynchronize(stream));  // the buffers are reused by this chunk
+    const int64_t bytes = gr.jobs[size_t(i1 - 1)].ws_off + gr.jobs[size_t(i1 - 1)].ws_bytes - base_off;
+    tk_status st = ensure(t, ws, bytes + 256, "workspace");
+    if (st) return st;
+    std::vector<Job> chunk(gr.jobs.begin() + i0, gr.jobs.begin() + i1);
+    for (Job& jb : chunk) jb.ws_off -= base_off;
+    st = ensure(t, djobs, int64_t(chunk.size() * sizeof(Job)), "jobs");
+    if (st) return st;
+    TK_HIP(t, hipMemcpyAsync(djobs->p, chunk.data(), chunk.size() * sizeof(Job), hipMemcpyHostToDevice, stream));
+    StitchArgs a = base;
+    a.jobs = reinterpret_cast<const Job*>(djobs->p);
+    a.ws = ws->p;
+    a.n_jobs = int(i1 - i0);
+    a.n_lds = gr.n_lds;
+    int grid = a.n_jobs;
+    if (per_cu > 0) {
+      const int64_t res = int64_t(per_cu) * t->n_cu;
+      if (res < grid) grid = int(res);
+      a.queue = reinterpret_cast<int*>(lane->queue.p) + gr.bin;
+      TK_HIP(t, launch_reset_queue(a.queue, 1, stream));
+    } else {
+      a.queue = nullptr;
+    }
+    TK_HIP(t, launch_stitch(a, grid, lds_bytes, gr.threads, stream));
+    i0 = i1;
+  }
+  return TK_OK;
+}
+
+}  // namespace
+
+tk_status run_plan(tk_tree* t, Lane* lane, Plan& plan, int max_iter, double tol, bool fork) {
+  if (plan.n_jobs == 0) return TK_OK;
+  tk_status st = ensure(t, &lane->hits, int64_t(plan.hits.size() * sizeof(Hit)) + 64, "hits");
   if (st) return st;
-  const int K = tk::root_level(b1);
+  st = ensure(t, &lane->queue, kMaxGroups * 64, "queue");
+  if (st) return st;
+  if (!plan.hits.empty())
+    TK_HIP(t, hipMemcpyAsync(lane->hits.p, plan.hits.data(), plan.hits.size() * sizeof(Hit), hipMemcpyHostToDevice,
+                             lane->stream));
+  StitchArgs base = stitch_args(t, max_iter, tol);
+  base.hits = reinterpret_cast<Hit*>(lane->hits.p);
+  if (!fork || plan.groups.size() <= 1) {
+    for (Group& gr : plan.groups) {
+      st = launch_group(t, lane, gr, base, lane->stream);
+      if (st) return st;
+    }
+    return TK_OK;
+  }
+  if (!lane->fork_ev) TK_HIP(t, hipEventCreateWithFlags(&lane->fork_ev, hipEventDisableTiming));
+  TK_HIP(t, hipEventRecord(lane->fork_ev, lane->stream));
+  for (Group& gr : plan.groups) {
+    const int b = gr.bin;
+    if (!lane->gstream[b]) {
+      TK_HIP(t, hipStreamCreateWithFlags(&lane->gstream[b], hipStreamNonBlocking));
+      TK_HIP(t, hipEventCreateWithFlags(&lane->gev[b], hipEventDisableTiming));
+    }
+    TK_HIP(t, hipStreamWaitEvent(lane->gstream[b], lane->fork_ev, 0));
+    st = launch_group(t, lane, gr, base, lane->gstream[b]);
+    if (st) return st;
+    TK_HIP(t, hipEventRecord(lane->gev[b], lane->gstream[b]));
+    TK_HIP(t, hipStreamWaitEvent(lane->stream, lane->gev[b], 0));
+  }
+  return TK_OK;
+}
+
+namespace {
+
+int nu2_trailing_ones(int64_t b) {
+  int n = 0;
+  while (b & 1) {
+    ++n;
+    b >>= 1;
+  }
+  return n;
+}
+
+tk_status run_leaves(tk_tree* t, Lane* lane, int64_t first_block, int64_t nb, const float* X) {
+  if (nb <= 0) return TK_OK;
+  LeafLayout lo;
+  leaf_layout(t->view, 1 << 30, &lo);
+  int cap = 128;
+  while (cap > 8 && int64_t(eig_doubles(cap)) * 8 > t->lds_limit - int64_t(leaf_static_lds())) cap -= 8;
+  const int n_lds = lo.neig < cap ? lo.neig : cap;
+  leaf_layout(t->view, n_lds, &lo);
+  const size_t lds_bytes = size_t(eig_doubles(n_lds)) * 8;
+  const int64_t per = lo.total;
+  int64_t chunk = kWsChunkBytes / (per > 0 ? per : 1);
+  if (chunk < 1) chunk = 1;
+  if (chunk > kMaxJobsPerLaunch) chunk = kMaxJobsPerLaunch;
+  const int64_t block_elems = t->ell * t->slice_elems;
+  for (int64_t i0 = 0; i0 < nb; i0 += chunk) {
+    const int64_t n = (nb - i0) < chunk ? (nb - i0) : chunk;
+    if (i0 > 0) TK_HIP(t, hipStreamSynchronize(lane->stream));  // jobs/ws are reused by this chunk
+    tk_status st = ensure(t, &lane->leaf_ws, n * per + 256, "workspace");
+    if (st) return st;
+    std::vector<LeafJob> jobs(static_cast<size_t>(n));
+    for (int64_t i = 0; i < n; ++i) {
+      jobs[i].X = X + (i0 + i) * block_elems;
+      jobs[i].block = first_block + i0 + i;
+      jobs[i].stats = nullptr;
+      jobs[i].ws_off = i * per;
+    }
+    st = ensure(t, &lane->leaf_jobs, n * int64_t(sizeof(LeafJob)), "jobs");
+    if (st) return st;
+    TK_HIP(t, hipMemcpyAsync(lane->leaf_jobs.p, jobs.data(), size_t(n) * sizeof(LeafJob), hipMemcpyHostToDevice,
+                             lane->stream));
+    LeafArgs a;
+    a.st = t->dview;
+    a.jobs = reinterpret_cast<const LeafJob*>(lane->leaf_jobs.p);
+    a.ws = lane->leaf_ws.p;
+    a.n_lds = n_lds;
+    a.max_iter = t->cfg.max_iter;
+    a.tol = t->cfg.tol;
+    TK_HIP(t, launch_leaf(a, int(n), lds_bytes, lane->stream));
+  }
+  return TK_OK;
+}
+
+}  // namespace
+
+tk_status commit_blocks(tk_tree* t, Lane* lane, int64_t nb, const float* Xdev) {
+  const int64_t b0 = t->Tb, b1 = t->Tb + nb;
+  tk_status st = run_leaves(t, lane, b0, nb, Xdev);
+  if (st) return st;
+  const int K = root_level(b1);
   int64_t merges = 0;
   for (int k = 1; k <= K; ++k) {
     // nodes (k, j) with (j+1) 2^k in (b0, b1]
@@ -319,9 +367,13 @@ tk_status commit_blocks(tk_tree* t, int64_t nb, const float* Xdev) {
     if (jhi < jlo) continue;
     std::vector<Job> jobs;
     std::vector<Hit> hits;
-    for (int64_t j = jlo; j <= jhi; ++j) merge_job(t, k, j, jobs, hits);
+    for (int64_t j = jlo; j <= jhi; ++j) make_merge_job(t, k, j, jobs, hits);
     merges += int64_t(jobs.size());
-    st = run_stitch(t, jobs, hits, t->cfg.max_iter, t->cfg.tol);
+    Plan plan;
+    st = plan_stitch(t, jobs, hits, &plan);
+    if (st) return st;
+    // one level's merges share a shape; groups run in order on the lane
+    st = run_plan(t, lane, plan, t->cfg.max_iter, t->cfg.tol, false);
     if (st) return st;
   }
   t->Tb = b1;
@@ -330,31 +382,17 @@ tk_status commit_blocks(tk_tree* t, int64_t nb, const float* Xdev) {
   return TK_OK;
 }
 
+}  // namespace tk
+
+using namespace tk;
+
+namespace {
+
 bool range_ok(const tk_tree* t, int64_t ts, int64_t te) {
   return ts >= 0 && ts < te && te <= t->Tb * t->ell;
 }
 
-tk_status build_query_job(tk_tree* t, int64_t ts, int64_t te, const tk_result* res, std::vector<Job>& jobs,
-                          std::vector<Hit>& hits) {
-  if (!range_ok(t, ts, te)) return fail(t, TK_ERANGE, "query range outside [0, T_c) or empty");
-  Hit buf[tk::MAXHITS];
-  const int n = tk::recall(ts, te, t->Tb, t->ell, t->cfg.theta_num, t->cfg.theta_den, buf, tk::MAXHITS);
-  if (n < 1 || n > tk::MAXHITS) return fail(t, TK_EINVAL, "hit set too large");
-  Job jb{};
-  jb.kind = 0;
-  jb.s = n;
-  jb.hit0 = int32_t(hits.size());
-  jb.L = te - ts;
-  tk::effective_ranks(t->p, te - ts, t->view.D, t->cfg.ranks, jb.rq);
-  if (!res->core) return fail(t, TK_EINVAL, "null core buffer");
-  for (int m = 0; m < t->p; ++m)
-    if (!res->factor[m]) return fail(t, TK_EINVAL, "null factor buffer");
-  jb.out_core = res->core;
-  for (int m = 0; m < t->p; ++m) jb.out_fac[m] = res->factor[m];
-  for (int i = 0; i < n; ++i) hits.push_back(buf[i]);
-  jobs.push_back(jb);
-  return TK_OK;
-}
+tk_status busy(tk_tree* t) { return fail(t, TK_EBUSY, "the tree is serving; stop the server first"); }
 
 }  // namespace
 
@@ -390,6 +428,7 @@ tk_status tk_create(const tk_config* cfg, void* hip_stream, tk_tree** out) {
   tk_tree* t = new tk_tree();
   t->cfg = *cfg;
   t->stream = static_cast<hipStream_t>(hip_stream);
+  t->main.stream = t->stream;
   t->p = p;
   t->ell = cfg->leaf_len;
   t->slice_elems = slice;
@@ -431,6 +470,12 @@ tk_status tk_create(const tk_config* cfg, void* hip_stream, tk_tree** out) {
   if (e != hipSuccess) {
     delete t;
     return fail_dev(nullptr, e, "hipGetDevice");
+  }
+  t->device = dev;
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+      t->n_cu = ncu;
   }
   void* ptr = nullptr;
   e = hipMalloc(&ptr, size_t(t->store_bytes));
@@ -497,22 +542,12 @@ tk_status tk_create(const tk_config* cfg, void* hip_stream, tk_tree** out) {
 
 void tk_destroy(tk_tree* t) {
   if (!t) return;
+  tk_serve_stop(t);
   (void)hipStreamSynchronize(t->stream);
-  char* bufs[] = {t->store, t->ws, t->djobs, t->dhits};
-  for (char* b : bufs)
-    if (b) (void)hipFree(b);
+  lane_destroy(&t->main);
+  if (t->store) (void)hipFree(t->store);
   if (t->dview) (void)hipFree(t->dview);
   if (t->block_buf) (void)hipFree(t->block_buf);
-  if (t->dstats) (void)hipFree(t->dstats);
-  if (t->xbuf) (void)hipFree(t->xbuf);
-  for (int b = 0; b < tk_tree::kBins; ++b) {
-    if (t->bstream[b]) (void)hipStreamSynchronize(t->bstream[b]);
-    if (t->bws[b]) (void)hipFree(t->bws[b]);
-    if (t->bjobs[b]) (void)hipFree(t->bjobs[b]);
-    if (t->bstream[b]) (void)hipStreamDestroy(t->bstream[b]);
-    if (t->bev[b]) (void)hipEventDestroy(t->bev[b]);
-  }
-  if (t->fork_ev) (void)hipEventDestroy(t->fork_ev);
   if (t->ev0) (void)hipEventDestroy(t->ev0);
   if (t->ev1) (void)hipEventDestroy(t->ev1);
   delete t;
@@ -520,6 +555,7 @@ void tk_destroy(tk_tree* t) {
 
 tk_status tk_append(tk_tree* t, const float* slice, int on_device) {
   if (!t || !slice) return fail(t, TK_EINVAL, "null argument");
+  if (t->server) return busy(t);
   if (t->poisoned) return TK_EDEVICE;
   if (t->T >= t->cap_blocks * t->ell) return fail(t, TK_ENOMEM, "capacity_T reached");
   const int64_t row = t->T % t->ell;
@@ -527,7 +563,7 @@ tk_status tk_append(tk_tree* t, const float* slice, int on_device) {
                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, t->stream));
   t->T += 1;
   if (t->T % t->ell == 0) {
-    tk_status st = commit_blocks(t, 1, t->block_buf);
+    tk_status st = commit_blocks(t, &t->main, 1, t->block_buf);
     if (st) return st;
     TK_HIP(t, hipStreamSynchronize(t->stream));
   }
@@ -536,6 +572,7 @@ tk_status tk_append(tk_tree* t, const float* slice, int on_device) {
 
 tk_status tk_build(tk_tree* t, const float* X, int64_t T, int on_device) {
   if (!t || (!X && T > 0) || T < 0) return fail(t, TK_EINVAL, "bad argument");
+  if (t->server) return busy(t);
   if (t->poisoned) return TK_EDEVICE;
   if (t->T + T > t->cap_blocks * t->ell) return fail(t, TK_ENOMEM, "capacity_T exceeded");
   int64_t done = 0;
@@ -545,12 +582,12 @@ tk_status tk_build(tk_tree* t, const float* X, int64_t T, int on_device) {
     if (nb > 0) {
       const float* Xd = X;
       if (!on_device) {
-        tk_status st = ensure(t, reinterpret_cast<char**>(&t->xbuf), &t->xbuf_cap, nb * block_elems * 4, "staging");
+        tk_status st = ensure(t, &t->main.xbuf, nb * block_elems * 4, "staging");
         if (st) return st;
-        TK_HIP(t, hipMemcpyAsync(t->xbuf, X, size_t(nb * block_elems) * 4, hipMemcpyHostToDevice, t->stream));
-        Xd = t->xbuf;
+        TK_HIP(t, hipMemcpyAsync(t->main.xbuf.p, X, size_t(nb * block_elems) * 4, hipMemcpyHostToDevice, t->stream));
+        Xd = reinterpret_cast<const float*>(t->main.xbuf.p);
       }
-      tk_status st = commit_blocks(t, nb, Xd);
+      tk_status st = commit_blocks(t, &t->main, nb, Xd);
       if (st) return st;
       t->T += nb * t->ell;
       done = nb * t->ell;
@@ -566,6 +603,7 @@ tk_status tk_build(tk_tree* t, const float* X, int64_t T, int on_device) {
 
 tk_status tk_hitset(const tk_tree* t, int64_t ts, int64_t te, tk_hit* out, int32_t cap, int32_t* n) {
   if (!t || !n || (cap > 0 && !out)) return TK_EINVAL;
+  if (t->server) return TK_EBUSY;
   if (!range_ok(t, ts, te)) return TK_ERANGE;
   Hit buf[tk::MAXHITS];
   const int m = tk::recall(ts, te, t->Tb, t->ell, t->cfg.theta_num, t->cfg.theta_den, buf, tk::MAXHITS);
@@ -586,6 +624,7 @@ tk_status tk_hitset(const tk_tree* t, int64_t ts, int64_t te, tk_hit* out, int32
 
 tk_status tk_query_shape(const tk_tree* t, int64_t ts, int64_t te, tk_shape* out) {
   if (!t || !out) return TK_EINVAL;
+  if (t->server) return TK_EBUSY;
   if (!range_ok(t, ts, te)) return TK_ERANGE;
   std::memset(out, 0, sizeof(*out));
   tk::effective_ranks(t->p, te - ts, t->view.D, t->cfg.ranks, out->ranks_eff);
@@ -596,46 +635,55 @@ tk_status tk_query_shape(const tk_tree* t, int64_t ts, int64_t te, tk_shape* out
   for (int n = 1; n < t->p; ++n) out->factor_elems[n] = t->view.D[n] * out->ranks_eff[n];
   Hit buf[tk::MAXHITS];
   out->n_hits = tk::recall(ts, te, t->Tb, t->ell, t->cfg.theta_num, t->cfg.theta_den, buf, tk::MAXHITS);
+  tk::StitchLayout lo;
+  tk::stitch_layout(t->view, buf, out->n_hits, out->ranks_eff, 0, &lo);
+  out->ws_bytes = lo.total;
   return TK_OK;
 }
 
 tk_status tk_query_batch(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* te, tk_result* res) {
   if (!t || n < 0 || (n > 0 && (!ts || !te || !res))) return fail(t, TK_EINVAL, "bad argument");
+  if (t->server) return busy(t);
   if (t->poisoned) return TK_EDEVICE;
   std::vector<Job> jobs;
   std::vector<Hit> hits;
   jobs.reserve(size_t(n));
   for (int32_t i = 0; i < n; ++i) {
-    tk_status st = build_query_job(t, ts[i], te[i], &res[i], jobs, hits);
+    tk_status st = make_query_job(t, ts[i], te[i], t->Tb, &res[i], true, jobs, hits);
     if (st) return st;
   }
   if (n == 0) return TK_OK;
-  tk_status st = ensure(t, reinterpret_cast<char**>(&t->dstats), &t->dstats_cap,
-                        int64_t(n) * tk::STAT_COUNT * 8, "stats");
+  tk_status st = ensure(t, &t->main.stats, int64_t(n) * STAT_COUNT * 8, "stats");
   if (st) return st;
-  for (int32_t i = 0; i < n; ++i) jobs[i].stats = t->dstats + tk::STAT_COUNT * int64_t(i);
+  double* dstats = reinterpret_cast<double*>(t->main.stats.p);
+  for (int32_t i = 0; i < n; ++i) jobs[i].stats = dstats + STAT_COUNT * int64_t(i);
+  Plan plan;
+  st = plan_stitch(t, jobs, hits, &plan);
+  if (st) return st;
   if (!t->ev0) {
     TK_HIP(t, hipEventCreate(&t->ev0));
     TK_HIP(t, hipEventCreate(&t->ev1));
   }
   t->ev_valid = false;
   TK_HIP(t, hipEventRecord(t->ev0, t->stream));
-  st = run_stitch(t, jobs, hits, t->q_max_iter, t->q_tol);
+  st = run_plan(t, &t->main, plan, t->q_max_iter, t->q_tol, true);
   if (st) return st;
   TK_HIP(t, hipEventRecord(t->ev1, t->stream));
   t->ev_valid = true;
   std::vector<double>& hs = t->last_stats;
-  hs.assign(size_t(n) * tk::STAT_COUNT, 0.0);
-  TK_HIP(t, hipMemcpyAsync(hs.data(), t->dstats, hs.size() * 8, hipMemcpyDeviceToHost, t->stream));
+  hs.assign(size_t(n) * STAT_COUNT, 0.0);
+  TK_HIP(t, hipMemcpyAsync(hs.data(), dstats, hs.size() * 8, hipMemcpyDeviceToHost, t->stream));
   TK_HIP(t, hipStreamSynchronize(t->stream));
   for (int32_t i = 0; i < n; ++i) {
-    const double* s = hs.data() + tk::STAT_COUNT * size_t(i);
-    for (int m = 0; m < tk::MAXP; ++m) res[i].ranks_eff[m] = m < t->p ? jobs[i].rq[m] : 0;
-    res[i].fit = s[tk::STAT_FIT];
-    res[i].err_model = s[tk::STAT_ERR];
-    res[i].norm_ytilde = s[tk::STAT_NORM];
-    res[i].sweeps = int32_t(s[tk::STAT_SWEEPS]);
-    res[i].converged = int32_t(s[tk::STAT_CONV]);
+    const double* s = hs.data() + STAT_COUNT * size_t(i);
+    if (s[STAT_STATUS] != 0.0)
+      return fail(t, TK_EDEVICE, "stitch kernel: device Recall or workspace disagrees with the host plan");
+    for (int m = 0; m < TK_MAX_MODES; ++m) res[i].ranks_eff[m] = m < t->p ? jobs[i].rq[m] : 0;
+    res[i].fit = s[STAT_FIT];
+    res[i].err_model = s[STAT_ERR];
+    res[i].norm_ytilde = s[STAT_NORM];
+    res[i].sweeps = int32_t(s[STAT_SWEEPS]);
+    res[i].converged = int32_t(s[STAT_CONV]);
     res[i].n_hits = jobs[i].s;
   }
   return TK_OK;
@@ -666,8 +714,33 @@ tk_status tk_last_query_profile(const tk_tree* t, int32_t i, double* phase_us) {
 
 tk_status tk_set_query_iters(tk_tree* t, int32_t max_iter, double tol) {
   if (!t || max_iter < 1 || !(tol >= 0.0)) return TK_EINVAL;
+  if (t->server) return busy(t);
   t->q_max_iter = max_iter;
   t->q_tol = tol;
+  return TK_OK;
+}
+
+tk_status tk_get_tuning(const tk_tree* t, tk_tuning* out) {
+  if (!t || !out) return TK_EINVAL;
+  out->wide_threshold = t->tuning.wide_threshold;
+  out->wide_threads = t->tuning.wide_threads;
+  out->persistent = t->tuning.persistent;
+  out->graph = t->tuning.graph;
+  return TK_OK;
+}
+
+tk_status tk_set_tuning(tk_tree* t, const tk_tuning* in) {
+  if (!t || !in) return TK_EINVAL;
+  if (t->server) return busy(t);
+  if (in->wide_threshold < 16 || in->wide_threshold > EIG_MAXK_HOST)
+    return fail(t, TK_EINVAL, "wide_threshold must be in [16, 1024]");
+  if (in->wide_threads != 128 && in->wide_threads != 256) return fail(t, TK_EINVAL, "wide_threads must be 128 or 256");
+  if (in->persistent != 0 && in->persistent != 1) return fail(t, TK_EINVAL, "persistent must be 0 or 1");
+  if (in->graph != 0 && in->graph != 1) return fail(t, TK_EINVAL, "graph must be 0 or 1");
+  t->tuning.wide_threshold = in->wide_threshold;
+  t->tuning.wide_threads = in->wide_threads;
+  t->tuning.persistent = in->persistent;
+  t->tuning.graph = in->graph;
   return TK_OK;
 }
 
@@ -696,6 +769,7 @@ tk_status tk_node_ranks(const tk_tree* t, int32_t level, int32_t* ranks_eff) {
 
 tk_status tk_read_node(tk_tree* t, int32_t level, int64_t index, float* core, float* const* factor) {
   if (!t || !core || !factor || level < 0 || level >= t->nlev || index < 0) return TK_EINVAL;
+  if (t->server) return busy(t);
   if (t->poisoned) return TK_EDEVICE;
   if (!tk::node_complete(level, index, t->Tb)) return fail(t, TK_ERANGE, "node not complete");
   for (int n = 0; n < t->p; ++n)
@@ -715,6 +789,7 @@ tk_status tk_read_node(tk_tree* t, int32_t level, int64_t index, float* core, fl
 
 tk_status tk_restore_begin(tk_tree* t, int64_t T) {
   if (!t || T < 0 || T > t->cap_blocks * t->ell) return TK_EINVAL;
+  if (t->server) return busy(t);
   if (t->poisoned) return TK_EDEVICE;
   t->T = T;
   t->Tb = T / t->ell;
@@ -726,6 +801,7 @@ tk_status tk_restore_begin(tk_tree* t, int64_t T) {
 tk_status tk_load_node(tk_tree* t, int32_t level, int64_t index, const float* core,
                        const float* const* factor) {
   if (!t || !core || !factor || level < 0 || level >= t->nlev || index < 0) return TK_EINVAL;
+  if (t->server) return busy(t);
   if (t->poisoned) return TK_EDEVICE;
   if (!tk::node_complete(level, index, t->Tb)) return fail(t, TK_ERANGE, "node not complete");
   for (int n = 0; n < t->p; ++n)

@@ -178,12 +178,18 @@ struct StoreView {
 TK_HD int64_t fac_elems(const StoreView& st, int k, int n) { return st.D[n] * st.rk[k][n]; }
 
 // A stitch job: a range query or the merge of two children (Alg. "insert").
+// A query job carries its range and the committed block count it was
+// admitted at; the kernel runs Recall on them itself, and the host's plan of
+// the same hit set only sizes the workspace (ws_bytes).
 struct Job {
   int32_t kind;  // 0 query, 1 merge
   int32_t s;     // hits
   int32_t hit0;  // first hit in the launch's hit array
   int32_t pad0;
   int64_t L;
+  int64_t ts;        // query range [ts, ts + L)
+  int64_t Tb;        // committed leaf blocks seen by the query
+  int64_t ws_bytes;  // workspace planned for the job
   int32_t rq[MAXP];          // output effective ranks
   float* out_core;           // prod(rq) floats
   float* out_fac[MAXP];      // [0]: L x rq[0] rows; [n]: D_n x rq[n]
@@ -199,12 +205,14 @@ struct LeafJob {
   int64_t ws_off;
 };
 
-// Per-job statistics; STAT_PHASE.. hold device time per phase in microseconds
+// Per-job statistics; STAT_STATUS is 0, or 1 when the kernel's Recall did
+// not reproduce the planned hit set, 2 when the workspace plan was too small
+// (the job then did nothing); STAT_PHASE.. hold device time per phase in microseconds
 // (trims, bases, init, temporal TTM+Gram, temporal eigen, other TTM+Gram,
 // other eigens, finalize); STAT_EIG.. hold eigensolver calls, Jacobi sweeps,
 // and microseconds in the rotation loop and in the extraction.
 enum {
-  STAT_FIT = 0, STAT_ERR = 1, STAT_NORM = 2, STAT_SWEEPS = 3, STAT_CONV = 4, STAT_HITS = 5,
+  STAT_FIT = 0, STAT_ERR = 1, STAT_NORM = 2, STAT_SWEEPS = 3, STAT_CONV = 4, STAT_HITS = 5, STAT_STATUS = 6,
   STAT_PHASE = 8, STAT_NPHASE = 8, STAT_EIG = 16, STAT_COUNT = 20
 };
 
@@ -243,6 +251,17 @@ struct StitchLayout {
 };
 
 TK_HD int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+// gram_rows (a trim's Gram over many rows) splits the rows among at most
+// GRAM_ROWS_TILES partial 4 x 4 tiles of 16 doubles, whatever the workgroup
+// size; the layout reserves that much scratch (in D1).  ntiles <= 36 for
+// ranks <= 32, so ntiles * split <= GRAM_ROWS_TILES.
+constexpr int GRAM_ROWS_TILES = 64;
+TK_HD int gram_rows_split(int ntiles, int nthreads) {
+  const int cap = nthreads < GRAM_ROWS_TILES ? nthreads : GRAM_ROWS_TILES;
+  const int s = cap / ntiles;
+  return s > 0 ? s : 1;
+}
 
 // Doubles needed by the eigensolver for an n x n problem: the matrix, then
 // column norms, Gram-Schmidt coefficients and eigenvalues.
@@ -322,8 +341,8 @@ TK_HD void stitch_layout(const StoreView& st, const Hit* hits, int s, const int3
     if (int64_t(Lo->qmax[n]) * rmax > tq) tq = int64_t(Lo->qmax[n]) * rmax;
   }
   if (tq > Lo->tmax) Lo->tmax = tq;
-  // partial Gram tiles of a trim (gram_rows): at most 64 x 16 doubles
-  if (Lo->tmax < 64 * 16) Lo->tmax = 64 * 16;
+  // partial Gram tiles of a trim (gram_rows): at most GRAM_ROWS_TILES x 16 doubles
+  if (Lo->tmax < GRAM_ROWS_TILES * 16) Lo->tmax = GRAM_ROWS_TILES * 16;
   Lo->T1 = take(Lo->tmax * 4);
   Lo->T2 = take(Lo->tmax * 4);
   Lo->D1 = take(Lo->tmax * 8);

@@ -200,12 +200,13 @@ __device__ __forceinline__ void gram_mode(const float* __restrict__ X, int64_t a
 // Gram of the rows of a tall, narrow matrix: G = V^T V for V (l x k,
 // row-major), FP64 accumulation, k <= 32.  Threads split the rows; each owns
 // a 4 x 4 tile of G for its share of rows, and the partial tiles are summed
-// through part (ntiles x nsplit x 16 doubles of scratch).
+// through part (ntiles x nsplit x 16 doubles, at most GRAM_ROWS_TILES x 16,
+// for any workgroup size).
 __device__ __forceinline__ void gram_rows(const float* __restrict__ V, int64_t l, int k, double* __restrict__ G,
                                           int ld, double* __restrict__ part) {
   const int nb = (k + 3) / 4;
   const int ntiles = nb * (nb + 1) / 2;
-  const int nsplit = int(blockDim.x) / ntiles > 0 ? int(blockDim.x) / ntiles : 1;
+  const int nsplit = gram_rows_split(ntiles, int(blockDim.x));
   for (int w = threadIdx.x; w < ntiles * nsplit; w += blockDim.x) {
     const int t = w % ntiles, sp = w / ntiles;
     int bi = 0, rem = t;

@@ -1,0 +1,144 @@
+// Host-side state of a tree and the planning/launch helpers shared by the
+// synchronous calls (tk_capi.hip), prepared batches (tk_batch.hip) and the
+// serving engine (tk_serve.hip).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "tk_internal.hpp"
+#include "tucket.h"
+
+namespace tk {
+
+constexpr int kMaxRank = 32;
+constexpr int kMaxGroups = 7;                          // LDS bins of a stitch launch
+constexpr int64_t kMaxJobsPerLaunch = 1 << 16;
+constexpr int64_t kWsChunkBytes = int64_t(4) << 30;    // workspace per launch chunk
+constexpr size_t kLdsBytes = 160 * 1024;               // LDS per CU on gfx950
+
+struct DevBuf {
+  char* p = nullptr;
+  int64_t cap = 0;
+};
+
+// Launch tuning of the stitch kernel (tk_tuning).
+struct Tuning {
+  int wide_threshold = 48;  // jobs whose largest eigenproblem exceeds this use wide workgroups
+  int wide_threads = 256;
+  int persistent = 0;       // grid sized to residency; workgroups pull jobs from a queue
+  int graph = 1;            // prepared batches replay a captured HIP graph
+};
+
+// Stitch jobs that run in one launch: same dynamic LDS (n_lds) and block size.
+struct Group {
+  int bin = 0;     // index of the LDS bin (stable across calls: selects buffers)
+  int n_lds = 0;
+  int threads = 64;
+  std::vector<Job> jobs;
+  int64_t ws_total = 0;
+};
+
+// A stitch batch split into groups, each sorted heaviest first, with
+// workspace offsets relative to the group's buffer.
+struct Plan {
+  std::vector<Hit> hits;
+  std::vector<Group> groups;
+  int64_t n_jobs = 0;
+};
+
+// A stream with the device buffers of the stitch work issued on it.  Groups
+// of one batch run on the lane's group streams when forked, else one after
+// the other on the lane's stream.
+struct Lane {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  DevBuf hits, stats, queue;
+  DevBuf ws[kMaxGroups], jobs[kMaxGroups];
+  DevBuf leaf_ws, leaf_jobs, xbuf;
+  hipStream_t gstream[kMaxGroups] = {};
+  hipEvent_t gev[kMaxGroups] = {};
+  hipEvent_t fork_ev = nullptr;
+};
+
+struct Server;  // tk_serve.hip
+
+}  // namespace tk
+
+struct tk_tree {
+  tk_config cfg{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int n_cu = 256;
+  int p = 0;
+  int64_t ell = 1;
+  int64_t cap_blocks = 0;
+  int nlev = 0;
+  tk::StoreView view{};
+  tk::StoreView* dview = nullptr;
+  char* store = nullptr;
+  int64_t store_bytes = 0;
+  float* block_buf = nullptr;
+  int64_t slice_elems = 0;
+  int64_t T = 0;
+  int64_t Tb = 0;
+  int64_t merges_total = 0;
+  int64_t merges_last = 0;
+  tk::Lane main;  // the tree's stream: synchronous calls
+  int q_max_iter = 20;
+  double q_tol = 0.01;
+  int64_t lds_limit = 65536;  // dynamic + static LDS a workgroup may use
+  tk::Tuning tuning;
+  bool poisoned = false;
+  std::string err;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the last query launches
+  std::vector<double> last_stats;           // per-job stats of the last query batch
+  bool ev_valid = false;
+  tk::Server* server = nullptr;             // non-null while serving
+};
+
+namespace tk {
+
+tk_status fail(tk_tree* t, tk_status st, const std::string& msg);
+tk_status fail_dev(tk_tree* t, hipError_t e, const char* what);
+
+#define TK_HIP(t, call)                                         \
+  do {                                                          \
+    hipError_t e_ = (call);                                     \
+    if (e_ != hipSuccess) return ::tk::fail_dev(t, e_, #call); \
+  } while (0)
+
+// Grow b to at least need bytes (waits for the device before freeing).
+tk_status ensure(tk_tree* t, DevBuf* b, int64_t need, const char* what);
+void release(DevBuf* b);
+void lane_destroy(Lane* l);
+
+// Largest eigenproblem of a stitch job (its LDS bin).
+int eig_need(const StitchLayout& lo, const StoreView& st);
+
+// Recall plus effective ranks of a query at snapshot Tb: one job (hits
+// appended to `hits`).  Output buffers from res (may be null when
+// check_outputs is false).
+tk_status make_query_job(tk_tree* t, int64_t ts, int64_t te, int64_t Tb, const tk_result* res, bool check_outputs,
+                         std::vector<Job>& jobs, std::vector<Hit>& hits);
+// Merge job for node (k, j): Stitch of its two children (Alg. "insert").
+void make_merge_job(tk_tree* t, int k, int64_t j, std::vector<Job>& jobs, std::vector<Hit>& hits);
+
+// Group jobs by LDS bin under the tree's tuning, sort each group heaviest
+// first and lay out its workspace.
+tk_status plan_stitch(tk_tree* t, std::vector<Job>& jobs, std::vector<Hit>& hits, Plan* plan);
+
+// Issue a plan on a lane: hits and jobs uploaded, groups launched (forked
+// onto group streams when fork is set and there are several groups), the
+// lane's stream joined.  Groups too large for one launch are chunked, with a
+// host wait between chunks.
+tk_status run_plan(tk_tree* t, Lane* lane, Plan& plan, int max_iter, double tol, bool fork);
+
+// Leaves for blocks [Tb, Tb + nb) from device data, then every merge they
+// complete, level by level, on the lane.  Updates Tb and the merge counts.
+tk_status commit_blocks(tk_tree* t, Lane* lane, int64_t nb, const float* Xdev);
+
+StitchArgs stitch_args(tk_tree* t, int max_iter, double tol);
+int lds_cap(const tk_tree* t);
+
+}  // namespace tk

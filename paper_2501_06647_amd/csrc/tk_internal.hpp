@@ -5,20 +5,22 @@
 
 namespace tk {
 
-constexpr int NT_STITCH = 64;        // one wavefront per stitch job
-constexpr int NT_STITCH_WIDE = 256;  // four wavefronts for jobs with large eigenproblems
-constexpr int NT_LEAF = 256;    // four wavefronts per leaf job
+constexpr int NT_STITCH = 64;  // one wavefront per stitch job
+constexpr int NT_LEAF = 256;   // four wavefronts per leaf job
 
 struct StitchArgs {
   const StoreView* st;
   const Job* jobs;
-  const Hit* hits;
+  Hit* hits;           // merge jobs: read; query jobs: written by the kernel's own Recall
   char* ws;
+  int n_jobs;
+  int* queue;          // non-null: persistent launch, workgroups take jobs from this counter
   int n_lds;           // eigenproblems up to n_lds x n_lds run in LDS
   int max_iter;        // query jobs
   double tol;
   int merge_max_iter;  // merge jobs (node construction)
   double merge_tol;
+  int64_t theta_num, theta_den;
 };
 
 struct LeafArgs {
@@ -30,9 +32,16 @@ struct LeafArgs {
   double tol;
 };
 
-hipError_t launch_stitch(const StitchArgs& a, int n_jobs, size_t lds_bytes, bool wide, hipStream_t stream);
+// threads: 64 (one wavefront per job), 128 or 256 (jobs with large
+// eigenproblems).  grid <= n_jobs; with a.queue set the grid may be smaller
+// than n_jobs and the queue counter must read 0 at launch (reset_queue).
+hipError_t launch_stitch(const StitchArgs& a, int grid, size_t lds_bytes, int threads, hipStream_t stream);
+hipError_t launch_reset_queue(int* queue, int n, hipStream_t stream);
 hipError_t launch_leaf(const LeafArgs& a, int n_jobs, size_t lds_bytes, hipStream_t stream);
 hipError_t set_lds_limits(size_t stitch_bytes, size_t leaf_bytes);
+// workgroups of the stitch kernel with `threads` threads and lds_bytes of
+// dynamic LDS that one CU holds at once
+int stitch_blocks_per_cu(int threads, size_t lds_bytes);
 size_t stitch_static_lds();
 size_t leaf_static_lds();
 

@@ -94,6 +94,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
       job.stats[STAT_SWEEPS] = 0.0;
       job.stats[STAT_CONV] = 1.0;
       job.stats[STAT_HITS] = 1.0;
+      job.stats[STAT_STATUS] = 0.0;
     }
     return;
   }
@@ -107,6 +108,10 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
   __threadfence_block();
   __syncthreads();
   const StitchLayout& lo = *lop;
+  if (lo.total > job.ws_bytes) {
+    if (tid == 0 && job.stats) job.stats[STAT_STATUS] = 2.0;
+    return;
+  }
   double* red = sh.red;
   auto Fp = [&](int64_t off) { return reinterpret_cast<float*>(ws + off); };
   auto Dp = [&](int64_t off) { return reinterpret_cast<double*>(ws + off); };
@@ -516,6 +521,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     g2 = block_sum(part, red);
   }
   if (tid == 0 && job.stats) {
+    job.stats[STAT_STATUS] = 0.0;
     job.stats[STAT_FIT] = fit;
     job.stats[STAT_ERR] = ny2 > 0.0 ? sqrt(fmax(0.0, ny2 - g2)) / sqrt(ny2) : 0.0;
     job.stats[STAT_NORM] = sqrt(ny2);
@@ -533,17 +539,60 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
   }
 }
 
-// One wavefront per job for jobs whose eigenproblems are small; four
+// One wavefront per job for jobs whose eigenproblems are small; two or four
 // wavefronts for jobs with large ones (more lanes per rotation pair and per
 // contraction shorten their latency, which bounds a batch's completion).
+// A query job first runs Recall (Alg. "recall") on its own range and
+// snapshot, into LDS, and publishes the hits to its slots of args.hits.
+// With args.queue set the launch is persistent: each workgroup takes jobs
+// from the queue counter (heaviest first, as the host sorted them) until it
+// runs past n_jobs, so every workgroup reaches the exit.
 template <int NTT>
 __global__ __launch_bounds__(NTT) void stitch_kernel(StitchArgs args) {
   extern __shared__ double lds[];
   __shared__ StitchShared sh;
-  const Job& job = args.jobs[blockIdx.x];
-  stitch_one(*args.st, job, args.hits + job.hit0, args.ws + job.ws_off, args.n_lds,
-             job.kind == 1 ? args.merge_max_iter : args.max_iter, job.kind == 1 ? args.merge_tol : args.tol, sh,
-             lds);
+  __shared__ Hit qh[MAXHITS];
+  __shared__ int next_job;
+  __shared__ int n_rec;
+  const StoreView& st = *args.st;
+  int jn = blockIdx.x;
+  for (;;) {
+    if (args.queue) {
+      if (threadIdx.x == 0) next_job = atomicAdd(args.queue, 1);
+      __syncthreads();
+      jn = next_job;
+      __syncthreads();
+    }
+    if (jn >= args.n_jobs) break;
+    const Job& job = args.jobs[jn];
+    const Hit* hits = args.hits + job.hit0;
+    if (job.kind == 0) {
+      if (threadIdx.x == 0) {
+        const int n = recall(job.ts, job.ts + job.L, job.Tb, st.ell, args.theta_num, args.theta_den, qh, MAXHITS);
+        n_rec = n;
+        if (n == job.s)
+          for (int i = 0; i < n; ++i) args.hits[job.hit0 + i] = qh[i];
+      }
+      __syncthreads();
+      if (n_rec != job.s) {
+        if (threadIdx.x == 0 && job.stats) {
+          job.stats[STAT_STATUS] = 1.0;
+          job.stats[STAT_HITS] = double(n_rec);
+        }
+        if (!args.queue) break;
+        continue;
+      }
+      hits = qh;
+    }
+    stitch_one(st, job, hits, args.ws + job.ws_off, args.n_lds,
+               job.kind == 1 ? args.merge_max_iter : args.max_iter, job.kind == 1 ? args.merge_tol : args.tol, sh,
+               lds);
+    if (!args.queue) break;
+  }
+}
+
+__global__ void reset_queue_kernel(int* queue, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) queue[i] = 0;
 }
 
 // ------------------------------------------------------------------------------
@@ -702,12 +751,28 @@ __global__ __launch_bounds__(NT_LEAF) void leaf_kernel(LeafArgs args) {
 // ------------------------------------------------------------------------------
 // Launchers
 // ------------------------------------------------------------------------------
-hipError_t launch_stitch(const StitchArgs& a, int n_jobs, size_t lds_bytes, bool wide, hipStream_t stream) {
-  if (n_jobs <= 0) return hipSuccess;
-  if (wide)
-    hipLaunchKernelGGL(stitch_kernel<NT_STITCH_WIDE>, dim3(n_jobs), dim3(NT_STITCH_WIDE), lds_bytes, stream, a);
-  else
-    hipLaunchKernelGGL(stitch_kernel<NT_STITCH>, dim3(n_jobs), dim3(NT_STITCH), lds_bytes, stream, a);
+hipError_t launch_stitch(const StitchArgs& a, int grid, size_t lds_bytes, int threads, hipStream_t stream) {
+  if (grid <= 0 || a.n_jobs <= 0) return hipSuccess;
+  if (grid > a.n_jobs || (!a.queue && grid != a.n_jobs)) return hipErrorInvalidValue;
+  switch (threads) {
+    case 64:
+      hipLaunchKernelGGL(stitch_kernel<64>, dim3(grid), dim3(64), lds_bytes, stream, a);
+      break;
+    case 128:
+      hipLaunchKernelGGL(stitch_kernel<128>, dim3(grid), dim3(128), lds_bytes, stream, a);
+      break;
+    case 256:
+      hipLaunchKernelGGL(stitch_kernel<256>, dim3(grid), dim3(256), lds_bytes, stream, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_queue(int* queue, int n, hipStream_t stream) {
+  if (!queue || n <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, stream, queue, n);
   return hipGetLastError();
 }
 
@@ -718,17 +783,31 @@ hipError_t launch_leaf(const LeafArgs& a, int n_jobs, size_t lds_bytes, hipStrea
 }
 
 hipError_t set_lds_limits(size_t stitch_bytes, size_t leaf_bytes) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(stitch_kernel<NT_STITCH>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(stitch_bytes));
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(stitch_kernel<NT_STITCH_WIDE>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, int(stitch_bytes));
-  if (e != hipSuccess) return e;
+  const void* fns[] = {reinterpret_cast<const void*>(stitch_kernel<64>),
+                       reinterpret_cast<const void*>(stitch_kernel<128>),
+                       reinterpret_cast<const void*>(stitch_kernel<256>)};
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(stitch_bytes));
+    if (e != hipSuccess) return e;
+  }
   return hipFuncSetAttribute(reinterpret_cast<const void*>(leaf_kernel),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(leaf_bytes));
 }
 
-size_t stitch_static_lds() { return sizeof(StitchShared) + 64; }
+int stitch_blocks_per_cu(int threads, size_t lds_bytes) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (threads == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stitch_kernel<64>, 64, lds_bytes);
+  if (threads == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stitch_kernel<128>, 128, lds_bytes);
+  if (threads == 256) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stitch_kernel<256>, 256, lds_bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return n > 0 ? n : 1;
+}
+
+size_t stitch_static_lds() { return sizeof(StitchShared) + sizeof(Hit) * MAXHITS + 64; }
 size_t leaf_static_lds() { return sizeof(LeafShared) + 64; }
 
 }  // namespace tk

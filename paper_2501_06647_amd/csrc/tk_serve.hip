@@ -1,0 +1,575 @@
+// Serving engine: continuous batching of range queries interleaved with
+// stream appends, on one device.
+//
+// Callers submit queries and appends from any thread and get tickets; a
+// scheduler thread owned by the tree admits work and issues it:
+//   * appends are staged in submission order and committed (leaf Tucker of
+//     each completed block, then its merges, level by level) on the append
+//     lane's stream, as many blocks per commit as have arrived;
+//   * a query sees the tree as of its submission (read-your-writes: the
+//     committed horizon T_c of every append submitted before it).  Completed
+//     nodes never change (Alg. "insert" only fills placeholders), so a query
+//     reads a consistent snapshot while later appends add nodes; its launch
+//     waits on the append commits it depends on;
+//   * queries are grouped into three size classes by their largest
+//     eigenproblem, each with its own stream and workspace budget.  A class
+//     launches a batch whenever its previous batch has completed and queries
+//     are waiting: it admits them in arrival order while the batch has job
+//     slots and workspace bytes left (queries that arrive while a batch runs
+//     are admitted into the next one), and batches of different classes and
+//     the append commits run on the device at the same time.
+// A query's result depends only on its range and snapshot: the kernel
+// variant is a function of the query's own eigenproblem size, so a query
+// returns the same bits alone and in any mix.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "tk_host.hpp"
+
+namespace tk {
+
+namespace {
+
+constexpr int kClasses = 3;
+
+double now_us(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+}
+
+enum { REQ_QUEUED = 0, REQ_RUNNING = 1, REQ_DONE = 2, REQ_FAILED = 3 };
+
+struct Request {
+  uint64_t ticket = 0;
+  int kind = 0;  // 0 query, 1 append
+  int cls = 0;
+  int64_t ts = 0, te = 0, Tb = 0;
+  tk_result* res = nullptr;
+  Job job{};
+  std::vector<Hit> hits;
+  std::vector<float> data;          // host append: a copy of the slice
+  const float* dev_slice = nullptr;  // device append
+  double t_submit = 0, t_launch = 0, t_done = 0;
+  int state = REQ_QUEUED;
+};
+
+struct ClassLane {
+  Lane lane;
+  int n_lds = 0;
+  int threads = 64;
+  int64_t ws_budget = 0;
+  std::deque<Request*> pending;
+  std::vector<Request*> inflight;
+  hipEvent_t done_ev = nullptr;
+  double* hstats = nullptr;  // pinned, max_batch x STAT_COUNT
+  bool busy = false;
+};
+
+}  // namespace
+
+struct Server {
+  tk_tree* t = nullptr;
+  tk_serve_config cfg{};
+  std::chrono::steady_clock::time_point t0;
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv;       // new work or stop
+  std::condition_variable done_cv;  // a request finished
+  bool stop = false;
+  bool failed = false;
+  std::vector<Request*> reqs;  // by ticket - 1
+  std::deque<Request*> inbox;
+  int64_t T_logical = 0;  // slices submitted
+  int64_t outstanding = 0;
+  tk_serve_stats stats{};
+  // engine-side state (scheduler thread only)
+  Lane alane;
+  std::deque<Request*> apending;
+  std::vector<Request*> ainflight;
+  hipEvent_t aev = nullptr;
+  bool abusy = false;
+  int64_t rows_staged = 0;  // rows of the current partial block in the staging buffer
+  int64_t Tb_issued = 0;    // blocks whose commit has been issued
+  int64_t Tb_done = 0;      // blocks whose commit has completed
+  hipEvent_t commit_ev = nullptr;
+  ClassLane cl[kClasses];
+  int bounds[kClasses] = {0, 0, 0};  // class c takes eigenproblems <= bounds[c]
+};
+
+namespace {
+
+tk_status serve_fail(Server* s, tk_status st) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->failed = true;
+  for (Request* r : s->reqs)
+    if (r->state < REQ_DONE) r->state = REQ_FAILED;
+  s->outstanding = 0;
+  s->done_cv.notify_all();
+  return st;
+}
+
+void finish(Server* s, Request* r, int state) {
+  r->t_done = now_us(s->t0);
+  std::lock_guard<std::mutex> lk(s->mu);
+  r->state = state;
+  r->data.clear();
+  r->data.shrink_to_fit();
+  r->hits.clear();
+  r->hits.shrink_to_fit();
+  s->outstanding -= 1;
+  s->stats.completed += 1;
+  s->done_cv.notify_all();
+}
+
+int class_of(const Server* s, int need) {
+  for (int c = 0; c < kClasses; ++c)
+    if (need <= s->bounds[c]) return c;
+  return kClasses - 1;
+}
+
+// Stage pending appends and commit the blocks they complete.
+tk_status issue_appends(Server* s) {
+  tk_tree* t = s->t;
+  if (s->abusy || s->apending.empty()) return TK_OK;
+  const int64_t ell = t->ell;
+  const int64_t cap_rows = int64_t(s->cfg.max_commit_blocks) * ell;
+  float* stage = reinterpret_cast<float*>(s->alane.xbuf.p);
+  const int64_t se = t->slice_elems;
+  const double tl = now_us(s->t0);
+  while (!s->apending.empty() && s->rows_staged < cap_rows) {
+    Request* r = s->apending.front();
+    s->apending.pop_front();
+    const float* src = r->kind == 1 && r->dev_slice ? r->dev_slice : r->data.data();
+    TK_HIP(t, hipMemcpyAsync(stage + s->rows_staged * se, src, size_t(se) * 4,
+                             r->dev_slice ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->alane.stream));
+    r->t_launch = tl;
+    r->state = REQ_RUNNING;
+    s->ainflight.push_back(r);
+    s->rows_staged += 1;
+  }
+  const int64_t nb = s->rows_staged / ell;
+  if (nb > 0) {
+    tk_status st = commit_blocks(t, &s->alane, nb, stage);
+    if (st) return st;
+    t->T += nb * ell;
+    const int64_t rem = s->rows_staged - nb * ell;
+    if (rem > 0)  // keep the partial block's rows at the front (no overlap: rem < ell <= nb ell)
+      TK_HIP(t, hipMemcpyAsync(stage, stage + nb * ell * se, size_t(rem * se) * 4, hipMemcpyDeviceToDevice,
+                               s->alane.stream));
+    s->rows_staged = rem;
+    s->Tb_issued = t->Tb;
+    TK_HIP(t, hipEventRecord(s->commit_ev, s->alane.stream));
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stats.commits += 1;
+  }
+  TK_HIP(t, hipEventRecord(s->aev, s->alane.stream));
+  s->abusy = true;
+  return TK_OK;
+}
+
+tk_status issue_queries(Server* s, ClassLane& c) {
+  tk_tree* t = s->t;
+  if (c.busy || c.pending.empty()) return TK_OK;
+  std::vector<Job> jobs;
+  std::vector<Hit> hits;
+  int64_t ws = 0;
+  int64_t Tb_need = 0;
+  while (!c.pending.empty() && int(jobs.size()) < s->cfg.max_batch) {
+    Request* r = c.pending.front();
+    if (r->Tb > s->Tb_issued) break;  // its appends are not committed yet (later queries neither)
+    if (!jobs.empty() && ws + r->job.ws_bytes > c.ws_budget) break;
+    c.pending.pop_front();
+    Job jb = r->job;
+    jb.hit0 = int32_t(hits.size());
+    jb.ws_off = ws;
+    jb.stats = reinterpret_cast<double*>(c.lane.stats.p) + STAT_COUNT * int64_t(jobs.size());
+    ws += jb.ws_bytes;
+    hits.insert(hits.end(), r->hits.begin(), r->hits.end());
+    jobs.push_back(jb);
+    c.inflight.push_back(r);
+    if (r->Tb > Tb_need) Tb_need = r->Tb;
+  }
+  if (jobs.empty()) return TK_OK;
+  const double tl = now_us(s->t0);
+  for (Request* r : c.inflight) {
+    r->t_launch = tl;
+    r->state = REQ_RUNNING;
+  }
+  hipStream_t st_ = c.lane.stream;
+  if (Tb_need > s->Tb_done) TK_HIP(t, hipStreamWaitEvent(st_, s->commit_ev, 0));
+  TK_HIP(t, hipMemcpyAsync(c.lane.jobs[0].p, jobs.data(), jobs.size() * sizeof(Job), hipMemcpyHostToDevice, st_));
+  StitchArgs a = stitch_args(t, t->q_max_iter, t->q_tol);
+  a.hits = reinterpret_cast<Hit*>(c.lane.hits.p);
+  a.jobs = reinterpret_cast<const Job*>(c.lane.jobs[0].p);
+  a.ws = c.lane.ws[0].p;
+  a.n_jobs = int(jobs.size());
+  a.n_lds = c.n_lds;
+  const size_t lds_bytes = size_t(eig_doubles(c.n_lds)) * 8;
+  int grid = a.n_jobs;
+  a.queue = nullptr;
+  if (t->tuning.persistent) {
+    const int64_t resident = int64_t(stitch_blocks_per_cu(c.threads, lds_bytes)) * t->n_cu;
+    if (resident < grid) grid = int(resident);
+    a.queue = reinterpret_cast<int*>(c.lane.queue.p);
+    TK_HIP(t, launch_reset_queue(a.queue, 1, st_));
+  }
+  TK_HIP(t, launch_stitch(a, grid, lds_bytes, c.threads, st_));
+  TK_HIP(t, hipMemcpyAsync(c.hstats, c.lane.stats.p, jobs.size() * STAT_COUNT * 8, hipMemcpyDeviceToHost, st_));
+  TK_HIP(t, hipEventRecord(c.done_ev, st_));
+  c.busy = true;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->stats.batches += 1;
+  if (int64_t(jobs.size()) > s->stats.max_batch_seen) s->stats.max_batch_seen = int64_t(jobs.size());
+  return TK_OK;
+}
+
+tk_status poll_completions(Server* s, bool* progress) {
+  tk_tree* t = s->t;
+  if (s->abusy) {
+    const hipError_t e = hipEventQuery(s->aev);
+    if (e == hipSuccess) {
+      s->abusy = false;
+      s->Tb_done = s->Tb_issued;
+      for (Request* r : s->ainflight) finish(s, r, REQ_DONE);
+      s->ainflight.clear();
+      *progress = true;
+    } else if (e != hipErrorNotReady) {
+      return fail_dev(t, e, "append commit");
+    }
+  }
+  for (ClassLane& c : s->cl) {
+    if (!c.busy) continue;
+    const hipError_t e = hipEventQuery(c.done_ev);
+    if (e == hipErrorNotReady) continue;
+    if (e != hipSuccess) return fail_dev(t, e, "query batch");
+    c.busy = false;
+    *progress = true;
+    for (size_t i = 0; i < c.inflight.size(); ++i) {
+      Request* r = c.inflight[i];
+      const double* st = c.hstats + STAT_COUNT * i;
+      int state = REQ_DONE;
+      if (st[STAT_STATUS] != 0.0) {
+        t->err = "stitch kernel: device Recall or workspace disagrees with the host plan";
+        state = REQ_FAILED;
+      }
+      tk_result& o = *r->res;
+      for (int m = 0; m < TK_MAX_MODES; ++m) o.ranks_eff[m] = m < t->p ? r->job.rq[m] : 0;
+      o.fit = st[STAT_FIT];
+      o.err_model = st[STAT_ERR];
+      o.norm_ytilde = st[STAT_NORM];
+      o.sweeps = int32_t(st[STAT_SWEEPS]);
+      o.converged = int32_t(st[STAT_CONV]);
+      o.n_hits = r->job.s;
+      finish(s, r, state);
+    }
+    c.inflight.clear();
+  }
+  return TK_OK;
+}
+
+void engine(Server* s) {
+  tk_tree* t = s->t;
+  (void)hipSetDevice(t->device);
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      const bool idle = !s->abusy && s->apending.empty() && s->inbox.empty() &&
+                        std::all_of(s->cl, s->cl + kClasses, [](const ClassLane& c) {
+                          return !c.busy && c.pending.empty();
+                        });
+      if (idle) {
+        if (s->stop) break;
+        s->cv.wait(lk, [&] { return s->stop || !s->inbox.empty(); });
+      }
+      while (!s->inbox.empty()) {
+        Request* r = s->inbox.front();
+        s->inbox.pop_front();
+        if (r->kind == 1) s->apending.push_back(r);
+        else s->cl[r->cls].pending.push_back(r);
+      }
+    }
+    bool progress = false;
+    tk_status st = poll_completions(s, &progress);
+    if (!st) st = issue_appends(s);
+    for (int c = 0; c < kClasses && !st; ++c) st = issue_queries(s, s->cl[c]);
+    if (st) {
+      serve_fail(s, st);
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv.wait(lk, [&] { return s->stop; });
+      break;
+    }
+    if (!progress) {
+      // work is in flight: poll its events again shortly, or take new work
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv.wait_for(lk, std::chrono::microseconds(20), [&] { return s->stop || !s->inbox.empty(); });
+    }
+  }
+}
+
+void server_free(Server* s) {
+  lane_destroy(&s->alane);
+  for (ClassLane& c : s->cl) {
+    lane_destroy(&c.lane);
+    if (c.done_ev) (void)hipEventDestroy(c.done_ev);
+    if (c.hstats) (void)hipHostFree(c.hstats);
+  }
+  if (s->aev) (void)hipEventDestroy(s->aev);
+  if (s->commit_ev) (void)hipEventDestroy(s->commit_ev);
+  for (Request* r : s->reqs) delete r;
+  delete s;
+}
+
+}  // namespace
+}  // namespace tk
+
+using namespace tk;
+
+extern "C" {
+
+tk_status tk_serve_start(tk_tree* t, const tk_serve_config* cfg) {
+  if (!t) return TK_EINVAL;
+  if (t->server) return fail(t, TK_EBUSY, "already serving");
+  if (t->poisoned) return TK_EDEVICE;
+  tk_serve_config c{};
+  c.max_batch = 256;
+  c.max_commit_blocks = 64;
+  c.ws_budget_bytes = int64_t(1) << 30;
+  c.max_queue = 1 << 20;
+  if (cfg) {
+    if (cfg->max_batch > 0) c.max_batch = cfg->max_batch;
+    if (cfg->max_commit_blocks > 0) c.max_commit_blocks = cfg->max_commit_blocks;
+    if (cfg->ws_budget_bytes > 0) c.ws_budget_bytes = cfg->ws_budget_bytes;
+    if (cfg->max_queue > 0) c.max_queue = cfg->max_queue;
+  }
+  if (c.max_batch > (1 << 16) || c.max_commit_blocks > (1 << 16)) return fail(t, TK_EINVAL, "serve config too large");
+  TK_HIP(t, hipStreamSynchronize(t->stream));
+  Server* s = new Server();
+  s->t = t;
+  s->cfg = c;
+  s->t0 = std::chrono::steady_clock::now();
+  s->T_logical = t->T;
+  s->Tb_issued = t->Tb;
+  s->Tb_done = t->Tb;
+  s->rows_staged = t->T % t->ell;
+  s->stats.T_submitted = t->T;
+  auto bail = [&](tk_status st) {
+    server_free(s);
+    return st;
+  };
+  hipError_t e = hipStreamCreateWithFlags(&s->alane.stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return bail(fail_dev(t, e, "serve: append stream"));
+  s->alane.own_stream = true;
+  tk_status st = ensure(t, &s->alane.xbuf, int64_t(c.max_commit_blocks) * t->ell * t->slice_elems * 4, "serve staging");
+  if (st) return bail(st);
+  if (s->rows_staged > 0) {  // rows of a partial block appended before serving
+    e = hipMemcpy(s->alane.xbuf.p, t->block_buf, size_t(s->rows_staged * t->slice_elems) * 4,
+                  hipMemcpyDeviceToDevice);
+    if (e != hipSuccess) return bail(fail_dev(t, e, "serve: staging"));
+  }
+  if ((e = hipEventCreateWithFlags(&s->aev, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&s->commit_ev, hipEventDisableTiming)) != hipSuccess)
+    return bail(fail_dev(t, e, "serve: events"));
+  // size classes: small and medium narrow jobs, then wide ones
+  const int cap = lds_cap(t);
+  const int thr = t->tuning.wide_threshold < cap ? t->tuning.wide_threshold : cap;
+  s->bounds[0] = thr < 32 ? thr : 32;
+  s->bounds[1] = thr;
+  s->bounds[2] = 1 << 30;
+  for (int k = 0; k < kClasses; ++k) {
+    ClassLane& cl = s->cl[k];
+    cl.n_lds = k < kClasses - 1 ? s->bounds[k] : cap;
+    const int hi = s->bounds[k];
+    cl.threads = hi <= t->tuning.wide_threshold ? NT_STITCH : t->tuning.wide_threads;
+    cl.ws_budget = c.ws_budget_bytes / kClasses;
+    if ((e = hipStreamCreateWithFlags(&cl.lane.stream, hipStreamNonBlocking)) != hipSuccess)
+      return bail(fail_dev(t, e, "serve: class stream"));
+    cl.lane.own_stream = true;
+    if ((e = hipEventCreateWithFlags(&cl.done_ev, hipEventDisableTiming)) != hipSuccess)
+      return bail(fail_dev(t, e, "serve: class event"));
+    if ((st = ensure(t, &cl.lane.ws[0], cl.ws_budget + 256, "serve workspace")) ||
+        (st = ensure(t, &cl.lane.jobs[0], int64_t(c.max_batch) * sizeof(Job), "serve jobs")) ||
+        (st = ensure(t, &cl.lane.hits, int64_t(c.max_batch) * MAXHITS * sizeof(Hit), "serve hits")) ||
+        (st = ensure(t, &cl.lane.stats, int64_t(c.max_batch) * STAT_COUNT * 8, "serve stats")) ||
+        (st = ensure(t, &cl.lane.queue, 64, "serve queue")))
+      return bail(st);
+    void* hp = nullptr;
+    if ((e = hipHostMalloc(&hp, size_t(c.max_batch) * STAT_COUNT * 8, hipHostMallocDefault)) != hipSuccess)
+      return bail(fail_dev(t, e, "serve: pinned stats"));
+    cl.hstats = static_cast<double*>(hp);
+  }
+  t->server = s;
+  s->th = std::thread(engine, s);
+  return TK_OK;
+}
+
+tk_status tk_serve_stop(tk_tree* t) {
+  if (!t || !t->server) return TK_OK;
+  Server* s = t->server;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  if (s->th.joinable()) s->th.join();
+  // committed blocks are on the append lane's stream: order the tree's
+  // stream after them, and keep a partial block's rows for tk_append
+  (void)hipStreamSynchronize(s->alane.stream);
+  if (s->rows_staged > 0 && !s->failed)
+    (void)hipMemcpy(t->block_buf, s->alane.xbuf.p, size_t(s->rows_staged * t->slice_elems) * 4,
+                    hipMemcpyDeviceToDevice);
+  t->T = s->T_logical;
+  const bool failed = s->failed;
+  t->server = nullptr;
+  server_free(s);
+  return failed ? TK_EDEVICE : TK_OK;
+}
+
+tk_status tk_submit_query(tk_tree* t, int64_t ts, int64_t te, tk_result* res, uint64_t* ticket) {
+  if (!t || !res || !ticket) return TK_EINVAL;
+  Server* s = t->server;
+  if (!s) return fail(t, TK_EINVAL, "not serving: call tk_serve_start");
+  if (!res->core) return TK_EINVAL;
+  for (int m = 0; m < t->p; ++m)
+    if (!res->factor[m]) return TK_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->failed) return TK_EDEVICE;
+  if (s->outstanding >= s->cfg.max_queue) {
+    s->stats.rejected += 1;
+    return TK_EBUSY;
+  }
+  const int64_t Tb = s->T_logical / t->ell;
+  if (!(ts >= 0 && ts < te && te <= Tb * t->ell)) return TK_ERANGE;
+  Request* r = new Request();
+  std::vector<Job> jobs;
+  // planning only reads immutable tree fields (config, store layout)
+  if (make_query_job(t, ts, te, Tb, res, true, jobs, r->hits) != TK_OK) {
+    delete r;
+    return TK_EINVAL;
+  }
+  r->job = jobs[0];
+  r->job.hit0 = 0;
+  StitchLayout lo;
+  stitch_layout(t->view, r->hits.data(), r->job.s, r->job.rq, 1 << 30, &lo);
+  r->cls = class_of(s, eig_need(lo, t->view));
+  stitch_layout(t->view, r->hits.data(), r->job.s, r->job.rq, s->cl[r->cls].n_lds, &lo);
+  r->job.ws_bytes = lo.total;
+  if (lo.total > s->cl[r->cls].ws_budget) {
+    delete r;
+    s->stats.rejected += 1;
+    return TK_ENOMEM;  // larger than the class's workspace budget
+  }
+  r->kind = 0;
+  r->ts = ts;
+  r->te = te;
+  r->Tb = Tb;
+  r->res = res;
+  r->ticket = uint64_t(s->reqs.size()) + 1;
+  r->t_submit = now_us(s->t0);
+  s->reqs.push_back(r);
+  s->inbox.push_back(r);
+  s->outstanding += 1;
+  s->stats.queries += 1;
+  *ticket = r->ticket;
+  s->cv.notify_all();
+  return TK_OK;
+}
+
+tk_status tk_submit_append(tk_tree* t, const float* slice, int on_device, uint64_t* ticket) {
+  if (!t || !slice || !ticket) return TK_EINVAL;
+  Server* s = t->server;
+  if (!s) return fail(t, TK_EINVAL, "not serving: call tk_serve_start");
+  Request* r = new Request();
+  r->kind = 1;
+  if (on_device) r->dev_slice = slice;
+  else r->data.assign(slice, slice + t->slice_elems);
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->failed) {
+    delete r;
+    return TK_EDEVICE;
+  }
+  if (s->T_logical >= t->cap_blocks * t->ell) {
+    delete r;
+    return TK_ENOMEM;
+  }
+  if (s->outstanding >= s->cfg.max_queue) {
+    delete r;
+    s->stats.rejected += 1;
+    return TK_EBUSY;
+  }
+  s->T_logical += 1;
+  r->ticket = uint64_t(s->reqs.size()) + 1;
+  r->t_submit = now_us(s->t0);
+  s->reqs.push_back(r);
+  s->inbox.push_back(r);
+  s->outstanding += 1;
+  s->stats.appends += 1;
+  s->stats.T_submitted = s->T_logical;
+  *ticket = r->ticket;
+  s->cv.notify_all();
+  return TK_OK;
+}
+
+tk_status tk_poll(tk_tree* t, uint64_t ticket, int32_t* done) {
+  if (!t || !done) return TK_EINVAL;
+  Server* s = t->server;
+  if (!s) return TK_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (ticket < 1 || ticket > s->reqs.size()) return TK_EINVAL;
+  const Request* r = s->reqs[ticket - 1];
+  *done = r->state >= REQ_DONE ? 1 : 0;
+  return r->state == REQ_FAILED ? TK_EDEVICE : TK_OK;
+}
+
+tk_status tk_wait(tk_tree* t, uint64_t ticket) {
+  if (!t) return TK_EINVAL;
+  Server* s = t->server;
+  if (!s) return TK_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (ticket < 1 || ticket > s->reqs.size()) return TK_EINVAL;
+  const Request* r = s->reqs[ticket - 1];
+  s->done_cv.wait(lk, [&] { return r->state >= REQ_DONE; });
+  return r->state == REQ_FAILED ? TK_EDEVICE : TK_OK;
+}
+
+tk_status tk_sync(tk_tree* t) {
+  if (!t) return TK_EINVAL;
+  Server* s = t->server;
+  if (!s) {
+    if (hipStreamSynchronize(t->stream) != hipSuccess) return TK_EDEVICE;
+    return TK_OK;
+  }
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->done_cv.wait(lk, [&] { return s->outstanding == 0; });
+  return s->failed ? TK_EDEVICE : TK_OK;
+}
+
+tk_status tk_ticket_times(tk_tree* t, uint64_t ticket, double* submit_us, double* launch_us, double* done_us) {
+  if (!t || !submit_us || !launch_us || !done_us) return TK_EINVAL;
+  Server* s = t->server;
+  if (!s) return TK_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (ticket < 1 || ticket > s->reqs.size()) return TK_EINVAL;
+  const Request* r = s->reqs[ticket - 1];
+  *submit_us = r->t_submit;
+  *launch_us = r->t_launch;
+  *done_us = r->state >= REQ_DONE ? r->t_done : -1.0;
+  return TK_OK;
+}
+
+tk_status tk_serve_stats_get(tk_tree* t, tk_serve_stats* out) {
+  if (!t || !out) return TK_EINVAL;
+  Server* s = t->server;
+  if (!s) return TK_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->stats;
+  out->T_committed = s->Tb_done * t->ell;
+  out->outstanding = s->outstanding;
+  return TK_OK;
+}
+
+}  // extern "C"

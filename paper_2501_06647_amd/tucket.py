@@ -40,7 +40,7 @@ class TkHit(ctypes.Structure):
 
 class TkShape(ctypes.Structure):
     _fields_ = [("ranks_eff", c_i32 * MAX_MODES), ("L", c_i64), ("core_elems", c_i64),
-                ("factor_elems", c_i64 * MAX_MODES), ("n_hits", c_i32)]
+                ("factor_elems", c_i64 * MAX_MODES), ("n_hits", c_i32), ("ws_bytes", c_i64)]
 
 
 class TkResult(ctypes.Structure):
@@ -53,6 +53,21 @@ class TkStats(ctypes.Structure):
     _fields_ = [("T", c_i64), ("T_committed", c_i64), ("blocks", c_i64), ("nodes", c_i64),
                 ("merges_total", c_i64), ("merges_last", c_i64), ("store_bytes", c_i64),
                 ("height", c_i32)]
+
+
+class TkTuning(ctypes.Structure):
+    _fields_ = [("wide_threshold", c_i32), ("wide_threads", c_i32), ("persistent", c_i32), ("graph", c_i32)]
+
+
+class TkServeConfig(ctypes.Structure):
+    _fields_ = [("max_batch", c_i32), ("max_commit_blocks", c_i32), ("ws_budget_bytes", c_i64),
+                ("max_queue", c_i64)]
+
+
+class TkServeStats(ctypes.Structure):
+    _fields_ = [("queries", c_i64), ("appends", c_i64), ("completed", c_i64), ("rejected", c_i64),
+                ("batches", c_i64), ("commits", c_i64), ("max_batch_seen", c_i64), ("outstanding", c_i64),
+                ("T_submitted", c_i64), ("T_committed", c_i64)]
 
 
 # (name, restype, argtypes) of every entry point declared in include/tucket.h
@@ -78,6 +93,28 @@ SIGNATURES = [
     ("tk_hitset_plan", c_i32, [ctypes.POINTER(TkConfig), c_i64, c_i64, c_i64, ctypes.POINTER(TkHit),
                                c_i32, ctypes.POINTER(c_i32)]),
     ("tk_effective_ranks", c_i32, [ctypes.POINTER(TkConfig), c_i64, ctypes.POINTER(c_i32)]),
+    ("tk_get_tuning", c_i32, [c_vp, ctypes.POINTER(TkTuning)]),
+    ("tk_set_tuning", c_i32, [c_vp, ctypes.POINTER(TkTuning)]),
+    ("tk_batch_create", c_i32, [c_vp, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
+                                ctypes.POINTER(TkResult), ctypes.POINTER(c_vp)]),
+    ("tk_batch_run", c_i32, [c_vp]),
+    ("tk_batch_wait", c_i32, [c_vp]),
+    ("tk_batch_kernel_ms", c_i32, [c_vp, ctypes.POINTER(c_dbl)]),
+    ("tk_batch_profile", c_i32, [c_vp, c_i32, ctypes.POINTER(c_dbl)]),
+    ("tk_batch_hits", c_i32, [c_vp, c_i32, ctypes.POINTER(TkHit), c_i32, ctypes.POINTER(c_i32)]),
+    ("tk_batch_destroy", None, [c_vp]),
+    ("tk_autotune", c_i32, [c_vp, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64), c_i32,
+                            ctypes.POINTER(TkTuning), ctypes.POINTER(c_dbl)]),
+    ("tk_serve_start", c_i32, [c_vp, ctypes.POINTER(TkServeConfig)]),
+    ("tk_serve_stop", c_i32, [c_vp]),
+    ("tk_submit_query", c_i32, [c_vp, c_i64, c_i64, ctypes.POINTER(TkResult), ctypes.POINTER(ctypes.c_uint64)]),
+    ("tk_submit_append", c_i32, [c_vp, c_vp, c_i32, ctypes.POINTER(ctypes.c_uint64)]),
+    ("tk_poll", c_i32, [c_vp, ctypes.c_uint64, ctypes.POINTER(c_i32)]),
+    ("tk_wait", c_i32, [c_vp, ctypes.c_uint64]),
+    ("tk_sync", c_i32, [c_vp]),
+    ("tk_ticket_times", c_i32, [c_vp, ctypes.c_uint64, ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl),
+                                ctypes.POINTER(c_dbl)]),
+    ("tk_serve_stats_get", c_i32, [c_vp, ctypes.POINTER(TkServeStats)]),
     ("tk_version", ctypes.c_char_p, []),
 ]
 
@@ -163,8 +200,25 @@ class QueryResult:
         self.norm_ytilde = res.norm_ytilde
 
 
+def _query_shapes(tree, ts, te):
+    """Output shapes of each query: core, U^(1), U^(2..p).  An empty or
+    negative range raises TK_ERANGE here; a range past the committed horizon
+    is refused by the library call that takes it."""
+    p = tree.p
+    out = []
+    for a, b in zip(ts, te):
+        if not (0 <= int(a) < int(b)):
+            raise TuckerError(TK_ERANGE, "query range [%d, %d) is empty or negative" % (int(a), int(b)))
+        r = effective_ranks(tree.cfg, int(b - a))
+        out.append([r, (int(b - a), r[0])] + [(tree.dims[m - 1], r[m]) for m in range(1, p)])
+    return out
+
+
 class PreparedBatch:
-    """A list of range queries with device output buffers allocated once."""
+    """A fixed list of range queries planned once (tk_batch_create): device
+    outputs allocated once, job descriptors resident, launches captured in a
+    HIP graph when the tree's tuning asks for it.  Every run() executes
+    Recall, trims and Stitch of every query on the device."""
 
     def __init__(self, tree: "Tree", ts, te):
         self.tree = tree
@@ -173,12 +227,7 @@ class PreparedBatch:
         n = len(self.ts)
         self.n = n
         p = tree.p
-        shapes_all = []
-        for i in range(n):
-            sh = tree.query_shape(int(self.ts[i]), int(self.te[i]))
-            r = tuple(sh.ranks_eff[:p])
-            shapes_all.append([r, (int(self.te[i] - self.ts[i]), r[0])] +
-                              [(tree.dims[m - 1], r[m]) for m in range(1, p)])
+        shapes_all = _query_shapes(tree, self.ts, self.te)
         self.buf, views = tree._alloc([s for shp in shapes_all for s in shp])
         self.res = (TkResult * max(n, 1))()
         self.outputs = []
@@ -192,9 +241,26 @@ class PreparedBatch:
             self.outputs.append((core, facs))
         self._ts = (c_i64 * max(n, 1))(*self.ts.tolist())
         self._te = (c_i64 * max(n, 1))(*self.te.tolist())
+        self._h = c_vp(0)
+        if n > 0:
+            tree._check(lib().tk_batch_create(tree._h, n, self._ts, self._te, self.res, ctypes.byref(self._h)),
+                        "tk_batch_create")
 
-    def run(self):
-        """One tk_query_batch call: Recall, trims and Stitch for every query."""
+    def run(self, wait: bool = True):
+        """One execution on the tree's stream (graph replay); with wait, block
+        and collect the per-query scalars."""
+        if self.n == 0:
+            return
+        self.tree._check(lib().tk_batch_run(self._h), "tk_batch_run")
+        if wait:
+            self.wait()
+
+    def wait(self):
+        self.tree._check(lib().tk_batch_wait(self._h), "tk_batch_wait")
+
+    def run_sync(self):
+        """The same queries through tk_query_batch: host Recall and planning,
+        then the launches, every call."""
         self.tree._check(lib().tk_query_batch(self.tree._h, self.n, self._ts, self._te, self.res),
                          "tk_query_batch")
 
@@ -205,8 +271,118 @@ class PreparedBatch:
         res = ctypes.cast(ctypes.addressof(self.res) + ctypes.sizeof(TkResult) * i, ctypes.POINTER(TkResult))
         self.tree._check(lib().tk_query_batch(self.tree._h, 1, ts, te, res), "tk_query")
 
+    def kernel_ms(self) -> float:
+        ms = c_dbl(0.0)
+        self.tree._check(lib().tk_batch_kernel_ms(self._h, ctypes.byref(ms)), "tk_batch_kernel_ms")
+        return ms.value
+
+    def profile(self, i: int) -> dict:
+        out = (c_dbl * 12)()
+        self.tree._check(lib().tk_batch_profile(self._h, i, out), "tk_batch_profile")
+        return dict(zip(Tree.PHASES + Tree.COUNTERS, list(out)))
+
+    def device_hits(self, i: int) -> List[dict]:
+        """The hit set query i's kernel computed on the device."""
+        n = c_i32(0)
+        buf = (TkHit * 128)()
+        self.tree._check(lib().tk_batch_hits(self._h, i, buf, 128, ctypes.byref(n)), "tk_batch_hits")
+        return _hits_to_list(buf, n.value)
+
     def results(self) -> List[QueryResult]:
         return [QueryResult(c, f, self.res[i], self.tree.p) for i, (c, f) in enumerate(self.outputs)]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().tk_batch_destroy(self._h)
+            self._h = c_vp(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request loop of a tree (tk_serve_start): queries
+    and appends are submitted and return tickets; results are read once a
+    ticket is done.  Output buffers are allocated per query on the device
+    and kept until the result is taken."""
+
+    def __init__(self, tree: "Tree", max_batch: int = 0, max_commit_blocks: int = 0,
+                 ws_budget_bytes: int = 0, max_queue: int = 0):
+        self.tree = tree
+        cfg = TkServeConfig(int(max_batch), int(max_commit_blocks), int(ws_budget_bytes), int(max_queue))
+        tree._check(lib().tk_serve_start(tree._h, ctypes.byref(cfg)), "tk_serve_start")
+        self._live = {}
+        self.running = True
+
+    def submit_query(self, ts: int, te: int) -> int:
+        tree = self.tree
+        shp = _query_shapes(tree, [ts], [te])[0]
+        buf, views = tree._alloc(shp)
+        res = TkResult()
+        res.core = views[0].data_ptr()
+        for m in range(tree.p):
+            res.factor[m] = views[1 + m].data_ptr()
+        t = ctypes.c_uint64(0)
+        tree._check(lib().tk_submit_query(tree._h, int(ts), int(te), ctypes.byref(res), ctypes.byref(t)),
+                    "tk_submit_query")
+        self._live[t.value] = (res, buf, views)
+        return t.value
+
+    def submit_append(self, slice_) -> int:
+        tree = self.tree
+        t = ctypes.c_uint64(0)
+        if isinstance(slice_, np.ndarray):
+            x = np.ascontiguousarray(slice_, dtype=np.float32)
+            assert x.shape == tree.dims
+            tree._check(lib().tk_submit_append(tree._h, c_vp(x.ctypes.data), 0, ctypes.byref(t)),
+                        "tk_submit_append")
+        else:
+            x = tree._device_f32(slice_)
+            assert tuple(x.shape) == tree.dims
+            tree._check(lib().tk_submit_append(tree._h, c_vp(x.data_ptr()), 1, ctypes.byref(t)),
+                        "tk_submit_append")
+            self._live[t.value] = (None, x, None)
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = c_i32(0)
+        self.tree._check(lib().tk_poll(self.tree._h, ticket, ctypes.byref(d)), "tk_poll")
+        return bool(d.value)
+
+    def wait(self, ticket: int):
+        self.tree._check(lib().tk_wait(self.tree._h, ticket), "tk_wait")
+
+    def sync(self):
+        self.tree._check(lib().tk_sync(self.tree._h), "tk_sync")
+
+    def result(self, ticket: int) -> QueryResult:
+        """The decomposition of a finished query (releases the ticket's buffers)."""
+        self.wait(ticket)
+        res, buf, views = self._live.pop(ticket)
+        return QueryResult(views[0], views[1:], res, self.tree.p)
+
+    def release(self, ticket: int):
+        self._live.pop(ticket, None)
+
+    def times(self, ticket: int) -> Tuple[float, float, float]:
+        a, b, c = c_dbl(), c_dbl(), c_dbl()
+        self.tree._check(lib().tk_ticket_times(self.tree._h, ticket, ctypes.byref(a), ctypes.byref(b),
+                                               ctypes.byref(c)), "tk_ticket_times")
+        return a.value, b.value, c.value
+
+    def stats(self) -> dict:
+        s = TkServeStats()
+        self.tree._check(lib().tk_serve_stats_get(self.tree._h, ctypes.byref(s)), "tk_serve_stats_get")
+        return {k: getattr(s, k) for k, _ in TkServeStats._fields_}
+
+    def stop(self):
+        if self.running:
+            self.running = False
+            self.tree._check(lib().tk_serve_stop(self.tree._h), "tk_serve_stop")
+            self._live.clear()
 
 
 class Tree:
@@ -289,13 +465,42 @@ class Tree:
         return buf, views
 
     def prepare_batch(self, ts, te) -> "PreparedBatch":
-        """Allocate the outputs of a fixed list of queries once; run() reuses them."""
+        """Plan a fixed list of queries once; run() replays them."""
         return PreparedBatch(self, ts, te)
 
     def query_batch(self, ts, te) -> List[QueryResult]:
+        """tk_query_batch: one synchronous batched call."""
         b = self.prepare_batch(ts, te)
-        b.run()
-        return b.results()
+        b.run_sync()
+        out = b.results()
+        b.close()
+        return out
+
+    # -- launch tuning and serving -----------------------------------------------------
+    def tuning(self) -> dict:
+        tu = TkTuning()
+        self._check(lib().tk_get_tuning(self._h, ctypes.byref(tu)), "tk_get_tuning")
+        return {k: getattr(tu, k) for k, _ in TkTuning._fields_}
+
+    def set_tuning(self, **kw):
+        cur = self.tuning()
+        cur.update(kw)
+        tu = TkTuning(**{k: int(v) for k, v in cur.items()})
+        self._check(lib().tk_set_tuning(self._h, ctypes.byref(tu)), "tk_set_tuning")
+
+    def autotune(self, ts, te, reps: int = 2) -> Tuple[dict, float]:
+        ts = np.asarray(ts, dtype=np.int64).reshape(-1)
+        te = np.asarray(te, dtype=np.int64).reshape(-1)
+        n = len(ts)
+        a = (c_i64 * n)(*ts.tolist())
+        b = (c_i64 * n)(*te.tolist())
+        tu = TkTuning()
+        ms = c_dbl(0.0)
+        self._check(lib().tk_autotune(self._h, n, a, b, reps, ctypes.byref(tu), ctypes.byref(ms)), "tk_autotune")
+        return {k: getattr(tu, k) for k, _ in TkTuning._fields_}, ms.value
+
+    def serve(self, **kw) -> "Server":
+        return Server(self, **kw)
 
     PHASES = ("trim", "basis", "init", "t_ttm_gram", "t_eig", "n_ttm_gram", "n_eig", "final")
     COUNTERS = ("eig_calls", "eig_sweeps", "eig_rot_us", "eig_tail_us")

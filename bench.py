@@ -246,7 +246,16 @@ def main():
     prof = [batch.profile(i) for i in range(nq)]
     phase_mean = {k: float(np.mean([pr[k] for pr in prof])) for k in tree.PHASES}
     tot = np.array([sum(pr[k] for k in tree.PHASES) for pr in prof])
-    counters = {k: float(np.mean([pr[k] for pr in prof])) for k in tree.COUNTERS}
+    counters = {k: float(np.mean([pr[k] for pr in prof])) for k in tree.COUNTERS[:4]}
+    t_s = np.array([pr["start_us"] for pr in prof])
+    t_e = np.array([pr["end_us"] for pr in prof])
+    t_base = t_s.min()
+    timeline = {"makespan_us": float(t_e.max() - t_base),
+                "start_offset_us_p50": float(np.median(t_s - t_base)),
+                "start_offset_us_max": float((t_s - t_base).max()),
+                "mean_concurrency": float((t_e - t_s).sum() / max(1e-9, t_e.max() - t_base))}
+    print("[bench] device timeline: %s" % json.dumps({k: round(v, 1) for k, v in timeline.items()}),
+          file=sys.stderr, flush=True)
     print("[bench] eigensolver per query: %s" % json.dumps({k: round(v, 1) for k, v in counters.items()}),
           file=sys.stderr, flush=True)
     slow = int(np.argmax(tot))
@@ -329,7 +338,8 @@ def main():
         "appends_per_s": wl.T / build_s,
         "sweeps_mean": float(np.mean(sweeps)),
         "device_us_per_query": {"mean": float(tot.mean()), "p50": float(np.median(tot)), "max": float(tot.max()),
-                                "phase_mean": phase_mean, "eig_counters_mean": counters},
+                                "phase_mean": phase_mean, "eig_counters_mean": counters,
+                                "timeline": timeline},
         "hits_mean": float(np.mean(hit_counts)),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,

@@ -162,9 +162,10 @@ tk_status tk_last_query_kernel_ms(const tk_tree* t, double* ms);
  * workgroup): partial-hit trims, factor-span bases, HOSVD initialisation,
  * temporal-mode contractions and Gram, temporal-mode eigensolve, other
  * modes' contractions and Grams (with the core update), their eigensolves,
- * and writing the result; then four eigensolver counters: calls, Jacobi
- * sweeps, microseconds in rotations, microseconds extracting vectors.
- * phase_us has 12 entries. */
+ * and writing the result; then four eigensolver counters: calls, bisection
+ * steps, microseconds computing eigenvalues (tridiagonalisation and
+ * bisection), microseconds computing eigenvectors; then the query's start
+ * and end on the device clock in microseconds.  phase_us has 14 entries. */
 tk_status tk_last_query_profile(const tk_tree* t, int32_t i, double* phase_us);
 
 /* Override the ALS sweep cap and tolerance for later queries (not merges). */
@@ -202,6 +203,8 @@ typedef struct {
   int32_t wide_threads;   /* 128 or 256, default 256                           */
   int32_t persistent;     /* 0 or 1, default 0                                 */
   int32_t graph;          /* 1: prepared batches replay a captured HIP graph   */
+  int32_t coarse;         /* 1: LDS bins {32, wide_threshold, 96} (fewer      */
+                          /* launches), 0: {24, 32, 48, 64, 96, threshold}    */
 } tk_tuning;
 
 tk_status tk_get_tuning(const tk_tree* t, tk_tuning* out);
@@ -233,7 +236,8 @@ tk_status tk_batch_hits(const tk_batch* b, int32_t i, tk_hit* out, int32_t cap, 
 void tk_batch_destroy(tk_batch* b);
 
 /* Time every candidate tuning (wide_threshold in {32, 48, 64, 96} x
- * wide_threads in {128, 256} x persistent in {0, 1}) on a prepared batch of
+ * wide_threads in {128, 256} x persistent in {0, 1} x coarse in {0, 1}) on a
+ * prepared batch of
  * the given queries (reps timed executions after one warm-up, results into
  * scratch buffers), keep the fastest on the tree and report it. */
 tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* te, int32_t reps,

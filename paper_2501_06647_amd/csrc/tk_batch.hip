@@ -63,11 +63,13 @@ tk_status issue(tk_batch* b, hipStream_t stream) {
   StitchArgs base = stitch_args(t, t->q_max_iter, t->q_tol);
   base.hits = reinterpret_cast<Hit*>(b->hits.p);
   const bool fork = b->plan.groups.size() > 1;
+  bool used[kForkStreams] = {false, false, false, false};
   if (fork) TK_HIP(t, hipEventRecord(b->fork_ev, stream));
   for (const Group& gr : b->plan.groups) {
     const int g = gr.bin;
-    hipStream_t s = fork ? b->gstream[g] : stream;
-    if (fork) TK_HIP(t, hipStreamWaitEvent(s, b->fork_ev, 0));
+    hipStream_t s = fork ? b->gstream[gr.slot] : stream;
+    if (fork && !used[gr.slot]) TK_HIP(t, hipStreamWaitEvent(s, b->fork_ev, 0));
+    if (fork) used[gr.slot] = true;
     const size_t lds_bytes = size_t(eig_doubles(gr.n_lds)) * 8;
     StitchArgs a = base;
     a.jobs = reinterpret_cast<const Job*>(b->jobs[g].p);
@@ -83,10 +85,11 @@ tk_status issue(tk_batch* b, hipStream_t stream) {
       TK_HIP(t, launch_reset_queue(a.queue, 1, s));
     }
     TK_HIP(t, launch_stitch(a, grid, lds_bytes, gr.threads, s));
-    if (fork) {
-      TK_HIP(t, hipEventRecord(b->gev[g], s));
-      TK_HIP(t, hipStreamWaitEvent(stream, b->gev[g], 0));
-    }
+  }
+  for (int sl = 0; sl < kForkStreams && fork; ++sl) {
+    if (!used[sl]) continue;
+    TK_HIP(t, hipEventRecord(b->gev[sl], b->gstream[sl]));
+    TK_HIP(t, hipStreamWaitEvent(stream, b->gev[sl], 0));
   }
   return TK_OK;
 }
@@ -139,9 +142,9 @@ tk_status tk_batch_create(tk_tree* t, int32_t n, const int64_t* ts, const int64_
     st = ensure(t, &b->jobs[gr.bin], int64_t(gr.jobs.size() * sizeof(Job)), "batch jobs");
     if (st) return bail(st);
     TK_HIP(t, hipMemcpy(b->jobs[gr.bin].p, gr.jobs.data(), gr.jobs.size() * sizeof(Job), hipMemcpyHostToDevice));
-    if (!b->gstream[gr.bin]) {
-      TK_HIP(t, hipStreamCreateWithFlags(&b->gstream[gr.bin], hipStreamNonBlocking));
-      TK_HIP(t, hipEventCreateWithFlags(&b->gev[gr.bin], hipEventDisableTiming));
+    if (!b->gstream[gr.slot]) {
+      TK_HIP(t, hipStreamCreateWithFlags(&b->gstream[gr.slot], hipStreamNonBlocking));
+      TK_HIP(t, hipEventCreateWithFlags(&b->gev[gr.slot], hipEventDisableTiming));
     }
   }
   TK_HIP(t, hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
@@ -217,7 +220,8 @@ tk_status tk_batch_kernel_ms(const tk_batch* b, double* ms) {
 tk_status tk_batch_profile(const tk_batch* b, int32_t i, double* phase_us) {
   if (!b || !phase_us || i < 0 || i >= b->n) return TK_EINVAL;
   if (b->hstats.size() != size_t(b->n) * STAT_COUNT) return TK_EINVAL;
-  for (int k = 0; k < STAT_NPHASE + 4; ++k) phase_us[k] = b->hstats[size_t(i) * STAT_COUNT + STAT_PHASE + k];
+  for (int k = 0; k < STAT_NPHASE + 6; ++k)
+    phase_us[k] = b->hstats[size_t(i) * STAT_COUNT + STAT_PHASE + k] * (k >= STAT_NPHASE + 4 ? 0.01 : 1.0);
   return TK_OK;
 }
 
@@ -286,11 +290,12 @@ tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* t
   const int wth[] = {128, 256};
   for (int th : thr)
     for (int wt : wth)
-      for (int pers = 0; pers < 2; ++pers) {
+      for (int pc = 0; pc < 4; ++pc) {
         t->tuning = saved;
         t->tuning.wide_threshold = th;
         t->tuning.wide_threads = wt;
-        t->tuning.persistent = pers;
+        t->tuning.persistent = pc & 1;
+        t->tuning.coarse = pc >> 1;
         tk_batch* b = nullptr;
         st = tk_batch_create(t, n, ts, te, res.data(), &b);
         double sum = 0.0;
@@ -320,6 +325,7 @@ tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* t
     best->wide_threads = bestt.wide_threads;
     best->persistent = bestt.persistent;
     best->graph = bestt.graph;
+    best->coarse = bestt.coarse;
   }
   if (best_ms) *best_ms = bms;
   return TK_OK;

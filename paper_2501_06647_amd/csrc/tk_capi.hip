@@ -169,7 +169,7 @@ tk_status plan_stitch(tk_tree* t, std::vector<Job>& jobs, std::vector<Hit>& hits
   const Tuning& tu = t->tuning;
   // bin bounds: fixed sizes plus the wide threshold, capped by the LDS limit;
   // the last bin takes everything above (eigenproblems beyond cap run in HBM)
-  std::vector<int> bounds = {24, 32, 48, 64, 96};
+  std::vector<int> bounds = tu.coarse ? std::vector<int>{32, 96} : std::vector<int>{24, 32, 48, 64, 96};
   if (tu.wide_threshold < cap) bounds.push_back(tu.wide_threshold);
   for (int& b : bounds) b = b < cap ? b : cap;
   std::sort(bounds.begin(), bounds.end());
@@ -212,6 +212,11 @@ tk_status plan_stitch(tk_tree* t, std::vector<Job>& jobs, std::vector<Hit>& hits
     gr.ws_total = off;
     plan->groups.push_back(std::move(gr));
   }
+  // heaviest group first; groups are dealt to the fork streams in that order
+  std::stable_sort(plan->groups.begin(), plan->groups.end(), [](const Group& a, const Group& b) {
+    return a.jobs[0].s * a.jobs[0].L > b.jobs[0].s * b.jobs[0].L;
+  });
+  for (size_t i = 0; i < plan->groups.size(); ++i) plan->groups[i].slot = int(i % kForkStreams);
   plan->hits = hits;
   return TK_OK;
 }
@@ -284,17 +289,24 @@ tk_status run_plan(tk_tree* t, Lane* lane, Plan& plan, int max_iter, double tol,
   }
   if (!lane->fork_ev) TK_HIP(t, hipEventCreateWithFlags(&lane->fork_ev, hipEventDisableTiming));
   TK_HIP(t, hipEventRecord(lane->fork_ev, lane->stream));
+  bool used[kForkStreams] = {false, false, false, false};
   for (Group& gr : plan.groups) {
-    const int b = gr.bin;
-    if (!lane->gstream[b]) {
-      TK_HIP(t, hipStreamCreateWithFlags(&lane->gstream[b], hipStreamNonBlocking));
-      TK_HIP(t, hipEventCreateWithFlags(&lane->gev[b], hipEventDisableTiming));
+    const int sl = gr.slot;
+    if (!lane->gstream[sl]) {
+      TK_HIP(t, hipStreamCreateWithFlags(&lane->gstream[sl], hipStreamNonBlocking));
+      TK_HIP(t, hipEventCreateWithFlags(&lane->gev[sl], hipEventDisableTiming));
     }
-    TK_HIP(t, hipStreamWaitEvent(lane->gstream[b], lane->fork_ev, 0));
-    st = launch_group(t, lane, gr, base, lane->gstream[b]);
+    if (!used[sl]) TK_HIP(t, hipStreamWaitEvent(lane->gstream[sl], lane->fork_ev, 0));
+    used[sl] = true;
+    st = launch_group(t, lane, gr, base, lane->gstream[sl]);
     if (st) return st;
-    TK_HIP(t, hipEventRecord(lane->gev[b], lane->gstream[b]));
-    TK_HIP(t, hipStreamWaitEvent(lane->stream, lane->gev[b], 0));
+  }
+  // join only after every group is queued (a join between launches would
+  // hold back the groups queued behind it)
+  for (int sl = 0; sl < kForkStreams; ++sl) {
+    if (!used[sl]) continue;
+    TK_HIP(t, hipEventRecord(lane->gev[sl], lane->gstream[sl]));
+    TK_HIP(t, hipStreamWaitEvent(lane->stream, lane->gev[sl], 0));
   }
   return TK_OK;
 }
@@ -707,8 +719,9 @@ tk_status tk_last_query_profile(const tk_tree* t, int32_t i, double* phase_us) {
   if (!t || !phase_us || i < 0) return TK_EINVAL;
   const int64_t n = int64_t(t->last_stats.size()) / tk::STAT_COUNT;
   if (i >= n) return TK_EINVAL;
-  for (int k = 0; k < tk::STAT_NPHASE + 4; ++k)
-    phase_us[k] = t->last_stats[size_t(i) * tk::STAT_COUNT + tk::STAT_PHASE + k];
+  for (int k = 0; k < tk::STAT_NPHASE + 6; ++k)
+    phase_us[k] = t->last_stats[size_t(i) * tk::STAT_COUNT + tk::STAT_PHASE + k] *
+                  (k >= tk::STAT_NPHASE + 4 ? 0.01 : 1.0);
   return TK_OK;
 }
 
@@ -726,6 +739,7 @@ tk_status tk_get_tuning(const tk_tree* t, tk_tuning* out) {
   out->wide_threads = t->tuning.wide_threads;
   out->persistent = t->tuning.persistent;
   out->graph = t->tuning.graph;
+  out->coarse = t->tuning.coarse;
   return TK_OK;
 }
 
@@ -737,10 +751,12 @@ tk_status tk_set_tuning(tk_tree* t, const tk_tuning* in) {
   if (in->wide_threads != 128 && in->wide_threads != 256) return fail(t, TK_EINVAL, "wide_threads must be 128 or 256");
   if (in->persistent != 0 && in->persistent != 1) return fail(t, TK_EINVAL, "persistent must be 0 or 1");
   if (in->graph != 0 && in->graph != 1) return fail(t, TK_EINVAL, "graph must be 0 or 1");
+  if (in->coarse != 0 && in->coarse != 1) return fail(t, TK_EINVAL, "coarse must be 0 or 1");
   t->tuning.wide_threshold = in->wide_threshold;
   t->tuning.wide_threads = in->wide_threads;
   t->tuning.persistent = in->persistent;
   t->tuning.graph = in->graph;
+  t->tuning.coarse = in->coarse;
   return TK_OK;
 }
 

@@ -209,11 +209,12 @@ struct LeafJob {
 // not reproduce the planned hit set, 2 when the workspace plan was too small
 // (the job then did nothing); STAT_PHASE.. hold device time per phase in microseconds
 // (trims, bases, init, temporal TTM+Gram, temporal eigen, other TTM+Gram,
-// other eigens, finalize); STAT_EIG.. hold eigensolver calls, Jacobi sweeps,
+// other eigens, finalize); STAT_T0/STAT_T1 the job's start and end on the
+// device's 100 MHz clock; STAT_EIG.. hold eigensolver calls, bisection steps,
 // and microseconds in the rotation loop and in the extraction.
 enum {
   STAT_FIT = 0, STAT_ERR = 1, STAT_NORM = 2, STAT_SWEEPS = 3, STAT_CONV = 4, STAT_HITS = 5, STAT_STATUS = 6,
-  STAT_PHASE = 8, STAT_NPHASE = 8, STAT_EIG = 16, STAT_COUNT = 20
+  STAT_PHASE = 8, STAT_NPHASE = 8, STAT_EIG = 16, STAT_T0 = 20, STAT_T1 = 21, STAT_COUNT = 24
 };
 
 // ---------------------------------------------------------------------------
@@ -240,7 +241,7 @@ struct StitchLayout {
   int64_t S;                  // double 32 x 32 (mode Gram of one core)
   int64_t G;                  // float prod(rq)
   int64_t G64;                // double prod(rq)
-  int64_t TMP;                // double neig^2 (eigensolver / Cholesky scratch)
+  int64_t TMP;                // double eig_tmp_doubles(neig) (eigensolver / Cholesky scratch)
   int64_t EIG;                // double eig_doubles(neig) (only when neig > n_lds)
   int64_t total;
   int32_t sr[MAXP];           // sum over hits of r_i^(n)
@@ -264,8 +265,15 @@ TK_HD int gram_rows_split(int ntiles, int nthreads) {
 }
 
 // Doubles needed by the eigensolver for an n x n problem: the matrix, then
-// column norms, Gram-Schmidt coefficients and eigenvalues.
-TK_HD int64_t eig_doubles(int64_t n) { return n * n + 3 * n; }
+// eight vectors of n (tridiagonal, reflector coefficients, eigenvalues,
+// work vectors, brackets) and 256 doubles of per-thread partial results.
+TK_HD int64_t eig_doubles(int64_t n) { return n * n + 8 * n + 256; }
+
+// Scratch of the eigensolver besides its buffer (inverse-iteration LU
+// factors and, when they do not fit in the matrix buffer, vectors: 4 n k
+// doubles for k <= 32 wanted eigenvectors), also used as n x n scratch by
+// the Cholesky steps.
+TK_HD int64_t eig_tmp_doubles(int64_t n) { return n * (n > 4 * 32 ? n : 4 * 32); }
 
 // The layout record itself occupies the head of the job's workspace.
 TK_HD void stitch_layout(const StoreView& st, const Hit* hits, int s, const int32_t* rq,
@@ -353,7 +361,7 @@ TK_HD void stitch_layout(const StoreView& st, const Hit* hits, int s, const int3
   Lo->G = take(gel * 4);
   Lo->G64 = take(gel * 8);
   Lo->neig = neig;
-  Lo->TMP = take(int64_t(neig) * neig * 8);
+  Lo->TMP = take(eig_tmp_doubles(neig) * 8);
   Lo->EIG = neig > n_lds ? take(eig_doubles(neig) * 8) : -1;
   Lo->total = off;
 }
@@ -365,7 +373,7 @@ struct LeafLayout {
   int64_t T1, T2;    // float, size of the raw block
   int64_t V;         // double N x rq (other-side route)
   int64_t G;         // float prod(rq)
-  int64_t TMP;       // double neig^2 (eigensolver scratch)
+  int64_t TMP;       // double eig_tmp_doubles(neig) (eigensolver scratch)
   int64_t EIG;       // double eig_doubles(neig) when neig > n_lds
   int64_t total;
   int32_t neig;
@@ -409,7 +417,7 @@ TK_HD void leaf_layout(const StoreView& st, int n_lds, LeafLayout* Lo) {
   for (int n = 0; n < p; ++n) gel *= rq[n];
   Lo->G = take(gel * 4);
   Lo->neig = neig;
-  Lo->TMP = take(int64_t(neig) * neig * 8);
+  Lo->TMP = take(eig_tmp_doubles(neig) * 8);
   Lo->EIG = neig > n_lds ? take(eig_doubles(neig) * 8) : -1;
   Lo->total = off;
 }

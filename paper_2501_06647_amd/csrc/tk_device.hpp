@@ -73,6 +73,14 @@ __device__ __forceinline__ double fast_rcp(double x) {
   return y;
 }
 
+// 1/x for finite nonzero x of either sign.
+__device__ __forceinline__ double fast_rcp_signed(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+
 __device__ __forceinline__ double fast_rsqrt(double x) {
   double y = __builtin_amdgcn_rsq(x);
   const double hx = 0.5 * x;
@@ -468,8 +476,8 @@ struct EigCounters {
 // W must hold eig_doubles(n) doubles (the scratch follows the matrix; the
 // eigenvalues stay valid until W is reused); tmp: n x n doubles.  When k > n
 // only n eigenpairs exist and the extra columns of E are zero.
-__device__ __forceinline__ const double* eig_top(double* W, int n, int k, double* E, int lde, double* red, double* Ef,
-                                 double* tmp, bool warm, EigCounters* cnt) {
+__device__ __forceinline__ const double* eig_top_jacobi(double* W, int n, int k, double* E, int lde, double* red,
+                                                        double* Ef, double* tmp, bool warm, EigCounters* cnt) {
   __shared__ int s_flag;
   const uint64_t t_start = wall_clock64();
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -653,6 +661,347 @@ __device__ __forceinline__ const double* eig_top(double* W, int n, int k, double
     cnt->tail_ticks += wall_clock64() - t_jac;
   }
   return lam;
+}
+
+
+// Leading eigenpairs of a symmetric n x n matrix S through the tridiagonal
+// route (Golub & Van Loan, Secs. 8.3-8.4; the scheme of LAPACK's
+// dsytrd/dstebz/dstein/dormtr):
+//   1. Householder tridiagonalisation Q^T S Q = T (S in W is overwritten;
+//      reflector i is kept in column i of W below the subdiagonal);
+//   2. the k largest eigenvalues of T by multisection on Sturm counts (the
+//      LDL^T pivots of T - x I), nt / k lanes per eigenvalue;
+//   3. their eigenvectors by inverse iteration on T (tridiagonal LU with
+//      partial pivoting, recomputed with the forward pass of each of three
+//      solves, one lane per vector); vectors whose eigenvalues lie within
+//      1e-9 |T| of each other are re-orthogonalised after every solve;
+//   4. back-transformation by the reflectors, Rayleigh quotients for the
+//      eigenvalues, and a final orthonormality check (CGS2 if needed).
+// The eigenvectors live in W's free upper triangle while k < n / 2 (vector
+// j in rows j and n-2-j), else in tmp.  Same contract as eig_top_jacobi (E:
+// n x k, row stride lde, descending eigenvalues; returns the k
+// eigenvalues), without warm starts.  W must hold eig_doubles(n) doubles;
+// tmp: 4 n k doubles.
+__device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, double* E, int lde, double* red,
+                                                     double* tmp, EigCounters* cnt) {
+  __shared__ int s_flag;
+  __shared__ int s_busy;
+  const uint64_t t_start = wall_clock64();
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* d = W + int64_t(n) * n;
+  double* e = d + n;
+  double* tau = e + n;
+  double* lam = tau + n;
+  double* vv = lam + n;         // reflector of the current step, then e^2
+  double* pw = vv + n;          // p, then w, of the current step
+  double* iv = pw + n;          // bisection brackets, two per eigenvalue
+  double* part = iv + 2 * n;    // nt doubles of partial results
+  if (n <= 0) return lam;
+  const int kk = k < n ? k : n;
+
+  // ---- 1. tridiagonalisation ---------------------------------------------------
+  for (int i = 0; i + 2 < n; ++i) {
+    const int m = n - i - 1;
+    const double* Wi = W + int64_t(i) * n;  // row i = column i (symmetric)
+    double s2 = 0.0;
+    for (int c = i + 2 + tid; c < n; c += nt) s2 += Wi[c] * Wi[c];
+    s2 = block_sum(s2, red);
+    const double alpha = Wi[i + 1];
+    double beta = alpha, t = 0.0, scale = 0.0;
+    if (s2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + s2), alpha);
+      t = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    for (int c = i + 1 + tid; c < n; c += nt) vv[c] = c == i + 1 ? 1.0 : Wi[c] * scale;
+    __syncthreads();
+    for (int c = i + 2 + tid; c < n; c += nt) W[int64_t(c) * n + i] = vv[c];  // reflector -> column i
+    if (tid == 0) {
+      d[i] = Wi[i];
+      e[i] = beta;
+      tau[i] = t;
+    }
+    if (t == 0.0) {
+      __syncthreads();
+      continue;
+    }
+    // p = t A u on the trailing block A = W[i+1:, i+1:] (symmetric: read by columns)
+    const int nsplit = nt >= 2 * m ? nt / m : 1;
+    if (nsplit == 1) {
+      for (int r = i + 1 + tid; r < n; r += nt) {
+        double acc = 0.0;
+        for (int c = i + 1; c < n; ++c) acc += W[int64_t(c) * n + r] * vv[c];
+        pw[r] = t * acc;
+      }
+    } else {
+      const int r = tid % m, sp = tid / m;
+      if (sp < nsplit) {
+        double acc = 0.0;
+        for (int c = i + 1 + sp; c < n; c += nsplit) acc += W[int64_t(c) * n + i + 1 + r] * vv[c];
+        part[sp * m + r] = acc;
+      }
+      __syncthreads();
+      for (int rr = tid; rr < m; rr += nt) {
+        double acc = 0.0;
+        for (int q = 0; q < nsplit; ++q) acc += part[q * m + rr];
+        pw[i + 1 + rr] = t * acc;
+      }
+    }
+    __syncthreads();
+    double kd = 0.0;
+    for (int r = i + 1 + tid; r < n; r += nt) kd += pw[r] * vv[r];
+    const double K = 0.5 * t * block_sum(kd, red);
+    __syncthreads();
+    for (int r = i + 1 + tid; r < n; r += nt) pw[r] -= K * vv[r];
+    __syncthreads();
+    for (int x = tid; x < m * m; x += nt) {
+      const int r = i + 1 + x / m, c = i + 1 + x % m;
+      W[int64_t(r) * n + c] -= vv[r] * pw[c] + pw[r] * vv[c];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (n >= 2) {
+      d[n - 2] = W[int64_t(n - 2) * n + n - 2];
+      e[n - 2] = W[int64_t(n - 2) * n + n - 1];
+      tau[n - 2] = 0.0;
+    }
+    d[n - 1] = W[int64_t(n - 1) * n + n - 1];
+    e[n - 1] = 0.0;
+    tau[n - 1] = 0.0;
+  }
+  __syncthreads();
+
+  // ---- 2. eigenvalues: multisection on Sturm counts -------------------------------
+  double gmax = 0.0;
+  for (int i = tid; i < n; i += nt)
+    gmax = fmax(gmax, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + fabs(e[i]));
+  {
+    int dummy = 0;
+    block_argmax(gmax, dummy, red, reinterpret_cast<int*>(part));
+  }
+  __syncthreads();
+  if (!(gmax > 0.0)) {  // T = 0: any orthonormal basis
+    for (int64_t x = tid; x < int64_t(n) * k; x += nt) {
+      const int r = int(x / k), j = int(x % k);
+      E[int64_t(r) * lde + j] = (j < kk && r == j) ? 1.0 : 0.0;
+    }
+    for (int j = tid; j < kk; j += nt) lam[j] = 0.0;
+    __syncthreads();
+    return lam;
+  }
+  const double ginv = 1.0 / gmax;
+  for (int i = tid; i < n; i += nt) {
+    d[i] *= ginv;
+    e[i] *= ginv;
+    vv[i] = e[i] * e[i];
+  }
+  const double pivmin = 1e-250;
+  const int g = nt / kk;  // lanes per eigenvalue
+  for (int j = tid; j < kk; j += nt) {
+    iv[2 * j] = -1.0 - 1e-12;
+    iv[2 * j + 1] = 1.0 + 1e-12;
+  }
+  __syncthreads();
+  int iters = 0;
+  for (; iters < 80; ++iters) {
+    const int j = tid / g, tg = tid % g;
+    int cntv = 0;
+    if (j < kk) {
+      const double a = iv[2 * j], b = iv[2 * j + 1];
+      const double x = a + (b - a) * double(tg + 1) / double(g + 1);
+      double q = d[0] - x;
+      if (fabs(q) < pivmin) q = -pivmin;
+      cntv = q < 0.0 ? 1 : 0;
+      for (int r = 1; r < n; ++r) {
+        double y = __builtin_amdgcn_rcp(q);
+        y = fma(y, fma(-q, y, 1.0), y);
+        q = (d[r] - x) - vv[r - 1] * y;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cntv += q < 0.0 ? 1 : 0;
+      }
+    }
+    part[tid] = double(cntv);
+    __syncthreads();
+    int open = 0;
+    if (j < kk && tg == 0) {
+      const int idx = n - 1 - j;  // ascending index of the eigenvalue
+      const double a = iv[2 * j], b = iv[2 * j + 1];
+      double na = a, nb = b;
+      for (int u = 0; u < g; ++u) {
+        const double xu = a + (b - a) * double(u + 1) / double(g + 1);
+        if (int(part[j * g + u]) <= idx) na = xu;
+        else if (nb == b) nb = xu;
+      }
+      iv[2 * j] = na;
+      iv[2 * j + 1] = nb;
+      open = (nb - na) > 1e-13 * fmax(1.0, fabs(na) + fabs(nb)) ? 1 : 0;
+    }
+    if (!__syncthreads_or(open)) break;
+  }
+  const uint64_t t_bis = wall_clock64();
+
+  // ---- 3. inverse iteration on T ------------------------------------------------------
+  // vector j, entry r: in W's upper triangle (rows j and n-2-j) or in tmp
+  const bool in_w = 2 * kk < n;
+  auto X = [&](int j, int r) -> double& {
+    if (in_w) return r < n - 1 - j ? W[int64_t(j) * n + j + 1 + r] : W[int64_t(n - 2 - j) * n + r];
+    return tmp[int64_t(3) * n * kk + int64_t(r) * kk + j];
+  };
+  double* U1 = tmp;                    // pivot rows of the LU factors (n x kk each)
+  double* U2 = U1 + int64_t(n) * kk;
+  double* U3 = U2 + int64_t(n) * kk;
+  const double ptiny = 1e-15;  // pivot floor of the scaled problem
+  int* clus = reinterpret_cast<int*>(part);  // cluster start of each eigenvalue, and its position
+  if (tid == 0) {
+    int maxpos = 0, start = 0;
+    for (int j = 0; j < kk; ++j) {
+      const double xj = 0.5 * (iv[2 * j] + iv[2 * j + 1]);
+      if (j > 0 && fabs(0.5 * (iv[2 * j - 2] + iv[2 * j - 1]) - xj) > 1e-9) start = j;
+      clus[2 * j] = start;
+      clus[2 * j + 1] = j - start;
+      if (j - start > maxpos) maxpos = j - start;
+    }
+    s_busy = maxpos;
+  }
+  if (tid < kk) {  // start vector: a fixed pseudo-random pattern per eigenvalue
+    for (int r = 0; r < n; ++r) {
+      const uint32_t h = (uint32_t(r) * 2654435761u) ^ (uint32_t(tid + 1) * 2246822519u);
+      X(tid, r) = 0.5 + double((h >> 8) & 0xFFFF) / 65536.0;
+    }
+  }
+  __syncthreads();
+  const int maxpos = s_busy;
+  for (int it = 0; it < 3; ++it) {
+    if (tid < kk) {
+      const int j = tid;
+      const double sg = 0.5 * (iv[2 * j] + iv[2 * j + 1]);
+      // LU of T - sg I with partial pivoting, applied to the right-hand side
+      // as it is formed; U rows stored for the back substitution
+      double w0 = d[0] - sg, w1 = n > 1 ? e[0] : 0.0;
+      double xr = X(j, 0);
+      for (int r = 0; r + 1 < n; ++r) {
+        const double c = e[r], a1 = d[r + 1] - sg, b1 = r + 2 < n ? e[r + 1] : 0.0;
+        const double xs = X(j, r + 1);
+        const int64_t o = int64_t(r) * kk + j;
+        double nxr;
+        if (fabs(w0) >= fabs(c)) {
+          if (fabs(w0) < ptiny) w0 = w0 < 0.0 ? -ptiny : ptiny;
+          const double l = c / w0;
+          U1[o] = w0;
+          U2[o] = w1;
+          U3[o] = 0.0;
+          X(j, r) = xr;
+          nxr = xs - l * xr;
+          w0 = a1 - l * w1;
+          w1 = b1;
+        } else {
+          const double l = w0 / c;
+          U1[o] = c;
+          U2[o] = a1;
+          U3[o] = b1;
+          X(j, r) = xs;
+          nxr = xr - l * xs;
+          w0 = w1 - l * a1;
+          w1 = -l * b1;
+        }
+        xr = nxr;
+      }
+      if (fabs(w0) < ptiny) w0 = w0 < 0.0 ? -ptiny : ptiny;
+      // back substitution, values carried in registers
+      double x1 = xr / w0, x2 = 0.0;
+      X(j, n - 1) = x1;
+      for (int r = n - 2; r >= 0; --r) {
+        const int64_t o = int64_t(r) * kk + j;
+        const double v = (X(j, r) - U2[o] * x1 - U3[o] * x2) / U1[o];
+        x2 = x1;
+        x1 = v;
+        X(j, r) = v;
+        if (fabs(v) > 1e150) {
+          for (int q = r; q < n; ++q) X(j, q) *= 1e-150;
+          x1 *= 1e-150;
+          x2 *= 1e-150;
+        }
+      }
+      double s = 0.0;
+      for (int r = 0; r < n; ++r) s += X(j, r) * X(j, r);
+      s = 1.0 / sqrt(s);
+      for (int r = 0; r < n; ++r) X(j, r) *= s;
+    }
+    __syncthreads();
+    // vectors of one cluster: modified Gram-Schmidt in cluster order
+    for (int pos = 1; pos <= maxpos; ++pos) {
+      if (tid < kk && clus[2 * tid + 1] == pos) {
+        const int j = tid;
+        for (int j2 = clus[2 * j]; j2 < j; ++j2) {
+          double dt = 0.0;
+          for (int r = 0; r < n; ++r) dt += X(j2, r) * X(j, r);
+          for (int r = 0; r < n; ++r) X(j, r) -= dt * X(j2, r);
+        }
+        double s = 0.0;
+        for (int r = 0; r < n; ++r) s += X(j, r) * X(j, r);
+        s = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+        for (int r = 0; r < n; ++r) X(j, r) *= s;
+      }
+      __syncthreads();
+    }
+  }
+  // Rayleigh quotients y^T T y (scaled back)
+  if (tid < kk) {
+    const int j = tid;
+    double s = 0.0, xm = 0.0, x0 = X(j, 0);
+    for (int r = 0; r < n; ++r) {
+      const double xp = r + 1 < n ? X(j, r + 1) : 0.0;
+      double ty = d[r] * x0 + e[r] * xp;
+      if (r > 0) ty += e[r - 1] * xm;
+      s += x0 * ty;
+      xm = x0;
+      x0 = xp;
+    }
+    lam[j] = s * gmax;
+  }
+  __syncthreads();
+
+  // ---- 4. back-transformation x = H_0 ... H_{n-3} y -------------------------------------
+  const int g2 = nt / kk;
+  for (int i = n - 3; i >= 0; --i) {
+    const double ti = tau[i];
+    if (ti == 0.0) continue;
+    const int j = tid / g2, sp = tid % g2;
+    double acc = 0.0;
+    if (j < kk)
+      for (int r = i + 1 + sp; r < n; r += g2) acc += (r == i + 1 ? 1.0 : W[int64_t(r) * n + i]) * X(j, r);
+    part[tid] = acc;
+    __syncthreads();
+    if (j < kk) {
+      double sj = 0.0;
+      for (int q = 0; q < g2; ++q) sj += part[j * g2 + q];
+      sj *= ti;
+      for (int r = i + 1 + sp; r < n; r += g2) X(j, r) -= sj * (r == i + 1 ? 1.0 : W[int64_t(r) * n + i]);
+    }
+    __syncthreads();
+  }
+  for (int64_t x = tid; x < int64_t(n) * k; x += nt) {
+    const int r = int(x / k), j = int(x % k);
+    E[int64_t(r) * lde + j] = j < kk ? X(j, r) : 0.0;
+  }
+  __syncthreads();
+  orthonormalize(E, n, kk, lde, 1, pw, red, &s_flag);
+  if (cnt && tid == 0) {
+    cnt->calls += 1;
+    cnt->sweeps += uint64_t(iters + 1);
+    cnt->jacobi_ticks += t_bis - t_start;
+    cnt->tail_ticks += wall_clock64() - t_bis;
+  }
+  return lam;
+}
+
+// The eigensolver the kernels use.
+__device__ __forceinline__ const double* eig_top(double* W, int n, int k, double* E, int lde, double* red, double* Ef,
+                                                 double* tmp, bool warm, EigCounters* cnt) {
+  (void)Ef;
+  (void)warm;
+  return eig_top_tri(W, n, k, E, lde, red, tmp, cnt);
 }
 
 }  // namespace tk

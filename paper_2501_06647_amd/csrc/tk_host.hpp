@@ -13,6 +13,10 @@ namespace tk {
 
 constexpr int kMaxRank = 32;
 constexpr int kMaxGroups = 7;                          // LDS bins of a stitch launch
+// Streams a batch's groups are spread over (the process has four hardware
+// queues); groups beyond this many share streams, lighter groups after
+// heavier ones.
+constexpr int kForkStreams = 4;
 constexpr int64_t kMaxJobsPerLaunch = 1 << 16;
 constexpr int64_t kWsChunkBytes = int64_t(4) << 30;    // workspace per launch chunk
 constexpr size_t kLdsBytes = 160 * 1024;               // LDS per CU on gfx950
@@ -28,11 +32,13 @@ struct Tuning {
   int wide_threads = 256;
   int persistent = 0;       // grid sized to residency; workgroups pull jobs from a queue
   int graph = 1;            // prepared batches replay a captured HIP graph
+  int coarse = 0;           // 1: LDS bins {32, wide_threshold, 96} instead of {24, 32, 48, 64, 96, threshold}
 };
 
 // Stitch jobs that run in one launch: same dynamic LDS (n_lds) and block size.
 struct Group {
   int bin = 0;     // index of the LDS bin (stable across calls: selects buffers)
+  int slot = 0;    // fork stream of the group
   int n_lds = 0;
   int threads = 64;
   std::vector<Job> jobs;

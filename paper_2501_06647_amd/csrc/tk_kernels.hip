@@ -584,9 +584,14 @@ __global__ __launch_bounds__(NTT) void stitch_kernel(StitchArgs args) {
       }
       hits = qh;
     }
+    const uint64_t t_begin = wall_clock64();
     stitch_one(st, job, hits, args.ws + job.ws_off, args.n_lds,
                job.kind == 1 ? args.merge_max_iter : args.max_iter, job.kind == 1 ? args.merge_tol : args.tol, sh,
                lds);
+    if (threadIdx.x == 0 && job.stats) {
+      job.stats[STAT_T0] = double(t_begin);
+      job.stats[STAT_T1] = double(wall_clock64());
+    }
     if (!args.queue) break;
   }
 }

@@ -56,7 +56,8 @@ class TkStats(ctypes.Structure):
 
 
 class TkTuning(ctypes.Structure):
-    _fields_ = [("wide_threshold", c_i32), ("wide_threads", c_i32), ("persistent", c_i32), ("graph", c_i32)]
+    _fields_ = [("wide_threshold", c_i32), ("wide_threads", c_i32), ("persistent", c_i32), ("graph", c_i32),
+                ("coarse", c_i32)]
 
 
 class TkServeConfig(ctypes.Structure):
@@ -277,7 +278,7 @@ class PreparedBatch:
         return ms.value
 
     def profile(self, i: int) -> dict:
-        out = (c_dbl * 12)()
+        out = (c_dbl * 14)()
         self.tree._check(lib().tk_batch_profile(self._h, i, out), "tk_batch_profile")
         return dict(zip(Tree.PHASES + Tree.COUNTERS, list(out)))
 
@@ -503,10 +504,10 @@ class Tree:
         return Server(self, **kw)
 
     PHASES = ("trim", "basis", "init", "t_ttm_gram", "t_eig", "n_ttm_gram", "n_eig", "final")
-    COUNTERS = ("eig_calls", "eig_sweeps", "eig_rot_us", "eig_tail_us")
+    COUNTERS = ("eig_calls", "eig_bisect_steps", "eig_values_us", "eig_vectors_us", "start_us", "end_us")
 
     def last_profile(self, i: int) -> dict:
-        out = (c_dbl * 12)()
+        out = (c_dbl * 14)()
         self._check(lib().tk_last_query_profile(self._h, i, out), "tk_last_query_profile")
         return dict(zip(self.PHASES + self.COUNTERS, list(out)))
 

@@ -147,11 +147,61 @@ __device__ __forceinline__ void mode_product_t(const TX* __restrict__ X, int64_t
   __syncthreads();
 }
 
+typedef float tk_f4 __attribute__((ext_vector_type(4)));
+
+// The same product on the matrix cores, FP32 operands and accumulation: a
+// GEMM with M = m outputs, K = r, and N = a b fibers f = (x, y).  Each
+// wavefront takes 16 x 16 output tiles (16 outputs of 16 fibers) and runs
+// v_mfma_f32_16x16x4f32 over K in steps of 4: lane l supplies A(16 I + l %
+// 16, 4 c + l / 16) and X at fiber 16 J + l % 16, index 4 c + l / 16, and
+// holds Y rows 16 I + 4 (l / 16) + v of fiber 16 J + l % 16.  Y must not
+// overlap X; with acc the tile is added to Y.
+__device__ __forceinline__ void mode_product_mfma(const float* __restrict__ X, int64_t a, int r, int64_t b,
+                                                  const float* __restrict__ A, int64_t as, int64_t bs, int m,
+                                                  float* __restrict__ Y, bool acc) {
+  const int nw = int(blockDim.x) >> 6, w = int(threadIdx.x) >> 6, l = int(threadIdx.x) & 63;
+  const int lr = l & 15, lk = l >> 4;
+  const int64_t F = a * b;
+  const int mt = (m + 15) >> 4;
+  const int64_t ntiles = int64_t(mt) * ((F + 15) >> 4);
+  for (int64_t t = w; t < ntiles; t += nw) {
+    const int I = int(t % mt);
+    const int64_t f = (t / mt) * 16 + lr;
+    // out-of-range rows, fibers and indices read a valid element, masked to 0
+    const float fm = f < F ? 1.f : 0.f;
+    const int64_t fc = f < F ? f : F - 1;
+    const int64_t x = fc / b, y = fc % b;
+    const int ia = I * 16 + lr;
+    const float im = ia < m ? 1.f : 0.f;
+    const int64_t ic = ia < m ? ia : m - 1;
+    tk_f4 c = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < r; k0 += 4) {
+      const int j = k0 + lk;
+      const float jm = j < r ? 1.f : 0.f;
+      const int64_t jc = j < r ? j : r - 1;
+      const float av = A[ic * as + jc * bs] * (im * jm);
+      const float bv = X[(x * r + jc) * b + y] * (fm * jm);
+      c = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, c, 0, 0, 0);
+    }
+    if (f < F) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = I * 16 + 4 * lk + v;
+        if (i < m) {
+          const int64_t o = (x * m + i) * b + y;
+          Y[o] = acc ? Y[o] + c[v] : c[v];
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // FP32 operands with FP32 accumulation (the contractions of the ALS loop).
 __device__ __forceinline__ void mode_product(const float* __restrict__ X, int64_t a, int r, int64_t b,
                                     const float* __restrict__ A, int64_t as, int64_t bs, int m,
                                     float* __restrict__ Y, bool acc) {
-  mode_product_t<float, float, float, float>(X, a, r, b, A, as, bs, m, Y, acc);
+  mode_product_mfma(X, a, r, b, A, as, bs, m, Y, acc);
 }
 
 // Mode Gram G = mat_n(X) mat_n(X)^T (q x q, written as FP64 with leading
@@ -201,6 +251,65 @@ __device__ __forceinline__ void gram_mode(const float* __restrict__ X, int64_t a
           G[j * ld + i] = double(s[ii][jj]);
         }
       }
+  }
+  __syncthreads();
+}
+
+typedef double tk_d4 __attribute__((ext_vector_type(4)));
+
+// Mode Gram on the matrix cores: G = mat_n(X) mat_n(X)^T (q x q, FP64, leading
+// dimension ld; both triangles written) for X (FP32) viewed as (a, q, b).
+// Each wavefront takes 16 x 16 tiles of the upper triangle and accumulates
+// them with v_mfma_f64_16x16x4f64 over the a b columns, four per step: lane
+// l supplies row 16 I + l % 16 (and 16 J + l % 16) of column 4 c + l / 16,
+// and holds G[16 I + l / 16 + 4 v][16 J + l % 16] for v < 4.  The FP32
+// products are exact in FP64 and the sums are FP64.
+__device__ __forceinline__ void gram_mode_mfma(const float* __restrict__ X, int64_t a, int q, int64_t b,
+                                               double* __restrict__ G, int ld) {
+  const int nw = int(blockDim.x) >> 6, w = int(threadIdx.x) >> 6, l = int(threadIdx.x) & 63;
+  const int nb = (q + 15) >> 4;
+  const int ntiles = nb * (nb + 1) / 2;
+  const int64_t N = a * b;
+  const int lr = l & 15, lk = l >> 4;
+  for (int t = w; t < ntiles; t += nw) {
+    int bi = 0, rem = t;
+    while (rem >= nb - bi) {
+      rem -= nb - bi;
+      ++bi;
+    }
+    const int bj = bi + rem;
+    const int i = bi * 16 + lr, j = bj * 16 + lr;
+    const bool iv = i < q, jv = j < q;
+    const int64_t io = int64_t(i) * b, jo = int64_t(j) * b;
+    tk_d4 acc = {0.0, 0.0, 0.0, 0.0};
+    // this lane's column k = 4 c + lk as (x, y), advanced by 4 per step
+    int64_t x = lk / b, y = lk % b;
+    const int64_t xs = 4 / b, ys = 4 % b;
+#pragma unroll 4
+    for (int64_t k0 = 0; k0 < N; k0 += 4) {
+      double av = 0.0, bv = 0.0;
+      if (k0 + lk < N) {
+        const float* col = X + x * q * b + y;
+        av = iv ? double(col[io]) : 0.0;
+        bv = jv ? double(col[jo]) : 0.0;
+      }
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      x += xs;
+      y += ys;
+      if (y >= b) {
+        y -= b;
+        ++x;
+      }
+    }
+    const int cj = bj * 16 + lr;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ri = bi * 16 + lk + 4 * v;
+      if (ri < q && cj < q) {
+        G[int64_t(ri) * ld + cj] = acc[v];
+        G[int64_t(cj) * ld + ri] = acc[v];
+      }
+    }
   }
   __syncthreads();
 }
@@ -843,10 +952,20 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
 
   // ---- 3. inverse iteration on T ------------------------------------------------------
   // vector j, entry r: in W's upper triangle (rows j and n-2-j) or in tmp
-  const bool in_w = 2 * kk < n;
-  auto X = [&](int j, int r) -> double& {
-    if (in_w) return r < n - 1 - j ? W[int64_t(j) * n + j + 1 + r] : W[int64_t(n - 2 - j) * n + r];
-    return tmp[int64_t(3) * n * kk + int64_t(r) * kk + j];
+  // eigenvector j, entry r: in W's free upper triangle (rows j and n-2-j)
+  // while 2 k < n, else in tmp.  The two placements are separate
+  // instantiations so that every access has one address space.
+  struct XinW {
+    double* W;
+    int n;
+    __device__ __forceinline__ double& operator()(int j, int r) const {
+      return r < n - 1 - j ? W[int64_t(j) * n + j + 1 + r] : W[int64_t(n - 2 - j) * n + r];
+    }
+  };
+  struct XinT {
+    double* T;
+    int kk;
+    __device__ __forceinline__ double& operator()(int j, int r) const { return T[int64_t(r) * kk + j]; }
   };
   double* U1 = tmp;                    // pivot rows of the LU factors (n x kk each)
   double* U2 = U1 + int64_t(n) * kk;
@@ -864,6 +983,7 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
     }
     s_busy = maxpos;
   }
+  auto vectors = [&](auto X) {
   if (tid < kk) {  // start vector: a fixed pseudo-random pattern per eigenvalue
     for (int r = 0; r < n; ++r) {
       const uint32_t h = (uint32_t(r) * 2654435761u) ^ (uint32_t(tid + 1) * 2246822519u);
@@ -987,6 +1107,9 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
   }
   __syncthreads();
   orthonormalize(E, n, kk, lde, 1, pw, red, &s_flag);
+  };
+  if (2 * kk < n) vectors(XinW{W, n});
+  else vectors(XinT{tmp + int64_t(3) * n * kk, kk});
   if (cnt && tid == 0) {
     cnt->calls += 1;
     cnt->sweeps += uint64_t(iters + 1);

@@ -271,7 +271,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
       int32_t dims[MAXP];
       dims[0] = sh.kp[i];
       for (int m = 1; m < p; ++m) dims[m] = st.rk[lev][m];
-      gram_mode<double>(core_of(i), prod_range(dims, 0, n), r, prod_range(dims, n + 1, p), S, r);
+      gram_mode_mfma(core_of(i), prod_range(dims, 0, n), r, prod_range(dims, n + 1, p), S, r);
       const int c0 = sh.roff[n][i];
       for (int e = tid; e < q * r; e += nt) {
         const int dd = e / r, j = e % r;
@@ -326,7 +326,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     }
     const int sk = sh.koff[s];
     with_buf(sk, [&](double* Wm) {
-      gram_mode<double>(M, 1, sk, Rhat[0], Wm, sk);
+      gram_mode_mfma(M, 1, sk, Rhat[0], Wm, sk);
       clk.mark(3);
       eig_top(Wm, sk, rq[0], Dp(lo.Pd[0]), rq[0], red, Dp(lo.EF[0]), TMP, it > 1, &ec);
     });
@@ -372,7 +372,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
                      Fp(lo.C[n]) + sh.roff[n][i], lo.sr[n], 1, q, K, i > 0);
       }
       with_buf(q, [&](double* Wn) {
-        gram_mode<double>(K, ka, q, kb, Wn, q);
+        gram_mode_mfma(K, ka, q, kb, Wn, q);
         clk.mark(5);
         eig_top(Wn, q, rq[n], Dp(lo.Pd[n]), rq[n], red, Dp(lo.EF[n]), TMP, true, &ec);
       });
@@ -565,25 +565,29 @@ __global__ __launch_bounds__(NTT) void stitch_kernel(StitchArgs args) {
     }
     if (jn >= args.n_jobs) break;
     const Job& job = args.jobs[jn];
-    const Hit* hits = args.hits + job.hit0;
-    if (job.kind == 0) {
-      if (threadIdx.x == 0) {
-        const int n = recall(job.ts, job.ts + job.L, job.Tb, st.ell, args.theta_num, args.theta_den, qh, MAXHITS);
-        n_rec = n;
+    // the job's hits go to LDS: a query's from its own Recall (published to
+    // its slots of args.hits), a merge's two children from args.hits
+    if (threadIdx.x == 0) {
+      int n = job.s;
+      if (job.kind == 0) {
+        n = recall(job.ts, job.ts + job.L, job.Tb, st.ell, args.theta_num, args.theta_den, qh, MAXHITS);
         if (n == job.s)
           for (int i = 0; i < n; ++i) args.hits[job.hit0 + i] = qh[i];
+      } else {
+        for (int i = 0; i < n && i < MAXHITS; ++i) qh[i] = args.hits[job.hit0 + i];
       }
-      __syncthreads();
-      if (n_rec != job.s) {
-        if (threadIdx.x == 0 && job.stats) {
-          job.stats[STAT_STATUS] = 1.0;
-          job.stats[STAT_HITS] = double(n_rec);
-        }
-        if (!args.queue) break;
-        continue;
-      }
-      hits = qh;
+      n_rec = n;
     }
+    __syncthreads();
+    if (n_rec != job.s) {
+      if (threadIdx.x == 0 && job.stats) {
+        job.stats[STAT_STATUS] = 1.0;
+        job.stats[STAT_HITS] = double(n_rec);
+      }
+      if (!args.queue) break;
+      continue;
+    }
+    const Hit* hits = qh;
     const uint64_t t_begin = wall_clock64();
     stitch_one(st, job, hits, args.ws + job.ws_off, args.n_lds,
                job.kind == 1 ? args.merge_max_iter : args.max_iter, job.kind == 1 ? args.merge_tol : args.tol, sh,
@@ -622,7 +626,7 @@ __device__ __forceinline__ void leading_left(const float* Y, const int32_t* dims
   double* TMP = reinterpret_cast<double*>(ws + lo.TMP);
   if (D <= N) {
     double* Wm = D <= n_lds ? lds : reinterpret_cast<double*>(ws + lo.EIG);
-    gram_mode<double>(Y, a, D, b, Wm, D);
+    gram_mode_mfma(Y, a, D, b, Wm, D);
     eig_top(Wm, D, r, U, r, sh.red, nullptr, TMP, false, nullptr);
     return;
   }

@@ -163,6 +163,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tuning", default=None, help="JSON tuning to use instead of autotuning")
     ap.add_argument("--serve", action="store_true", help="serving run instead of the batched benchmark")
     ap.add_argument("--qps", type=float, default=2000.0)
     ap.add_argument("--aps", type=float, default=1000.0)
@@ -198,7 +199,9 @@ def main():
     ts, te = synth.queries(wl)
     nq = len(ts)
     tuning, tune_ms = None, None
-    if not args.no_tune:
+    if args.tuning:
+        tree.set_tuning(**json.loads(args.tuning))
+    elif not args.no_tune:
         t0 = time.perf_counter()
         tuning, tune_ms = tree.autotune(ts, te, reps=2)
         print("[bench] autotune: %s (%.3f ms per batch) in %.1f s" % (tuning, tune_ms, time.perf_counter() - t0),

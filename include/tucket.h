@@ -48,9 +48,13 @@ typedef enum {
   TK_EBUSY = 5    /* serving: queue full, or a call that the server excludes  */
 } tk_status;
 
+/* Arithmetic of the stitch's ALS contractions (TTM chains, the mode
+ * unfoldings Z^(n), the core update) and of their Grams, on the matrix
+ * cores.  Eigensolves, orthonormalisation, trims, the final core and the
+ * error norms are FP64 in both modes; stored data and outputs are FP32. */
 typedef enum {
-  TK_F32 = 1,  /* contractions and Grams in FP32                             */
-  TK_BF16 = 2  /* BF16 operands, FP32 accumulation                           */
+  TK_F32 = 1,  /* FP32 operands, FP32 accumulation (Grams: FP64 sums)      */
+  TK_BF16 = 2  /* BF16 operands (round to nearest even), FP32 accumulation */
 } tk_prec;
 
 typedef struct tk_tree tk_tree;
@@ -65,7 +69,7 @@ typedef struct {
   int32_t theta_num, theta_den;   /* pruning threshold theta = num/den       */
   int32_t max_iter;               /* ALS sweep cap (>= 1)                    */
   double tol;                     /* stop when |fit_k - fit_{k-1}| < tol     */
-  int32_t prec;                   /* tk_prec                                 */
+  int32_t prec;                   /* tk_prec of merges and (initially) queries */
   int64_t capacity_T;             /* maximum number of slices                */
   int64_t mem_budget_bytes;       /* device bytes the tree may use; 0 = any  */
 } tk_config;
@@ -170,6 +174,10 @@ tk_status tk_last_query_profile(const tk_tree* t, int32_t i, double* phase_us);
 
 /* Override the ALS sweep cap and tolerance for later queries (not merges). */
 tk_status tk_set_query_iters(tk_tree* t, int32_t max_iter, double tol);
+
+/* Arithmetic (tk_prec) of later queries; merges keep cfg.prec.  Lets one
+ * node store answer the same queries in FP32 and in BF16. */
+tk_status tk_set_query_prec(tk_tree* t, int32_t prec);
 
 tk_status tk_stats_get(const tk_tree* t, tk_stats* out);
 

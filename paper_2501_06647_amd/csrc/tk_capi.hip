@@ -107,6 +107,8 @@ StitchArgs stitch_args(tk_tree* t, int max_iter, double tol) {
   a.tol = tol;
   a.merge_max_iter = t->cfg.max_iter;
   a.merge_tol = t->cfg.tol;
+  a.bf16 = t->q_prec == TK_BF16 ? 1 : 0;
+  a.merge_bf16 = t->cfg.prec == TK_BF16 ? 1 : 0;
   a.theta_num = t->cfg.theta_num;
   a.theta_den = t->cfg.theta_den;
   return a;
@@ -433,7 +435,7 @@ tk_status tk_create(const tk_config* cfg, void* hip_stream, tk_tree** out) {
     return fail(nullptr, TK_EINVAL, "theta must be num/den in (0, 1]");
   if (cfg->max_iter < 1 || cfg->max_iter > 100000) return fail(nullptr, TK_EINVAL, "bad max_iter");
   if (!(cfg->tol >= 0.0) || !std::isfinite(cfg->tol)) return fail(nullptr, TK_EINVAL, "bad tol");
-  if (cfg->prec != TK_F32) return fail(nullptr, TK_EINVAL, "only TK_F32 is available");
+  if (cfg->prec != TK_F32 && cfg->prec != TK_BF16) return fail(nullptr, TK_EINVAL, "prec must be TK_F32 or TK_BF16");
   if (cfg->capacity_T < cfg->leaf_len || cfg->capacity_T > (int64_t(1) << 40))
     return fail(nullptr, TK_EINVAL, "bad capacity_T");
 
@@ -448,6 +450,7 @@ tk_status tk_create(const tk_config* cfg, void* hip_stream, tk_tree** out) {
   t->nlev = tk::root_level(t->cap_blocks) + 1;
   t->q_max_iter = cfg->max_iter;
   t->q_tol = cfg->tol;
+  t->q_prec = cfg->prec;
   StoreView& v = t->view;
   v.p = p;
   v.nlev = t->nlev;
@@ -730,6 +733,13 @@ tk_status tk_set_query_iters(tk_tree* t, int32_t max_iter, double tol) {
   if (t->server) return busy(t);
   t->q_max_iter = max_iter;
   t->q_tol = tol;
+  return TK_OK;
+}
+
+tk_status tk_set_query_prec(tk_tree* t, int32_t prec) {
+  if (!t || (prec != TK_F32 && prec != TK_BF16)) return TK_EINVAL;
+  if (t->server) return busy(t);
+  t->q_prec = prec;
   return TK_OK;
 }
 

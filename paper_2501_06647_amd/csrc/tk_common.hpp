@@ -94,10 +94,12 @@ struct Hit {
 // below the threshold (it has no children).  Hits come out in time order.
 // Returns the number of hits (writes at most cap of them), or -1 if the range
 // is outside [0, Tb ell) or empty.
-TK_HD int recall(int64_t ts, int64_t te, int64_t Tb, int64_t ell, int64_t num, int64_t den,
-                 Hit* out, int cap) {
+constexpr int RECALL_STACK = 2 * MAXLEV + 4;
+
+// sk: RECALL_STACK int64 of scratch (the device passes LDS).
+TK_HD int recall_with_stack(int64_t ts, int64_t te, int64_t Tb, int64_t ell, int64_t num, int64_t den,
+                            Hit* out, int cap, int64_t* sk) {
   if (!(ts >= 0 && ts < te && te <= Tb * ell)) return -1;
-  int64_t sk[2 * MAXLEV + 4];
   int sp = 0;
   const int K = root_level(Tb);
   sk[sp++] = (int64_t(K) << 56) | 0;  // (level << 56) | index
@@ -134,6 +136,11 @@ TK_HD int recall(int64_t ts, int64_t te, int64_t Tb, int64_t ell, int64_t num, i
     }
   }
   return n;
+}
+
+TK_HD int recall(int64_t ts, int64_t te, int64_t Tb, int64_t ell, int64_t num, int64_t den, Hit* out, int cap) {
+  int64_t sk[RECALL_STACK];
+  return recall_with_stack(ts, te, Tb, ell, num, den, out, cap, sk);
 }
 
 // Effective ranks of a len x D_1 x ... x D_{p-1} range: r_0 <= len,

@@ -197,6 +197,57 @@ __device__ __forceinline__ void mode_product_mfma(const float* __restrict__ X, i
   __syncthreads();
 }
 
+typedef __bf16 tk_b8 __attribute__((ext_vector_type(8)));
+
+// The same product with BF16 operands (rounded to nearest even from FP32)
+// and FP32 accumulation, v_mfma_f32_16x16x32_bf16 over K in steps of 32:
+// lane l supplies A(16 I + l % 16, 32 c + 8 (l / 16) + v) and X at fiber
+// 16 J + l % 16, index 32 c + 8 (l / 16) + v, for v < 8; the output layout
+// is that of mode_product_mfma.
+__device__ __forceinline__ void mode_product_bf16(const float* __restrict__ X, int64_t a, int r, int64_t b,
+                                                  const float* __restrict__ A, int64_t as, int64_t bs, int m,
+                                                  float* __restrict__ Y, bool acc) {
+  const int nw = int(blockDim.x) >> 6, w = int(threadIdx.x) >> 6, l = int(threadIdx.x) & 63;
+  const int lr = l & 15, lk = l >> 4;
+  const int64_t F = a * b;
+  const int mt = (m + 15) >> 4;
+  const int64_t ntiles = int64_t(mt) * ((F + 15) >> 4);
+  for (int64_t t = w; t < ntiles; t += nw) {
+    const int I = int(t % mt);
+    const int64_t f = (t / mt) * 16 + lr;
+    const float fm = f < F ? 1.f : 0.f;
+    const int64_t fc = f < F ? f : F - 1;
+    const int64_t x = fc / b, y = fc % b;
+    const int ia = I * 16 + lr;
+    const float im = ia < m ? 1.f : 0.f;
+    const int64_t ic = ia < m ? ia : m - 1;
+    tk_f4 c = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < r; k0 += 32) {
+      tk_b8 av, bv;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int j = k0 + 8 * lk + v;
+        const float jm = j < r ? 1.f : 0.f;
+        const int64_t jc = j < r ? j : r - 1;
+        av[v] = (__bf16)(A[ic * as + jc * bs] * (im * jm));
+        bv[v] = (__bf16)(X[(x * r + jc) * b + y] * (fm * jm));
+      }
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+    }
+    if (f < F) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = I * 16 + 4 * lk + v;
+        if (i < m) {
+          const int64_t o = (x * m + i) * b + y;
+          Y[o] = acc ? Y[o] + c[v] : c[v];
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // FP32 operands with FP32 accumulation (the contractions of the ALS loop).
 __device__ __forceinline__ void mode_product(const float* __restrict__ X, int64_t a, int r, int64_t b,
                                     const float* __restrict__ A, int64_t as, int64_t bs, int m,
@@ -308,6 +359,67 @@ __device__ __forceinline__ void gram_mode_mfma(const float* __restrict__ X, int6
       if (ri < q && cj < q) {
         G[int64_t(ri) * ld + cj] = acc[v];
         G[int64_t(cj) * ld + ri] = acc[v];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Mode Gram with BF16 operands and FP32 accumulation
+// (v_mfma_f32_16x16x32_bf16, 32 columns per step; lane l supplies rows
+// 16 I + l % 16 and 16 J + l % 16 of columns 32 c + 8 (l / 16) + v), stored
+// as FP64 like gram_mode_mfma.
+__device__ __forceinline__ void gram_mode_bf16(const float* __restrict__ X, int64_t a, int q, int64_t b,
+                                               double* __restrict__ G, int ld) {
+  const int nw = int(blockDim.x) >> 6, w = int(threadIdx.x) >> 6, l = int(threadIdx.x) & 63;
+  const int nb = (q + 15) >> 4;
+  const int ntiles = nb * (nb + 1) / 2;
+  const int64_t N = a * b;
+  const int lr = l & 15, lk = l >> 4;
+  for (int t = w; t < ntiles; t += nw) {
+    int bi = 0, rem = t;
+    while (rem >= nb - bi) {
+      rem -= nb - bi;
+      ++bi;
+    }
+    const int bj = bi + rem;
+    const int i = bi * 16 + lr, j = bj * 16 + lr;
+    const float imk = i < q ? 1.f : 0.f, jmk = j < q ? 1.f : 0.f;
+    const int64_t io = int64_t(i < q ? i : q - 1) * b, jo = int64_t(j < q ? j : q - 1) * b;
+    tk_f4 acc = {0.f, 0.f, 0.f, 0.f};
+    // this lane's first column 32 c + 8 lk as (x, y), advanced by 32 per step
+    int64_t x = (8 * lk) / b, y = (8 * lk) % b;
+    const int64_t xs = 32 / b, ys = 32 % b;
+    for (int64_t k0 = 0; k0 < N; k0 += 32) {
+      tk_b8 av, bv;
+      int64_t xv = x, yv = y;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const bool kin = k0 + 8 * lk + v < N;
+        const float* col = X + (kin ? xv * q * b + yv : 0);
+        const float km = kin ? 1.f : 0.f;
+        av[v] = (__bf16)(col[io] * (imk * km));
+        bv[v] = (__bf16)(col[jo] * (jmk * km));
+        if (++yv == b) {
+          yv = 0;
+          ++xv;
+        }
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+      x += xs;
+      y += ys;
+      if (y >= b) {
+        y -= b;
+        ++x;
+      }
+    }
+    const int cj = bj * 16 + lr;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ri = bi * 16 + 4 * lk + v;
+      if (ri < q && cj < q) {
+        G[int64_t(ri) * ld + cj] = double(acc[v]);
+        G[int64_t(cj) * ld + ri] = double(acc[v]);
       }
     }
   }
@@ -559,8 +671,8 @@ __device__ __forceinline__ void pchol_basis(const double* L, const int* piv, int
 // Symmetric eigenproblems
 // ---------------------------------------------------------------------------
 
-struct EigCounters {
-  uint64_t calls = 0, sweeps = 0, jacobi_ticks = 0, tail_ticks = 0;
+struct EigCounters {  // zeroed by the owner (it may live in LDS)
+  uint64_t calls, sweeps, jacobi_ticks, tail_ticks;
 };
 
 // Leading eigenpairs of a symmetric positive semi-definite n x n matrix S by

@@ -93,6 +93,7 @@ struct tk_tree {
   tk::Lane main;  // the tree's stream: synchronous calls
   int q_max_iter = 20;
   double q_tol = 0.01;
+  int q_prec = TK_F32;  // arithmetic of query stitches (merges follow cfg.prec)
   int64_t lds_limit = 65536;  // dynamic + static LDS a workgroup may use
   tk::Tuning tuning;
   bool poisoned = false;

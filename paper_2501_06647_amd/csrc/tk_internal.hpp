@@ -20,6 +20,8 @@ struct StitchArgs {
   double tol;
   int merge_max_iter;  // merge jobs (node construction)
   double merge_tol;
+  int bf16;            // query jobs: BF16 operands in the ALS contractions
+  int merge_bf16;      // merge jobs: the same
   int64_t theta_num, theta_den;
 };
 

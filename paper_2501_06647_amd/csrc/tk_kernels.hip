@@ -41,12 +41,16 @@ __device__ __forceinline__ int64_t prod_range(const int32_t* d, int lo, int hi) 
   return r;
 }
 
-// Phase timer: thread 0 accumulates the 100 MHz wall clock between marks.
+// Phase timer: thread 0 accumulates the 100 MHz wall clock between marks
+// (state in LDS, so it costs no registers over the kernel's lifetime).
 struct PhaseClock {
-  uint64_t last = 0;
-  uint64_t acc[STAT_NPHASE] = {0, 0, 0, 0, 0, 0, 0, 0};
+  uint64_t last;
+  uint64_t acc[STAT_NPHASE];
   __device__ __forceinline__ void start() {
-    if (threadIdx.x == 0) last = wall_clock64();
+    if (threadIdx.x == 0) {
+      last = wall_clock64();
+      for (int i = 0; i < STAT_NPHASE; ++i) acc[i] = 0;
+    }
   }
   __device__ __forceinline__ void mark(int ph) {
     if (threadIdx.x == 0) {
@@ -62,6 +66,9 @@ struct PhaseClock {
 };
 
 struct StitchShared {
+  PhaseClock clk;
+  EigCounters ec;
+  int64_t recall_stack[RECALL_STACK];
   int32_t kp[MAXHITS];              // temporal rank of each piece after its trim
   int32_t koff[MAXHITS + 1];        // offsets of the pieces in the stacked temporal coordinates
   int32_t roff[MAXP][MAXHITS + 1];  // offsets of the pieces' columns in C^(n)
@@ -72,7 +79,7 @@ struct StitchShared {
 };
 
 __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, const Hit* hits, char* ws, int n_lds,
-                           int max_iter, double tol, StitchShared& sh, double* lds) {
+                           int max_iter, double tol, bool lowp, StitchShared& sh, double* lds) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int p = st.p;
   const int s = job.s;
@@ -99,8 +106,9 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     return;
   }
 
-  PhaseClock clk;
-  EigCounters ec;
+  PhaseClock& clk = sh.clk;
+  EigCounters& ec = sh.ec;
+  if (tid == 0) ec.calls = ec.sweeps = ec.jacobi_ticks = ec.tail_ticks = 0;
   clk.start();
   // the layout record lives at the head of the workspace
   StitchLayout* lop = reinterpret_cast<StitchLayout*>(ws);
@@ -113,6 +121,17 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     return;
   }
   double* red = sh.red;
+  // the ALS contractions (TTM chains, Z^(n), core update) and their Grams:
+  // FP32 on the matrix cores, or BF16 operands with FP32 accumulation
+  auto ttm = [&](const float* X, int64_t a, int r, int64_t b, const float* A, int64_t as, int64_t bs, int m,
+                 float* Y, bool acc) {
+    if (lowp) mode_product_bf16(X, a, r, b, A, as, bs, m, Y, acc);
+    else mode_product(X, a, r, b, A, as, bs, m, Y, acc);
+  };
+  auto gram = [&](const float* X, int64_t a, int q, int64_t b, double* G, int ld) {
+    if (lowp) gram_mode_bf16(X, a, q, b, G, ld);
+    else gram_mode_mfma(X, a, q, b, G, ld);
+  };
   auto Fp = [&](int64_t off) { return reinterpret_cast<float*>(ws + off); };
   auto Dp = [&](int64_t off) { return reinterpret_cast<double*>(ws + off); };
   double* TMP = Dp(lo.TMP);
@@ -318,15 +337,15 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
       const float* cur = core_of(i);
       for (int n = 1; n < p; ++n) {
         float* out = (n == p - 1) ? M + int64_t(sh.koff[i]) * Rhat[0] : ((n & 1) ? T1 : T2);
-        mode_product(cur, prod_range(dims, 0, n), dims[n], prod_range(dims, n + 1, p),
-                     Fp(lo.A[i]) + A_off(i, n), dims[n], 1, rq[n], out, false);
+        ttm(cur, prod_range(dims, 0, n), dims[n], prod_range(dims, n + 1, p),
+            Fp(lo.A[i]) + A_off(i, n), dims[n], 1, rq[n], out, false);
         dims[n] = rq[n];
         cur = out;
       }
     }
     const int sk = sh.koff[s];
     with_buf(sk, [&](double* Wm) {
-      gram_mode_mfma(M, 1, sk, Rhat[0], Wm, sk);
+      gram(M, 1, sk, Rhat[0], Wm, sk);
       clk.mark(3);
       eig_top(Wm, sk, rq[0], Dp(lo.Pd[0]), rq[0], red, Dp(lo.EF[0]), TMP, it > 1, &ec);
     });
@@ -354,25 +373,25 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
         float* bufs[2] = {T1, T2};
         int nb = 0;
         // x_1 P_i^T : A(c, j) = P0[(koff_i + j) rq_0 + c]
-        mode_product(cur, 1, dims[0], prod_range(dims, 1, p), P0f + int64_t(sh.koff[i]) * rq[0], 1, rq[0],
+        ttm(cur, 1, dims[0], prod_range(dims, 1, p), P0f + int64_t(sh.koff[i]) * rq[0], 1, rq[0],
                      rq[0], bufs[nb], false);
         dims[0] = rq[0];
         cur = bufs[nb];
         nb ^= 1;
         for (int m = 1; m < p; ++m) {
           if (m == n) continue;
-          mode_product(cur, prod_range(dims, 0, m), dims[m], prod_range(dims, m + 1, p),
+          ttm(cur, prod_range(dims, 0, m), dims[m], prod_range(dims, m + 1, p),
                        Fp(lo.A[i]) + A_off(i, m), dims[m], 1, rq[m], bufs[nb], false);
           dims[m] = rq[m];
           cur = bufs[nb];
           nb ^= 1;
         }
         // x_n C_i accumulated into K_n
-        mode_product(cur, prod_range(dims, 0, n), dims[n], prod_range(dims, n + 1, p),
-                     Fp(lo.C[n]) + sh.roff[n][i], lo.sr[n], 1, q, K, i > 0);
+        ttm(cur, prod_range(dims, 0, n), dims[n], prod_range(dims, n + 1, p),
+            Fp(lo.C[n]) + sh.roff[n][i], lo.sr[n], 1, q, K, i > 0);
       }
       with_buf(q, [&](double* Wn) {
-        gram_mode_mfma(K, ka, q, kb, Wn, q);
+        gram(K, ka, q, kb, Wn, q);
         clk.mark(5);
         eig_top(Wn, q, rq[n], Dp(lo.Pd[n]), rq[n], red, Dp(lo.EF[n]), TMP, true, &ec);
       });
@@ -382,7 +401,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     // core update: G = Z^(p) x_p U^(p)T, here K_p x_p P_p^T
     {
       const int q = sh.q[p - 1];
-      mode_product(K, prod_range(rq, 0, p - 1), q, 1, Fp(lo.Pf[p - 1]), 1, rq[p - 1], rq[p - 1], G, false);
+      ttm(K, prod_range(rq, 0, p - 1), q, 1, Fp(lo.Pf[p - 1]), 1, rq[p - 1], rq[p - 1], G, false);
       const int64_t gel = prod_range(rq, 0, p);
       double part = 0.0;
       for (int64_t e = tid; e < gel; e += nt) part += double(G[e]) * double(G[e]);
@@ -547,8 +566,10 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
 // With args.queue set the launch is persistent: each workgroup takes jobs
 // from the queue counter (heaviest first, as the host sorted them) until it
 // runs past n_jobs, so every workgroup reaches the exit.
+// Register budget: at most 256 VGPRs, so that two wavefronts share a SIMD
+// (one job's latency hides behind another's).
 template <int NTT>
-__global__ __launch_bounds__(NTT) void stitch_kernel(StitchArgs args) {
+__global__ __launch_bounds__(NTT, 2) void stitch_kernel(StitchArgs args) {
   extern __shared__ double lds[];
   __shared__ StitchShared sh;
   __shared__ Hit qh[MAXHITS];
@@ -570,7 +591,8 @@ __global__ __launch_bounds__(NTT) void stitch_kernel(StitchArgs args) {
     if (threadIdx.x == 0) {
       int n = job.s;
       if (job.kind == 0) {
-        n = recall(job.ts, job.ts + job.L, job.Tb, st.ell, args.theta_num, args.theta_den, qh, MAXHITS);
+        n = recall_with_stack(job.ts, job.ts + job.L, job.Tb, st.ell, args.theta_num, args.theta_den, qh, MAXHITS,
+                              sh.recall_stack);
         if (n == job.s)
           for (int i = 0; i < n; ++i) args.hits[job.hit0 + i] = qh[i];
       } else {
@@ -590,8 +612,8 @@ __global__ __launch_bounds__(NTT) void stitch_kernel(StitchArgs args) {
     const Hit* hits = qh;
     const uint64_t t_begin = wall_clock64();
     stitch_one(st, job, hits, args.ws + job.ws_off, args.n_lds,
-               job.kind == 1 ? args.merge_max_iter : args.max_iter, job.kind == 1 ? args.merge_tol : args.tol, sh,
-               lds);
+               job.kind == 1 ? args.merge_max_iter : args.max_iter, job.kind == 1 ? args.merge_tol : args.tol,
+               job.kind == 1 ? args.merge_bf16 != 0 : args.bf16 != 0, sh, lds);
     if (threadIdx.x == 0 && job.stats) {
       job.stats[STAT_T0] = double(t_begin);
       job.stats[STAT_T1] = double(wall_clock64());

@@ -94,6 +94,7 @@ SIGNATURES = [
     ("tk_hitset_plan", c_i32, [ctypes.POINTER(TkConfig), c_i64, c_i64, c_i64, ctypes.POINTER(TkHit),
                                c_i32, ctypes.POINTER(c_i32)]),
     ("tk_effective_ranks", c_i32, [ctypes.POINTER(TkConfig), c_i64, ctypes.POINTER(c_i32)]),
+    ("tk_set_query_prec", c_i32, [c_vp, c_i32]),
     ("tk_get_tuning", c_i32, [c_vp, ctypes.POINTER(TkTuning)]),
     ("tk_set_tuning", c_i32, [c_vp, ctypes.POINTER(TkTuning)]),
     ("tk_batch_create", c_i32, [c_vp, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
@@ -521,6 +522,10 @@ class Tree:
 
     def set_query_iters(self, max_iter: int, tol: float):
         self._check(lib().tk_set_query_iters(self._h, max_iter, tol), "tk_set_query_iters")
+
+    def set_query_prec(self, prec: int):
+        """TK_F32 or TK_BF16 arithmetic for later queries."""
+        self._check(lib().tk_set_query_prec(self._h, int(prec)), "tk_set_query_prec")
 
     # -- store access ---------------------------------------------------------------------
     def stats(self) -> dict:

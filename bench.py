@@ -26,6 +26,24 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_TFLOPS = 157.3     # MI355X dense FP32 (MFMA and packed vector)
 HBM_TBPS = 8.0
 
+# HBM bytes per step of the plain workload's stitch launches, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE per dispatch, summed over the
+# step's launches) scaled by the counters of a 1 GiB reference copy (FETCH
+# reads half the bytes moved, WRITE all of them); valid only for the kernel
+# sources they were taken with.
+TRAFFIC_KERNEL_SHA = "76b20110a4ede29e"
+TRAFFIC_BYTES_PER_STEP = {"plain": {"fetch": 788.0e6, "write": 820.1e6}}
+KERNEL_SOURCES = ("tk_common.hpp", "tk_device.hpp", "tk_internal.hpp", "tk_kernels.hip")
+
+
+def kernel_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2501_06647_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def stitch_flops(p, D, rq, hits, node_ranks, sweeps, L):
     """Algorithmic FLOPs of one query (Alg. "stitch" on its hit set), counted
@@ -311,6 +329,13 @@ def main():
         accuracy = {"n_checked": done, "max_err_ratio_delta": float(max(deltas)),
                     "median_rel_err": float(np.median(errs)), "gate": 1e-5}
 
+    traffic, traffic_detail = None, None
+    tb = TRAFFIC_BYTES_PER_STEP.get(wl.name)
+    if tb and kernel_sha() == TRAFFIC_KERNEL_SHA:
+        traffic = tb["fetch"] + tb["write"]
+        traffic_detail = {"fetch_bytes": tb["fetch"], "write_bytes": tb["write"],
+                          "GBps_at_kernel_ms": traffic / kernel_s / 1e9,
+                          "source": "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE per dispatch, copy-calibrated"}
     out = {
         "metric": "range queries/sec at fixed rel. error; p50/p99 query latency vs plain GPU path",
         "value": qps,
@@ -345,7 +370,8 @@ def main():
                                 "timeline": timeline},
         "hits_mean": float(np.mean(hit_counts)),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                     "traffic_detail": traffic_detail,
                      "kernel": "stitch_kernel", "kernel_ms": float(np.mean(kms)),
                      "gflop_per_launch": flops / 1e9},
         "accuracy_vs_oracle": accuracy,

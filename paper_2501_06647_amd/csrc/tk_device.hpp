@@ -308,6 +308,76 @@ __device__ __forceinline__ void gram_mode(const float* __restrict__ X, int64_t a
 
 typedef double tk_d4 __attribute__((ext_vector_type(4)));
 
+// C = A B in FP64 on the matrix cores (v_mfma_f64_16x16x4f64): 16 x 16
+// output tiles per wavefront, K in steps of 4.  a(i, k) and b(k, j) return
+// operands (called only in range), put(i, j, v) stores result (i, j).  Lane
+// l supplies a(16 I + l % 16, 4 c + l / 16) and b(4 c + l / 16, 16 J + l % 16)
+// and holds C(16 I + l / 16 + 4 v, 16 J + l % 16) for v < 4.
+template <typename FA, typename FB, typename FP>
+__device__ __forceinline__ void gemm_f64(int M, int N, int K, FA&& a, FB&& b, FP&& put) {
+  const int nw = int(blockDim.x) >> 6, w = int(threadIdx.x) >> 6, l = int(threadIdx.x) & 63;
+  const int lr = l & 15, lk = l >> 4;
+  const int mt = (M + 15) >> 4, ntl = (N + 15) >> 4;
+  for (int t = w; t < mt * ntl; t += nw) {
+    const int I = t % mt, J = t / mt;
+    const int i = I * 16 + lr, j = J * 16 + lr;
+    tk_d4 c = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int k = k0 + lk;
+      const double av = (i < M && k < K) ? double(a(i, k)) : 0.0;
+      const double bv = (j < N && k < K) ? double(b(k, j)) : 0.0;
+      c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ri = I * 16 + lk + 4 * v;
+      if (ri < M && j < N) put(ri, j, c[v]);
+    }
+  }
+  __syncthreads();
+}
+
+// Mode product in FP64 on the matrix cores: Y[x][i][y] (+)= sum_j A(i, j)
+// X[x][j][y] (X FP32 or FP64, A and Y FP64), the layout of mode_product_mfma
+// with v_mfma_f64_16x16x4f64 (fibers f = (x, y) as the N dimension).
+template <typename TX>
+__device__ __forceinline__ void mode_product_f64(const TX* __restrict__ X, int64_t a, int r, int64_t b,
+                                                 const double* __restrict__ A, int64_t as, int64_t bs, int m,
+                                                 double* __restrict__ Y, bool acc) {
+  const int nw = int(blockDim.x) >> 6, w = int(threadIdx.x) >> 6, l = int(threadIdx.x) & 63;
+  const int lr = l & 15, lk = l >> 4;
+  const int64_t F = a * b;
+  const int mt = (m + 15) >> 4;
+  const int64_t ntiles = int64_t(mt) * ((F + 15) >> 4);
+  for (int64_t t = w; t < ntiles; t += nw) {
+    const int I = int(t % mt);
+    const int64_t fo = (t / mt) * 16;  // first fiber of the tile
+    const int64_t f = fo + lr;         // this lane's fiber (B operand column)
+    const bool fv = f < F;
+    const int64_t x = fv ? f / b : 0, y = fv ? f % b : 0;
+    const int ia = I * 16 + lr;
+    const bool iav = ia < m;
+    tk_d4 c = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < r; k0 += 4) {
+      const int j = k0 + lk;
+      const double av = (iav && j < r) ? A[int64_t(ia) * as + int64_t(j) * bs] : 0.0;
+      const double bv = (fv && j < r) ? double(X[(x * r + j) * b + y]) : 0.0;
+      c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
+    }
+    if (fv) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = I * 16 + lk + 4 * v;
+        if (i < m) {
+          const int64_t o = (x * m + i) * b + y;
+          Y[o] = acc ? Y[o] + c[v] : c[v];
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // Mode Gram on the matrix cores: G = mat_n(X) mat_n(X)^T (q x q, FP64, leading
 // dimension ld; both triangles written) for X (FP32) viewed as (a, q, b).
 // Each wavefront takes 16 x 16 tiles of the upper triangle and accumulates

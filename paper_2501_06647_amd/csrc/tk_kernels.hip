@@ -201,6 +201,15 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     for (int m = 1; m < n; ++m) off += int64_t(rq[m]) * st.rk[hits[i].level][m];
     return off;
   };
+  auto hit_of_col = [&](int n, int c) {  // the hit whose mode-n factor holds column c of V_cat
+    int i = 0;
+    while (c >= sh.roff[n][i + 1]) ++i;
+    return i;
+  };
+  auto vcat = [&](int n, int64_t dd, int c) -> float {  // V_cat[dd][c]
+    const int i = hit_of_col(n, c);
+    return fac_of(i, n)[dd * st.rk[hits[i].level][n] + (c - sh.roff[n][i])];
+  };
 
   // ---- orthonormal bases of the non-temporal spans -----------------------------
   for (int n = 1; n < p; ++n) {
@@ -211,19 +220,13 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     int use_basis = 0;
     if (sr < Dn) {
       with_buf(sr, [&](double* Gm) {
+        // Gram of V_cat = [V~_1^(n) .. V~_s^(n)] over its D_n rows, FP64 on
+        // the matrix cores, then mirrored so that it is exactly symmetric
+        gemm_f64(sr, sr, int(Dn), [&](int x, int dd) { return vcat(n, dd, x); },
+                 [&](int dd, int y) { return vcat(n, dd, y); }, [&](int x, int y, double v) { Gm[x * sr + y] = v; });
         for (int e = tid; e < sr * sr; e += nt) {
           const int x = e / sr, y = e % sr;
-          if (y < x) continue;
-          int ix = 0, iy = 0;
-          while (x >= sh.roff[n][ix + 1]) ++ix;
-          while (y >= sh.roff[n][iy + 1]) ++iy;
-          const int rx = st.rk[hits[ix].level][n], ry = st.rk[hits[iy].level][n];
-          const float* Vx = fac_of(ix, n) + (x - sh.roff[n][ix]);
-          const float* Vy = fac_of(iy, n) + (y - sh.roff[n][iy]);
-          double acc = 0.0;
-          for (int64_t dd = 0; dd < Dn; ++dd) acc += double(Vx[dd * rx]) * double(Vy[dd * ry]);
-          Gm[x * sr + y] = acc;
-          Gm[y * sr + x] = acc;
+          if (y < x) Gm[e] = Gm[y * sr + x];
         }
         __syncthreads();
         double* d = Gm + sr * sr;
@@ -259,17 +262,14 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     const int q = sh.q[n], sr = lo.sr[n], r_out = rq[n];
     const double* P = Dp(lo.Pd[n]);
     const double* C64 = Dp(lo.C64[n]);
-    for (int i = 0; i < s; ++i) {
-      const int r = st.rk[hits[i].level][n];
-      float* A = Fp(lo.A[i]) + A_off(i, n);
-      const int c0 = sh.roff[n][i];
-      for (int e = tid; e < r_out * r; e += nt) {
-        const int c = e / r, j = e % r;
-        double acc = 0.0;
-        for (int dd = 0; dd < q; ++dd) acc += P[dd * r_out + c] * C64[dd * sr + c0 + j];
-        A[e] = float(acc);
-      }
-    }
+    // [A_1 .. A_s] = P_n^T C^(n) (r_out x sr); A_i is stored r_out x r_i
+    gemm_f64(r_out, sr, q, [&](int c, int dd) { return P[dd * r_out + c]; },
+             [&](int dd, int col) { return C64[int64_t(dd) * sr + col]; },
+             [&](int c, int col, double v) {
+               const int i = hit_of_col(n, col);
+               const int r = st.rk[hits[i].level][n];
+               Fp(lo.A[i])[A_off(i, n) + int64_t(c) * r + (col - sh.roff[n][i])] = float(v);
+             });
     float* Pf = Fp(lo.Pf[n]);
     for (int e = tid; e < q * r_out; e += nt) Pf[e] = float(P[e]);
     __syncthreads();
@@ -292,20 +292,12 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
       for (int m = 1; m < p; ++m) dims[m] = st.rk[lev][m];
       gram_mode_mfma(core_of(i), prod_range(dims, 0, n), r, prod_range(dims, n + 1, p), S, r);
       const int c0 = sh.roff[n][i];
-      for (int e = tid; e < q * r; e += nt) {
-        const int dd = e / r, j = e % r;
-        double acc = 0.0;
-        for (int c = 0; c < r; ++c) acc += C64[dd * sr + c0 + c] * S[c * r + j];
-        T[e] = acc;
-      }
-      __syncthreads();
-      for (int e = tid; e < q * q; e += nt) {
-        const int dd = e / q, d2 = e % q;
-        double acc = 0.0;
-        for (int j = 0; j < r; ++j) acc += T[dd * r + j] * C64[d2 * sr + c0 + j];
-        Wm[e] += acc;
-      }
-      __syncthreads();
+      // T = C_i S_i (q x r), then Wm += T C_i^T
+      gemm_f64(q, r, r, [&](int dd, int c) { return C64[int64_t(dd) * sr + c0 + c]; },
+               [&](int c, int j) { return S[c * r + j]; }, [&](int dd, int j, double v) { T[dd * r + j] = v; });
+      gemm_f64(q, q, r, [&](int dd, int j) { return T[dd * r + j]; },
+               [&](int j, int d2) { return C64[int64_t(d2) * sr + c0 + j]; },
+               [&](int dd, int d2, double v) { Wm[dd * q + d2] += v; });
     }
     eig_top(Wm, q, rq[n], Dp(lo.Pd[n]), rq[n], red, Dp(lo.EF[n]), TMP, false, &ec);
     });
@@ -418,7 +410,8 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
   }
 
   // ---- write the result ----------------------------------------------------------
-  // U^(n) = B P_n (= V_cat F_n P_n on the basis route), formed in FP64
+  // (FP64 products on the matrix cores, FP32 stores)
+  // U^(n) = B P_n (= V_cat F_n P_n on the basis route)
   for (int n = 1; n < p; ++n) {
     const int64_t Dn = st.D[n];
     const int r_out = rq[n];
@@ -428,25 +421,12 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
       const int sr = lo.sr[n], q = sh.q[n];
       const double* Fn = Dp(lo.Fn[n]);
       double* Fh = Dp(lo.Fh[n]);
-      for (int e = tid; e < sr * r_out; e += nt) {
-        const int c = e / r_out, j = e % r_out;
-        double acc = 0.0;
-        for (int dd = 0; dd < q; ++dd) acc += Fn[c * sr + dd] * P[dd * r_out + j];
-        Fh[e] = acc;
-      }
-      __syncthreads();
-      for (int64_t e = tid; e < Dn * r_out; e += nt) {
-        const int64_t dd = e / r_out;
-        const int j = int(e % r_out);
-        double acc = 0.0;
-        for (int i = 0; i < s; ++i) {
-          const int r = st.rk[hits[i].level][n];
-          const float* V = fac_of(i, n) + dd * r;
-          const double* f = Fh + int64_t(sh.roff[n][i]) * r_out + j;
-          for (int c = 0; c < r; ++c) acc += double(V[c]) * f[int64_t(c) * r_out];
-        }
-        out[e] = float(acc);
-      }
+      gemm_f64(sr, r_out, q, [&](int c, int dd) { return Fn[c * sr + dd]; },
+               [&](int dd, int j) { return P[dd * r_out + j]; },
+               [&](int c, int j, double v) { Fh[c * r_out + j] = v; });
+      gemm_f64(int(Dn), r_out, sr, [&](int dd, int c) { return vcat(n, dd, c); },
+               [&](int c, int j) { return Fh[c * r_out + j]; },
+               [&](int dd, int j, double v) { out[int64_t(dd) * r_out + j] = float(v); });
     } else {
       for (int64_t e = tid; e < Dn * r_out; e += nt) out[e] = float(P[e]);
     }
@@ -465,27 +445,18 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
       const double* Pi = P0 + int64_t(sh.koff[i]) * r0;
       if (h.partial) {
         const double* Fi = Dp(lo.F[i]);
-        for (int e = tid; e < k * r0; e += nt) {
-          const int c = e / r0, j = e % r0;
-          double acc = 0.0;
-          for (int m = 0; m < kp; ++m) acc += Fi[c * k + m] * Pi[m * r0 + j];
-          F0[e] = acc;
-        }
+        gemm_f64(k, r0, kp, [&](int c, int m) { return Fi[c * k + m]; }, [&](int m, int j) { return Pi[m * r0 + j]; },
+                 [&](int c, int j, double v) { F0[c * r0 + j] = v; });
       } else {
         for (int e = tid; e < k * r0; e += nt) F0[e] = Pi[e];
+        __syncthreads();
       }
-      __syncthreads();
       const float* V = st.plane[lev] + ((h.index << lev) * st.ell + h.a) * k;
       float* out = job.out_fac[0] + t * r0;
-      for (int64_t e = tid; e < h.l * r0; e += nt) {
-        const int64_t row = e / r0;
-        const int j = int(e % r0);
-        double acc = 0.0;
-        for (int c = 0; c < k; ++c) acc += double(V[row * k + c]) * F0[c * r0 + j];
-        out[e] = float(acc);
-      }
+      gemm_f64(int(h.l), r0, k, [&](int row, int c) { return V[int64_t(row) * k + c]; },
+               [&](int c, int j) { return F0[c * r0 + j]; },
+               [&](int row, int j, double v) { out[int64_t(row) * r0 + j] = float(v); });
       t += h.l;
-      __syncthreads();
     }
   }
   // final core in FP64: G = sum_i H~_i x_1 P_i^T x_{n>=2} (P_n^T C_i), and
@@ -496,37 +467,33 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     double* D1 = Dp(lo.D1);
     double* D2 = Dp(lo.D2);
     const double* P0 = Dp(lo.Pd[0]);
+    // [A64_1 .. A64_s] = P_n^T C^(n) for every mode
+    for (int n = 1; n < p; ++n) {
+      const int q = sh.q[n], sr = lo.sr[n], r_out = rq[n];
+      const double* P = Dp(lo.Pd[n]);
+      const double* C = Dp(lo.C64[n]);
+      gemm_f64(r_out, sr, q, [&](int c, int dd) { return P[dd * r_out + c]; },
+               [&](int dd, int col) { return C[int64_t(dd) * sr + col]; },
+               [&](int c, int col, double v) {
+                 const int i = hit_of_col(n, col);
+                 const int r = st.rk[hits[i].level][n];
+                 Dp(lo.A64[i])[A_off(i, n) + int64_t(c) * r + (col - sh.roff[n][i])] = v;
+               });
+    }
     for (int i = 0; i < s; ++i) {
-      for (int n = 1; n < p; ++n) {
-        const int q = sh.q[n], sr = lo.sr[n], r_out = rq[n];
-        const int r = st.rk[hits[i].level][n];
-        const double* P = Dp(lo.Pd[n]);
-        const double* C = Dp(lo.C64[n]);
-        double* A = Dp(lo.A64[i]) + A_off(i, n);
-        const int c0 = sh.roff[n][i];
-        for (int e = tid; e < r_out * r; e += nt) {
-          const int c = e / r, j = e % r;
-          double acc = 0.0;
-          for (int dd = 0; dd < q; ++dd) acc += P[dd * r_out + c] * C[dd * sr + c0 + j];
-          A[e] = acc;
-        }
-      }
-      __syncthreads();
       int32_t dims[MAXP];
       dims[0] = sh.kp[i];
       for (int m = 1; m < p; ++m) dims[m] = st.rk[hits[i].level][m];
-      mode_product_t<float, double, double, double>(core_of(i), 1, dims[0], prod_range(dims, 1, p),
-                                                    P0 + int64_t(sh.koff[i]) * rq[0], 1, rq[0], rq[0], D1,
-                                                    false);
+      mode_product_f64<float>(core_of(i), 1, dims[0], prod_range(dims, 1, p), P0 + int64_t(sh.koff[i]) * rq[0], 1,
+                              rq[0], rq[0], D1, false);
       dims[0] = rq[0];
       const double* cur = D1;
       double* bufs[2] = {D2, D1};
       int nb = 0;
       for (int n = 1; n < p; ++n) {
         double* out = (n == p - 1) ? G64 : bufs[nb];
-        mode_product_t<double, double, double, double>(cur, prod_range(dims, 0, n), dims[n],
-                                                       prod_range(dims, n + 1, p), Dp(lo.A64[i]) + A_off(i, n),
-                                                       dims[n], 1, rq[n], out, n == p - 1 && i > 0);
+        mode_product_f64<double>(cur, prod_range(dims, 0, n), dims[n], prod_range(dims, n + 1, p),
+                                 Dp(lo.A64[i]) + A_off(i, n), dims[n], 1, rq[n], out, n == p - 1 && i > 0);
         dims[n] = rq[n];
         cur = out;
         nb ^= 1;

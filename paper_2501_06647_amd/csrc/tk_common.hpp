@@ -243,6 +243,7 @@ struct StitchLayout {
   int64_t EF[MAXP];           // double eigenbasis kept for warm starts: [0] sk x sk, [n] D_n x D_n
   int64_t M;                  // float sk x Rhat_0
   int64_t K;                  // float max_n D_n Rhat_n
+  int64_t WS;                 // float max_n sr_n Rhat_n (stacked W_i^(n))
   int64_t T1, T2;             // float tmax
   int64_t D1, D2;             // double tmax (init and final FP64 core)
   int64_t S;                  // double 32 x 32 (mode Gram of one core)
@@ -347,6 +348,10 @@ TK_HD void stitch_layout(const StoreView& st, const Hit* hits, int s, const int3
   Lo->EF[0] = take(int64_t(Lo->sk) * Lo->sk * 8);
   Lo->M = take(int64_t(Lo->sk) * Rhat[0] * 4);
   Lo->K = take(kmax * 4);
+  int64_t wmax = 0;
+  for (int n = 1; n < p; ++n)
+    if (int64_t(Lo->sr[n]) * Rhat[n] > wmax) wmax = int64_t(Lo->sr[n]) * Rhat[n];
+  Lo->WS = take(wmax * 4);
   // the HOSVD init keeps C_i S_i (q x r) in D1
   int64_t tq = 0;
   for (int n = 1; n < p; ++n) {

@@ -175,13 +175,20 @@ __device__ __forceinline__ void mode_product_mfma(const float* __restrict__ X, i
     const float im = ia < m ? 1.f : 0.f;
     const int64_t ic = ia < m ? ia : m - 1;
     tk_f4 c = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < r; k0 += 4) {
-      const int j = k0 + lk;
-      const float jm = j < r ? 1.f : 0.f;
-      const int64_t jc = j < r ? j : r - 1;
-      const float av = A[ic * as + jc * bs] * (im * jm);
-      const float bv = X[(x * r + jc) * b + y] * (fm * jm);
-      c = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, c, 0, 0, 0);
+    // eight K steps per round: all loads issued before the MFMAs that use them
+    for (int k0 = 0; k0 < r; k0 += 32) {
+      float av[8], bv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = k0 + 4 * u + lk;
+        const float jm = j < r ? 1.f : 0.f;
+        const int64_t jc = j < r ? j : r - 1;
+        av[u] = A[ic * as + jc * bs] * (im * jm);
+        bv[u] = X[(x * r + jc) * b + y] * (fm * jm);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k0 + 4 * u < r) c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[u], c, 0, 0, 0);
     }
     if (f < F) {
 #pragma unroll
@@ -322,11 +329,17 @@ __device__ __forceinline__ void gemm_f64(int M, int N, int K, FA&& a, FB&& b, FP
     const int I = t % mt, J = t / mt;
     const int i = I * 16 + lr, j = J * 16 + lr;
     tk_d4 c = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < K; k0 += 4) {
-      const int k = k0 + lk;
-      const double av = (i < M && k < K) ? double(a(i, k)) : 0.0;
-      const double bv = (j < N && k < K) ? double(b(k, j)) : 0.0;
-      c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + 4 * u + lk;
+        av[u] = (i < M && k < K) ? double(a(i, k)) : 0.0;
+        bv[u] = (j < N && k < K) ? double(b(k, j)) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (k0 + 4 * u < K) c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], c, 0, 0, 0);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -358,11 +371,17 @@ __device__ __forceinline__ void mode_product_f64(const TX* __restrict__ X, int64
     const int ia = I * 16 + lr;
     const bool iav = ia < m;
     tk_d4 c = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < r; k0 += 4) {
-      const int j = k0 + lk;
-      const double av = (iav && j < r) ? A[int64_t(ia) * as + int64_t(j) * bs] : 0.0;
-      const double bv = (fv && j < r) ? double(X[(x * r + j) * b + y]) : 0.0;
-      c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
+    for (int k0 = 0; k0 < r; k0 += 16) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = k0 + 4 * u + lk;
+        av[u] = (iav && j < r) ? A[int64_t(ia) * as + int64_t(j) * bs] : 0.0;
+        bv[u] = (fv && j < r) ? double(X[(x * r + j) * b + y]) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (k0 + 4 * u < r) c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], c, 0, 0, 0);
     }
     if (fv) {
 #pragma unroll
@@ -406,21 +425,28 @@ __device__ __forceinline__ void gram_mode_mfma(const float* __restrict__ X, int6
     // this lane's column k = 4 c + lk as (x, y), advanced by 4 per step
     int64_t x = lk / b, y = lk % b;
     const int64_t xs = 4 / b, ys = 4 % b;
-#pragma unroll 4
-    for (int64_t k0 = 0; k0 < N; k0 += 4) {
-      double av = 0.0, bv = 0.0;
-      if (k0 + lk < N) {
-        const float* col = X + x * q * b + y;
-        av = iv ? double(col[io]) : 0.0;
-        bv = jv ? double(col[jo]) : 0.0;
+    // eight steps per round: the loads of a round are issued before its MFMAs
+    for (int64_t k0 = 0; k0 < N; k0 += 32) {
+      double av[8], bv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        av[u] = 0.0;
+        bv[u] = 0.0;
+        if (k0 + 4 * u + lk < N) {
+          const float* col = X + x * q * b + y;
+          av[u] = iv ? double(col[io]) : 0.0;
+          bv[u] = jv ? double(col[jo]) : 0.0;
+        }
+        x += xs;
+        y += ys;
+        if (y >= b) {
+          y -= b;
+          ++x;
+        }
       }
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-      x += xs;
-      y += ys;
-      if (y >= b) {
-        y -= b;
-        ++x;
-      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k0 + 4 * u < N) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
     }
     const int cj = bj * 16 + lr;
 #pragma unroll
@@ -1189,8 +1215,9 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
         double nxr;
         if (fabs(w0) >= fabs(c)) {
           if (fabs(w0) < ptiny) w0 = w0 < 0.0 ? -ptiny : ptiny;
-          const double l = c / w0;
-          U1[o] = w0;
+          const double inv = 1.0 / w0;
+          const double l = c * inv;
+          U1[o] = inv;  // reciprocal pivot
           U2[o] = w1;
           U3[o] = 0.0;
           X(j, r) = xr;
@@ -1198,8 +1225,9 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
           w0 = a1 - l * w1;
           w1 = b1;
         } else {
-          const double l = w0 / c;
-          U1[o] = c;
+          const double inv = 1.0 / c;
+          const double l = w0 * inv;
+          U1[o] = inv;
           U2[o] = a1;
           U3[o] = b1;
           X(j, r) = xs;
@@ -1210,19 +1238,42 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
         xr = nxr;
       }
       if (fabs(w0) < ptiny) w0 = w0 < 0.0 ? -ptiny : ptiny;
-      // back substitution, values carried in registers
+      // back substitution, eight rows per round with their factors loaded
+      // first; values carried in registers.  Should a component exceed
+      // 1e150 the whole system (solved part and remaining right-hand side)
+      // is scaled by 1e-150.
       double x1 = xr / w0, x2 = 0.0;
       X(j, n - 1) = x1;
-      for (int r = n - 2; r >= 0; --r) {
-        const int64_t o = int64_t(r) * kk + j;
-        const double v = (X(j, r) - U2[o] * x1 - U3[o] * x2) / U1[o];
-        x2 = x1;
-        x1 = v;
-        X(j, r) = v;
-        if (fabs(v) > 1e150) {
-          for (int q = r; q < n; ++q) X(j, q) *= 1e-150;
-          x1 *= 1e-150;
-          x2 *= 1e-150;
+      for (int r0 = n - 2; r0 >= 0; r0 -= 8) {
+        double u1[8], u2[8], u3[8], rh[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int r = r0 - u;
+          if (r >= 0) {
+            const int64_t o = int64_t(r) * kk + j;
+            u1[u] = U1[o];
+            u2[u] = U2[o];
+            u3[u] = U3[o];
+            rh[u] = X(j, r);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int r = r0 - u;
+          if (r >= 0) {
+            double v = (rh[u] - u2[u] * x1 - u3[u] * x2) * u1[u];
+            if (fabs(v) > 1e150) {
+              for (int q = 0; q < n; ++q) X(j, q) *= 1e-150;
+#pragma unroll
+              for (int w = 0; w < 8; ++w) rh[w] *= 1e-150;
+              x1 *= 1e-150;
+              x2 *= 1e-150;
+              v *= 1e-150;
+            }
+            x2 = x1;
+            x1 = v;
+            X(j, r) = v;
+          }
         }
       }
       double s = 0.0;

@@ -350,6 +350,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     clk.mark(4);
     // non-temporal modes: K_n = sum_i W_i^(n) x_n C_i, P_n = leading eigvecs of its Gram
     float* K = Fp(lo.K);
+    float* Wst = Fp(lo.WS);
     for (int n = 1; n < p; ++n) {
       const int q = sh.q[n];
       int32_t kd[MAXP];
@@ -378,10 +379,18 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
           cur = bufs[nb];
           nb ^= 1;
         }
-        // x_n C_i accumulated into K_n
-        ttm(cur, prod_range(dims, 0, n), dims[n], prod_range(dims, n + 1, p),
-            Fp(lo.C[n]) + sh.roff[n][i], lo.sr[n], 1, q, K, i > 0);
+        // W_i^(n) into the stack Wst (ka x sr_n x kb) at mode-n rows roff_i
+        const int ri = dims[n];
+        const int64_t rb = int64_t(ri) * kb;
+        const int srn = lo.sr[n];
+        for (int64_t e = tid; e < ka * rb; e += nt) {
+          const int64_t x = e / rb, jy = e - x * rb;
+          Wst[(x * srn + sh.roff[n][i]) * kb + jy] = cur[e];
+        }
+        __syncthreads();
       }
+      // K_n = sum_i W_i^(n) x_n C_i: one product over the stacked mode
+      ttm(Wst, ka, lo.sr[n], kb, Fp(lo.C[n]), lo.sr[n], 1, q, K, false);
       with_buf(q, [&](double* Wn) {
         gram(K, ka, q, kb, Wn, q);
         clk.mark(5);

@@ -267,7 +267,7 @@ def main():
     prof = [batch.profile(i) for i in range(nq)]
     phase_mean = {k: float(np.mean([pr[k] for pr in prof])) for k in tree.PHASES}
     tot = np.array([sum(pr[k] for k in tree.PHASES) for pr in prof])
-    counters = {k: float(np.mean([pr[k] for pr in prof])) for k in tree.COUNTERS[:4]}
+    counters = {k: float(np.mean([pr[k] for pr in prof])) for k in tree.COUNTERS[:4] + tree.COUNTERS[6:]}
     t_s = np.array([pr["start_us"] for pr in prof])
     t_e = np.array([pr["end_us"] for pr in prof])
     t_base = t_s.min()

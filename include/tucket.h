@@ -169,7 +169,9 @@ tk_status tk_last_query_kernel_ms(const tk_tree* t, double* ms);
  * and writing the result; then four eigensolver counters: calls, bisection
  * steps, microseconds computing eigenvalues (tridiagonalisation and
  * bisection), microseconds computing eigenvectors; then the query's start
- * and end on the device clock in microseconds.  phase_us has 14 entries. */
+ * and end on the device clock in microseconds; then the number of
+ * eigensolves whose vectors needed the Gram-Schmidt fallback.  phase_us has
+ * 15 entries. */
 tk_status tk_last_query_profile(const tk_tree* t, int32_t i, double* phase_us);
 
 /* Override the ALS sweep cap and tolerance for later queries (not merges). */

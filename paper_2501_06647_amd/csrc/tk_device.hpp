@@ -768,7 +768,7 @@ __device__ __forceinline__ void pchol_basis(const double* L, const int* piv, int
 // ---------------------------------------------------------------------------
 
 struct EigCounters {  // zeroed by the owner (it may live in LDS)
-  uint64_t calls, sweeps, jacobi_ticks, tail_ticks;
+  uint64_t calls, sweeps, jacobi_ticks, tail_ticks, fallbacks;
 };
 
 // Leading eigenpairs of a symmetric positive semi-definite n x n matrix S by
@@ -1299,6 +1299,51 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
       __syncthreads();
     }
   }
+  // Cholesky QR of the vectors (their Gram is the identity to ~eps/gap
+  // after inverse iteration; one pass leaves them orthonormal to ~eps):
+  // Gram in U1 (free now), R^T R = Gram by thread 0, rows of X times R^-1
+  {
+    double* Gq = U1;
+    for (int e2 = tid; e2 < kk * kk; e2 += nt) {
+      const int a = e2 / kk, b = e2 % kk;
+      if (b < a) continue;
+      double dt = 0.0;
+      for (int r = 0; r < n; ++r) dt += X(a, r) * X(b, r);
+      Gq[a * kk + b] = dt;
+      Gq[b * kk + a] = dt;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int ok = 1;
+      for (int j2 = 0; j2 < kk && ok; ++j2) {
+        double dg = Gq[j2 * kk + j2];
+        for (int t2 = 0; t2 < j2; ++t2) dg -= Gq[t2 * kk + j2] * Gq[t2 * kk + j2];
+        if (!(dg > 0.25)) {
+          ok = 0;
+          break;
+        }
+        const double rjj = sqrt(dg);
+        Gq[j2 * kk + j2] = rjj;
+        for (int c2 = j2 + 1; c2 < kk; ++c2) {
+          double v = Gq[j2 * kk + c2];
+          for (int t2 = 0; t2 < j2; ++t2) v -= Gq[t2 * kk + j2] * Gq[t2 * kk + c2];
+          Gq[j2 * kk + c2] = v / rjj;
+        }
+      }
+      s_busy = ok;
+    }
+    __syncthreads();
+    if (s_busy) {
+      for (int r = tid; r < n; r += nt) {
+        for (int j2 = 0; j2 < kk; ++j2) {
+          double v = X(j2, r);
+          for (int t2 = 0; t2 < j2; ++t2) v -= X(t2, r) * Gq[t2 * kk + j2];
+          X(j2, r) = v / Gq[j2 * kk + j2];
+        }
+      }
+    }
+    __syncthreads();
+  }
   // Rayleigh quotients y^T T y (scaled back)
   if (tid < kk) {
     const int j = tid;
@@ -1340,6 +1385,7 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
   }
   __syncthreads();
   orthonormalize(E, n, kk, lde, 1, pw, red, &s_flag);
+  if (cnt && tid == 0 && s_flag) cnt->fallbacks += 1;
   };
   if (2 * kk < n) vectors(XinW{W, n});
   else vectors(XinT{tmp + int64_t(3) * n * kk, kk});

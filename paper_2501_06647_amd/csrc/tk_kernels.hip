@@ -108,7 +108,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
 
   PhaseClock& clk = sh.clk;
   EigCounters& ec = sh.ec;
-  if (tid == 0) ec.calls = ec.sweeps = ec.jacobi_ticks = ec.tail_ticks = 0;
+  if (tid == 0) ec.calls = ec.sweeps = ec.jacobi_ticks = ec.tail_ticks = ec.fallbacks = 0;
   clk.start();
   // the layout record lives at the head of the workspace
   StitchLayout* lop = reinterpret_cast<StitchLayout*>(ws);
@@ -531,6 +531,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     job.stats[STAT_EIG + 1] = double(ec.sweeps);
     job.stats[STAT_EIG + 2] = double(ec.jacobi_ticks) * 0.01;
     job.stats[STAT_EIG + 3] = double(ec.tail_ticks) * 0.01;
+    job.stats[STAT_EIG_FALLBACK] = double(ec.fallbacks);
   }
 }
 

@@ -279,7 +279,7 @@ class PreparedBatch:
         return ms.value
 
     def profile(self, i: int) -> dict:
-        out = (c_dbl * 14)()
+        out = (c_dbl * 15)()
         self.tree._check(lib().tk_batch_profile(self._h, i, out), "tk_batch_profile")
         return dict(zip(Tree.PHASES + Tree.COUNTERS, list(out)))
 
@@ -505,10 +505,11 @@ class Tree:
         return Server(self, **kw)
 
     PHASES = ("trim", "basis", "init", "t_ttm_gram", "t_eig", "n_ttm_gram", "n_eig", "final")
-    COUNTERS = ("eig_calls", "eig_bisect_steps", "eig_values_us", "eig_vectors_us", "start_us", "end_us")
+    COUNTERS = ("eig_calls", "eig_bisect_steps", "eig_values_us", "eig_vectors_us", "start_us", "end_us",
+                "eig_fallbacks")
 
     def last_profile(self, i: int) -> dict:
-        out = (c_dbl * 14)()
+        out = (c_dbl * 15)()
         self._check(lib().tk_last_query_profile(self._h, i, out), "tk_last_query_profile")
         return dict(zip(self.PHASES + self.COUNTERS, list(out)))
 

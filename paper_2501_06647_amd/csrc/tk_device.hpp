@@ -1114,7 +1114,9 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
     vv[i] = e[i] * e[i];
   }
   const double pivmin = 1e-250;
-  const int g = nt / kk;  // lanes per eigenvalue
+  const int g = nt / kk;                // lanes per eigenvalue
+  const int pl = nt <= 128 ? 2 : 1;     // points per lane (two independent Sturm chains)
+  const int gp = g * pl;                // points per eigenvalue and step
   for (int j = tid; j < kk; j += nt) {
     iv[2 * j] = -1.0 - 1e-12;
     iv[2 * j + 1] = 1.0 + 1e-12;
@@ -1123,31 +1125,39 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
   int iters = 0;
   for (; iters < 80; ++iters) {
     const int j = tid / g, tg = tid % g;
-    int cntv = 0;
+    int c0 = 0, c1 = 0;
     if (j < kk) {
       const double a = iv[2 * j], b = iv[2 * j + 1];
-      const double x = a + (b - a) * double(tg + 1) / double(g + 1);
-      double q = d[0] - x;
-      if (fabs(q) < pivmin) q = -pivmin;
-      cntv = q < 0.0 ? 1 : 0;
+      const double x0 = a + (b - a) * double(pl * tg + 1) / double(gp + 1);
+      const double x1 = a + (b - a) * double(pl * tg + 2) / double(gp + 1);
+      double q0 = d[0] - x0, q1 = d[0] - x1;
+      if (fabs(q0) < pivmin) q0 = -pivmin;
+      if (fabs(q1) < pivmin) q1 = -pivmin;
+      c0 = q0 < 0.0 ? 1 : 0;
+      c1 = q1 < 0.0 ? 1 : 0;
       for (int r = 1; r < n; ++r) {
-        double y = __builtin_amdgcn_rcp(q);
-        y = fma(y, fma(-q, y, 1.0), y);
-        q = (d[r] - x) - vv[r - 1] * y;
-        if (fabs(q) < pivmin) q = -pivmin;
-        cntv += q < 0.0 ? 1 : 0;
+        double y0 = __builtin_amdgcn_rcp(q0), y1 = __builtin_amdgcn_rcp(q1);
+        y0 = fma(y0, fma(-q0, y0, 1.0), y0);
+        y1 = fma(y1, fma(-q1, y1, 1.0), y1);
+        q0 = (d[r] - x0) - vv[r - 1] * y0;
+        q1 = (d[r] - x1) - vv[r - 1] * y1;
+        if (fabs(q0) < pivmin) q0 = -pivmin;
+        if (fabs(q1) < pivmin) q1 = -pivmin;
+        c0 += q0 < 0.0 ? 1 : 0;
+        c1 += q1 < 0.0 ? 1 : 0;
       }
     }
-    part[tid] = double(cntv);
+    part[pl * tid] = double(c0);
+    if (pl == 2) part[pl * tid + 1] = double(c1);
     __syncthreads();
     int open = 0;
     if (j < kk && tg == 0) {
       const int idx = n - 1 - j;  // ascending index of the eigenvalue
       const double a = iv[2 * j], b = iv[2 * j + 1];
       double na = a, nb = b;
-      for (int u = 0; u < g; ++u) {
-        const double xu = a + (b - a) * double(u + 1) / double(g + 1);
-        if (int(part[j * g + u]) <= idx) na = xu;
+      for (int u = 0; u < gp; ++u) {
+        const double xu = a + (b - a) * double(u + 1) / double(gp + 1);
+        if (int(part[j * gp + u]) <= idx) na = xu;
         else if (nb == b) nb = xu;
       }
       iv[2 * j] = na;
@@ -1361,21 +1371,26 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
   __syncthreads();
 
   // ---- 4. back-transformation x = H_0 ... H_{n-3} y -------------------------------------
-  const int g2 = nt / kk;
-  for (int i = n - 3; i >= 0; --i) {
-    const double ti = tau[i];
-    if (ti == 0.0) continue;
-    const int j = tid / g2, sp = tid % g2;
-    double acc = 0.0;
-    if (j < kk)
-      for (int r = i + 1 + sp; r < n; r += g2) acc += (r == i + 1 ? 1.0 : W[int64_t(r) * n + i]) * X(j, r);
-    part[tid] = acc;
-    __syncthreads();
-    if (j < kk) {
-      double sj = 0.0;
-      for (int q = 0; q < g2; ++q) sj += part[j * g2 + q];
-      sj *= ti;
-      for (int r = i + 1 + sp; r < n; r += g2) X(j, r) -= sj * (r == i + 1 ? 1.0 : W[int64_t(r) * n + i]);
+  // A group of gs lanes (a power of two, inside one wavefront) per vector;
+  // lane sp of a group always owns the rows r = sp (mod gs), so the groups
+  // share nothing and the partial dot products are summed with shuffles:
+  // no barrier inside the loop.
+  {
+    int gs = 1;
+    while (gs < 64 && 2 * gs * kk <= nt) gs *= 2;
+    const int j = tid / gs, sp = tid % gs;
+    for (int i = n - 3; i >= 0; --i) {
+      const double ti = tau[i];
+      if (ti == 0.0) continue;
+      const int r0 = i + 1 + ((sp - (i + 1)) % gs + gs) % gs;
+      double acc = 0.0;
+      if (j < kk)
+        for (int r = r0; r < n; r += gs) acc += (r == i + 1 ? 1.0 : W[int64_t(r) * n + i]) * X(j, r);
+      for (int o = gs >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if (j < kk) {
+        const double sj = acc * ti;
+        for (int r = r0; r < n; r += gs) X(j, r) -= sj * (r == i + 1 ? 1.0 : W[int64_t(r) * n + i]);
+      }
     }
     __syncthreads();
   }
@@ -1384,8 +1399,12 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
     E[int64_t(r) * lde + j] = j < kk ? X(j, r) : 0.0;
   }
   __syncthreads();
-  orthonormalize(E, n, kk, lde, 1, pw, red, &s_flag);
-  if (cnt && tid == 0 && s_flag) cnt->fallbacks += 1;
+  // after the Cholesky QR the vectors are orthonormal to ~eps and the
+  // reflectors keep them so; the check (and CGS2) only without it
+  if (!s_busy) {
+    orthonormalize(E, n, kk, lde, 1, pw, red, &s_flag);
+    if (cnt && tid == 0 && s_flag) cnt->fallbacks += 1;
+  }
   };
   if (2 * kk < n) vectors(XinW{W, n});
   else vectors(XinT{tmp + int64_t(3) * n * kk, kk});

@@ -215,6 +215,9 @@ typedef struct {
   int32_t graph;          /* 1: prepared batches replay a captured HIP graph   */
   int32_t coarse;         /* 1: LDS bins {32, wide_threshold, 96} (fewer      */
                           /* launches), 0: {24, 32, 48, 64, 96, threshold}    */
+  int32_t lds_n;          /* largest eigenproblem kept in LDS, 0 = as large   */
+                          /* as fits; else >= wide_threshold (larger ones     */
+                          /* run in HBM, more jobs share a CU)                */
 } tk_tuning;
 
 tk_status tk_get_tuning(const tk_tree* t, tk_tuning* out);
@@ -246,8 +249,8 @@ tk_status tk_batch_hits(const tk_batch* b, int32_t i, tk_hit* out, int32_t cap, 
 void tk_batch_destroy(tk_batch* b);
 
 /* Time every candidate tuning (wide_threshold in {32, 48, 64, 96} x
- * wide_threads in {128, 256} x persistent in {0, 1} x coarse in {0, 1}) on a
- * prepared batch of
+ * wide_threads in {128, 256} x lds_n in {64, 96, 0} (>= the threshold) x
+ * persistent in {0, 1} x coarse in {0, 1}) on a prepared batch of
  * the given queries (reps timed executions after one warm-up, results into
  * scratch buffers), keep the fastest on the tree and report it. */
 tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* te, int32_t reps,

@@ -289,12 +289,16 @@ tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* t
   double bms = 1e300;
   const int thr[] = {32, 48, 64, 96};
   const int wth[] = {128, 256};
+  const int ldsn[] = {64, 96, 0};
   for (int th : thr)
     for (int wt : wth)
+      for (int ln : ldsn)
       for (int pc = 0; pc < 4; ++pc) {
+        if (ln != 0 && ln < th) continue;
         t->tuning = saved;
         t->tuning.wide_threshold = th;
         t->tuning.wide_threads = wt;
+        t->tuning.lds_n = ln;
         t->tuning.persistent = pc & 1;
         t->tuning.coarse = pc >> 1;
         tk_batch* b = nullptr;
@@ -327,6 +331,7 @@ tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* t
     best->persistent = bestt.persistent;
     best->graph = bestt.graph;
     best->coarse = bestt.coarse;
+    best->lds_n = bestt.lds_n;
   }
   if (best_ms) *best_ms = bms;
   return TK_OK;

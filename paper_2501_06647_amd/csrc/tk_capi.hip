@@ -97,6 +97,7 @@ int eig_need(const StitchLayout& lo, const StoreView& st) {
 int lds_cap(const tk_tree* t) {
   int cap = 128;
   while (cap > 8 && int64_t(eig_doubles(cap)) * 8 > t->lds_limit - int64_t(stitch_static_lds())) cap -= 8;
+  if (t->tuning.lds_n > 0 && t->tuning.lds_n < cap) cap = t->tuning.lds_n;
   return cap;
 }
 
@@ -750,6 +751,7 @@ tk_status tk_get_tuning(const tk_tree* t, tk_tuning* out) {
   out->persistent = t->tuning.persistent;
   out->graph = t->tuning.graph;
   out->coarse = t->tuning.coarse;
+  out->lds_n = t->tuning.lds_n;
   return TK_OK;
 }
 
@@ -762,11 +764,14 @@ tk_status tk_set_tuning(tk_tree* t, const tk_tuning* in) {
   if (in->persistent != 0 && in->persistent != 1) return fail(t, TK_EINVAL, "persistent must be 0 or 1");
   if (in->graph != 0 && in->graph != 1) return fail(t, TK_EINVAL, "graph must be 0 or 1");
   if (in->coarse != 0 && in->coarse != 1) return fail(t, TK_EINVAL, "coarse must be 0 or 1");
+  if (in->lds_n != 0 && (in->lds_n < 16 || in->lds_n < in->wide_threshold))
+    return fail(t, TK_EINVAL, "lds_n must be 0 or in [max(16, wide_threshold), ...]");
   t->tuning.wide_threshold = in->wide_threshold;
   t->tuning.wide_threads = in->wide_threads;
   t->tuning.persistent = in->persistent;
   t->tuning.graph = in->graph;
   t->tuning.coarse = in->coarse;
+  t->tuning.lds_n = in->lds_n;
   return TK_OK;
 }
 

@@ -33,6 +33,7 @@ struct Tuning {
   int persistent = 0;       // grid sized to residency; workgroups pull jobs from a queue
   int graph = 1;            // prepared batches replay a captured HIP graph
   int coarse = 0;           // 1: LDS bins {32, wide_threshold, 96} instead of {24, 32, 48, 64, 96, threshold}
+  int lds_n = 0;            // largest eigenproblem held in LDS (0: as large as fits); >= wide_threshold
 };
 
 // Stitch jobs that run in one launch: same dynamic LDS (n_lds) and block size.

@@ -285,6 +285,11 @@ def main():
     print("[bench] per-query device us: mean %.1f p50 %.1f max %.1f (query %d, %d hits, L=%d)"
           % (tot.mean(), np.median(tot), tot.max(), slow, hit_counts[slow], int(te[slow] - ts[slow])),
           file=sys.stderr, flush=True)
+    slowest = {"query": slow, "hits": hit_counts[slow], "L": int(te[slow] - ts[slow]),
+               "sweeps": int(sweeps[slow]), "ranks": [int(r) for r in results[slow].ranks],
+               "phases_us": {k: float(prof[slow][k]) for k in tree.PHASES},
+               "eig": {k: float(prof[slow][k]) for k in tree.COUNTERS[:4]}}
+    print("[bench] slowest query: %s" % json.dumps(slowest), file=sys.stderr, flush=True)
 
     plain = None
     if not args.no_plain:
@@ -367,7 +372,7 @@ def main():
         "sweeps_mean": float(np.mean(sweeps)),
         "device_us_per_query": {"mean": float(tot.mean()), "p50": float(np.median(tot)), "max": float(tot.max()),
                                 "phase_mean": phase_mean, "eig_counters_mean": counters,
-                                "timeline": timeline},
+                                "timeline": timeline, "slowest": slowest},
         "hits_mean": float(np.mean(hit_counts)),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,

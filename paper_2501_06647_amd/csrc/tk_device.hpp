@@ -30,6 +30,18 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
+// block_sum with a single barrier: buf (one double per wavefront) must not
+// be written again before a later barrier has passed.
+__device__ __forceinline__ double block_sum_once(double v, double* buf) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (blockDim.x <= 64) return v;
+  if ((threadIdx.x & 63) == 0) buf[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < int(blockDim.x >> 6); ++w) s += buf[w];
+  return s;
+}
+
 // Largest v over the workgroup with its index (smallest index on ties).
 __device__ __forceinline__ void block_argmax(double& v, int& idx, double* red, int* redi) {
   for (int o = 32; o > 0; o >>= 1) {
@@ -1017,67 +1029,109 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
   const int kk = k < n ? k : n;
 
   // ---- 1. tridiagonalisation ---------------------------------------------------
+  // Step i forms reflector u_i from row i, which is up to date, then makes one
+  // pass over the trailing block [i+1:, i+1:] that applies the rank-two update
+  // of step i-1 and accumulates p = t A u_i from the updated entries; with
+  // w = p - (t/2)(p.u) u it brings row i+1 up to date right away, so the next
+  // reflector is ready and the update of step i waits for the next pass.
+  // Reflector/update vectors alternate between (vv, pw) and (lam, iv).
+  double* red2 = red + 4;  // second reduction buffer (nt <= 256)
+  double s2 = 0.0;
+  if (n > 2) {
+    for (int c = 2 + tid; c < n; c += nt) s2 += W[c] * W[c];
+    s2 = block_sum(s2, red);
+  }
   for (int i = 0; i + 2 < n; ++i) {
     const int m = n - i - 1;
-    const double* Wi = W + int64_t(i) * n;  // row i = column i (symmetric)
-    double s2 = 0.0;
-    for (int c = i + 2 + tid; c < n; c += nt) s2 += Wi[c] * Wi[c];
-    s2 = block_sum(s2, red);
+    const double* Wi = W + int64_t(i) * n;  // row i
+    double* uc = (i & 1) ? lam : vv;        // u_i
+    double* wc = (i & 1) ? iv : pw;         // p_i, then w_i
+    const double* uo = (i & 1) ? vv : lam;  // u_{i-1}
+    const double* wo = (i & 1) ? pw : iv;   // w_{i-1}
     const double alpha = Wi[i + 1];
     double beta = alpha, t = 0.0, scale = 0.0;
     if (s2 > 0.0) {
       beta = -copysign(sqrt(alpha * alpha + s2), alpha);
-      t = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
+      t = (beta - alpha) * fast_rcp_signed(beta);
+      scale = fast_rcp_signed(alpha - beta);
     }
-    for (int c = i + 1 + tid; c < n; c += nt) vv[c] = c == i + 1 ? 1.0 : Wi[c] * scale;
-    __syncthreads();
-    for (int c = i + 2 + tid; c < n; c += nt) W[int64_t(c) * n + i] = vv[c];  // reflector -> column i
+    for (int c = i + 1 + tid; c < n; c += nt) {
+      const double u = c == i + 1 ? 1.0 : Wi[c] * scale;
+      uc[c] = u;
+      if (c > i + 1) W[int64_t(c) * n + i] = u;  // reflector -> column i
+    }
     if (tid == 0) {
       d[i] = Wi[i];
       e[i] = beta;
       tau[i] = t;
     }
-    if (t == 0.0) {
-      __syncthreads();
-      continue;
-    }
-    // p = t A u on the trailing block A = W[i+1:, i+1:] (symmetric: read by columns)
+    __syncthreads();
+    // the pass: A <- A - (u_{i-1} w_{i-1}^T + w_{i-1} u_{i-1}^T), p = t A u_i,
+    // thread (r, sp) taking column r (row r by symmetry), rows c = sp mod nsplit
     const int nsplit = nt >= 2 * m ? nt / m : 1;
+    const int r0 = nsplit == 1 ? tid : tid % m;
+    const int sp = nsplit == 1 ? 0 : tid / m;
+    const int rstep = nsplit == 1 ? nt : m;
+    if (sp < nsplit) {
+      for (int r = i + 1 + r0; r < n; r += rstep) {
+        double acc = 0.0;
+        if (i > 0) {
+          const double ur = uo[r], wr = wo[r];
+          for (int c = i + 1 + sp; c < n; c += nsplit) {
+            double* a = W + int64_t(c) * n + r;
+            const double x = *a - (uo[c] * wr + wo[c] * ur);
+            *a = x;
+            acc += x * uc[c];
+          }
+        } else {
+          for (int c = i + 1 + sp; c < n; c += nsplit) acc += W[int64_t(c) * n + r] * uc[c];
+        }
+        if (nsplit == 1)
+          wc[r] = t * acc;
+        else
+          part[sp * m + (r - i - 1)] = acc;
+      }
+    }
+    __syncthreads();
+    // p_{i+1} for every thread (read before anyone overwrites it with w)
+    double p1;
     if (nsplit == 1) {
-      for (int r = i + 1 + tid; r < n; r += nt) {
-        double acc = 0.0;
-        for (int c = i + 1; c < n; ++c) acc += W[int64_t(c) * n + r] * vv[c];
-        pw[r] = t * acc;
-      }
+      p1 = wc[i + 1];
     } else {
-      const int r = tid % m, sp = tid / m;
-      if (sp < nsplit) {
-        double acc = 0.0;
-        for (int c = i + 1 + sp; c < n; c += nsplit) acc += W[int64_t(c) * n + i + 1 + r] * vv[c];
-        part[sp * m + r] = acc;
-      }
-      __syncthreads();
-      for (int rr = tid; rr < m; rr += nt) {
-        double acc = 0.0;
-        for (int q = 0; q < nsplit; ++q) acc += part[q * m + rr];
-        pw[i + 1 + rr] = t * acc;
-      }
+      double acc = 0.0;
+      for (int q = 0; q < nsplit; ++q) acc += part[q * m];
+      p1 = t * acc;
     }
-    __syncthreads();
     double kd = 0.0;
-    for (int r = i + 1 + tid; r < n; r += nt) kd += pw[r] * vv[r];
-    const double K = 0.5 * t * block_sum(kd, red);
-    __syncthreads();
-    for (int r = i + 1 + tid; r < n; r += nt) pw[r] -= K * vv[r];
-    __syncthreads();
-    for (int x = tid; x < m * m; x += nt) {
-      const int r = i + 1 + x / m, c = i + 1 + x % m;
-      W[int64_t(r) * n + c] -= vv[r] * pw[c] + pw[r] * vv[c];
+    for (int r = i + 1 + tid; r < n; r += nt) {
+      if (nsplit > 1) {
+        double acc = 0.0;
+        for (int q = 0; q < nsplit; ++q) acc += part[q * m + r - i - 1];
+        wc[r] = t * acc;
+      }
+      kd += wc[r] * uc[r];
     }
-    __syncthreads();
+    const double K = 0.5 * t * block_sum_once(kd, red);
+    const double w1 = p1 - K * uc[i + 1];
+    double s2n = 0.0;
+    for (int r = i + 1 + tid; r < n; r += nt) {
+      const double w = wc[r] - K * uc[r];
+      wc[r] = w;
+      double* a = W + int64_t(i + 1) * n + r;  // row i+1 brought up to date
+      const double x = *a - (uc[i + 1] * w + w1 * uc[r]);
+      *a = x;
+      if (r > i + 2) s2n += x * x;
+    }
+    s2 = block_sum_once(s2n, red2);
+    if (nt <= 64) __syncthreads();  // row i+1 written before the next step reads it
   }
+  __syncthreads();
   if (tid == 0) {
+    if (n > 2) {  // the last step's update on the final diagonal entry
+      const double* ul = ((n - 3) & 1) ? lam : vv;
+      const double* wl = ((n - 3) & 1) ? iv : pw;
+      W[int64_t(n - 1) * n + n - 1] -= ul[n - 1] * wl[n - 1] + wl[n - 1] * ul[n - 1];
+    }
     if (n >= 2) {
       d[n - 2] = W[int64_t(n - 2) * n + n - 2];
       e[n - 2] = W[int64_t(n - 2) * n + n - 1];
@@ -1117,6 +1171,7 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
   const int g = nt / kk;                // lanes per eigenvalue
   const int pl = nt <= 128 ? 2 : 1;     // points per lane (two independent Sturm chains)
   const int gp = g * pl;                // points per eigenvalue and step
+  const double igp = 1.0 / double(gp + 1);
   for (int j = tid; j < kk; j += nt) {
     iv[2 * j] = -1.0 - 1e-12;
     iv[2 * j + 1] = 1.0 + 1e-12;
@@ -1128,8 +1183,8 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
     int c0 = 0, c1 = 0;
     if (j < kk) {
       const double a = iv[2 * j], b = iv[2 * j + 1];
-      const double x0 = a + (b - a) * double(pl * tg + 1) / double(gp + 1);
-      const double x1 = a + (b - a) * double(pl * tg + 2) / double(gp + 1);
+      const double x0 = a + (b - a) * (double(pl * tg + 1) * igp);
+      const double x1 = a + (b - a) * (double(pl * tg + 2) * igp);
       double q0 = d[0] - x0, q1 = d[0] - x1;
       if (fabs(q0) < pivmin) q0 = -pivmin;
       if (fabs(q1) < pivmin) q1 = -pivmin;
@@ -1156,7 +1211,7 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
       const double a = iv[2 * j], b = iv[2 * j + 1];
       double na = a, nb = b;
       for (int u = 0; u < gp; ++u) {
-        const double xu = a + (b - a) * double(u + 1) / double(gp + 1);
+        const double xu = a + (b - a) * (double(u + 1) * igp);
         if (int(part[j * gp + u]) <= idx) na = xu;
         else if (nb == b) nb = xu;
       }
@@ -1225,7 +1280,7 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
         double nxr;
         if (fabs(w0) >= fabs(c)) {
           if (fabs(w0) < ptiny) w0 = w0 < 0.0 ? -ptiny : ptiny;
-          const double inv = 1.0 / w0;
+          const double inv = fast_rcp_signed(w0);
           const double l = c * inv;
           U1[o] = inv;  // reciprocal pivot
           U2[o] = w1;
@@ -1235,7 +1290,7 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
           w0 = a1 - l * w1;
           w1 = b1;
         } else {
-          const double inv = 1.0 / c;
+          const double inv = fast_rcp_signed(c);
           const double l = w0 * inv;
           U1[o] = inv;
           U2[o] = a1;

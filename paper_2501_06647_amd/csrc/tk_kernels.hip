@@ -74,7 +74,7 @@ struct StitchShared {
   int32_t roff[MAXP][MAXHITS + 1];  // offsets of the pieces' columns in C^(n)
   int32_t q[MAXP];                  // size of the reduced coordinates of mode n
   int32_t basis[MAXP];              // 1: C^(n) from the Cholesky basis; 0: C^(n) = V~
-  double red[4];
+  double red[8];
   int redi[4];
 };
 

@@ -70,12 +70,13 @@ tk_status issue(tk_batch* b, hipStream_t stream) {
     hipStream_t s = fork ? b->gstream[gr.slot] : stream;
     if (fork && !used[gr.slot]) TK_HIP(t, hipStreamWaitEvent(s, b->fork_ev, 0));
     if (fork) used[gr.slot] = true;
-    const size_t lds_bytes = size_t(eig_doubles(gr.n_lds)) * 8;
+    const size_t lds_bytes = size_t(gr.lds_doubles) * 8;
     StitchArgs a = base;
     a.jobs = reinterpret_cast<const Job*>(b->jobs[g].p);
     a.ws = b->ws[g].p;
     a.n_jobs = int(gr.jobs.size());
     a.n_lds = gr.n_lds;
+    a.lds_doubles = gr.lds_doubles;
     int grid = a.n_jobs;
     a.queue = nullptr;
     if (t->tuning.persistent) {
@@ -195,7 +196,7 @@ tk_status tk_batch_wait(tk_batch* b) {
   for (int32_t i = 0; i < b->n; ++i) {
     const double* s = b->hstats.data() + STAT_COUNT * size_t(i);
     if (s[STAT_STATUS] != 0.0)
-      return fail(t, TK_EDEVICE, "stitch kernel: device Recall or workspace disagrees with the host plan");
+      return fail(t, TK_EDEVICE, "stitch kernel: device Recall, workspace or LDS size disagrees with the host plan");
     tk_result& r = b->res[i];
     for (int m = 0; m < TK_MAX_MODES; ++m) r.ranks_eff[m] = m < t->p ? b->qjobs[i].rq[m] : 0;
     r.fit = s[STAT_FIT];

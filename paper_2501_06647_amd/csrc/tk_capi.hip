@@ -85,13 +85,10 @@ void lane_destroy(Lane* l) {
   l->stream = nullptr;
 }
 
-int eig_need(const StitchLayout& lo, const StoreView& st) {
-  int n = lo.sk;
-  for (int m = 1; m < st.p; ++m) {
-    const int e = lo.sr[m] < st.D[m] ? lo.sr[m] : int(st.D[m]);
-    if (e > n) n = e;
-  }
-  return n;
+int eig_need(const StitchLayout& lo, const StoreView& st) { return stitch_eig_need(lo, st); }
+
+int64_t group_lds_doubles(int n_lds, int need) {
+  return std::max(eig_doubles(n_lds), need > n_lds ? eig_vec_doubles(need) : int64_t(0));
 }
 
 int lds_cap(const tk_tree* t) {
@@ -186,6 +183,7 @@ tk_status plan_stitch(tk_tree* t, std::vector<Job>& jobs, std::vector<Hit>& hits
     const int hi = b < nb - 1 ? bounds[b] : (1 << 30);
     g[b].threads = hi <= tu.wide_threshold ? NT_STITCH : tu.wide_threads;
   }
+  std::vector<int> maxneed(static_cast<size_t>(nb), 0);
   for (Job& jb : jobs) {
     StitchLayout lo;
     stitch_layout(t->view, hits.data() + jb.hit0, jb.s, jb.rq, 1 << 30, &lo);
@@ -198,9 +196,14 @@ tk_status plan_stitch(tk_tree* t, std::vector<Job>& jobs, std::vector<Hit>& hits
         break;
       }
     g[b].jobs.push_back(jb);
+    maxneed[b] = std::max(maxneed[b], need);
   }
   for (Group& gr : g) {
     if (gr.jobs.empty()) continue;
+    const int64_t ld = group_lds_doubles(gr.n_lds, maxneed[gr.bin]);
+    if (ld * 8 + int64_t(stitch_static_lds()) > t->lds_limit)
+      return fail(t, TK_EINVAL, "eigenproblem vectors exceed the LDS limit");
+    gr.lds_doubles = int(ld);
     std::stable_sort(gr.jobs.begin(), gr.jobs.end(), [](const Job& a, const Job& b) {
       return a.s * a.L > b.s * b.L;  // longer ranges with more hits take longer
     });
@@ -230,7 +233,7 @@ namespace {
 tk_status launch_group(tk_tree* t, Lane* lane, Group& gr, const StitchArgs& base, hipStream_t stream) {
   const int64_t nj = int64_t(gr.jobs.size());
   if (nj == 0) return TK_OK;
-  const size_t lds_bytes = size_t(eig_doubles(gr.n_lds)) * 8;
+  const size_t lds_bytes = size_t(gr.lds_doubles) * 8;
   const int per_cu = t->tuning.persistent ? stitch_blocks_per_cu(gr.threads, lds_bytes) : 0;
   DevBuf* ws = &lane->ws[gr.bin];
   DevBuf* djobs = &lane->jobs[gr.bin];
@@ -255,6 +258,7 @@ tk_status launch_group(tk_tree* t, Lane* lane, Group& gr, const StitchArgs& base
     a.ws = ws->p;
     a.n_jobs = int(i1 - i0);
     a.n_lds = gr.n_lds;
+    a.lds_doubles = gr.lds_doubles;
     int grid = a.n_jobs;
     if (per_cu > 0) {
       const int64_t res = int64_t(per_cu) * t->n_cu;
@@ -693,7 +697,7 @@ tk_status tk_query_batch(tk_tree* t, int32_t n, const int64_t* ts, const int64_t
   for (int32_t i = 0; i < n; ++i) {
     const double* s = hs.data() + STAT_COUNT * size_t(i);
     if (s[STAT_STATUS] != 0.0)
-      return fail(t, TK_EDEVICE, "stitch kernel: device Recall or workspace disagrees with the host plan");
+      return fail(t, TK_EDEVICE, "stitch kernel: device Recall, workspace or LDS size disagrees with the host plan");
     for (int m = 0; m < TK_MAX_MODES; ++m) res[i].ranks_eff[m] = m < t->p ? jobs[i].rq[m] : 0;
     res[i].fit = s[STAT_FIT];
     res[i].err_model = s[STAT_ERR];

@@ -277,7 +277,11 @@ TK_HD int gram_rows_split(int ntiles, int nthreads) {
 // Doubles needed by the eigensolver for an n x n problem: the matrix, then
 // eight vectors of n (tridiagonal, reflector coefficients, eigenvalues,
 // work vectors, brackets) and 256 doubles of per-thread partial results.
-TK_HD int64_t eig_doubles(int64_t n) { return n * n + 8 * n + 256; }
+// The vector part of an eigen buffer (tridiagonal, reflector scalars,
+// eigenvalues, work vectors, brackets, workgroup partials): it can live in
+// LDS when the n x n matrix part does not.
+TK_HD int64_t eig_vec_doubles(int64_t n) { return 8 * n + 256; }
+TK_HD int64_t eig_doubles(int64_t n) { return n * n + eig_vec_doubles(n); }
 
 // Scratch of the eigensolver besides its buffer (inverse-iteration LU
 // factors and, when they do not fit in the matrix buffer, vectors: 4 n k
@@ -378,6 +382,18 @@ TK_HD void stitch_layout(const StoreView& st, const Hit* hits, int s, const int3
   Lo->TMP = take(eig_tmp_doubles(neig) * 8);
   Lo->EIG = neig > n_lds ? take(eig_doubles(neig) * 8) : -1;
   Lo->total = off;
+}
+
+// Largest eigenproblem of a stitch job: the temporal one (sk) and, per mode,
+// the reduced coordinates (q_n <= min(sr_n, D_n)).  Cholesky factorisations
+// of the trims and bases (up to neig) need no vector part.
+TK_HD int stitch_eig_need(const StitchLayout& lo, const StoreView& st) {
+  int n = lo.sk;
+  for (int m = 1; m < st.p; ++m) {
+    const int e = lo.sr[m] < st.D[m] ? lo.sr[m] : int(st.D[m]);
+    if (e > n) n = e;
+  }
+  return n;
 }
 
 // Workspace of a leaf job.

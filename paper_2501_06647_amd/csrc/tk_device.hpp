@@ -1009,15 +1009,17 @@ __device__ __forceinline__ const double* eig_top_jacobi(double* W, int n, int k,
 // The eigenvectors live in W's free upper triangle while k < n / 2 (vector
 // j in rows j and n-2-j), else in tmp.  Same contract as eig_top_jacobi (E:
 // n x k, row stride lde, descending eigenvalues; returns the k
-// eigenvalues), without warm starts.  W must hold eig_doubles(n) doubles;
-// tmp: 4 n k doubles.
+// eigenvalues), without warm starts.  W holds the n x n matrix, vec the
+// eig_vec_doubles(n) doubles of vectors and workgroup partials (W + n n when
+// both share one buffer); tmp: 4 n k doubles.  The returned eigenvalues
+// live in vec.
 __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, double* E, int lde, double* red,
-                                                     double* tmp, EigCounters* cnt) {
+                                                     double* tmp, EigCounters* cnt, double* vec) {
   __shared__ int s_flag;
   __shared__ int s_busy;
   const uint64_t t_start = wall_clock64();
   const int tid = threadIdx.x, nt = blockDim.x;
-  double* d = W + int64_t(n) * n;
+  double* d = vec;
   double* e = d + n;
   double* tau = e + n;
   double* lam = tau + n;
@@ -1474,10 +1476,10 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
 
 // The eigensolver the kernels use.
 __device__ __forceinline__ const double* eig_top(double* W, int n, int k, double* E, int lde, double* red, double* Ef,
-                                                 double* tmp, bool warm, EigCounters* cnt) {
+                                                 double* tmp, bool warm, EigCounters* cnt, double* vec) {
   (void)Ef;
   (void)warm;
-  return eig_top_tri(W, n, k, E, lde, red, tmp, cnt);
+  return eig_top_tri(W, n, k, E, lde, red, tmp, cnt, vec);
 }
 
 }  // namespace tk

@@ -41,10 +41,15 @@ struct Group {
   int bin = 0;     // index of the LDS bin (stable across calls: selects buffers)
   int slot = 0;    // fork stream of the group
   int n_lds = 0;
+  int lds_doubles = 0;  // dynamic LDS: the n_lds eigen buffer, or the vector part of the largest job's
   int threads = 64;
   std::vector<Job> jobs;
   int64_t ws_total = 0;
 };
+
+// Dynamic LDS (doubles) of a launch whose eigenproblems up to n_lds run in
+// LDS and whose largest has size need.
+int64_t group_lds_doubles(int n_lds, int need);
 
 // A stitch batch split into groups, each sorted heaviest first, with
 // workspace offsets relative to the group's buffer.

@@ -16,6 +16,8 @@ struct StitchArgs {
   int n_jobs;
   int* queue;          // non-null: persistent launch, workgroups take jobs from this counter
   int n_lds;           // eigenproblems up to n_lds x n_lds run in LDS
+  int lds_doubles;     // dynamic LDS of the launch, in doubles; larger eigenproblems keep
+                       // their vectors there (eig_vec_doubles(n) <= lds_doubles required)
   int max_iter;        // query jobs
   double tol;
   int merge_max_iter;  // merge jobs (node construction)

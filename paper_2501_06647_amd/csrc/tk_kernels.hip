@@ -79,7 +79,7 @@ struct StitchShared {
 };
 
 __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, const Hit* hits, char* ws, int n_lds,
-                           int max_iter, double tol, bool lowp, StitchShared& sh, double* lds) {
+                           int lds_doubles, int max_iter, double tol, bool lowp, StitchShared& sh, double* lds) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int p = st.p;
   const int s = job.s;
@@ -120,6 +120,10 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     if (tid == 0 && job.stats) job.stats[STAT_STATUS] = 2.0;
     return;
   }
+  if (stitch_eig_need(lo, st) > n_lds && eig_vec_doubles(stitch_eig_need(lo, st)) > lds_doubles) {  // too little LDS
+    if (tid == 0 && job.stats) job.stats[STAT_STATUS] = 3.0;
+    return;
+  }
   double* red = sh.red;
   // the ALS contractions (TTM chains, Z^(n), core update) and their Grams:
   // FP32 on the matrix cores, or BF16 operands with FP32 accumulation
@@ -135,12 +139,13 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
   auto Fp = [&](int64_t off) { return reinterpret_cast<float*>(ws + off); };
   auto Dp = [&](int64_t off) { return reinterpret_cast<double*>(ws + off); };
   double* TMP = Dp(lo.TMP);
-  // Run f on the eigen/Cholesky buffer: LDS when the problem fits, else the
-  // job's global buffer.  Calling f from two branches lets each inlined copy
-  // address its buffer directly (LDS instructions on the first).
+  // Run f on the eigen/Cholesky buffer (matrix part, vector part): both in
+  // LDS when the problem fits, else the matrix in the job's global buffer and
+  // the vectors in LDS.  Calling f from two branches lets each inlined copy
+  // address its buffers directly (LDS instructions where they are in LDS).
   auto with_buf = [&](int n, auto&& f) {
-    if (n <= n_lds) f(lds);
-    else f(Dp(lo.EIG));
+    if (n <= n_lds) f(lds, lds + int64_t(n) * n);
+    else f(Dp(lo.EIG), lds);
   };
 
   // ---- trims (Eq. "partial-tucker") and |Y~|^2 ------------------------------
@@ -163,7 +168,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     const float* V = st.plane[lev] + ((h.index << lev) * st.ell + h.a) * k;
     float* Rt = Fp(lo.T1);  // R~, kp x k
     int kp = 0;
-    with_buf(k, [&](double* Gm) {
+    with_buf(k, [&](double* Gm, double*) {
       gram_rows(V, h.l, k, Gm, k, Dp(lo.D1));
       double* d = Gm + k * k;
       int* piv = reinterpret_cast<int*>(Gm + k * k + k);
@@ -219,7 +224,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     double* C64 = Dp(lo.C64[n]);
     int use_basis = 0;
     if (sr < Dn) {
-      with_buf(sr, [&](double* Gm) {
+      with_buf(sr, [&](double* Gm, double*) {
         // Gram of V_cat = [V~_1^(n) .. V~_s^(n)] over its D_n rows, FP64 on
         // the matrix cores, then mirrored so that it is exactly symmetric
         gemm_f64(sr, sr, int(Dn), [&](int x, int dd) { return vcat(n, dd, x); },
@@ -278,7 +283,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
   // ---- HOSVD initialisation of U^(2..p) (Gram of Y~ in reduced coordinates)
   for (int n = 1; n < p; ++n) {
     const int q = sh.q[n], sr = lo.sr[n];
-    with_buf(q, [&](double* Wm) {
+    with_buf(q, [&](double* Wm, double* Wv) {
     for (int e = tid; e < q * q; e += nt) Wm[e] = 0.0;
     __syncthreads();
     double* S = Dp(lo.S);
@@ -299,7 +304,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
                [&](int j, int d2) { return C64[int64_t(d2) * sr + c0 + j]; },
                [&](int dd, int d2, double v) { Wm[dd * q + d2] += v; });
     }
-    eig_top(Wm, q, rq[n], Dp(lo.Pd[n]), rq[n], red, Dp(lo.EF[n]), TMP, false, &ec);
+    eig_top(Wm, q, rq[n], Dp(lo.Pd[n]), rq[n], red, Dp(lo.EF[n]), TMP, false, &ec, Wv);
     });
     update_A(n);
   }
@@ -336,10 +341,10 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
       }
     }
     const int sk = sh.koff[s];
-    with_buf(sk, [&](double* Wm) {
+    with_buf(sk, [&](double* Wm, double* Wv) {
       gram(M, 1, sk, Rhat[0], Wm, sk);
       clk.mark(3);
-      eig_top(Wm, sk, rq[0], Dp(lo.Pd[0]), rq[0], red, Dp(lo.EF[0]), TMP, it > 1, &ec);
+      eig_top(Wm, sk, rq[0], Dp(lo.Pd[0]), rq[0], red, Dp(lo.EF[0]), TMP, it > 1, &ec, Wv);
     });
     float* P0f = Fp(lo.Pf[0]);
     {
@@ -391,10 +396,10 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
       }
       // K_n = sum_i W_i^(n) x_n C_i: one product over the stacked mode
       ttm(Wst, ka, lo.sr[n], kb, Fp(lo.C[n]), lo.sr[n], 1, q, K, false);
-      with_buf(q, [&](double* Wn) {
+      with_buf(q, [&](double* Wn, double* Wv) {
         gram(K, ka, q, kb, Wn, q);
         clk.mark(5);
-        eig_top(Wn, q, rq[n], Dp(lo.Pd[n]), rq[n], red, Dp(lo.EF[n]), TMP, true, &ec);
+        eig_top(Wn, q, rq[n], Dp(lo.Pd[n]), rq[n], red, Dp(lo.EF[n]), TMP, true, &ec, Wv);
       });
       update_A(n);
       clk.mark(6);
@@ -588,7 +593,7 @@ __global__ __launch_bounds__(NTT, 2) void stitch_kernel(StitchArgs args) {
     }
     const Hit* hits = qh;
     const uint64_t t_begin = wall_clock64();
-    stitch_one(st, job, hits, args.ws + job.ws_off, args.n_lds,
+    stitch_one(st, job, hits, args.ws + job.ws_off, args.n_lds, args.lds_doubles,
                job.kind == 1 ? args.merge_max_iter : args.max_iter, job.kind == 1 ? args.merge_tol : args.tol,
                job.kind == 1 ? args.merge_bf16 != 0 : args.bf16 != 0, sh, lds);
     if (threadIdx.x == 0 && job.stats) {
@@ -626,13 +631,13 @@ __device__ __forceinline__ void leading_left(const float* Y, const int32_t* dims
   if (D <= N) {
     double* Wm = D <= n_lds ? lds : reinterpret_cast<double*>(ws + lo.EIG);
     gram_mode_mfma(Y, a, D, b, Wm, D);
-    eig_top(Wm, D, r, U, r, sh.red, nullptr, TMP, false, nullptr);
+    eig_top(Wm, D, r, U, r, sh.red, nullptr, TMP, false, nullptr, Wm + int64_t(D) * D);
     return;
   }
   const int Ni = int(N);
   double* Wm = Ni <= n_lds ? lds : reinterpret_cast<double*>(ws + lo.EIG);
   gram_other(Y, a, D, b, Wm, Ni);
-  const double* lam = eig_top(Wm, Ni, r, Vbuf, r, sh.red, nullptr, TMP, false, nullptr);
+  const double* lam = eig_top(Wm, Ni, r, Vbuf, r, sh.red, nullptr, TMP, false, nullptr, Wm + int64_t(Ni) * Ni);
   for (int64_t e = tid; e < int64_t(D) * r; e += nt) {
     const int d = int(e / r), j = int(e % r);
     double acc = 0.0;

@@ -56,6 +56,7 @@ struct Request {
   const float* dev_slice = nullptr;  // device append
   double t_submit = 0, t_launch = 0, t_done = 0;
   int state = REQ_QUEUED;
+  int need = 0;  // size of the query's largest eigenproblem
 };
 
 struct ClassLane {
@@ -179,6 +180,7 @@ tk_status issue_queries(Server* s, ClassLane& c) {
   std::vector<Hit> hits;
   int64_t ws = 0;
   int64_t Tb_need = 0;
+  int need = 0;
   while (!c.pending.empty() && int(jobs.size()) < s->cfg.max_batch) {
     Request* r = c.pending.front();
     if (r->Tb > s->Tb_issued) break;  // its appends are not committed yet (later queries neither)
@@ -193,6 +195,7 @@ tk_status issue_queries(Server* s, ClassLane& c) {
     jobs.push_back(jb);
     c.inflight.push_back(r);
     if (r->Tb > Tb_need) Tb_need = r->Tb;
+    if (r->need > need) need = r->need;
   }
   if (jobs.empty()) return TK_OK;
   const double tl = now_us(s->t0);
@@ -209,7 +212,8 @@ tk_status issue_queries(Server* s, ClassLane& c) {
   a.ws = c.lane.ws[0].p;
   a.n_jobs = int(jobs.size());
   a.n_lds = c.n_lds;
-  const size_t lds_bytes = size_t(eig_doubles(c.n_lds)) * 8;
+  a.lds_doubles = int(group_lds_doubles(c.n_lds, need));
+  const size_t lds_bytes = size_t(a.lds_doubles) * 8;
   int grid = a.n_jobs;
   a.queue = nullptr;
   if (t->tuning.persistent) {
@@ -254,7 +258,7 @@ tk_status poll_completions(Server* s, bool* progress) {
       const double* st = c.hstats + STAT_COUNT * i;
       int state = REQ_DONE;
       if (st[STAT_STATUS] != 0.0) {
-        t->err = "stitch kernel: device Recall or workspace disagrees with the host plan";
+        t->err = "stitch kernel: device Recall, workspace or LDS size disagrees with the host plan";
         state = REQ_FAILED;
       }
       tk_result& o = *r->res;
@@ -455,7 +459,12 @@ tk_status tk_submit_query(tk_tree* t, int64_t ts, int64_t te, tk_result* res, ui
   r->job.hit0 = 0;
   StitchLayout lo;
   stitch_layout(t->view, r->hits.data(), r->job.s, r->job.rq, 1 << 30, &lo);
-  r->cls = class_of(s, eig_need(lo, t->view));
+  r->need = eig_need(lo, t->view);
+  r->cls = class_of(s, r->need);
+  if (group_lds_doubles(s->cl[r->cls].n_lds, r->need) * 8 + int64_t(stitch_static_lds()) > t->lds_limit) {
+    delete r;
+    return TK_EINVAL;  // its eigenproblem's vectors do not fit in LDS
+  }
   stitch_layout(t->view, r->hits.data(), r->job.s, r->job.rq, s->cl[r->cls].n_lds, &lo);
   r->job.ws_bytes = lo.total;
   if (lo.total > s->cl[r->cls].ws_budget) {

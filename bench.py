@@ -288,7 +288,7 @@ def main():
     slowest = {"query": slow, "hits": hit_counts[slow], "L": int(te[slow] - ts[slow]),
                "sweeps": int(sweeps[slow]), "ranks": [int(r) for r in results[slow].ranks],
                "phases_us": {k: float(prof[slow][k]) for k in tree.PHASES},
-               "eig": {k: float(prof[slow][k]) for k in tree.COUNTERS[:4]}}
+               "eig": {k: float(prof[slow][k]) for k in tree.COUNTERS[:4] + tree.COUNTERS[7:]}}
     print("[bench] slowest query: %s" % json.dumps(slowest), file=sys.stderr, flush=True)
 
     plain = None

@@ -170,8 +170,9 @@ tk_status tk_last_query_kernel_ms(const tk_tree* t, double* ms);
  * steps, microseconds computing eigenvalues (tridiagonalisation and
  * bisection), microseconds computing eigenvectors; then the query's start
  * and end on the device clock in microseconds; then the number of
- * eigensolves whose vectors needed the Gram-Schmidt fallback.  phase_us has
- * 15 entries. */
+ * eigensolves whose vectors needed the Gram-Schmidt fallback; then the
+ * microseconds of the eigenvalue time spent tridiagonalising and of the
+ * eigenvector time spent in inverse iteration.  phase_us has 17 entries. */
 tk_status tk_last_query_profile(const tk_tree* t, int32_t i, double* phase_us);
 
 /* Override the ALS sweep cap and tolerance for later queries (not merges). */
@@ -249,7 +250,7 @@ tk_status tk_batch_hits(const tk_batch* b, int32_t i, tk_hit* out, int32_t cap, 
 void tk_batch_destroy(tk_batch* b);
 
 /* Time every candidate tuning (wide_threshold in {32, 48, 64, 96} x
- * wide_threads in {128, 256} x lds_n in {64, 96, 0} (>= the threshold) x
+ * wide_threads in {128, 256} x lds_n in {32, 48, 64, 96, 0} (>= the threshold) x
  * persistent in {0, 1} x coarse in {0, 1}) on a prepared batch of
  * the given queries (reps timed executions after one warm-up, results into
  * scratch buffers), keep the fastest on the tree and report it. */

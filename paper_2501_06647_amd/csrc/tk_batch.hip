@@ -221,7 +221,7 @@ tk_status tk_batch_kernel_ms(const tk_batch* b, double* ms) {
 tk_status tk_batch_profile(const tk_batch* b, int32_t i, double* phase_us) {
   if (!b || !phase_us || i < 0 || i >= b->n) return TK_EINVAL;
   if (b->hstats.size() != size_t(b->n) * STAT_COUNT) return TK_EINVAL;
-  for (int k = 0; k < STAT_NPHASE + 7; ++k)
+  for (int k = 0; k < STAT_NPHASE + 9; ++k)
     phase_us[k] = b->hstats[size_t(i) * STAT_COUNT + STAT_PHASE + k] *
                   (k == STAT_NPHASE + 4 || k == STAT_NPHASE + 5 ? 0.01 : 1.0);
   return TK_OK;
@@ -290,7 +290,7 @@ tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* t
   double bms = 1e300;
   const int thr[] = {32, 48, 64, 96};
   const int wth[] = {128, 256};
-  const int ldsn[] = {64, 96, 0};
+  const int ldsn[] = {32, 48, 64, 96, 0};
   for (int th : thr)
     for (int wt : wth)
       for (int ln : ldsn)

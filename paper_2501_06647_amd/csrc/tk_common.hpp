@@ -219,11 +219,13 @@ struct LeafJob {
 // other eigens, finalize); STAT_T0/STAT_T1 the job's start and end on the
 // device's 100 MHz clock; STAT_EIG_FALLBACK counts eigensolves whose vectors
 // needed the Gram-Schmidt fallback; STAT_EIG.. hold eigensolver calls, bisection steps,
-// and microseconds in the rotation loop and in the extraction.
+// and microseconds computing eigenvalues and eigenvectors; STAT_EIG_TRI and
+// STAT_EIG_INVIT the parts of those spent in tridiagonalisation and in
+// inverse iteration.
 enum {
   STAT_FIT = 0, STAT_ERR = 1, STAT_NORM = 2, STAT_SWEEPS = 3, STAT_CONV = 4, STAT_HITS = 5, STAT_STATUS = 6,
   STAT_PHASE = 8, STAT_NPHASE = 8, STAT_EIG = 16, STAT_T0 = 20, STAT_T1 = 21, STAT_EIG_FALLBACK = 22,
-  STAT_COUNT = 24
+  STAT_EIG_TRI = 23, STAT_EIG_INVIT = 24, STAT_COUNT = 26
 };
 
 // ---------------------------------------------------------------------------

@@ -781,6 +781,7 @@ __device__ __forceinline__ void pchol_basis(const double* L, const int* piv, int
 
 struct EigCounters {  // zeroed by the owner (it may live in LDS)
   uint64_t calls, sweeps, jacobi_ticks, tail_ticks, fallbacks;
+  uint64_t tri_ticks, invit_ticks;  // parts of the two above: tridiagonalisation, inverse iteration
 };
 
 // Leading eigenpairs of a symmetric positive semi-definite n x n matrix S by
@@ -1146,6 +1147,7 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
   __syncthreads();
 
   // ---- 2. eigenvalues: multisection on Sturm counts -------------------------------
+  const uint64_t t_tri = wall_clock64();
   double gmax = 0.0;
   for (int i = tid; i < n; i += nt)
     gmax = fmax(gmax, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + fabs(e[i]));
@@ -1258,6 +1260,7 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
     }
     s_busy = maxpos;
   }
+  uint64_t t_inv = 0;
   auto vectors = [&](auto X) {
   if (tid < kk) {  // start vector: a fixed pseudo-random pattern per eigenvalue
     for (int r = 0; r < n; ++r) {
@@ -1428,6 +1431,7 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
   __syncthreads();
 
   // ---- 4. back-transformation x = H_0 ... H_{n-3} y -------------------------------------
+  t_inv = wall_clock64();
   // A group of gs lanes (a power of two, inside one wavefront) per vector;
   // lane sp of a group always owns the rows r = sp (mod gs), so the groups
   // share nothing and the partial dot products are summed with shuffles:
@@ -1470,6 +1474,8 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
     cnt->sweeps += uint64_t(iters + 1);
     cnt->jacobi_ticks += t_bis - t_start;
     cnt->tail_ticks += wall_clock64() - t_bis;
+    cnt->tri_ticks += t_tri - t_start;
+    cnt->invit_ticks += t_inv - t_bis;
   }
   return lam;
 }

@@ -108,7 +108,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
 
   PhaseClock& clk = sh.clk;
   EigCounters& ec = sh.ec;
-  if (tid == 0) ec.calls = ec.sweeps = ec.jacobi_ticks = ec.tail_ticks = ec.fallbacks = 0;
+  if (tid == 0) ec.calls = ec.sweeps = ec.jacobi_ticks = ec.tail_ticks = ec.fallbacks = ec.tri_ticks = ec.invit_ticks = 0;
   clk.start();
   // the layout record lives at the head of the workspace
   StitchLayout* lop = reinterpret_cast<StitchLayout*>(ws);
@@ -537,6 +537,8 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     job.stats[STAT_EIG + 2] = double(ec.jacobi_ticks) * 0.01;
     job.stats[STAT_EIG + 3] = double(ec.tail_ticks) * 0.01;
     job.stats[STAT_EIG_FALLBACK] = double(ec.fallbacks);
+    job.stats[STAT_EIG_TRI] = double(ec.tri_ticks) * 0.01;
+    job.stats[STAT_EIG_INVIT] = double(ec.invit_ticks) * 0.01;
   }
 }
 

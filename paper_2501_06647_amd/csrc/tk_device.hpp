@@ -1270,6 +1270,10 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
   }
   __syncthreads();
   const int maxpos = s_busy;
+  // a solve's output is normalised lazily: its norm is summed during the
+  // back substitution and the scale sc applied when the next solve reads
+  // the right-hand side (or by an explicit pass after the last solve)
+  double sc = 1.0;
   for (int it = 0; it < 3; ++it) {
     if (tid < kk) {
       const int j = tid;
@@ -1277,10 +1281,10 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
       // LU of T - sg I with partial pivoting, applied to the right-hand side
       // as it is formed; U rows stored for the back substitution
       double w0 = d[0] - sg, w1 = n > 1 ? e[0] : 0.0;
-      double xr = X(j, 0);
+      double xr = X(j, 0) * sc;
       for (int r = 0; r + 1 < n; ++r) {
         const double c = e[r], a1 = d[r + 1] - sg, b1 = r + 2 < n ? e[r + 1] : 0.0;
-        const double xs = X(j, r + 1);
+        const double xs = X(j, r + 1) * sc;
         const int64_t o = int64_t(r) * kk + j;
         double nxr;
         if (fabs(w0) >= fabs(c)) {
@@ -1314,6 +1318,7 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
       // is scaled by 1e-150.
       double x1 = xr / w0, x2 = 0.0;
       X(j, n - 1) = x1;
+      double ss = x1 * x1;
       for (int r0 = n - 2; r0 >= 0; r0 -= 8) {
         double u1[8], u2[8], u3[8], rh[8];
 #pragma unroll
@@ -1339,17 +1344,20 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
               x1 *= 1e-150;
               x2 *= 1e-150;
               v *= 1e-150;
+              ss *= 1e-300;
             }
             x2 = x1;
             x1 = v;
             X(j, r) = v;
+            ss += v * v;
           }
         }
       }
-      double s = 0.0;
-      for (int r = 0; r < n; ++r) s += X(j, r) * X(j, r);
-      s = 1.0 / sqrt(s);
-      for (int r = 0; r < n; ++r) X(j, r) *= s;
+      sc = 1.0 / sqrt(ss);
+      if (it == 2 || maxpos > 0) {  // the last solve, or clusters to orthogonalise: scale now
+        for (int r = 0; r < n; ++r) X(j, r) *= sc;
+        sc = 1.0;
+      }
     }
     __syncthreads();
     // vectors of one cluster: modified Gram-Schmidt in cluster order
@@ -1370,10 +1378,15 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
     }
   }
   // Cholesky QR of the vectors (their Gram is the identity to ~eps/gap
-  // after inverse iteration; one pass leaves them orthonormal to ~eps):
-  // Gram in U1 (free now), R^T R = Gram by thread 0, rows of X times R^-1
+  // after inverse iteration; one pass leaves them orthonormal to ~eps).
+  // Gram in U1 (free now); when it is the identity to 1e-12 the vectors
+  // are kept as they are, else R^T R = Gram (right-looking, the workgroup
+  // updating the trailing block per column) and the rows of X are
+  // multiplied by R^-1 (reciprocal diagonal in U2).
   {
     double* Gq = U1;
+    double* rinv = U2;
+    double dev = 0.0;
     for (int e2 = tid; e2 < kk * kk; e2 += nt) {
       const int a = e2 / kk, b = e2 % kk;
       if (b < a) continue;
@@ -1381,37 +1394,46 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
       for (int r = 0; r < n; ++r) dt += X(a, r) * X(b, r);
       Gq[a * kk + b] = dt;
       Gq[b * kk + a] = dt;
+      dev = fmax(dev, fabs(a == b ? dt - 1.0 : dt));
     }
-    __syncthreads();
-    if (tid == 0) {
-      int ok = 1;
-      for (int j2 = 0; j2 < kk && ok; ++j2) {
-        double dg = Gq[j2 * kk + j2];
-        for (int t2 = 0; t2 < j2; ++t2) dg -= Gq[t2 * kk + j2] * Gq[t2 * kk + j2];
-        if (!(dg > 0.25)) {
+    {
+      int dummy = 0;
+      block_argmax(dev, dummy, red, reinterpret_cast<int*>(part));
+    }
+    int ok = 1;
+    if (dev > 1e-12) {
+      for (int jj = 0; jj < kk; ++jj) {
+        const double dg = Gq[jj * kk + jj];
+        if (!(dg > 0.25)) {  // the same decision on every thread
           ok = 0;
           break;
         }
-        const double rjj = sqrt(dg);
-        Gq[j2 * kk + j2] = rjj;
-        for (int c2 = j2 + 1; c2 < kk; ++c2) {
-          double v = Gq[j2 * kk + c2];
-          for (int t2 = 0; t2 < j2; ++t2) v -= Gq[t2 * kk + j2] * Gq[t2 * kk + c2];
-          Gq[j2 * kk + c2] = v / rjj;
+        const double rj = sqrt(dg), ir = 1.0 / rj;
+        __syncthreads();  // every thread has read the pivot
+        for (int c2 = jj + 1 + tid; c2 < kk; c2 += nt) Gq[jj * kk + c2] *= ir;
+        if (tid == 0) {
+          Gq[jj * kk + jj] = rj;
+          rinv[jj] = ir;
+        }
+        __syncthreads();
+        const int m2 = kk - jj - 1;
+        for (int e2 = tid; e2 < m2 * m2; e2 += nt) {
+          const int a = jj + 1 + e2 / m2, b = jj + 1 + e2 % m2;
+          if (b >= a) Gq[a * kk + b] -= Gq[jj * kk + a] * Gq[jj * kk + b];
+        }
+        __syncthreads();
+      }
+      if (ok) {
+        for (int r = tid; r < n; r += nt) {
+          for (int j2 = 0; j2 < kk; ++j2) {
+            double v = X(j2, r);
+            for (int t2 = 0; t2 < j2; ++t2) v -= X(t2, r) * Gq[t2 * kk + j2];
+            X(j2, r) = v * rinv[j2];
+          }
         }
       }
-      s_busy = ok;
     }
-    __syncthreads();
-    if (s_busy) {
-      for (int r = tid; r < n; r += nt) {
-        for (int j2 = 0; j2 < kk; ++j2) {
-          double v = X(j2, r);
-          for (int t2 = 0; t2 < j2; ++t2) v -= X(t2, r) * Gq[t2 * kk + j2];
-          X(j2, r) = v / Gq[j2 * kk + j2];
-        }
-      }
-    }
+    if (tid == 0) s_busy = ok;
     __syncthreads();
   }
   // Rayleigh quotients y^T T y (scaled back)

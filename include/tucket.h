@@ -206,8 +206,12 @@ tk_status tk_load_node(tk_tree* t, int32_t level, int64_t index, const float* co
  * eigenproblem.  Jobs up to wide_threshold run one wavefront per workgroup;
  * larger ones run wide_threads threads.  With persistent = 1 a launch has at
  * most as many workgroups as the device holds at once and each workgroup
- * takes jobs from a queue, heaviest first.  A job's result depends on the
- * tuning only through wide_threshold and wide_threads (reduction orders).
+ * takes jobs from a queue, heaviest first.  A query's mode n works in an
+ * orthonormal basis of its pieces' mode-n factor spans (sr_n concatenated
+ * columns of length D_n) when 100 sr_n < basis_pct D_n, else in the D_n
+ * coordinates.  A job's result depends on the tuning only through
+ * wide_threshold, wide_threads (reduction orders) and basis_pct (the
+ * coordinates: equal in exact arithmetic).
  * ------------------------------------------------------------------------- */
 typedef struct {
   int32_t wide_threshold; /* 16..1024, default 48                              */
@@ -219,6 +223,7 @@ typedef struct {
   int32_t lds_n;          /* largest eigenproblem kept in LDS, 0 = as large   */
                           /* as fits; else >= wide_threshold (larger ones     */
                           /* run in HBM, more jobs share a CU)                */
+  int32_t basis_pct;      /* 1..100, default 75 (see above)                   */
 } tk_tuning;
 
 tk_status tk_get_tuning(const tk_tree* t, tk_tuning* out);
@@ -251,7 +256,8 @@ void tk_batch_destroy(tk_batch* b);
 
 /* Time every candidate tuning (wide_threshold in {32, 48, 64, 96} x
  * wide_threads in {128, 256} x lds_n in {32, 48, 64, 96, 0} (>= the threshold) x
- * persistent in {0, 1} x coarse in {0, 1}) on a prepared batch of
+ * persistent in {0, 1} x coarse in {0, 1} at basis_pct 75, then basis_pct in
+ * {60, 90, 100} for the best of those) on a prepared batch of
  * the given queries (reps timed executions after one warm-up, results into
  * scratch buffers), keep the fastest on the tree and report it. */
 tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* te, int32_t reps,

@@ -61,6 +61,7 @@ void batch_free(tk_batch* b) {
 tk_status issue(tk_batch* b, hipStream_t stream) {
   tk_tree* t = b->t;
   StitchArgs base = stitch_args(t, t->q_max_iter, t->q_tol);
+  base.basis_pct = b->plan.basis_pct;
   base.hits = reinterpret_cast<Hit*>(b->hits.p);
   const bool fork = b->plan.groups.size() > 1;
   bool used[kForkStreams] = {false, false, false, false};
@@ -288,42 +289,58 @@ tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* t
   const Tuning saved = t->tuning;
   Tuning bestt = saved;
   double bms = 1e300;
+  // time the tree's current tuning on the sample; false on an error (st set)
+  auto trial = [&]() {
+    tk_batch* b = nullptr;
+    st = tk_batch_create(t, n, ts, te, res.data(), &b);
+    double sum = 0.0;
+    for (int r = 0; r <= reps && st == TK_OK; ++r) {
+      st = tk_batch_run(b);
+      if (st == TK_OK) st = tk_batch_wait(b);
+      double ms = 0.0;
+      if (st == TK_OK) st = tk_batch_kernel_ms(b, &ms);
+      if (r > 0) sum += ms;  // the first run warms up
+    }
+    tk_batch_destroy(b);
+    if (st) return false;
+    const double ms = sum / reps;
+    if (ms < bms) {
+      bms = ms;
+      bestt = t->tuning;
+    }
+    return true;
+  };
   const int thr[] = {32, 48, 64, 96};
   const int wth[] = {128, 256};
   const int ldsn[] = {32, 48, 64, 96, 0};
+  bool ok = true;
   for (int th : thr)
     for (int wt : wth)
       for (int ln : ldsn)
-      for (int pc = 0; pc < 4; ++pc) {
-        if (ln != 0 && ln < th) continue;
-        t->tuning = saved;
-        t->tuning.wide_threshold = th;
-        t->tuning.wide_threads = wt;
-        t->tuning.lds_n = ln;
-        t->tuning.persistent = pc & 1;
-        t->tuning.coarse = pc >> 1;
-        tk_batch* b = nullptr;
-        st = tk_batch_create(t, n, ts, te, res.data(), &b);
-        double sum = 0.0;
-        for (int r = 0; r <= reps && st == TK_OK; ++r) {
-          st = tk_batch_run(b);
-          if (st == TK_OK) st = tk_batch_wait(b);
-          double ms = 0.0;
-          if (st == TK_OK) st = tk_batch_kernel_ms(b, &ms);
-          if (r > 0) sum += ms;  // the first run warms up
-        }
-        tk_batch_destroy(b);
-        if (st) {
+        for (int pc = 0; pc < 4 && ok; ++pc) {
+          if (ln != 0 && ln < th) continue;
           t->tuning = saved;
-          release(&outbuf);
-          return st;
+          t->tuning.wide_threshold = th;
+          t->tuning.wide_threads = wt;
+          t->tuning.lds_n = ln;
+          t->tuning.persistent = pc & 1;
+          t->tuning.coarse = pc >> 1;
+          t->tuning.basis_pct = 75;
+          ok = trial();
         }
-        const double ms = sum / reps;
-        if (ms < bms) {
-          bms = ms;
-          bestt = t->tuning;
-        }
-      }
+  const int bpct[] = {60, 90, 100};
+  const Tuning grid_best = bestt;
+  for (int bp : bpct) {
+    if (!ok) break;
+    t->tuning = grid_best;
+    t->tuning.basis_pct = bp;
+    ok = trial();
+  }
+  if (!ok) {
+    t->tuning = saved;
+    release(&outbuf);
+    return st;
+  }
   t->tuning = bestt;
   release(&outbuf);
   if (best) {
@@ -333,6 +350,7 @@ tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* t
     best->graph = bestt.graph;
     best->coarse = bestt.coarse;
     best->lds_n = bestt.lds_n;
+    best->basis_pct = bestt.basis_pct;
   }
   if (best_ms) *best_ms = bms;
   return TK_OK;

@@ -85,7 +85,7 @@ void lane_destroy(Lane* l) {
   l->stream = nullptr;
 }
 
-int eig_need(const StitchLayout& lo, const StoreView& st) { return stitch_eig_need(lo, st); }
+int eig_need(const tk_tree* t, const StitchLayout& lo) { return stitch_eig_need(lo, t->view, t->tuning.basis_pct); }
 
 int64_t group_lds_doubles(int n_lds, int need) {
   return std::max(eig_doubles(n_lds), need > n_lds ? eig_vec_doubles(need) : int64_t(0));
@@ -105,6 +105,7 @@ StitchArgs stitch_args(tk_tree* t, int max_iter, double tol) {
   a.tol = tol;
   a.merge_max_iter = t->cfg.max_iter;
   a.merge_tol = t->cfg.tol;
+  a.basis_pct = t->tuning.basis_pct;
   a.bf16 = t->q_prec == TK_BF16 ? 1 : 0;
   a.merge_bf16 = t->cfg.prec == TK_BF16 ? 1 : 0;
   a.theta_num = t->cfg.theta_num;
@@ -165,6 +166,7 @@ void make_merge_job(tk_tree* t, int k, int64_t j, std::vector<Job>& jobs, std::v
 tk_status plan_stitch(tk_tree* t, std::vector<Job>& jobs, std::vector<Hit>& hits, Plan* plan) {
   plan->groups.clear();
   plan->n_jobs = int64_t(jobs.size());
+  plan->basis_pct = t->tuning.basis_pct;
   const int cap = lds_cap(t);
   const Tuning& tu = t->tuning;
   // bin bounds: fixed sizes plus the wide threshold, capped by the LDS limit;
@@ -187,7 +189,7 @@ tk_status plan_stitch(tk_tree* t, std::vector<Job>& jobs, std::vector<Hit>& hits
   for (Job& jb : jobs) {
     StitchLayout lo;
     stitch_layout(t->view, hits.data() + jb.hit0, jb.s, jb.rq, 1 << 30, &lo);
-    const int need = eig_need(lo, t->view);
+    const int need = eig_need(t, lo);
     if (need > EIG_MAXK_HOST) return fail(t, TK_EINVAL, "query needs an eigenproblem above 1024");
     int b = nb - 1;
     for (int k = 0; k < nb - 1; ++k)
@@ -286,6 +288,7 @@ tk_status run_plan(tk_tree* t, Lane* lane, Plan& plan, int max_iter, double tol,
     TK_HIP(t, hipMemcpyAsync(lane->hits.p, plan.hits.data(), plan.hits.size() * sizeof(Hit), hipMemcpyHostToDevice,
                              lane->stream));
   StitchArgs base = stitch_args(t, max_iter, tol);
+  base.basis_pct = plan.basis_pct;
   base.hits = reinterpret_cast<Hit*>(lane->hits.p);
   if (!fork || plan.groups.size() <= 1) {
     for (Group& gr : plan.groups) {
@@ -756,6 +759,7 @@ tk_status tk_get_tuning(const tk_tree* t, tk_tuning* out) {
   out->graph = t->tuning.graph;
   out->coarse = t->tuning.coarse;
   out->lds_n = t->tuning.lds_n;
+  out->basis_pct = t->tuning.basis_pct;
   return TK_OK;
 }
 
@@ -770,12 +774,14 @@ tk_status tk_set_tuning(tk_tree* t, const tk_tuning* in) {
   if (in->coarse != 0 && in->coarse != 1) return fail(t, TK_EINVAL, "coarse must be 0 or 1");
   if (in->lds_n != 0 && (in->lds_n < 16 || in->lds_n < in->wide_threshold))
     return fail(t, TK_EINVAL, "lds_n must be 0 or in [max(16, wide_threshold), ...]");
+  if (in->basis_pct < 1 || in->basis_pct > 100) return fail(t, TK_EINVAL, "basis_pct must be in [1, 100]");
   t->tuning.wide_threshold = in->wide_threshold;
   t->tuning.wide_threads = in->wide_threads;
   t->tuning.persistent = in->persistent;
   t->tuning.graph = in->graph;
   t->tuning.coarse = in->coarse;
   t->tuning.lds_n = in->lds_n;
+  t->tuning.basis_pct = in->basis_pct;
   return TK_OK;
 }
 

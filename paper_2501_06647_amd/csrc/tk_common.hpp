@@ -386,13 +386,23 @@ TK_HD void stitch_layout(const StoreView& st, const Hit* hits, int s, const int3
   Lo->total = off;
 }
 
+// Whether a stitch works on mode n in the coordinates of an orthonormal
+// basis of the pieces' factor spans (sr_n concatenated columns of length
+// D_n): when sr_n < pct% of D_n, i.e. when that shrinks the mode's
+// eigenproblems enough to pay for the basis (a pivoted Cholesky
+// factorisation and a triangular inverse of sr_n steps each); otherwise the
+// D_n-dimensional coordinates are used as they are.
+TK_HD bool span_basis(int sr, int64_t D, int pct) { return 100 * int64_t(sr) < int64_t(pct) * D; }
+
 // Largest eigenproblem of a stitch job: the temporal one (sk) and, per mode,
-// the reduced coordinates (q_n <= min(sr_n, D_n)).  Cholesky factorisations
-// of the trims and bases (up to neig) need no vector part.
-TK_HD int stitch_eig_need(const StitchLayout& lo, const StoreView& st) {
+// the reduced coordinates (q_n <= sr_n on the basis route, else D_n).  A
+// basis found rank-deficient falls back to D_n; that rare case keeps all
+// of its eigen buffer in the job's workspace.  Cholesky factorisations of
+// the trims and bases need no vector part.
+TK_HD int stitch_eig_need(const StitchLayout& lo, const StoreView& st, int pct) {
   int n = lo.sk;
   for (int m = 1; m < st.p; ++m) {
-    const int e = lo.sr[m] < st.D[m] ? lo.sr[m] : int(st.D[m]);
+    const int e = span_basis(lo.sr[m], st.D[m], pct) ? lo.sr[m] : int(st.D[m]);
     if (e > n) n = e;
   }
   return n;

@@ -34,6 +34,7 @@ struct Tuning {
   int graph = 1;            // prepared batches replay a captured HIP graph
   int coarse = 0;           // 1: LDS bins {32, wide_threshold, 96} instead of {24, 32, 48, 64, 96, threshold}
   int lds_n = 0;            // largest eigenproblem held in LDS (0: as large as fits); >= wide_threshold
+  int basis_pct = 75;       // mode n uses the span basis when 100 sr_n < basis_pct D_n
 };
 
 // Stitch jobs that run in one launch: same dynamic LDS (n_lds) and block size.
@@ -57,6 +58,7 @@ struct Plan {
   std::vector<Hit> hits;
   std::vector<Group> groups;
   int64_t n_jobs = 0;
+  int basis_pct = 75;  // the tuning the plan was made under
 };
 
 // A stream with the device buffers of the stitch work issued on it.  Groups
@@ -127,7 +129,7 @@ void release(DevBuf* b);
 void lane_destroy(Lane* l);
 
 // Largest eigenproblem of a stitch job (its LDS bin).
-int eig_need(const StitchLayout& lo, const StoreView& st);
+int eig_need(const tk_tree* t, const StitchLayout& lo);
 
 // Recall plus effective ranks of a query at snapshot Tb: one job (hits
 // appended to `hits`).  Output buffers from res (may be null when

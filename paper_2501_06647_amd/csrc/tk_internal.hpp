@@ -18,6 +18,7 @@ struct StitchArgs {
   int n_lds;           // eigenproblems up to n_lds x n_lds run in LDS
   int lds_doubles;     // dynamic LDS of the launch, in doubles; larger eigenproblems keep
                        // their vectors there (eig_vec_doubles(n) <= lds_doubles required)
+  int basis_pct;       // span-basis rule (tk_tuning.basis_pct) of the plan
   int max_iter;        // query jobs
   double tol;
   int merge_max_iter;  // merge jobs (node construction)

@@ -79,7 +79,8 @@ struct StitchShared {
 };
 
 __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, const Hit* hits, char* ws, int n_lds,
-                           int lds_doubles, int max_iter, double tol, bool lowp, StitchShared& sh, double* lds) {
+                           int lds_doubles, int basis_pct, int max_iter, double tol, bool lowp, StitchShared& sh,
+                           double* lds) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int p = st.p;
   const int s = job.s;
@@ -120,7 +121,8 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     if (tid == 0 && job.stats) job.stats[STAT_STATUS] = 2.0;
     return;
   }
-  if (stitch_eig_need(lo, st) > n_lds && eig_vec_doubles(stitch_eig_need(lo, st)) > lds_doubles) {  // too little LDS
+  const int eneed = stitch_eig_need(lo, st, basis_pct);
+  if (eneed > n_lds && eig_vec_doubles(eneed) > lds_doubles) {  // launched with too little LDS
     if (tid == 0 && job.stats) job.stats[STAT_STATUS] = 3.0;
     return;
   }
@@ -146,6 +148,14 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
   auto with_buf = [&](int n, auto&& f) {
     if (n <= n_lds) f(lds, lds + int64_t(n) * n);
     else f(Dp(lo.EIG), lds);
+  };
+  // the same for a mode's eigenproblem, which may exceed the planned size
+  // (a rank-deficient basis falls back to D_n): vectors in LDS only when
+  // the launch has room for them
+  auto with_eig_buf = [&](int n, auto&& f) {
+    if (n <= n_lds) f(lds, lds + int64_t(n) * n);
+    else if (eig_vec_doubles(n) <= lds_doubles) f(Dp(lo.EIG), lds);
+    else f(Dp(lo.EIG), Dp(lo.EIG) + int64_t(n) * n);
   };
 
   // ---- trims (Eq. "partial-tucker") and |Y~|^2 ------------------------------
@@ -223,7 +233,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     float* C = Fp(lo.C[n]);  // q x sr, leading dimension sr
     double* C64 = Dp(lo.C64[n]);
     int use_basis = 0;
-    if (sr < Dn) {
+    if (span_basis(sr, Dn, basis_pct)) {
       with_buf(sr, [&](double* Gm, double*) {
         // Gram of V_cat = [V~_1^(n) .. V~_s^(n)] over its D_n rows, FP64 on
         // the matrix cores, then mirrored so that it is exactly symmetric
@@ -283,7 +293,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
   // ---- HOSVD initialisation of U^(2..p) (Gram of Y~ in reduced coordinates)
   for (int n = 1; n < p; ++n) {
     const int q = sh.q[n], sr = lo.sr[n];
-    with_buf(q, [&](double* Wm, double* Wv) {
+    with_eig_buf(q, [&](double* Wm, double* Wv) {
     for (int e = tid; e < q * q; e += nt) Wm[e] = 0.0;
     __syncthreads();
     double* S = Dp(lo.S);
@@ -396,7 +406,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
       }
       // K_n = sum_i W_i^(n) x_n C_i: one product over the stacked mode
       ttm(Wst, ka, lo.sr[n], kb, Fp(lo.C[n]), lo.sr[n], 1, q, K, false);
-      with_buf(q, [&](double* Wn, double* Wv) {
+      with_eig_buf(q, [&](double* Wn, double* Wv) {
         gram(K, ka, q, kb, Wn, q);
         clk.mark(5);
         eig_top(Wn, q, rq[n], Dp(lo.Pd[n]), rq[n], red, Dp(lo.EF[n]), TMP, true, &ec, Wv);
@@ -595,7 +605,7 @@ __global__ __launch_bounds__(NTT, 2) void stitch_kernel(StitchArgs args) {
     }
     const Hit* hits = qh;
     const uint64_t t_begin = wall_clock64();
-    stitch_one(st, job, hits, args.ws + job.ws_off, args.n_lds, args.lds_doubles,
+    stitch_one(st, job, hits, args.ws + job.ws_off, args.n_lds, args.lds_doubles, args.basis_pct,
                job.kind == 1 ? args.merge_max_iter : args.max_iter, job.kind == 1 ? args.merge_tol : args.tol,
                job.kind == 1 ? args.merge_bf16 != 0 : args.bf16 != 0, sh, lds);
     if (threadIdx.x == 0 && job.stats) {

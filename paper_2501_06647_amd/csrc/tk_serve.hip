@@ -459,7 +459,7 @@ tk_status tk_submit_query(tk_tree* t, int64_t ts, int64_t te, tk_result* res, ui
   r->job.hit0 = 0;
   StitchLayout lo;
   stitch_layout(t->view, r->hits.data(), r->job.s, r->job.rq, 1 << 30, &lo);
-  r->need = eig_need(lo, t->view);
+  r->need = eig_need(t, lo);
   r->cls = class_of(s, r->need);
   if (group_lds_doubles(s->cl[r->cls].n_lds, r->need) * 8 + int64_t(stitch_static_lds()) > t->lds_limit) {
     delete r;

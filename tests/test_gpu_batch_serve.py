@@ -118,6 +118,8 @@ def test_graph_replays_equal_sync_batch(tiny, torch):
     dict(wide_threshold=16, wide_threads=256, persistent=0),
     dict(wide_threshold=32, wide_threads=256, persistent=1, graph=0),
     dict(wide_threshold=96, wide_threads=128, persistent=1),
+    dict(basis_pct=1),    # every mode in its full coordinates
+    dict(basis_pct=100),  # the span basis whenever it is smaller
 ])
 def test_tunings_keep_parity(tiny, tuning):
     wl, X, orc = tiny

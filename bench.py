@@ -31,8 +31,10 @@ HBM_TBPS = 8.0
 # step's launches) scaled by the counters of a 1 GiB reference copy (FETCH
 # reads half the bytes moved, WRITE all of them); valid only for the kernel
 # sources they were taken with.
-TRAFFIC_KERNEL_SHA = "76b20110a4ede29e"
-TRAFFIC_BYTES_PER_STEP = {"plain": {"fetch": 788.0e6, "write": 820.1e6}}
+TRAFFIC_KERNEL_SHA = "9001c1e5eeb5c8c2"
+TRAFFIC_BYTES_PER_STEP = {"plain": {"fetch": 1070.6e6, "write": 941.0e6,
+                                    "tuning": {"wide_threshold": 32, "wide_threads": 128, "persistent": 0, "graph": 1,
+                                               "coarse": 1, "lds_n": 64, "basis_pct": 75}}}
 KERNEL_SOURCES = ("tk_common.hpp", "tk_device.hpp", "tk_internal.hpp", "tk_kernels.hip")
 
 
@@ -340,6 +342,7 @@ def main():
         traffic = tb["fetch"] + tb["write"]
         traffic_detail = {"fetch_bytes": tb["fetch"], "write_bytes": tb["write"],
                           "GBps_at_kernel_ms": traffic / kernel_s / 1e9,
+                          "measured_with_tuning": tb["tuning"],
                           "source": "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE per dispatch, copy-calibrated"}
     out = {
         "metric": "range queries/sec at fixed rel. error; p50/p99 query latency vs plain GPU path",

@@ -224,6 +224,8 @@ typedef struct {
                           /* as fits; else >= wide_threshold (larger ones     */
                           /* run in HBM, more jobs share a CU)                */
   int32_t basis_pct;      /* 1..100, default 75 (see above)                   */
+  int32_t rest_threads;   /* block size of the bin above the LDS cap (its     */
+                          /* matrices in HBM): 128, 256, or 0 = wide_threads  */
 } tk_tuning;
 
 tk_status tk_get_tuning(const tk_tree* t, tk_tuning* out);
@@ -256,8 +258,9 @@ void tk_batch_destroy(tk_batch* b);
 
 /* Time every candidate tuning (wide_threshold in {32, 48, 64, 96} x
  * wide_threads in {128, 256} x lds_n in {32, 48, 64, 96, 0} (>= the threshold) x
- * persistent in {0, 1} x coarse in {0, 1} at basis_pct 75, then basis_pct in
- * {60, 90, 100} for the best of those) on a prepared batch of
+ * persistent in {0, 1} x coarse in {0, 1} at basis_pct 75 and rest_threads 0,
+ * then basis_pct in {60, 90, 100} and rest_threads in {128, 256} one after
+ * the other from the best point) on a prepared batch of
  * the given queries (reps timed executions after one warm-up, results into
  * scratch buffers), keep the fastest on the tree and report it. */
 tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* te, int32_t reps,

@@ -326,14 +326,23 @@ tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* t
           t->tuning.persistent = pc & 1;
           t->tuning.coarse = pc >> 1;
           t->tuning.basis_pct = 75;
+          t->tuning.rest_threads = 0;
           ok = trial();
         }
   const int bpct[] = {60, 90, 100};
-  const Tuning grid_best = bestt;
+  Tuning from = bestt;
   for (int bp : bpct) {
     if (!ok) break;
-    t->tuning = grid_best;
+    t->tuning = from;
     t->tuning.basis_pct = bp;
+    ok = trial();
+  }
+  const int rth[] = {128, 256};
+  from = bestt;
+  for (int rt : rth) {
+    if (!ok || rt == from.wide_threads) continue;
+    t->tuning = from;
+    t->tuning.rest_threads = rt;
     ok = trial();
   }
   if (!ok) {
@@ -351,6 +360,7 @@ tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* t
     best->coarse = bestt.coarse;
     best->lds_n = bestt.lds_n;
     best->basis_pct = bestt.basis_pct;
+    best->rest_threads = bestt.rest_threads;
   }
   if (best_ms) *best_ms = bms;
   return TK_OK;

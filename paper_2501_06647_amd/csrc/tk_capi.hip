@@ -183,7 +183,8 @@ tk_status plan_stitch(tk_tree* t, std::vector<Job>& jobs, std::vector<Hit>& hits
     g[b].bin = b;
     g[b].n_lds = b < nb - 1 ? bounds[b] : cap;
     const int hi = b < nb - 1 ? bounds[b] : (1 << 30);
-    g[b].threads = hi <= tu.wide_threshold ? NT_STITCH : tu.wide_threads;
+    const int wide = b == nb - 1 && tu.rest_threads ? tu.rest_threads : tu.wide_threads;
+    g[b].threads = hi <= tu.wide_threshold ? NT_STITCH : wide;
   }
   std::vector<int> maxneed(static_cast<size_t>(nb), 0);
   for (Job& jb : jobs) {
@@ -760,6 +761,7 @@ tk_status tk_get_tuning(const tk_tree* t, tk_tuning* out) {
   out->coarse = t->tuning.coarse;
   out->lds_n = t->tuning.lds_n;
   out->basis_pct = t->tuning.basis_pct;
+  out->rest_threads = t->tuning.rest_threads;
   return TK_OK;
 }
 
@@ -775,6 +777,8 @@ tk_status tk_set_tuning(tk_tree* t, const tk_tuning* in) {
   if (in->lds_n != 0 && (in->lds_n < 16 || in->lds_n < in->wide_threshold))
     return fail(t, TK_EINVAL, "lds_n must be 0 or in [max(16, wide_threshold), ...]");
   if (in->basis_pct < 1 || in->basis_pct > 100) return fail(t, TK_EINVAL, "basis_pct must be in [1, 100]");
+  if (in->rest_threads != 0 && in->rest_threads != 128 && in->rest_threads != 256)
+    return fail(t, TK_EINVAL, "rest_threads must be 0, 128 or 256");
   t->tuning.wide_threshold = in->wide_threshold;
   t->tuning.wide_threads = in->wide_threads;
   t->tuning.persistent = in->persistent;
@@ -782,6 +786,7 @@ tk_status tk_set_tuning(tk_tree* t, const tk_tuning* in) {
   t->tuning.coarse = in->coarse;
   t->tuning.lds_n = in->lds_n;
   t->tuning.basis_pct = in->basis_pct;
+  t->tuning.rest_threads = in->rest_threads;
   return TK_OK;
 }
 

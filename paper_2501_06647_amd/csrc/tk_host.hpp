@@ -35,6 +35,7 @@ struct Tuning {
   int coarse = 0;           // 1: LDS bins {32, wide_threshold, 96} instead of {24, 32, 48, 64, 96, threshold}
   int lds_n = 0;            // largest eigenproblem held in LDS (0: as large as fits); >= wide_threshold
   int basis_pct = 75;       // mode n uses the span basis when 100 sr_n < basis_pct D_n
+  int rest_threads = 0;     // block size of the bin above the LDS cap (0: wide_threads)
 };
 
 // Stitch jobs that run in one launch: same dynamic LDS (n_lds) and block size.

@@ -120,6 +120,7 @@ def test_graph_replays_equal_sync_batch(tiny, torch):
     dict(wide_threshold=96, wide_threads=128, persistent=1),
     dict(basis_pct=1),    # every mode in its full coordinates
     dict(basis_pct=100),  # the span basis whenever it is smaller
+    dict(wide_threshold=16, lds_n=16, rest_threads=256),  # most jobs above the LDS cap, 256 threads
 ])
 def test_tunings_keep_parity(tiny, tuning):
     wl, X, orc = tiny

@@ -693,7 +693,7 @@ __device__ __forceinline__ const float* project(const float* X, const int32_t* D
   return cur;
 }
 
-__global__ __launch_bounds__(NT_LEAF) void leaf_kernel(LeafArgs args) {
+__global__ __launch_bounds__(NT_LEAF, 2) void leaf_kernel(LeafArgs args) {
   extern __shared__ double lds[];
   __shared__ LeafShared sh;
   const StoreView& st = *args.st;

@@ -182,6 +182,15 @@ tk_status tk_set_query_iters(tk_tree* t, int32_t max_iter, double tol);
  * node store answer the same queries in FP32 and in BF16. */
 tk_status tk_set_query_prec(tk_tree* t, int32_t prec);
 
+/* Output ranks r_1..r_p of later queries (Alg. "stitch" takes the target
+ * ranks as an input): ranks[n] in [1, cfg.ranks[n]], clipped like the node
+ * ranks to what each range admits (tk_query_shape reports them); NULL
+ * restores cfg.ranks.  A range equal to one stored node is returned verbatim
+ * only at the node's own ranks, else it is stitched from that node alone.
+ * Merges keep cfg.ranks.  TK_EINVAL if out of range, TK_EBUSY while
+ * serving. */
+tk_status tk_set_query_ranks(tk_tree* t, const int32_t* ranks);
+
 tk_status tk_stats_get(const tk_tree* t, tk_stats* out);
 
 /* Node store access (checkpoint/restore and tests).  A node (level, index)

@@ -171,13 +171,22 @@ class StreamSegmentTree:
 
     # -- Sec. 6.1 query ----------------------------------------------------------
     def query(self, ts: int, te: int, max_iter: Optional[int] = None,
-              tol: Optional[float] = None):
+              tol: Optional[float] = None, ranks: Optional[Sequence[int]] = None):
         """Tucker decomposition of X[ts:te): Recall, trims, Stitch.
+        ranks: output ranks r_1..r_p, each at most the tree's (default: the
+        tree's); Alg. "stitch" takes the target ranks as an input, so a query
+        may ask for less than the nodes hold.  A range equal to one stored
+        node is returned verbatim only at the node's own ranks.
         Returns (G, [U^(1)..U^(p)], info)."""
         max_iter = self.max_iter if max_iter is None else max_iter
         tol = self.tol if tol is None else tol
+        req = self.ranks if ranks is None else tuple(int(x) for x in ranks)
+        if len(req) != len(self.ranks) or any(not (1 <= x <= R) for x, R in zip(req, self.ranks)):
+            raise ValueError("query ranks must be in [1, node rank] per mode")
+        r = effective_ranks(te - ts, self.dims, req)
         hits = self.recall(ts, te)
-        if len(hits) == 1 and hits[0][1] == self.sigma(hits[0][0]) and hits[0][2] == self.tau(hits[0][0]):
+        if len(hits) == 1 and hits[0][1] == self.sigma(hits[0][0]) and hits[0][2] == self.tau(hits[0][0]) \
+                and r == tuple(hits[0][0].H.shape):
             v = hits[0][0]
             return v.H.copy(), [U.copy() for U in v.V], {
                 "sweeps": 0, "fits": [], "converged": True, "hits": hits,
@@ -188,7 +197,6 @@ class StreamSegmentTree:
                 pieces.append(stitch_mod.Piece(v.H, list(v.V)))
             else:
                 pieces.append(stitch_mod.trim(v.H, v.V, lo - self.sigma(v), hi - lo))
-        r = effective_ranks(te - ts, self.dims, self.ranks)
         G, U, info = stitch_mod.stitch(pieces, r, max_iter, tol)
         info["hits"] = hits
         return G, U, info

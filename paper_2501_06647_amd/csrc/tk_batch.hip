@@ -264,7 +264,7 @@ tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* t
   for (int32_t i = 0; i < n; ++i) {
     if (!(ts[i] >= 0 && ts[i] < te[i] && te[i] <= t->Tb * t->ell)) return fail(t, TK_ERANGE, "query range");
     int32_t r[MAXP];
-    effective_ranks(t->p, te[i] - ts[i], t->view.D, t->cfg.ranks, r);
+    query_ranks(t, te[i] - ts[i], r);
     int64_t ce = 1;
     for (int m = 0; m < t->p; ++m) ce *= r[m];
     off[size_t(i) * (t->p + 1)] = total;

@@ -87,6 +87,12 @@ void lane_destroy(Lane* l) {
 
 int eig_need(const tk_tree* t, const StitchLayout& lo) { return stitch_eig_need(lo, t->view, t->tuning.basis_pct); }
 
+void query_ranks(const tk_tree* t, int64_t len, int32_t* out) {
+  int32_t req[MAXP];
+  for (int n = 0; n < t->p; ++n) req[n] = t->q_ranks[n] > 0 ? t->q_ranks[n] : t->cfg.ranks[n];
+  effective_ranks(t->p, len, t->view.D, req, out);
+}
+
 int64_t group_lds_doubles(int n_lds, int need) {
   return std::max(eig_doubles(n_lds), need > n_lds ? eig_vec_doubles(need) : int64_t(0));
 }
@@ -126,7 +132,7 @@ tk_status make_query_job(tk_tree* t, int64_t ts, int64_t te, int64_t Tb, const t
   jb.L = te - ts;
   jb.ts = ts;
   jb.Tb = Tb;
-  effective_ranks(t->p, te - ts, t->view.D, t->cfg.ranks, jb.rq);
+  query_ranks(t, te - ts, jb.rq);
   if (check_outputs) {
     if (!res || !res->core) return fail(t, TK_EINVAL, "null core buffer");
     for (int m = 0; m < t->p; ++m)
@@ -651,7 +657,7 @@ tk_status tk_query_shape(const tk_tree* t, int64_t ts, int64_t te, tk_shape* out
   if (t->server) return TK_EBUSY;
   if (!range_ok(t, ts, te)) return TK_ERANGE;
   std::memset(out, 0, sizeof(*out));
-  tk::effective_ranks(t->p, te - ts, t->view.D, t->cfg.ranks, out->ranks_eff);
+  tk::query_ranks(t, te - ts, out->ranks_eff);
   out->L = te - ts;
   out->core_elems = 1;
   for (int n = 0; n < t->p; ++n) out->core_elems *= out->ranks_eff[n];
@@ -749,6 +755,16 @@ tk_status tk_set_query_prec(tk_tree* t, int32_t prec) {
   if (!t || (prec != TK_F32 && prec != TK_BF16)) return TK_EINVAL;
   if (t->server) return busy(t);
   t->q_prec = prec;
+  return TK_OK;
+}
+
+tk_status tk_set_query_ranks(tk_tree* t, const int32_t* ranks) {
+  if (!t) return TK_EINVAL;
+  if (t->server) return busy(t);
+  if (ranks)
+    for (int n = 0; n < t->p; ++n)
+      if (ranks[n] < 1 || ranks[n] > t->cfg.ranks[n]) return fail(t, TK_EINVAL, "query ranks must be in [1, cfg.ranks]");
+  for (int n = 0; n < TK_MAX_MODES; ++n) t->q_ranks[n] = ranks && n < t->p ? ranks[n] : 0;
   return TK_OK;
 }
 

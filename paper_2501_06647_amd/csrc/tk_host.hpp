@@ -103,6 +103,7 @@ struct tk_tree {
   int q_max_iter = 20;
   double q_tol = 0.01;
   int q_prec = TK_F32;  // arithmetic of query stitches (merges follow cfg.prec)
+  int32_t q_ranks[TK_MAX_MODES] = {};  // output ranks of queries (0: cfg.ranks)
   int64_t lds_limit = 65536;  // dynamic + static LDS a workgroup may use
   tk::Tuning tuning;
   bool poisoned = false;
@@ -155,6 +156,8 @@ tk_status run_plan(tk_tree* t, Lane* lane, Plan& plan, int max_iter, double tol,
 tk_status commit_blocks(tk_tree* t, Lane* lane, int64_t nb, const float* Xdev);
 
 StitchArgs stitch_args(tk_tree* t, int max_iter, double tol);
+// Output ranks of a query of length len (tk_set_query_ranks, clipped).
+void query_ranks(const tk_tree* t, int64_t len, int32_t* out);
 int lds_cap(const tk_tree* t);
 
 }  // namespace tk

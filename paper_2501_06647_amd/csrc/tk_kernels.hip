@@ -86,8 +86,11 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
   const int s = job.s;
   const int32_t* rq = job.rq;
 
-  // One entire hit: the range is a stored node; return it verbatim.
-  if (s == 1 && !hits[0].partial) {
+  // One entire hit at the node's own ranks: the range is a stored node;
+  // return it verbatim.
+  bool node_ranks = s == 1 && !hits[0].partial;
+  for (int n = 0; n < p && node_ranks; ++n) node_ranks = rq[n] == st.rk[hits[0].level][n];
+  if (node_ranks) {
     const Hit h = hits[0];
     const int lev = h.level;
     wg_copy(job.out_core, st.core[lev] + h.index * st.core_elems[lev], st.core_elems[lev]);

@@ -96,6 +96,7 @@ SIGNATURES = [
                                c_i32, ctypes.POINTER(c_i32)]),
     ("tk_effective_ranks", c_i32, [ctypes.POINTER(TkConfig), c_i64, ctypes.POINTER(c_i32)]),
     ("tk_set_query_prec", c_i32, [c_vp, c_i32]),
+    ("tk_set_query_ranks", c_i32, [c_vp, c_vp]),
     ("tk_get_tuning", c_i32, [c_vp, ctypes.POINTER(TkTuning)]),
     ("tk_set_tuning", c_i32, [c_vp, ctypes.POINTER(TkTuning)]),
     ("tk_batch_create", c_i32, [c_vp, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
@@ -212,7 +213,7 @@ def _query_shapes(tree, ts, te):
     for a, b in zip(ts, te):
         if not (0 <= int(a) < int(b)):
             raise TuckerError(TK_ERANGE, "query range [%d, %d) is empty or negative" % (int(a), int(b)))
-        r = effective_ranks(tree.cfg, int(b - a))
+        r = effective_ranks(tree.query_cfg(), int(b - a))
         out.append([r, (int(b - a), r[0])] + [(tree.dims[m - 1], r[m]) for m in range(1, p)])
     return out
 
@@ -528,6 +529,27 @@ class Tree:
     def set_query_prec(self, prec: int):
         """TK_F32 or TK_BF16 arithmetic for later queries."""
         self._check(lib().tk_set_query_prec(self._h, int(prec)), "tk_set_query_prec")
+
+    def set_query_ranks(self, ranks=None):
+        """Output ranks r_1..r_p of later queries (each at most the node
+        rank); None restores the tree's ranks."""
+        if ranks is None:
+            arg = None
+        else:
+            arg = (c_i32 * MAX_MODES)(*[int(r) for r in ranks])
+        self._check(lib().tk_set_query_ranks(self._h, arg), "tk_set_query_ranks")
+        self._q_ranks = None if ranks is None else tuple(int(r) for r in ranks)
+
+    def query_cfg(self) -> TkConfig:
+        """The tree's config with the query output ranks in place of its ranks."""
+        q = getattr(self, "_q_ranks", None)
+        if q is None:
+            return self.cfg
+        c = TkConfig()
+        ctypes.pointer(c)[0] = self.cfg
+        for n, r in enumerate(q):
+            c.ranks[n] = r
+        return c
 
     # -- store access ---------------------------------------------------------------------
     def stats(self) -> dict:

@@ -144,6 +144,39 @@ def test_tunings_keep_parity(tiny, tuning):
     b.close()
 
 
+def test_query_output_ranks(tiny, torch):
+    """Queries at output ranks (3, 3, 3) below the nodes' (5, 5, 5): the
+    tiny workload's query list plus two stored nodes' own ranges (which the
+    stitch then runs on one entire hit), against the oracle's query at the
+    same ranks, three sweeps each; back at the nodes' ranks such a range is
+    the stored node again (no sweeps)."""
+    wl, X, orc = tiny
+    gpu = _gpu_tree(wl, wl.T)
+    load_store(gpu, orc)
+    gpu.set_query_ranks((3, 3, 3))
+    gpu.set_query_iters(3, 0.0)
+    ts, te = synth.queries(wl)
+    ts = np.concatenate([ts, [0, 128]])
+    te = np.concatenate([te, [64, 192]])
+    b = gpu.prepare_batch(ts, te)
+    b.run()
+    res = b.results()
+    worst = 0.0
+    for i, (a, c) in enumerate(zip(ts.tolist(), te.tolist())):
+        Go, Uo, info = orc.query(a, c, max_iter=3, tol=0.0, ranks=(3, 3, 3))
+        G, U = to_np(res[i])
+        assert G.shape == Go.shape, (a, c, G.shape, Go.shape)
+        d, orth, _, _, _ = compare(X, a, c, G, U, Go, Uo)
+        assert res[i].sweeps == info["sweeps"] and orth <= ORTH, (a, c, orth)
+        worst = max(worst, d)
+    say("output ranks (3, 3, 3): worst delta %.2e over %d queries" % (worst, len(ts)))
+    assert worst <= DELTA
+    b.close()
+    gpu.set_query_ranks(None)
+    r = gpu.query(0, 64)
+    assert r.sweeps == 0 and tuple(r.ranks) == (5, 5, 5)
+
+
 def test_autotune_picks_a_valid_tuning(torch):
     wl = synth.get("plain")
     T = 1024

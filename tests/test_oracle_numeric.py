@@ -248,6 +248,36 @@ def test_single_node_range_returns_the_node(tiny_tree_noise_free):
         assert np.array_equal(G, v.H) and all(np.array_equal(a, b) for a, b in zip(U, v.V))
 
 
+def test_query_output_ranks(tiny_tree_noise_free):
+    """Output ranks below the nodes' (Alg. "stitch" takes the target ranks
+    as an input).  Noise-free tiny data has multilinear rank (4, 4, 4) and the
+    nodes hold (5, 5, 5): asking for (4, 4, 4) still reconstructs every query
+    exactly, (3, 3, 3) leaves a positive error with factors of 3 columns, and
+    a stored node's own range at reduced ranks goes through the stitch and
+    agrees with Tucker-ALS on the node's materialised tensor."""
+    wl, X, t = tiny_tree_noise_free
+    ts, te = synth.queries(wl)
+    for a, b in list(zip(ts.tolist(), te.tolist()))[:12]:
+        G4, U4, _ = t.query(a, b, ranks=wl.true_ranks)
+        assert G4.shape == effective_ranks(b - a, wl.dims, wl.true_ranks)
+        assert relative_error(X[a:b], G4, U4) < 1e-10
+        G3, U3, _ = t.query(a, b, ranks=(3, 3, 3))
+        assert all(Un.shape[1] == min(3, Un.shape[0]) for Un in U3)
+        if b - a >= 4:
+            assert relative_error(X[a:b], G3, U3) > 1e-6
+        for Un in U3:
+            assert orthonormality_error(Un) < 1e-12
+    for v in t.complete_nodes():
+        if (t.tau(v) - t.sigma(v)) >= 16:
+            break
+    G, U, info = t.query(t.sigma(v), t.tau(v), max_iter=3, tol=0.0, ranks=(3, 3, 3))
+    assert info["sweeps"] == 3
+    Gh, Uh, _ = hooi(tucker_to_tensor(v.H, v.V), (3, 3, 3), max_iter=3, tol=0.0)
+    assert np.allclose(tucker_to_tensor(G, U), tucker_to_tensor(Gh, Uh), atol=1e-9)
+    with pytest.raises(ValueError):
+        t.query(0, 8, ranks=(6, 5, 5))
+
+
 def test_error_bound_on_noisy_tiny():
     """Prop. "err": |X - Y| / |X| <= 3 eps when X = W + E, eps = |E|/|X|."""
     wl = synth.get("tiny")

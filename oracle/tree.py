@@ -169,14 +169,41 @@ class StreamSegmentTree:
         rec(self.root)
         return [(v, max(ts, self.sigma(v)), min(te, self.tau(v))) for v in out]
 
+    def fixed_block_hits(self, ts: int, te: int, level: int) -> List[Tuple[Node, int, int]]:
+        """The fixed-block variant of the hit set (the flat partition the
+        paper compares against): every complete node of `level` (blocks of
+        leaf_len 2^level slices) that overlaps [ts, te), clipped to it; the
+        part of the range past the last complete node of that level (less
+        than one block, near the committed end) comes from Alg. "recall" on
+        that remainder.  In time order, tiling [ts, te)."""
+        if not (0 <= ts < te <= self.T):
+            raise ValueError("range [%d,%d) not inside [0,%d)" % (ts, te, self.T))
+        B = self.leaf_len << level
+        full_end = (self.T_b >> level) * B
+        level_nodes = {}
+        for v in self.complete_nodes():
+            if v.hi - v.lo == (1 << level):
+                level_nodes[v.lo >> level] = v
+        out = []
+        j = ts // B
+        while j * B < min(te, full_end):
+            v = level_nodes[j]
+            out.append((v, max(ts, j * B), min(te, (j + 1) * B)))
+            j += 1
+        if te > full_end:
+            out += self.recall(max(ts, full_end), te)
+        return out
+
     # -- Sec. 6.1 query ----------------------------------------------------------
     def query(self, ts: int, te: int, max_iter: Optional[int] = None,
-              tol: Optional[float] = None, ranks: Optional[Sequence[int]] = None):
+              tol: Optional[float] = None, ranks: Optional[Sequence[int]] = None,
+              level: Optional[int] = None):
         """Tucker decomposition of X[ts:te): Recall, trims, Stitch.
         ranks: output ranks r_1..r_p, each at most the tree's (default: the
         tree's); Alg. "stitch" takes the target ranks as an input, so a query
         may ask for less than the nodes hold.  A range equal to one stored
-        node is returned verbatim only at the node's own ranks.
+        node is returned verbatim only at the node's own ranks.  level: the
+        fixed-block hit set of that level instead of Alg. "recall".
         Returns (G, [U^(1)..U^(p)], info)."""
         max_iter = self.max_iter if max_iter is None else max_iter
         tol = self.tol if tol is None else tol
@@ -184,7 +211,7 @@ class StreamSegmentTree:
         if len(req) != len(self.ranks) or any(not (1 <= x <= R) for x, R in zip(req, self.ranks)):
             raise ValueError("query ranks must be in [1, node rank] per mode")
         r = effective_ranks(te - ts, self.dims, req)
-        hits = self.recall(ts, te)
+        hits = self.recall(ts, te) if level is None else self.fixed_block_hits(ts, te, level)
         if len(hits) == 1 and hits[0][1] == self.sigma(hits[0][0]) and hits[0][2] == self.tau(hits[0][0]) \
                 and r == tuple(hits[0][0].H.shape):
             v = hits[0][0]

@@ -278,6 +278,17 @@ def test_query_output_ranks(tiny_tree_noise_free):
         t.query(0, 8, ranks=(6, 5, 5))
 
 
+def test_fixed_block_queries_recover_noise_free_data(tiny_tree_noise_free):
+    """Queries stitched from the fixed-block hit set (level 2: blocks of 16
+    slices) reconstruct noise-free data exactly, like Alg. "recall"'s."""
+    wl, X, t = tiny_tree_noise_free
+    ts, te = synth.queries(wl)
+    for a, b in list(zip(ts.tolist(), te.tolist()))[:16]:
+        G, U, info = t.query(a, b, level=2)
+        assert all(t.tau(v) - t.sigma(v) == 4 * wl.leaf_len for v, lo, hi in info["hits"][:-1])
+        assert relative_error(X[a:b], G, U) < 1e-10
+
+
 def test_error_bound_on_noisy_tiny():
     """Prop. "err": |X - Y| / |X| <= 3 eps when X = W + E, eps = |E|/|X|."""
     wl = synth.get("tiny")

@@ -10,6 +10,7 @@ brute-force minimum of Eq. "prune-obj".
 import math
 import os
 
+import numpy as np
 import pytest
 
 from oracle.evaluate import min_hitset_size
@@ -162,3 +163,43 @@ def test_recall_rejects_out_of_range():
     for ts, te in [(0, 0), (3, 2), (-1, 2), (0, 11)]:
         with pytest.raises(ValueError):
             t.recall(ts, te)
+
+
+# --- the fixed-block hit set (the flat partition of the efficiency-accuracy comparison) ---
+
+def test_fixed_block_hits_worked_examples():
+    """Worked by hand.  64 blocks of one slice, level 2 (blocks of 4): the
+    range [5, 19) takes [4,8) clipped to [5,8), [8,12), [12,16) and [16,20)
+    clipped to [16,19).  22 blocks, level 3 (blocks of 8): only [0,8) and
+    [8,16) are complete, so [3, 21) takes [3,8), [8,16) and then Alg.
+    "recall" on [16, 21): the node [16,20) and the leaf [20,21)."""
+    t = _structure_tree(64)
+    got = [(t.sigma(v), t.tau(v), lo, hi) for v, lo, hi in t.fixed_block_hits(5, 19, 2)]
+    assert got == [(4, 8, 5, 8), (8, 12, 8, 12), (12, 16, 12, 16), (16, 20, 16, 19)]
+    t = _structure_tree(22)
+    got = [(t.sigma(v), t.tau(v), lo, hi) for v, lo, hi in t.fixed_block_hits(3, 21, 3)]
+    assert got == [(0, 8, 3, 8), (8, 16, 8, 16), (16, 20, 16, 20), (20, 21, 20, 21)]
+
+
+@pytest.mark.parametrize("T_b,leaf_len,level", [(100, 1, 3), (37, 4, 2), (256, 2, 5), (9, 1, 0)])
+def test_fixed_block_hits_tile_the_range(T_b, leaf_len, level):
+    """Every range: the hits tile it in time order, each is clipped to its
+    node, and all hits before the last complete block boundary are nodes of
+    the chosen level."""
+    t = _structure_tree(T_b, leaf_len=leaf_len)
+    T = T_b * leaf_len
+    B = leaf_len << level
+    full_end = (T_b >> level) * B
+    rng = np.random.default_rng(T_b + level)
+    for _ in range(200):
+        ts, te = sorted(rng.choice(T + 1, size=2, replace=False).tolist())
+        hits = t.fixed_block_hits(ts, te, level)
+        pos = ts
+        for v, lo, hi in hits:
+            assert lo == pos and lo < hi and t.sigma(v) <= lo and hi <= t.tau(v)
+            if hi <= full_end:
+                assert t.tau(v) - t.sigma(v) == B
+            else:
+                assert lo >= full_end
+            pos = hi
+        assert pos == te

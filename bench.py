@@ -173,6 +173,85 @@ def serve_main(args):
     print(json.dumps(out), flush=True)
 
 
+def _rel_err(X, G, Us):
+    """|X - G x_1 U1 ... x_p Up|_F / |X|_F in FP64 (the paper's error metric)."""
+    Y = np.asarray(G, dtype=np.float64)
+    for n, U in enumerate(Us):
+        Y = np.moveaxis(np.tensordot(np.asarray(U, dtype=np.float64), Y, axes=(1, n)), 0, n)
+    X = np.asarray(X, dtype=np.float64)
+    return float(np.linalg.norm((X - Y).ravel()) / max(1e-300, np.linalg.norm(X.ravel())))
+
+
+def tradeoff_main(args):
+    """The efficiency-accuracy comparison on the plain workload's
+    regime-switched synthetic series: Alg. "recall" at theta 1/2, 7/10, 9/10
+    and 1, and the fixed-block variant (blocks of about T / (2 ceil(log2 T))
+    slices), each the whole query list as one prepared batch under one
+    tuning; error of every sampled result against the raw data."""
+    import torch
+    import synth
+    from paper_2501_06647_amd import Tree
+
+    wl = synth.get(args.workload)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    X = synth.series(wl)
+    Xd = torch.from_numpy(X.astype(np.float32)).to(dev)
+    ts, te = synth.queries(wl)
+    nq = len(ts)
+    block = wl.T / (2 * math.ceil(math.log2(wl.T)))
+    level = max(0, int(round(math.log2(block / wl.leaf_len))))
+    sample = np.random.default_rng(3).choice(nq, size=min(nq, 256), replace=False)
+    settings = [("recall", th) for th in ((1, 2), (7, 10), (9, 10), (1, 1))] + [("fixed", level)]
+    tuning = None
+    rows = []
+    for kind, arg in settings:
+        theta = arg if kind == "recall" else wl.theta
+        tree = Tree(wl.dims, wl.node_ranks, wl.leaf_len, theta, wl.max_iter, wl.tol, capacity_T=wl.T)
+        tree.build(Xd)
+        if kind == "fixed":
+            tree.set_query_recall(level)
+        if tuning is None:
+            tuning, _ = tree.autotune(ts, te, reps=2)
+        else:
+            tree.set_tuning(**tuning)
+        b = tree.prepare_batch(ts, te)
+        for _ in range(args.warmup):
+            b.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kms = []
+        for _ in range(args.steps):
+            b.run()
+            kms.append(b.kernel_ms())
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t0) / args.steps
+        res = b.results()
+        hits = [len(tree.hitset(int(ts[i]), int(te[i]))) for i in range(nq)]
+        errs = []
+        for i in sample:
+            G = res[i].core.double().cpu().numpy()
+            Us = [u.double().cpu().numpy() for u in res[i].factors]
+            errs.append(_rel_err(X[int(ts[i]):int(te[i])], G, Us))
+        row = {"hit_set": "recall theta %d/%d" % arg if kind == "recall" else
+               "fixed blocks of %d slices (level %d)" % (wl.leaf_len << level, level),
+               "queries_per_s": nq / (ms / 1000.0), "ms_per_step": ms, "kernel_ms": float(np.mean(kms)),
+               "hits_mean": float(np.mean(hits)), "rel_err_mean": float(np.mean(errs)),
+               "rel_err_p90": float(np.percentile(errs, 90)), "sweeps_mean": float(np.mean([r.sweeps for r in res]))}
+        rows.append(row)
+        print("[tradeoff] %s" % json.dumps(row), file=sys.stderr, flush=True)
+        b.close()
+        tree.close()
+    out = {"metric": "efficiency-accuracy tradeoff: range queries/s and relative error vs hit-set rule",
+           "value": rows[1]["queries_per_s"], "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "%s: %s x T=%d, leaf %d, ranks %s, %d queries, error sample %d"
+                      % (wl.name, "x".join(str(d) for d in wl.dims), wl.T, wl.leaf_len, wl.node_ranks, nq,
+                         len(sample)), "tuning": tuning},
+           "settings": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +268,8 @@ def main():
     ap.add_argument("--aps", type=float, default=1000.0)
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--serve-prefix", type=int, default=4096)
+    ap.add_argument("--tradeoff", action="store_true",
+                    help="theta sweep and fixed-block variant: throughput and error per hit-set rule")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -198,6 +279,8 @@ def main():
         if args.workload == "plain":
             args.workload = "serving"
         return serve_main(args)
+    if args.tradeoff:
+        return tradeoff_main(args)
 
     import torch
     import synth

@@ -141,7 +141,8 @@ tk_status tk_append(tk_tree* t, const float* slice, int on_device);
 tk_status tk_build(tk_tree* t, const float* X, int64_t T, int on_device);
 
 /* Pruned hit set of [t_s, t_e) in time order (host-side, bit-exact
- * integer Alg. "recall").  Writes at most cap hits; *n = hits needed. */
+ * integer Alg. "recall", or the fixed-block set if tk_set_query_recall
+ * chose one).  Writes at most cap hits; *n = hits needed. */
 tk_status tk_hitset(const tk_tree* t, int64_t ts, int64_t te, tk_hit* out,
                     int32_t cap, int32_t* n);
 
@@ -190,6 +191,15 @@ tk_status tk_set_query_prec(tk_tree* t, int32_t prec);
  * Merges keep cfg.ranks.  TK_EINVAL if out of range, TK_EBUSY while
  * serving. */
 tk_status tk_set_query_ranks(tk_tree* t, const int32_t* ranks);
+
+/* Hit sets of later queries: level -1 (default) is Alg. "recall" with the
+ * tree's theta; level >= 0 the fixed-block variant of the paper's
+ * efficiency-accuracy comparison: every complete node of that level
+ * (blocks of leaf_len 2^level slices) overlapping the range, clipped, and
+ * Alg. "recall" on the part past the last complete block.  The stitch is
+ * the same; tk_hitset reports the set in use.  TK_EINVAL for a level the
+ * tree does not have, TK_EBUSY while serving. */
+tk_status tk_set_query_recall(tk_tree* t, int32_t level);
 
 tk_status tk_stats_get(const tk_tree* t, tk_stats* out);
 

@@ -129,10 +129,22 @@ tk_status tk_batch_create(tk_tree* t, int32_t n, const int64_t* ts, const int64_
   for (int32_t i = 0; i < n; ++i) jobs[i].stats = dstats + STAT_COUNT * int64_t(i);
   st = plan_stitch(t, jobs, hits, &b->plan);
   if (st) return bail(st);
-  // the kernels run Recall themselves and write the hits; the slots start zeroed
+  // the kernels run Recall themselves and write the hits; their slots start
+  // zeroed (queries on host-planned hits, kind 2, get the plan's)
   st = ensure(t, &b->hits, int64_t(hits.size() * sizeof(Hit)) + 64, "hits");
   if (st) return bail(st);
   TK_HIP(t, hipMemset(b->hits.p, 0, size_t(b->hits.cap)));
+  {
+    std::vector<Hit> planned(hits.size(), Hit{});
+    bool any = false;
+    for (const Job& jb : b->qjobs)
+      if (jb.kind == 2) {
+        for (int k = 0; k < jb.s; ++k) planned[size_t(jb.hit0 + k)] = hits[size_t(jb.hit0 + k)];
+        any = true;
+      }
+    if (any)
+      TK_HIP(t, hipMemcpy(b->hits.p, planned.data(), planned.size() * sizeof(Hit), hipMemcpyHostToDevice));
+  }
   st = ensure(t, &b->queue, kMaxGroups * 64, "queue");
   if (st) return bail(st);
   TK_HIP(t, hipMemset(b->queue.p, 0, size_t(b->queue.cap)));

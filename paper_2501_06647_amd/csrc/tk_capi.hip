@@ -87,6 +87,11 @@ void lane_destroy(Lane* l) {
 
 int eig_need(const tk_tree* t, const StitchLayout& lo) { return stitch_eig_need(lo, t->view, t->tuning.basis_pct); }
 
+int query_hits(const tk_tree* t, int64_t ts, int64_t te, int64_t Tb, Hit* out, int cap) {
+  if (t->q_level < 0) return recall(ts, te, Tb, t->ell, t->cfg.theta_num, t->cfg.theta_den, out, cap);
+  return fixed_block_hits(ts, te, Tb, t->ell, t->q_level, t->cfg.theta_num, t->cfg.theta_den, out, cap);
+}
+
 void query_ranks(const tk_tree* t, int64_t len, int32_t* out) {
   int32_t req[MAXP];
   for (int n = 0; n < t->p; ++n) req[n] = t->q_ranks[n] > 0 ? t->q_ranks[n] : t->cfg.ranks[n];
@@ -123,10 +128,10 @@ tk_status make_query_job(tk_tree* t, int64_t ts, int64_t te, int64_t Tb, const t
                          std::vector<Job>& jobs, std::vector<Hit>& hits) {
   if (!(ts >= 0 && ts < te && te <= Tb * t->ell)) return fail(t, TK_ERANGE, "query range outside [0, T_c) or empty");
   Hit buf[MAXHITS];
-  const int n = recall(ts, te, Tb, t->ell, t->cfg.theta_num, t->cfg.theta_den, buf, MAXHITS);
+  const int n = query_hits(t, ts, te, Tb, buf, MAXHITS);
   if (n < 1 || n > MAXHITS) return fail(t, TK_EINVAL, "hit set too large");
   Job jb{};
-  jb.kind = 0;
+  jb.kind = t->q_level < 0 ? 0 : 2;
   jb.s = n;
   jb.hit0 = int32_t(hits.size());
   jb.L = te - ts;
@@ -636,7 +641,7 @@ tk_status tk_hitset(const tk_tree* t, int64_t ts, int64_t te, tk_hit* out, int32
   if (t->server) return TK_EBUSY;
   if (!range_ok(t, ts, te)) return TK_ERANGE;
   Hit buf[tk::MAXHITS];
-  const int m = tk::recall(ts, te, t->Tb, t->ell, t->cfg.theta_num, t->cfg.theta_den, buf, tk::MAXHITS);
+  const int m = tk::query_hits(t, ts, te, t->Tb, buf, tk::MAXHITS);
   *n = m;
   for (int i = 0; i < m && i < cap && i < tk::MAXHITS; ++i) {
     const int64_t sig = (buf[i].index << buf[i].level) * t->ell;
@@ -755,6 +760,13 @@ tk_status tk_set_query_prec(tk_tree* t, int32_t prec) {
   if (!t || (prec != TK_F32 && prec != TK_BF16)) return TK_EINVAL;
   if (t->server) return busy(t);
   t->q_prec = prec;
+  return TK_OK;
+}
+
+tk_status tk_set_query_recall(tk_tree* t, int32_t level) {
+  if (!t || level < -1 || level >= t->nlev) return TK_EINVAL;
+  if (t->server) return busy(t);
+  t->q_level = level;
   return TK_OK;
 }
 

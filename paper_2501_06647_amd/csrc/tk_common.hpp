@@ -143,6 +143,31 @@ TK_HD int recall(int64_t ts, int64_t te, int64_t Tb, int64_t ell, int64_t num, i
   return recall_with_stack(ts, te, Tb, ell, num, den, out, cap, sk);
 }
 
+// The fixed-block hit set of [ts, te) at snapshot Tb (the flat partition of
+// the paper's efficiency-accuracy comparison): every complete node of
+// `level` (ell 2^level slices) overlapping the range, clipped to it, then
+// Alg. "recall" on the part past the last complete node of that level.  In
+// time order; writes at most cap hits and returns the number needed.
+inline int fixed_block_hits(int64_t ts, int64_t te, int64_t Tb, int64_t ell, int level, int64_t num, int64_t den,
+                            Hit* out, int cap) {
+  const int64_t B = ell << level;
+  const int64_t full_end = (Tb >> level) * B;
+  int n = 0;
+  for (int64_t j = ts / B; j * B < te && j * B < full_end; ++j, ++n) {
+    if (n >= cap) continue;
+    const int64_t lo = ts > j * B ? ts : j * B;
+    const int64_t hi = te < (j + 1) * B ? te : (j + 1) * B;
+    out[n] = Hit{level, (lo != j * B || hi != (j + 1) * B) ? 1 : 0, j, lo - j * B, hi - lo};
+  }
+  if (te > full_end) {
+    Hit rest[MAXHITS];
+    const int m = recall(ts > full_end ? ts : full_end, te, Tb, ell, num, den, rest, MAXHITS);
+    for (int i = 0; i < m && i < MAXHITS; ++i, ++n)
+      if (n < cap) out[n] = rest[i];
+  }
+  return n;
+}
+
 // Effective ranks of a len x D_1 x ... x D_{p-1} range: r_0 <= len,
 // r_n <= D_n, and r_n <= prod_{m != n} r_m, iterated to a fixed point (a mode
 // rank cannot exceed the product of the others).
@@ -189,7 +214,7 @@ TK_HD int64_t fac_elems(const StoreView& st, int k, int n) { return st.D[n] * st
 // admitted at; the kernel runs Recall on them itself, and the host's plan of
 // the same hit set only sizes the workspace (ws_bytes).
 struct Job {
-  int32_t kind;  // 0 query, 1 merge
+  int32_t kind;  // 0 query (Recall on the device), 1 merge, 2 query on host-planned hits
   int32_t s;     // hits
   int32_t hit0;  // first hit in the launch's hit array
   int32_t pad0;

@@ -104,6 +104,7 @@ struct tk_tree {
   double q_tol = 0.01;
   int q_prec = TK_F32;  // arithmetic of query stitches (merges follow cfg.prec)
   int32_t q_ranks[TK_MAX_MODES] = {};  // output ranks of queries (0: cfg.ranks)
+  int q_level = -1;                    // queries' hit sets: Alg. recall (-1) or fixed blocks of this level
   int64_t lds_limit = 65536;  // dynamic + static LDS a workgroup may use
   tk::Tuning tuning;
   bool poisoned = false;
@@ -158,6 +159,9 @@ tk_status commit_blocks(tk_tree* t, Lane* lane, int64_t nb, const float* Xdev);
 StitchArgs stitch_args(tk_tree* t, int max_iter, double tol);
 // Output ranks of a query of length len (tk_set_query_ranks, clipped).
 void query_ranks(const tk_tree* t, int64_t len, int32_t* out);
+// The hit set a query of the tree uses (tk_set_query_recall): Alg. recall or
+// fixed blocks; returns the number of hits needed.
+int query_hits(const tk_tree* t, int64_t ts, int64_t te, int64_t Tb, Hit* out, int cap);
 int lds_cap(const tk_tree* t);
 
 }  // namespace tk

@@ -207,6 +207,7 @@ tk_status issue_queries(Server* s, ClassLane& c) {
   if (Tb_need > s->Tb_done) TK_HIP(t, hipStreamWaitEvent(st_, s->commit_ev, 0));
   TK_HIP(t, hipMemcpyAsync(c.lane.jobs[0].p, jobs.data(), jobs.size() * sizeof(Job), hipMemcpyHostToDevice, st_));
   StitchArgs a = stitch_args(t, t->q_max_iter, t->q_tol);
+  TK_HIP(t, hipMemcpyAsync(c.lane.hits.p, hits.data(), hits.size() * sizeof(Hit), hipMemcpyHostToDevice, st_));
   a.hits = reinterpret_cast<Hit*>(c.lane.hits.p);
   a.jobs = reinterpret_cast<const Job*>(c.lane.jobs[0].p);
   a.ws = c.lane.ws[0].p;

@@ -97,6 +97,7 @@ SIGNATURES = [
     ("tk_effective_ranks", c_i32, [ctypes.POINTER(TkConfig), c_i64, ctypes.POINTER(c_i32)]),
     ("tk_set_query_prec", c_i32, [c_vp, c_i32]),
     ("tk_set_query_ranks", c_i32, [c_vp, c_vp]),
+    ("tk_set_query_recall", c_i32, [c_vp, c_i32]),
     ("tk_get_tuning", c_i32, [c_vp, ctypes.POINTER(TkTuning)]),
     ("tk_set_tuning", c_i32, [c_vp, ctypes.POINTER(TkTuning)]),
     ("tk_batch_create", c_i32, [c_vp, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
@@ -539,6 +540,12 @@ class Tree:
             arg = (c_i32 * MAX_MODES)(*[int(r) for r in ranks])
         self._check(lib().tk_set_query_ranks(self._h, arg), "tk_set_query_ranks")
         self._q_ranks = None if ranks is None else tuple(int(r) for r in ranks)
+
+    def set_query_recall(self, level=None):
+        """Hit sets of later queries: None for Alg. "recall", or the
+        fixed-block variant at that tree level."""
+        self._check(lib().tk_set_query_recall(self._h, -1 if level is None else int(level)),
+                    "tk_set_query_recall")
 
     def query_cfg(self) -> TkConfig:
         """The tree's config with the query output ranks in place of its ranks."""

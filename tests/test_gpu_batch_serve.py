@@ -11,8 +11,10 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import compare, load_store, oracle_tree, round_nodes, say, to_np
+from gpu_helpers import compare, level_index, load_store, oracle_tree, round_nodes, say, to_np
+from oracle import stitch as ostitch
 from oracle.tree import StreamSegmentTree
+from oracle.tucker import effective_ranks
 
 pytestmark = pytest.mark.gpu
 
@@ -175,6 +177,108 @@ def test_query_output_ranks(tiny, torch):
     gpu.set_query_ranks(None)
     r = gpu.query(0, 64)
     assert r.sweeps == 0 and tuple(r.ranks) == (5, 5, 5)
+
+
+@pytest.mark.parametrize("theta", [(1, 2), (9, 10), (1, 1)])
+def test_theta_sweep_parity(tiny, torch, theta):
+    """Alg. "recall" at other thresholds (the theta sweep of the paper's
+    efficiency-accuracy comparison).  Nodes do not depend on theta, so the
+    tiny store is loaded into a tree of that theta: device hit sets
+    bit-exact against the oracle's Recall at the same theta, results within
+    the FP32 tolerance (three sweeps)."""
+    from paper_2501_06647_amd import Tree
+    wl, X, orc = tiny
+    gpu = Tree(wl.dims, wl.node_ranks, wl.leaf_len, theta, max_iter=wl.max_iter, tol=wl.tol, capacity_T=wl.T)
+    load_store(gpu, orc)
+    gpu.set_query_iters(3, 0.0)
+    saved = orc.theta
+    orc.theta = theta
+    try:
+        ts, te = synth.queries(wl)
+        b = gpu.prepare_batch(ts, te)
+        b.run()
+        res = b.results()
+        worst, hits = 0.0, 0
+        for i, (a, c) in enumerate(zip(ts.tolist(), te.tolist())):
+            want = orc.recall(a, c)
+            got = [(h["node_id"], h["lo"], h["hi"]) for h in b.device_hits(i)]
+            assert got == [(v.id, lo, hi) for v, lo, hi in want], (a, c)
+            hits += len(want)
+            Go, Uo, info = orc.query(a, c, max_iter=3, tol=0.0)
+            G, U = to_np(res[i])
+            d, orth, _, _, _ = compare(X, a, c, G, U, Go, Uo)
+            assert orth <= ORTH and res[i].sweeps == info["sweeps"], (a, c)
+            worst = max(worst, d)
+        say("theta %d/%d: %.2f hits per query, worst delta %.2e" % (theta[0], theta[1], hits / len(ts), worst))
+        assert worst <= DELTA
+        b.close()
+    finally:
+        orc.theta = saved
+
+
+def test_fixed_block_parity(tiny, torch):
+    """The fixed-block hit set (level 2: blocks of 16 slices), queries on
+    host-planned hits: on the full tiny store, hit sets (host and device)
+    bit-exact against the oracle's and results within the FP32 tolerance;
+    on the store cut to 200 slices (12 complete blocks, the rest from Alg.
+    "recall"), the same against a 50-block oracle tree holding the same
+    nodes."""
+    wl, X, orc = tiny
+    gpu = _gpu_tree(wl, wl.T)
+    load_store(gpu, orc)
+    gpu.set_query_iters(3, 0.0)
+    gpu.set_query_recall(2)
+    ts, te = synth.queries(wl)
+    b = gpu.prepare_batch(ts, te)
+    b.run()
+    res = b.results()
+    worst = 0.0
+    for i, (a, c) in enumerate(zip(ts.tolist(), te.tolist())):
+        want = [(v.id, lo, hi) for v, lo, hi in orc.fixed_block_hits(a, c, 2)]
+        assert [(h["node_id"], h["lo"], h["hi"]) for h in b.device_hits(i)] == want, (a, c)
+        assert [(h["node_id"], h["lo"], h["hi"]) for h in gpu.hitset(a, c)] == want, (a, c)
+        Go, Uo, info = orc.query(a, c, max_iter=3, tol=0.0, level=2)
+        G, U = to_np(res[i])
+        d, orth, _, _, _ = compare(X, a, c, G, U, Go, Uo)
+        assert orth <= ORTH and res[i].sweeps == info["sweeps"], (a, c)
+        worst = max(worst, d)
+    b.close()
+    # the store cut to 50 blocks: the last 8 slices come from Alg. "recall"
+    T50 = 200
+    g50 = _gpu_tree(wl, wl.T)
+    g50.restore_begin(T50)
+    by_range = {}
+    for v in orc.complete_nodes():
+        if v.hi <= T50 // wl.leaf_len:
+            k, j = level_index(v)
+            g50.load_node(k, j, v.H, v.V)
+            by_range[(v.lo, v.hi)] = v
+    g50.set_query_iters(3, 0.0)
+    g50.set_query_recall(2)
+    so = _structure_oracle(wl, T50)
+    rng = np.random.default_rng(11)
+    pairs = [(int(a), T50) for a in rng.choice(T50, size=6, replace=False)] + [(190, 199), (3, 196)]
+    for a, c in pairs:
+        hits = so.fixed_block_hits(a, c, 2)
+        got = [(h["node_id"], h["lo"], h["hi"]) for h in g50.hitset(a, c)]
+        assert got == [(v.id, lo, hi) for v, lo, hi in hits], (a, c)
+        pieces = []
+        for v, lo, hi in hits:
+            node = by_range[(v.lo, v.hi)]
+            if lo == so.sigma(v) and hi == so.tau(v):
+                pieces.append(ostitch.Piece(node.H, list(node.V)))
+            else:
+                pieces.append(ostitch.trim(node.H, node.V, lo - so.sigma(v), hi - lo))
+        r = g50.query(a, c)
+        if len(hits) == 1 and hits[0][1] == so.sigma(hits[0][0]) and hits[0][2] == so.tau(hits[0][0]):
+            continue
+        Go, Uo, info = ostitch.stitch(pieces, effective_ranks(c - a, wl.dims, wl.node_ranks), 3, 0.0)
+        G, U = to_np(r)
+        d, orth, _, _, _ = compare(X, a, c, G, U, Go, Uo)
+        assert orth <= ORTH and r.sweeps == info["sweeps"], (a, c)
+        worst = max(worst, d)
+    say("fixed blocks (level 2): worst delta %.2e" % worst)
+    assert worst <= DELTA
 
 
 def test_autotune_picks_a_valid_tuning(torch):

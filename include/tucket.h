@@ -192,6 +192,17 @@ tk_status tk_set_query_prec(tk_tree* t, int32_t prec);
  * serving. */
 tk_status tk_set_query_ranks(tk_tree* t, const int32_t* ranks);
 
+/* Tucker-ALS from scratch on raw ranges (the accuracy reference and naive
+ * baseline of the paper's comparisons): X[i] is a DEVICE array of L[i]
+ * slices (L[i] x D_2 x ... x D_p floats, C order), res[i] sized by
+ * tk_query_shape for a range of that length (same output ranks as a query,
+ * tk_set_query_ranks included).  HOSVD init of U^(2..p), sweeps from the
+ * temporal mode, the query sweep cap and tolerance, fields filled as for a
+ * query (err_model against X, n_hits 0).  One workgroup per range, all
+ * ranges in one launch (chunked by workspace); synchronous on the tree's
+ * stream.  TK_EINVAL for null buffers or L outside [1, 2^30]. */
+tk_status tk_raw_tucker(tk_tree* t, int32_t n, const float* const* X, const int64_t* L, tk_result* res);
+
 /* Hit sets of later queries: level -1 (default) is Alg. "recall" with the
  * tree's theta; level >= 0 the fixed-block variant of the paper's
  * efficiency-accuracy comparison: every complete node of that level

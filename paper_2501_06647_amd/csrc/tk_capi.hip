@@ -728,6 +728,98 @@ tk_status tk_query(tk_tree* t, int64_t ts, int64_t te, tk_result* res) {
   return tk_query_batch(t, 1, &ts, &te, res);
 }
 
+tk_status tk_raw_tucker(tk_tree* t, int32_t n, const float* const* X, const int64_t* L, tk_result* res) {
+  using namespace tk;
+  if (!t || n < 0 || (n > 0 && (!X || !L || !res))) return TK_EINVAL;
+  if (t->server) return busy(t);
+  if (t->poisoned) return TK_EDEVICE;
+  if (n == 0) return TK_OK;
+  const int p = t->p;
+  int cap = 128;
+  while (cap > 8 && int64_t(eig_doubles(cap)) * 8 > t->lds_limit - int64_t(leaf_static_lds())) cap -= 8;
+  std::vector<RawJob> jobs(static_cast<size_t>(n));
+  int neig = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    if (!X[i] || L[i] < 1 || L[i] > (int64_t(1) << 30)) return fail(t, TK_EINVAL, "raw range: null data or bad length");
+    if (!res[i].core) return fail(t, TK_EINVAL, "null core buffer");
+    RawJob& jb = jobs[size_t(i)];
+    jb = RawJob{};
+    jb.X = X[i];
+    jb.L = L[i];
+    query_ranks(t, L[i], jb.rq);
+    jb.out_core = res[i].core;
+    for (int m = 0; m < p; ++m) {
+      if (!res[i].factor[m]) return fail(t, TK_EINVAL, "null factor buffer");
+      jb.out_fac[m] = res[i].factor[m];
+    }
+    int32_t Dm[MAXP];
+    Dm[0] = int32_t(L[i]);
+    for (int m = 1; m < p; ++m) Dm[m] = int32_t(t->view.D[m]);
+    LeafLayout lo;
+    raw_layout(p, Dm, jb.rq, 1 << 30, &lo);
+    if (lo.neig > EIG_MAXK_HOST) return fail(t, TK_EINVAL, "raw range needs an eigenproblem above 1024");
+    if (lo.neig > neig) neig = lo.neig;
+  }
+  const int n_lds = neig < cap ? neig : cap;
+  const size_t lds_bytes = size_t(eig_doubles(n_lds)) * 8;
+  std::vector<int64_t> bytes(static_cast<size_t>(n));
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t Dm[MAXP];
+    Dm[0] = int32_t(L[i]);
+    for (int m = 1; m < p; ++m) Dm[m] = int32_t(t->view.D[m]);
+    LeafLayout lo;
+    raw_layout(p, Dm, jobs[size_t(i)].rq, n_lds, &lo);
+    bytes[size_t(i)] = lo.total;
+  }
+  Lane* lane = &t->main;
+  tk_status st = ensure(t, &lane->stats, int64_t(n) * STAT_COUNT * 8, "stats");
+  if (st) return st;
+  TK_HIP(t, hipMemsetAsync(lane->stats.p, 0, size_t(n) * STAT_COUNT * 8, lane->stream));
+  double* dstats = reinterpret_cast<double*>(lane->stats.p);
+  RawArgs a{};
+  a.p = p;
+  for (int m = 1; m < p; ++m) a.D[m] = int32_t(t->view.D[m]);
+  a.n_lds = n_lds;
+  a.max_iter = t->q_max_iter;
+  a.tol = t->q_tol;
+  int32_t i0 = 0;
+  while (i0 < n) {
+    int64_t ws = 0;
+    int32_t i1 = i0;
+    while (i1 < n && i1 - i0 < kMaxJobsPerLaunch && (i1 == i0 || ws + bytes[size_t(i1)] <= kWsChunkBytes)) {
+      jobs[size_t(i1)].ws_off = ws;
+      jobs[size_t(i1)].stats = dstats + STAT_COUNT * int64_t(i1);
+      ws += bytes[size_t(i1)];
+      ++i1;
+    }
+    if (i0 > 0) TK_HIP(t, hipStreamSynchronize(lane->stream));  // buffers are reused by this chunk
+    st = ensure(t, &lane->leaf_ws, ws + 256, "workspace");
+    if (st) return st;
+    st = ensure(t, &lane->leaf_jobs, int64_t(i1 - i0) * int64_t(sizeof(RawJob)), "jobs");
+    if (st) return st;
+    TK_HIP(t, hipMemcpyAsync(lane->leaf_jobs.p, jobs.data() + i0, size_t(i1 - i0) * sizeof(RawJob),
+                             hipMemcpyHostToDevice, lane->stream));
+    a.jobs = reinterpret_cast<const RawJob*>(lane->leaf_jobs.p);
+    a.ws = lane->leaf_ws.p;
+    TK_HIP(t, launch_raw(a, i1 - i0, lds_bytes, lane->stream));
+    i0 = i1;
+  }
+  std::vector<double> hs(size_t(n) * STAT_COUNT, 0.0);
+  TK_HIP(t, hipMemcpyAsync(hs.data(), dstats, hs.size() * 8, hipMemcpyDeviceToHost, lane->stream));
+  TK_HIP(t, hipStreamSynchronize(lane->stream));
+  for (int32_t i = 0; i < n; ++i) {
+    const double* s = hs.data() + STAT_COUNT * size_t(i);
+    for (int m = 0; m < TK_MAX_MODES; ++m) res[i].ranks_eff[m] = m < p ? jobs[size_t(i)].rq[m] : 0;
+    res[i].fit = s[STAT_FIT];
+    res[i].err_model = s[STAT_ERR];
+    res[i].norm_ytilde = s[STAT_NORM];
+    res[i].sweeps = int32_t(s[STAT_SWEEPS]);
+    res[i].converged = int32_t(s[STAT_CONV]);
+    res[i].n_hits = 0;
+  }
+  return TK_OK;
+}
+
 tk_status tk_last_query_kernel_ms(const tk_tree* t, double* ms) {
   if (!t || !ms) return TK_EINVAL;
   if (!t->ev_valid) return TK_EINVAL;

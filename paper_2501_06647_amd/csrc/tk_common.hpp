@@ -489,4 +489,94 @@ TK_HD void leaf_layout(const StoreView& st, int n_lds, LeafLayout* Lo) {
   Lo->total = off;
 }
 
+// Tucker-ALS from scratch on a raw range (the paper's accuracy reference
+// and naive baseline): X holds L slices, C order.
+struct RawJob {
+  const float* X;
+  int64_t L;
+  int32_t rq[MAXP];
+  float* out_core;
+  float* out_fac[MAXP];
+  double* stats;
+  int64_t ws_off;
+};
+
+// Largest intermediate of the projections X x_{m != skip} U_m^T (every skip,
+// and the core), taking modes in the order of the block kernels: the largest
+// D_m / r_m reduction first.
+TK_HD int64_t projection_max_elems(int p, const int32_t* Dm, const int32_t* rq) {
+  int64_t best = 0;
+  for (int skip = -1; skip < p; ++skip) {
+    int64_t dims[MAXP];
+    bool done[MAXP];
+    for (int m = 0; m < p; ++m) {
+      dims[m] = Dm[m];
+      done[m] = false;
+    }
+    for (int step = 0; step < p; ++step) {
+      int pick = -1;
+      double ratio = 0.0;
+      for (int m = 0; m < p; ++m) {
+        if (m == skip || done[m]) continue;
+        const double r = double(Dm[m]) / double(rq[m]);
+        if (pick < 0 || r > ratio) {
+          pick = m;
+          ratio = r;
+        }
+      }
+      if (pick < 0) break;
+      done[pick] = true;
+      dims[pick] = rq[pick];
+      int64_t e = 1;
+      for (int m = 0; m < p; ++m) e *= dims[m];
+      if (e > best) best = e;
+    }
+  }
+  return best;
+}
+
+// Workspace of a raw-range job (LeafLayout fields): factors, two projection
+// buffers, the other-side vectors, the core and the eigen scratch.  The
+// HOSVD initialises modes 1..p-1 only (the sweep starts with mode 0), so no
+// Gram of the L x L side is formed.
+TK_HD void raw_layout(int p, const int32_t* Dm, const int32_t* rq, int n_lds, LeafLayout* Lo) {
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t o = off;
+    off = align256(off + (bytes > 0 ? bytes : 0));
+    return o;
+  };
+  int64_t size = 1;
+  for (int n = 0; n < p; ++n) size *= Dm[n];
+  int neig = 0;
+  int64_t vmax = 0;
+  for (int n = 0; n < p; ++n) {
+    Lo->Ud[n] = take(int64_t(Dm[n]) * rq[n] * 8);
+    Lo->Uf[n] = take(int64_t(Dm[n]) * rq[n] * 4);
+    int64_t other = 1;
+    for (int m = 0; m < p; ++m)
+      if (m != n) other *= rq[m];
+    const int64_t other0 = size / Dm[n];
+    if (n > 0) {
+      const int64_t e1 = Dm[n] < other0 ? Dm[n] : other0;
+      if (e1 > neig) neig = int(e1);
+      if (Dm[n] > other0 && other0 * rq[n] > vmax) vmax = other0 * rq[n];
+    }
+    const int64_t e2 = Dm[n] < other ? Dm[n] : other;
+    if (e2 > neig) neig = int(e2);
+    if (Dm[n] > other && other * rq[n] > vmax) vmax = other * rq[n];
+  }
+  const int64_t tsz = projection_max_elems(p, Dm, rq);
+  Lo->T1 = take(tsz * 4);
+  Lo->T2 = take(tsz * 4);
+  Lo->V = take(vmax * 8);
+  int64_t gel = 1;
+  for (int n = 0; n < p; ++n) gel *= rq[n];
+  Lo->G = take(gel * 4);
+  Lo->neig = neig;
+  Lo->TMP = take(eig_tmp_doubles(neig) * 8);
+  Lo->EIG = neig > n_lds ? take(eig_doubles(neig) * 8) : -1;
+  Lo->total = off;
+}
+
 }  // namespace tk

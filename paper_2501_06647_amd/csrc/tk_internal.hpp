@@ -37,12 +37,24 @@ struct LeafArgs {
   double tol;
 };
 
+struct RawArgs {
+  const RawJob* jobs;
+  char* ws;
+  int p;
+  int32_t D[MAXP];  // D[1..p-1]: slice dimensions
+  int n_lds;
+  int max_iter;
+  double tol;
+};
+
 // threads: 64 (one wavefront per job), 128 or 256 (jobs with large
 // eigenproblems).  grid <= n_jobs; with a.queue set the grid may be smaller
 // than n_jobs and the queue counter must read 0 at launch (reset_queue).
 hipError_t launch_stitch(const StitchArgs& a, int grid, size_t lds_bytes, int threads, hipStream_t stream);
 hipError_t launch_reset_queue(int* queue, int n, hipStream_t stream);
 hipError_t launch_leaf(const LeafArgs& a, int n_jobs, size_t lds_bytes, hipStream_t stream);
+// one NT_LEAF workgroup per raw range
+hipError_t launch_raw(const RawArgs& a, int n_jobs, size_t lds_bytes, hipStream_t stream);
 hipError_t set_lds_limits(size_t stitch_bytes, size_t leaf_bytes);
 // workgroups of the stitch kernel with `threads` threads and lds_bytes of
 // dynamic LDS that one CU holds at once

@@ -696,24 +696,22 @@ __device__ __forceinline__ const float* project(const float* X, const int32_t* D
   return cur;
 }
 
-__global__ __launch_bounds__(NT_LEAF, 2) void leaf_kernel(LeafArgs args) {
-  extern __shared__ double lds[];
-  __shared__ LeafShared sh;
-  const StoreView& st = *args.st;
-  const LeafJob job = args.jobs[blockIdx.x];
-  char* ws = args.ws + job.ws_off;
+struct AlsResult {
+  double fit, nx2, g2;
+  int sweeps, conv;
+};
+
+// Tucker-ALS of an explicit block X (Dm[0] x ... x Dm[p-1], C order) at
+// ranks rq: HOSVD init of U^(init_from..p-1), sweeps over every mode from
+// mode 0, the fit stop rule of the stitch.  Leaves the FP32 factors in the
+// workspace (lo.Uf) and the core in lo.G.
+__device__ __forceinline__ AlsResult block_tucker_als(const float* X, const int32_t* Dm, const int32_t* rq, int p,
+                                                      int init_from, int max_iter, double tol, int n_lds,
+                                                      double* lds, char* ws, const LeafLayout& lo, LeafShared& sh) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int p = st.p;
-  if (tid == 0) leaf_layout(st, args.n_lds, &sh.lo);
-  __syncthreads();
-  const LeafLayout& lo = sh.lo;
-  const int32_t* rq = st.rk[0];
-  int32_t Dm[MAXP];
-  Dm[0] = int32_t(st.ell);
-  for (int n = 1; n < p; ++n) Dm[n] = int32_t(st.D[n]);
   const int64_t size = prod_range(Dm, 0, p);
   double part = 0.0;
-  for (int64_t e = tid; e < size; e += nt) part += double(job.X[e]) * double(job.X[e]);
+  for (int64_t e = tid; e < size; e += nt) part += double(X[e]) * double(X[e]);
   const double nx2 = block_sum(part, sh.red);
 
   float* Uf[MAXP];
@@ -731,21 +729,21 @@ __global__ __launch_bounds__(NT_LEAF, 2) void leaf_kernel(LeafArgs args) {
     __syncthreads();
   };
   // HOSVD: U^(n) = leading left singular vectors of mat_n(X)
-  for (int n = 0; n < p; ++n) {
-    leading_left(job.X, Dm, p, n, rq[n], Ud[n], Vbuf, args.n_lds, lds, ws, lo, sh);
+  for (int n = init_from; n < p; ++n) {
+    leading_left(X, Dm, p, n, rq[n], Ud[n], Vbuf, n_lds, lds, ws, lo, sh);
     to_f32(n);
   }
   double fit = 0.0, fit_prev = 0.0, g2 = 0.0;
   int sweeps = 0, conv = 0;
-  for (int it = 1; it <= args.max_iter; ++it) {
+  for (int it = 1; it <= max_iter; ++it) {
     for (int n = 0; n < p; ++n) {
       int32_t dims[MAXP];
-      const float* Y = project(job.X, Dm, p, n, Uf, rq, T1, T2, dims);
-      leading_left(Y, dims, p, n, rq[n], Ud[n], Vbuf, args.n_lds, lds, ws, lo, sh);
+      const float* Y = project(X, Dm, p, n, Uf, rq, T1, T2, dims);
+      leading_left(Y, dims, p, n, rq[n], Ud[n], Vbuf, n_lds, lds, ws, lo, sh);
       to_f32(n);
     }
     int32_t dims[MAXP];
-    const float* Gc = project(job.X, Dm, p, -1, Uf, rq, T1, T2, dims);
+    const float* Gc = project(X, Dm, p, -1, Uf, rq, T1, T2, dims);
     const int64_t gel = prod_range(rq, 0, p);
     part = 0.0;
     for (int64_t e = tid; e < gel; e += nt) {
@@ -755,25 +753,71 @@ __global__ __launch_bounds__(NT_LEAF, 2) void leaf_kernel(LeafArgs args) {
     g2 = block_sum(part, sh.red);
     fit = nx2 > 0.0 ? 1.0 - sqrt(fmax(0.0, nx2 - g2)) / sqrt(nx2) : 1.0;
     sweeps = it;
-    if (it >= 2 && fabs(fit - fit_prev) < args.tol) {
+    if (it >= 2 && fabs(fit - fit_prev) < tol) {
       conv = 1;
       break;
     }
     fit_prev = fit;
   }
+  return AlsResult{fit, nx2, g2, sweeps, conv};
+}
+
+__device__ __forceinline__ void als_stats(double* stats, const AlsResult& r) {
+  if (threadIdx.x == 0 && stats) {
+    stats[STAT_FIT] = r.fit;
+    stats[STAT_ERR] = r.nx2 > 0.0 ? sqrt(fmax(0.0, r.nx2 - r.g2)) / sqrt(r.nx2) : 0.0;
+    stats[STAT_NORM] = sqrt(r.nx2);
+    stats[STAT_SWEEPS] = double(r.sweeps);
+    stats[STAT_CONV] = double(r.conv);
+    stats[STAT_HITS] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(NT_LEAF, 2) void leaf_kernel(LeafArgs args) {
+  extern __shared__ double lds[];
+  __shared__ LeafShared sh;
+  const StoreView& st = *args.st;
+  const LeafJob job = args.jobs[blockIdx.x];
+  char* ws = args.ws + job.ws_off;
+  const int p = st.p;
+  if (threadIdx.x == 0) leaf_layout(st, args.n_lds, &sh.lo);
+  __syncthreads();
+  const LeafLayout& lo = sh.lo;
+  const int32_t* rq = st.rk[0];
+  int32_t Dm[MAXP];
+  Dm[0] = int32_t(st.ell);
+  for (int n = 1; n < p; ++n) Dm[n] = int32_t(st.D[n]);
+  const AlsResult r = block_tucker_als(job.X, Dm, rq, p, 0, args.max_iter, args.tol, args.n_lds, lds, ws, lo, sh);
   // store the leaf: core, non-temporal factors, temporal rows
   const int64_t b = job.block;
+  const float* G = reinterpret_cast<const float*>(ws + lo.G);
   wg_copy(st.core[0] + b * st.core_elems[0], G, st.core_elems[0]);
-  for (int n = 1; n < p; ++n) wg_copy(st.fac[0][n] + b * fac_elems(st, 0, n), Uf[n], fac_elems(st, 0, n));
-  wg_copy(st.plane[0] + b * st.ell * rq[0], Uf[0], st.ell * rq[0]);
-  if (tid == 0 && job.stats) {
-    job.stats[STAT_FIT] = fit;
-    job.stats[STAT_ERR] = nx2 > 0.0 ? sqrt(fmax(0.0, nx2 - g2)) / sqrt(nx2) : 0.0;
-    job.stats[STAT_NORM] = sqrt(nx2);
-    job.stats[STAT_SWEEPS] = double(sweeps);
-    job.stats[STAT_CONV] = double(conv);
-    job.stats[STAT_HITS] = 0.0;
-  }
+  for (int n = 1; n < p; ++n)
+    wg_copy(st.fac[0][n] + b * fac_elems(st, 0, n), reinterpret_cast<const float*>(ws + lo.Uf[n]),
+            fac_elems(st, 0, n));
+  wg_copy(st.plane[0] + b * st.ell * rq[0], reinterpret_cast<const float*>(ws + lo.Uf[0]), st.ell * rq[0]);
+  als_stats(job.stats, r);
+}
+
+// Tucker-ALS from scratch on one raw range per workgroup (HOSVD of modes
+// 1..p-1, sweeps from the temporal mode), written to the job's outputs.
+__global__ __launch_bounds__(NT_LEAF, 2) void raw_kernel(RawArgs args) {
+  extern __shared__ double lds[];
+  __shared__ LeafShared sh;
+  const RawJob job = args.jobs[blockIdx.x];
+  char* ws = args.ws + job.ws_off;
+  const int p = args.p;
+  int32_t Dm[MAXP];
+  Dm[0] = int32_t(job.L);
+  for (int n = 1; n < p; ++n) Dm[n] = args.D[n];
+  if (threadIdx.x == 0) raw_layout(p, Dm, job.rq, args.n_lds, &sh.lo);
+  __syncthreads();
+  const LeafLayout& lo = sh.lo;
+  const AlsResult r = block_tucker_als(job.X, Dm, job.rq, p, 1, args.max_iter, args.tol, args.n_lds, lds, ws, lo, sh);
+  wg_copy(job.out_core, reinterpret_cast<const float*>(ws + lo.G), prod_range(job.rq, 0, p));
+  for (int n = 0; n < p; ++n)
+    wg_copy(job.out_fac[n], reinterpret_cast<const float*>(ws + lo.Uf[n]), int64_t(Dm[n]) * job.rq[n]);
+  als_stats(job.stats, r);
 }
 
 // ------------------------------------------------------------------------------
@@ -804,6 +848,12 @@ hipError_t launch_reset_queue(int* queue, int n, hipStream_t stream) {
   return hipGetLastError();
 }
 
+hipError_t launch_raw(const RawArgs& a, int n_jobs, size_t lds_bytes, hipStream_t stream) {
+  if (n_jobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(raw_kernel, dim3(n_jobs), dim3(NT_LEAF), lds_bytes, stream, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_leaf(const LeafArgs& a, int n_jobs, size_t lds_bytes, hipStream_t stream) {
   if (n_jobs <= 0) return hipSuccess;
   hipLaunchKernelGGL(leaf_kernel, dim3(n_jobs), dim3(NT_LEAF), lds_bytes, stream, a);
@@ -818,8 +868,11 @@ hipError_t set_lds_limits(size_t stitch_bytes, size_t leaf_bytes) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(stitch_bytes));
     if (e != hipSuccess) return e;
   }
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(leaf_kernel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, int(leaf_bytes));
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(leaf_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(leaf_bytes));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(raw_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             int(leaf_bytes));
 }
 
 int stitch_blocks_per_cu(int threads, size_t lds_bytes) {

@@ -98,6 +98,7 @@ SIGNATURES = [
     ("tk_set_query_prec", c_i32, [c_vp, c_i32]),
     ("tk_set_query_ranks", c_i32, [c_vp, c_vp]),
     ("tk_set_query_recall", c_i32, [c_vp, c_i32]),
+    ("tk_raw_tucker", c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp]),
     ("tk_get_tuning", c_i32, [c_vp, ctypes.POINTER(TkTuning)]),
     ("tk_set_tuning", c_i32, [c_vp, ctypes.POINTER(TkTuning)]),
     ("tk_batch_create", c_i32, [c_vp, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
@@ -472,6 +473,37 @@ class Tree:
     def prepare_batch(self, ts, te) -> "PreparedBatch":
         """Plan a fixed list of queries once; run() replays them."""
         return PreparedBatch(self, ts, te)
+
+    def raw_tucker(self, X, ts, te) -> List[QueryResult]:
+        """tk_raw_tucker: Tucker-ALS from scratch on the ranges [ts_i, te_i)
+        of the series X (T x D_2 x ... x D_p; moved to the device if it is
+        not there), at the query output ranks."""
+        X = self._device_f32(X)
+        assert tuple(X.shape[1:]) == self.dims
+        ts = np.asarray(ts, dtype=np.int64).reshape(-1)
+        te = np.asarray(te, dtype=np.int64).reshape(-1)
+        n = len(ts)
+        if n and (te.max() > X.shape[0] or ts.min() < 0):
+            raise TuckerError(TK_ERANGE, "raw range outside the series")
+        p = self.p
+        shapes_all = _query_shapes(self, ts, te)
+        buf, views = self._alloc([s for shp in shapes_all for s in shp])
+        res = (TkResult * max(n, 1))()
+        outputs = []
+        k = 0
+        for i in range(n):
+            core, facs = views[k], views[k + 1:k + 1 + p]
+            k += 1 + p
+            res[i].core = core.data_ptr()
+            for m in range(p):
+                res[i].factor[m] = facs[m].data_ptr()
+            outputs.append((core, facs))
+        slice_bytes = int(np.prod(self.dims)) * 4
+        ptrs = (c_vp * max(n, 1))(*[X.data_ptr() + int(a) * slice_bytes for a in ts])
+        lens = (c_i64 * max(n, 1))(*(te - ts).tolist())
+        if n:
+            self._check(lib().tk_raw_tucker(self._h, n, ptrs, lens, res), "tk_raw_tucker")
+        return [QueryResult(c, f, res[i], p) for i, (c, f) in enumerate(outputs)]
 
     def query_batch(self, ts, te) -> List[QueryResult]:
         """tk_query_batch: one synchronous batched call."""

@@ -31,8 +31,8 @@ HBM_TBPS = 8.0
 # step's launches) scaled by the counters of a 1 GiB reference copy (FETCH
 # reads half the bytes moved, WRITE all of them); valid only for the kernel
 # sources they were taken with.
-TRAFFIC_KERNEL_SHA = "4c47f7b5668f2095"
-TRAFFIC_BYTES_PER_STEP = {"plain": {"fetch": 1076.8e6, "write": 941.0e6,
+TRAFFIC_KERNEL_SHA = "d0a3affeaacb61d3"
+TRAFFIC_BYTES_PER_STEP = {"plain": {"fetch": 1076.5e6, "write": 940.9e6,
                                     "tuning": {"wide_threshold": 32, "wide_threads": 128, "persistent": 0, "graph": 1,
                                                "coarse": 1, "lds_n": 64, "basis_pct": 75, "rest_threads": 256}}}
 KERNEL_SOURCES = ("tk_common.hpp", "tk_device.hpp", "tk_internal.hpp", "tk_kernels.hip")

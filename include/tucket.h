@@ -292,7 +292,7 @@ void tk_batch_destroy(tk_batch* b);
  * then basis_pct in {60, 90, 100} and rest_threads in {128, 256} one after
  * the other from the best point) on a prepared batch of
  * the given queries (reps timed executions after one warm-up, results into
- * scratch buffers); the four fastest are timed again with 3 reps
+ * scratch buffers); the eight fastest are timed again with 3 reps
  * executions, and the fastest of those is kept on the tree and reported. */
 tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* te, int32_t reps,
                       tk_tuning* best, double* best_ms);

@@ -363,7 +363,7 @@ tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* t
     t->tuning.rest_threads = rt;
     ok = trial();
   }
-  // single timings pick the luckiest point: the four fastest are timed
+  // single timings pick the luckiest point: the eight fastest are timed
   // again, three times as long, and the best mean wins
   if (ok && timed.size() > 1) {
     std::stable_sort(timed.begin(), timed.end(),
@@ -371,7 +371,7 @@ tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* t
                        return x.first < y.first;
                      });
     bms = 1e300;
-    for (size_t c = 0; c < timed.size() && c < 4 && ok; ++c) {
+    for (size_t c = 0; c < timed.size() && c < 8 && ok; ++c) {
       t->tuning = timed[c].second;
       double ms = 0.0;
       ok = time_it(3 * reps, &ms);

@@ -1,0 +1,73 @@
+"""More modes than the workloads have: p = 5 and p = 6 (the kernels take
+up to six modes), built on the device and queried, against the oracle.
+
+Bars: every node's relative error within 1e-5 of the oracle's (ratio
+form); queries within 1e-5, the same sweep counts, factor orthonormality
+<= 1e-6; Tucker-ALS from scratch on raw ranges the same.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import compare, oracle_tree, say, to_np
+from oracle.evaluate import relative_error
+from oracle.tucker import effective_ranks, hooi
+
+pytestmark = pytest.mark.gpu
+
+DELTA = 1e-5
+ORTH = 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.mark.parametrize("dims,ranks,seed", [
+    ((6, 5, 4, 3), (3, 3, 2, 2, 2), 2001),
+    ((4, 3, 3, 3, 2), (3, 2, 2, 2, 2, 2), 2002),
+])
+def test_many_modes_parity(torch, dims, ranks, seed):
+    from paper_2501_06647_amd import Tree
+    wl = synth.Workload("modes%d" % (len(dims) + 1), dims, 64, ranks, 0.05, 2, ranks, 24, "pairs", seed=seed)
+    X = synth.series(wl)
+    T = wl.T
+    gpu = Tree(wl.dims, wl.node_ranks, wl.leaf_len, wl.theta, max_iter=wl.max_iter, tol=wl.tol, capacity_T=T)
+    gpu.build(X.astype(np.float32))
+    orc = oracle_tree(wl, X.astype(np.float32).astype(np.float64), T)
+    worst = 0.0
+    for v in orc.complete_nodes():
+        k = (v.hi - v.lo).bit_length() - 1
+        core, facs = gpu.read_node(k, v.lo >> k)
+        Xi = X[orc.sigma(v):orc.tau(v)]
+        e_g = relative_error(Xi, core.astype(np.float64), [f.astype(np.float64) for f in facs])
+        e_o = relative_error(Xi, v.H, v.V)
+        worst = max(worst, abs(e_g / e_o - 1.0) if e_o > 0 else e_g)
+    say("p=%d: worst node delta %.2e over %d nodes" % (len(dims) + 1, worst, len(orc.complete_nodes())))
+    assert worst <= DELTA
+    ts, te = synth.queries(wl)
+    res = gpu.query_batch(ts, te)
+    worst = 0.0
+    for r, a, c in zip(res, ts.tolist(), te.tolist()):
+        Go, Uo, info = orc.query(a, c)
+        G, U = to_np(r)
+        d, orth, _, _, _ = compare(X, a, c, G, U, Go, Uo)
+        assert orth <= ORTH and r.sweeps == info["sweeps"], (a, c)
+        worst = max(worst, d)
+    say("p=%d: worst query delta %.2e over %d queries" % (len(dims) + 1, worst, len(ts)))
+    assert worst <= DELTA
+    raw = gpu.raw_tucker(X.astype(np.float32), ts[:8], te[:8])
+    worst = 0.0
+    for r, a, c in zip(raw, ts[:8].tolist(), te[:8].tolist()):
+        rq = effective_ranks(c - a, wl.dims, wl.node_ranks)
+        Go, Uo, info = hooi(X[a:c].astype(np.float32).astype(np.float64), rq, wl.max_iter, wl.tol)
+        G, U = to_np(r)
+        d, orth, _, _, _ = compare(X, a, c, G, U, Go, Uo)
+        assert orth <= ORTH and r.sweeps == info["sweeps"], (a, c)
+        worst = max(worst, d)
+    say("p=%d: raw Tucker-ALS worst delta %.2e" % (len(dims) + 1, worst))
+    assert worst <= DELTA

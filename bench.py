@@ -271,6 +271,79 @@ def tradeoff_main(args):
     print(json.dumps(out), flush=True)
 
 
+def pscale_main(args):
+    """Query latency and throughput against the number of modes on the
+    paper's many-mode shapes (every slice 10^6 elements, rank 5 per mode,
+    400 slices, leaf 1): p = 4, 5 and 6; queries of 98, 192 and 384 slices
+    from seeded random starts, one at a time (latency) and as one prepared
+    batch (throughput)."""
+    import torch
+    import synth
+    from synth.workloads import d5
+    from paper_2501_06647_amd import Tree
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rows = []
+    for p in (4, 5, 6):
+        wl = d5(p)
+        tree = Tree(wl.dims, wl.node_ranks, wl.leaf_len, wl.theta, wl.max_iter, wl.tol, capacity_T=wl.T)
+        gen_s, build_s = 0.0, 0.0
+        for t0 in range(0, wl.T, 128):
+            g0 = time.perf_counter()
+            X = synth.series(wl, t0, min(wl.T, t0 + 128)).astype(np.float32)
+            Xd = torch.from_numpy(X).to(dev)
+            gen_s += time.perf_counter() - g0
+            torch.cuda.synchronize()
+            b0 = time.perf_counter()
+            tree.build(Xd)
+            torch.cuda.synchronize()
+            build_s += time.perf_counter() - b0
+            print("[pscale] p=%d: slices [%d, %d) generated and appended" % (p, t0, min(wl.T, t0 + 128)),
+                  file=sys.stderr, flush=True)
+            del X, Xd
+        print("[pscale] p=%d %s: data %.1f s, build %.2f s" % (p, "x".join(str(d) for d in wl.dims), gen_s, build_s),
+              file=sys.stderr, flush=True)
+        rng = np.random.default_rng(40 + p)
+        tts = rng.integers(0, wl.T - 192 + 1, size=64).astype(np.int64)
+        tuning, _ = tree.autotune(tts, tts + 192, reps=1)
+        print("[pscale] p=%d autotune: %s" % (p, tuning), file=sys.stderr, flush=True)
+        for L in (98, 192, 384):
+            ts = rng.integers(0, wl.T - L + 1, size=64).astype(np.int64)
+            te = ts + L
+            lat = []
+            for a, c in zip(ts[:16].tolist(), te[:16].tolist()):
+                t1 = time.perf_counter()
+                tree.query(a, c)
+                lat.append(time.perf_counter() - t1)
+            b = tree.prepare_batch(ts, te)
+            for _ in range(args.warmup):
+                b.run()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                b.run()
+            torch.cuda.synchronize()
+            ms = 1000.0 * (time.perf_counter() - t1) / args.steps
+            res = b.results()
+            hits = [len(tree.hitset(int(a), int(c))) for a, c in zip(ts, te)]
+            row = {"p": p, "dims": list(wl.dims), "L": L, "tuning": tuning, "latency_p50_ms": 1000.0 * float(np.median(lat)),
+                   "latency_p99_ms": 1000.0 * float(np.percentile(lat, 99)), "batch_queries": len(ts),
+                   "batch_queries_per_s": len(ts) / (ms / 1000.0), "hits_mean": float(np.mean(hits)),
+                   "sweeps_mean": float(np.mean([r.sweeps for r in res]))}
+            rows.append(row)
+            print("[pscale] %s" % json.dumps(row), file=sys.stderr, flush=True)
+            b.close()
+        tree.close()
+    out = {"metric": "range-query latency vs number of modes (many-mode shapes, rank 5)",
+           "value": rows[-1]["latency_p50_ms"], "unit": "ms", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "slices of 10^6 elements (100^3, 100^2 x 10^2, 100 x 10^4), 400 slices, leaf 1, "
+                                  "rank 5, queries of 98/192/384 slices"},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -287,6 +360,7 @@ def main():
     ap.add_argument("--aps", type=float, default=1000.0)
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--serve-prefix", type=int, default=4096)
+    ap.add_argument("--pscale", action="store_true", help="latency against the number of modes (p = 4..6)")
     ap.add_argument("--tradeoff", action="store_true",
                     help="theta sweep and fixed-block variant: throughput and error per hit-set rule")
     args = ap.parse_args()
@@ -300,6 +374,8 @@ def main():
         return serve_main(args)
     if args.tradeoff:
         return tradeoff_main(args)
+    if args.pscale:
+        return pscale_main(args)
 
     import torch
     import synth

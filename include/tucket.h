@@ -256,6 +256,8 @@ typedef struct {
   int32_t basis_pct;      /* 1..100, default 75 (see above)                   */
   int32_t rest_threads;   /* block size of the bin above the LDS cap (its     */
                           /* matrices in HBM): 128, 256, or 0 = wide_threads  */
+  int32_t wide_core;      /* jobs whose core has more elements run in wide    */
+                          /* workgroups whatever their eigenproblems (0: off) */
 } tk_tuning;
 
 tk_status tk_get_tuning(const tk_tree* t, tk_tuning* out);
@@ -288,9 +290,10 @@ void tk_batch_destroy(tk_batch* b);
 
 /* Time every candidate tuning (wide_threshold in {32, 48, 64, 96} x
  * wide_threads in {128, 256} x lds_n in {32, 48, 64, 96, 0} (>= the threshold) x
- * persistent in {0, 1} x coarse in {0, 1} at basis_pct 75 and rest_threads 0,
- * then basis_pct in {60, 90, 100} and rest_threads in {128, 256} one after
- * the other from the best point) on a prepared batch of
+ * persistent in {0, 1} x coarse in {0, 1} at basis_pct 75, rest_threads 0
+ * and wide_core 0, then basis_pct in {60, 90, 100}, rest_threads in {128,
+ * 256} and wide_core in {2048, 8192} one after the other from the best
+ * point) on a prepared batch of
  * the given queries (reps timed executions after one warm-up, results into
  * scratch buffers); the eight fastest are timed again with 3 reps
  * executions, and the fastest of those is kept on the tree and reported. */

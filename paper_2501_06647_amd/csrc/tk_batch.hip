@@ -345,6 +345,7 @@ tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* t
           t->tuning.coarse = pc >> 1;
           t->tuning.basis_pct = 75;
           t->tuning.rest_threads = 0;
+          t->tuning.wide_core = 0;
           ok = trial();
         }
   const int bpct[] = {60, 90, 100};
@@ -361,6 +362,14 @@ tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* t
     if (!ok || rt == from.wide_threads) continue;
     t->tuning = from;
     t->tuning.rest_threads = rt;
+    ok = trial();
+  }
+  const int wcs[] = {2048, 8192};
+  from = bestt;
+  for (int wc : wcs) {
+    if (!ok) break;
+    t->tuning = from;
+    t->tuning.wide_core = wc;
     ok = trial();
   }
   // single timings pick the luckiest point: the eight fastest are timed
@@ -397,6 +406,7 @@ tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* t
     best->lds_n = bestt.lds_n;
     best->basis_pct = bestt.basis_pct;
     best->rest_threads = bestt.rest_threads;
+    best->wide_core = bestt.wide_core;
   }
   if (best_ms) *best_ms = bms;
   return TK_OK;

@@ -201,8 +201,13 @@ tk_status plan_stitch(tk_tree* t, std::vector<Job>& jobs, std::vector<Hit>& hits
   for (Job& jb : jobs) {
     StitchLayout lo;
     stitch_layout(t->view, hits.data() + jb.hit0, jb.s, jb.rq, 1 << 30, &lo);
-    const int need = eig_need(t, lo);
+    int need = eig_need(t, lo);
     if (need > EIG_MAXK_HOST) return fail(t, TK_EINVAL, "query needs an eigenproblem above 1024");
+    if (tu.wide_core > 0 && need <= tu.wide_threshold) {  // small eigenproblems, large contractions
+      int64_t core = 1;
+      for (int m = 0; m < t->p; ++m) core *= jb.rq[m];
+      if (core > tu.wide_core) need = tu.wide_threshold + 1;
+    }
     int b = nb - 1;
     for (int k = 0; k < nb - 1; ++k)
       if (need <= bounds[k]) {
@@ -882,6 +887,7 @@ tk_status tk_get_tuning(const tk_tree* t, tk_tuning* out) {
   out->lds_n = t->tuning.lds_n;
   out->basis_pct = t->tuning.basis_pct;
   out->rest_threads = t->tuning.rest_threads;
+  out->wide_core = t->tuning.wide_core;
   return TK_OK;
 }
 
@@ -899,6 +905,7 @@ tk_status tk_set_tuning(tk_tree* t, const tk_tuning* in) {
   if (in->basis_pct < 1 || in->basis_pct > 100) return fail(t, TK_EINVAL, "basis_pct must be in [1, 100]");
   if (in->rest_threads != 0 && in->rest_threads != 128 && in->rest_threads != 256)
     return fail(t, TK_EINVAL, "rest_threads must be 0, 128 or 256");
+  if (in->wide_core < 0) return fail(t, TK_EINVAL, "wide_core must be >= 0");
   t->tuning.wide_threshold = in->wide_threshold;
   t->tuning.wide_threads = in->wide_threads;
   t->tuning.persistent = in->persistent;
@@ -907,6 +914,7 @@ tk_status tk_set_tuning(tk_tree* t, const tk_tuning* in) {
   t->tuning.lds_n = in->lds_n;
   t->tuning.basis_pct = in->basis_pct;
   t->tuning.rest_threads = in->rest_threads;
+  t->tuning.wide_core = in->wide_core;
   return TK_OK;
 }
 

@@ -36,6 +36,7 @@ struct Tuning {
   int lds_n = 0;            // largest eigenproblem held in LDS (0: as large as fits); >= wide_threshold
   int basis_pct = 75;       // mode n uses the span basis when 100 sr_n < basis_pct D_n
   int rest_threads = 0;     // block size of the bin above the LDS cap (0: wide_threads)
+  int wide_core = 0;        // cores above this many elements run wide (0: off)
 };
 
 // Stitch jobs that run in one launch: same dynamic LDS (n_lds) and block size.

@@ -58,7 +58,7 @@ class TkStats(ctypes.Structure):
 class TkTuning(ctypes.Structure):
     _fields_ = [("wide_threshold", c_i32), ("wide_threads", c_i32), ("persistent", c_i32), ("graph", c_i32),
                 ("coarse", c_i32), ("lds_n", c_i32), ("basis_pct", c_i32),
-                ("rest_threads", c_i32)]
+                ("rest_threads", c_i32), ("wide_core", c_i32)]
 
 
 class TkServeConfig(ctypes.Structure):

@@ -87,6 +87,19 @@ WORKLOADS = {
 }
 
 
+# The paper's many-mode shapes (every slice 10^6 elements; time first):
+# 1000x1000, 100x100x100, 100x100x10x10, 100x10x10x10x10 (and a sixth
+# non-temporal mode of 10 at p = 7), rank 5 in every mode, here over 400
+# slices of one regime so that queries of 98, 192 and 384 slices fit.
+D5_SHAPES = {3: (1000, 1000), 4: (100, 100, 100), 5: (100, 100, 10, 10), 6: (100, 10, 10, 10, 10),
+             7: (10, 10, 10, 10, 10, 10)}
+
+
+def d5(p: int, T: int = 400) -> Workload:
+    dims = D5_SHAPES[p]
+    return Workload("d5_p%d" % p, dims, T, (5,) * p, 0.05, 1, (5,) * p, 256, "uniform_len", seed=3000 + p)
+
+
 def get(name: str) -> Workload:
     return WORKLOADS[name]
 

@@ -123,6 +123,7 @@ def test_graph_replays_equal_sync_batch(tiny, torch):
     dict(basis_pct=1),    # every mode in its full coordinates
     dict(basis_pct=100),  # the span basis whenever it is smaller
     dict(wide_threshold=16, lds_n=16, rest_threads=256),  # most jobs above the LDS cap, 256 threads
+    dict(wide_core=64),  # every tiny core (125 elements) in wide workgroups
 ])
 def test_tunings_keep_parity(tiny, tuning):
     wl, X, orc = tiny

@@ -195,15 +195,29 @@ class StreamSegmentTree:
         return out
 
     # -- Sec. 6.1 query ----------------------------------------------------------
+    def provisional_piece(self, tail):
+        """The decomposition of an incomplete block (1 <= m < leaf_len slices
+        appended past the last complete block): the leaf procedure (Tucker-ALS,
+        node ranks clipped to length m) on those slices; nothing is stored."""
+        X = np.asarray(tail, dtype=np.float64)
+        if not (1 <= X.shape[0] < self.leaf_len):
+            raise ValueError("a tail has 1 .. leaf_len-1 slices")
+        r = effective_ranks(X.shape[0], self.dims, self.ranks)
+        G, U, _ = hooi(X, r, self.max_iter, self.tol)
+        return canonical_signs(G, U)
+
     def query(self, ts: int, te: int, max_iter: Optional[int] = None,
               tol: Optional[float] = None, ranks: Optional[Sequence[int]] = None,
-              level: Optional[int] = None):
+              level: Optional[int] = None, tail=None):
         """Tucker decomposition of X[ts:te): Recall, trims, Stitch.
         ranks: output ranks r_1..r_p, each at most the tree's (default: the
         tree's); Alg. "stitch" takes the target ranks as an input, so a query
         may ask for less than the nodes hold.  A range equal to one stored
         node is returned verbatim only at the node's own ranks.  level: the
-        fixed-block hit set of that level instead of Alg. "recall".
+        fixed-block hit set of that level instead of Alg. "recall".  tail:
+        the slices appended past the last complete block; a range reaching
+        into them takes the provisional piece of that block, trimmed like a
+        partial hit, after the hits of its committed part.
         Returns (G, [U^(1)..U^(p)], info)."""
         max_iter = self.max_iter if max_iter is None else max_iter
         tol = self.tol if tol is None else tol
@@ -211,22 +225,38 @@ class StreamSegmentTree:
         if len(req) != len(self.ranks) or any(not (1 <= x <= R) for x, R in zip(req, self.ranks)):
             raise ValueError("query ranks must be in [1, node rank] per mode")
         r = effective_ranks(te - ts, self.dims, req)
-        hits = self.recall(ts, te) if level is None else self.fixed_block_hits(ts, te, level)
+        Tc = self.T
+        m = 0 if tail is None else len(tail)
+        if not (0 <= ts < te <= Tc + m):
+            raise ValueError("range [%d,%d) not inside [0,%d)" % (ts, te, Tc + m))
+        tec = min(te, Tc)
+        hits = []
+        if ts < tec:
+            hits = self.recall(ts, tec) if level is None else self.fixed_block_hits(ts, tec, level)
+        if te > Tc:
+            H, V = self.provisional_piece(tail)
+            lo = max(ts, Tc)
+            G, U, info = stitch_mod.stitch(
+                [self._piece(v, a, b) for v, a, b in hits] + [stitch_mod.trim(H, V, lo - Tc, te - lo)],
+                r, max_iter, tol)
+            info["hits"] = hits
+            info["tail"] = (lo, te)
+            return G, U, info
         if len(hits) == 1 and hits[0][1] == self.sigma(hits[0][0]) and hits[0][2] == self.tau(hits[0][0]) \
                 and r == tuple(hits[0][0].H.shape):
             v = hits[0][0]
             return v.H.copy(), [U.copy() for U in v.V], {
                 "sweeps": 0, "fits": [], "converged": True, "hits": hits,
                 "err_model": None, "norm_ytilde": None}
-        pieces = []
-        for v, lo, hi in hits:
-            if lo == self.sigma(v) and hi == self.tau(v):
-                pieces.append(stitch_mod.Piece(v.H, list(v.V)))
-            else:
-                pieces.append(stitch_mod.trim(v.H, v.V, lo - self.sigma(v), hi - lo))
-        G, U, info = stitch_mod.stitch(pieces, r, max_iter, tol)
+        G, U, info = stitch_mod.stitch([self._piece(v, lo, hi) for v, lo, hi in hits], r, max_iter, tol)
         info["hits"] = hits
         return G, U, info
+
+    def _piece(self, v: Node, lo: int, hi: int):
+        """A hit as a piece: the node itself, or its trim to [lo, hi)."""
+        if lo == self.sigma(v) and hi == self.tau(v):
+            return stitch_mod.Piece(v.H, list(v.V))
+        return stitch_mod.trim(v.H, v.V, lo - self.sigma(v), hi - lo)
 
     def pieces(self, ts: int, te: int):
         """The pieces Y~_i of a query (after trims), for the checks."""

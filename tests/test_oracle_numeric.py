@@ -289,6 +289,32 @@ def test_fixed_block_queries_recover_noise_free_data(tiny_tree_noise_free):
         assert relative_error(X[a:b], G, U) < 1e-10
 
 
+def test_tail_queries_recover_noise_free_data():
+    """Ranges reaching into an incomplete block take that block's provisional
+    piece (the leaf procedure on its slices), trimmed like a partial hit.
+    Noise-free tiny data, 63 complete blocks of 4 slices and a tail of 3:
+    every range ending in the tail reconstructs exactly, ranges inside the
+    tail included; a range inside the committed part is unaffected."""
+    wl = synth.get("tiny")
+    X = synth.series(wl, noise=0.0)
+    t = StreamSegmentTree(wl.dims, wl.node_ranks, wl.leaf_len, wl.theta, max_iter=6, tol=0.0)
+    for b in range(63):
+        t.append(X[b * wl.leaf_len:(b + 1) * wl.leaf_len])
+    Tc = t.T
+    tail = X[Tc:Tc + 3]
+    for a, c in [(0, 255), (100, 253), (250, 254), (252, 255), (253, 255), (254, 255)]:
+        G, U, info = t.query(a, c, tail=tail)
+        assert info["tail"] == (max(a, Tc), c)
+        assert relative_error(X[a:c], G, U) < 1e-10
+        for Un in U:
+            assert orthonormality_error(Un) < 1e-12
+    G1, U1, _ = t.query(10, 200)
+    G2, U2, _ = t.query(10, 200, tail=tail)
+    assert np.array_equal(G1, G2) and all(np.array_equal(a, b) for a, b in zip(U1, U2))
+    with pytest.raises(ValueError):
+        t.query(0, Tc + 4, tail=tail)
+
+
 def test_error_bound_on_noisy_tiny():
     """Prop. "err": |X - Y| / |X| <= 3 eps when X = W + E, eps = |E|/|X|."""
     wl = synth.get("tiny")

@@ -146,10 +146,19 @@ tk_status tk_build(tk_tree* t, const float* X, int64_t T, int on_device);
 tk_status tk_hitset(const tk_tree* t, int64_t ts, int64_t te, tk_hit* out,
                     int32_t cap, int32_t* n);
 
+/* Output shape of a query (ranges as tk_query accepts them). */
 tk_status tk_query_shape(const tk_tree* t, int64_t ts, int64_t te, tk_shape* out);
 
 /* Range query (Sec. 6.1): Recall, partial-hit trims (Eq. "partial-tucker")
- * and Stitch, one device launch.  Blocks until the result is written. */
+ * and Stitch, one device launch.  Blocks until the result is written.  The
+ * range may end past the last complete block (t_e <= T, leaf_len > 1):
+ * the incomplete block's slices then get a provisional leaf (its Tucker-ALS
+ * at the node ranks clipped to their count, computed once per horizon T in
+ * the next leaf slot and replaced by the real leaf when the block
+ * completes), stitched as a partial hit.  Only slices appended with
+ * tk_append / tk_build (or kept by tk_serve_stop) count; after
+ * tk_restore_begin the range ends at the last complete block.  Prepared
+ * batches and served queries end there too (TK_ERANGE). */
 tk_status tk_query(tk_tree* t, int64_t ts, int64_t te, tk_result* res);
 
 /* n range queries stitched in one device launch (one workgroup per query).

@@ -6,7 +6,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/tk_kernels.hip", "csrc/tk_capi.hip", "csrc/tk_batch.hip", "csrc/tk_serve.hip"]
+SOURCES = ["csrc/tk_kernels.hip", "csrc/tk_capi.hip", "csrc/tk_batch.hip", "csrc/tk_serve.hip", "csrc/tk_tail.hip"]
 HEADERS = ["csrc/tk_common.hpp", "csrc/tk_device.hpp", "csrc/tk_internal.hpp", "csrc/tk_host.hpp"]
 OUT = os.path.join(HERE, "libtucket.so")
 

@@ -124,14 +124,34 @@ StitchArgs stitch_args(tk_tree* t, int max_iter, double tol) {
   return a;
 }
 
+int plan_query_hits(const tk_tree* t, int64_t ts, int64_t te, int64_t Tb, bool tail_ok, Hit* out, int cap,
+                    bool* tail) {
+  const int64_t Tc = Tb * t->ell;
+  // the incomplete block is reachable when its slices were all appended here
+  // (not after a restore or a serving session)
+  const int64_t end = tail_ok && Tb == t->Tb && t->tail_rows == t->T - Tc ? t->T : Tc;
+  *tail = false;
+  if (!(ts >= 0 && ts < te && te <= end)) return -1;
+  const int64_t tec = te < Tc ? te : Tc;
+  int n = ts < tec ? query_hits(t, ts, tec, Tb, out, cap) : 0;
+  if (te > Tc) {
+    const int64_t lo = ts > Tc ? ts : Tc;
+    if (n < cap) out[n] = Hit{0, 1, Tb, lo - Tc, te - lo};
+    ++n;
+    *tail = true;
+  }
+  return n;
+}
+
 tk_status make_query_job(tk_tree* t, int64_t ts, int64_t te, int64_t Tb, const tk_result* res, bool check_outputs,
-                         std::vector<Job>& jobs, std::vector<Hit>& hits) {
-  if (!(ts >= 0 && ts < te && te <= Tb * t->ell)) return fail(t, TK_ERANGE, "query range outside [0, T_c) or empty");
+                         std::vector<Job>& jobs, std::vector<Hit>& hits, bool tail_ok) {
   Hit buf[MAXHITS];
-  const int n = query_hits(t, ts, te, Tb, buf, MAXHITS);
+  bool tail = false;
+  const int n = plan_query_hits(t, ts, te, Tb, tail_ok, buf, MAXHITS, &tail);
+  if (n < 0) return fail(t, TK_ERANGE, "query range outside [0, T_c) or empty");
   if (n < 1 || n > MAXHITS) return fail(t, TK_EINVAL, "hit set too large");
   Job jb{};
-  jb.kind = t->q_level < 0 ? 0 : 2;
+  jb.kind = t->q_level < 0 && !tail ? 0 : 2;
   jb.s = n;
   jb.hit0 = int32_t(hits.size());
   jb.L = te - ts;
@@ -588,6 +608,7 @@ void tk_destroy(tk_tree* t) {
   if (t->store) (void)hipFree(t->store);
   if (t->dview) (void)hipFree(t->dview);
   if (t->block_buf) (void)hipFree(t->block_buf);
+  tk::release(&t->prov_out);
   if (t->ev0) (void)hipEventDestroy(t->ev0);
   if (t->ev1) (void)hipEventDestroy(t->ev1);
   delete t;
@@ -601,11 +622,13 @@ tk_status tk_append(tk_tree* t, const float* slice, int on_device) {
   const int64_t row = t->T % t->ell;
   TK_HIP(t, hipMemcpyAsync(t->block_buf + row * t->slice_elems, slice, size_t(t->slice_elems) * 4,
                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, t->stream));
+  if (row == t->tail_rows) t->tail_rows = row + 1;
   t->T += 1;
   if (t->T % t->ell == 0) {
     tk_status st = commit_blocks(t, &t->main, 1, t->block_buf);
     if (st) return st;
     TK_HIP(t, hipStreamSynchronize(t->stream));
+    t->tail_rows = 0;
   }
   return TK_OK;
 }
@@ -665,7 +688,11 @@ tk_status tk_hitset(const tk_tree* t, int64_t ts, int64_t te, tk_hit* out, int32
 tk_status tk_query_shape(const tk_tree* t, int64_t ts, int64_t te, tk_shape* out) {
   if (!t || !out) return TK_EINVAL;
   if (t->server) return TK_EBUSY;
-  if (!range_ok(t, ts, te)) return TK_ERANGE;
+  Hit buf[tk::MAXHITS];
+  bool tail = false;
+  const int nh = tk::plan_query_hits(t, ts, te, t->Tb, true, buf, tk::MAXHITS, &tail);
+  if (nh < 0) return TK_ERANGE;
+  if (nh > tk::MAXHITS) return TK_EINVAL;
   std::memset(out, 0, sizeof(*out));
   tk::query_ranks(t, te - ts, out->ranks_eff);
   out->L = te - ts;
@@ -673,8 +700,7 @@ tk_status tk_query_shape(const tk_tree* t, int64_t ts, int64_t te, tk_shape* out
   for (int n = 0; n < t->p; ++n) out->core_elems *= out->ranks_eff[n];
   out->factor_elems[0] = out->L * out->ranks_eff[0];
   for (int n = 1; n < t->p; ++n) out->factor_elems[n] = t->view.D[n] * out->ranks_eff[n];
-  Hit buf[tk::MAXHITS];
-  out->n_hits = tk::recall(ts, te, t->Tb, t->ell, t->cfg.theta_num, t->cfg.theta_den, buf, tk::MAXHITS);
+  out->n_hits = nh;
   tk::StitchLayout lo;
   tk::stitch_layout(t->view, buf, out->n_hits, out->ranks_eff, 0, &lo);
   out->ws_bytes = lo.total;
@@ -688,11 +714,17 @@ tk_status tk_query_batch(tk_tree* t, int32_t n, const int64_t* ts, const int64_t
   std::vector<Job> jobs;
   std::vector<Hit> hits;
   jobs.reserve(size_t(n));
+  bool any_tail = false;
   for (int32_t i = 0; i < n; ++i) {
-    tk_status st = make_query_job(t, ts[i], te[i], t->Tb, &res[i], true, jobs, hits);
+    tk_status st = make_query_job(t, ts[i], te[i], t->Tb, &res[i], true, jobs, hits, true);
     if (st) return st;
+    any_tail = any_tail || te[i] > t->Tb * t->ell;
   }
   if (n == 0) return TK_OK;
+  if (any_tail) {
+    tk_status st = provisional_leaf(t);
+    if (st) return st;
+  }
   tk_status st = ensure(t, &t->main.stats, int64_t(n) * STAT_COUNT * 8, "stats");
   if (st) return st;
   double* dstats = reinterpret_cast<double*>(t->main.stats.p);
@@ -967,6 +999,8 @@ tk_status tk_restore_begin(tk_tree* t, int64_t T) {
   if (t->poisoned) return TK_EDEVICE;
   t->T = T;
   t->Tb = T / t->ell;
+  t->tail_rows = 0;
+  t->prov_T = -1;
   t->merges_total = 0;
   t->merges_last = 0;
   return TK_OK;

@@ -106,6 +106,9 @@ struct tk_tree {
   int q_prec = TK_F32;  // arithmetic of query stitches (merges follow cfg.prec)
   int32_t q_ranks[TK_MAX_MODES] = {};  // output ranks of queries (0: cfg.ranks)
   int q_level = -1;                    // queries' hit sets: Alg. recall (-1) or fixed blocks of this level
+  int64_t prov_T = -1;                 // T at which the provisional leaf in slot Tb was computed (-1: none)
+  int64_t tail_rows = 0;               // leading rows of block_buf holding the incomplete block's slices
+  tk::DevBuf prov_out;                 // its compact decomposition
   int64_t lds_limit = 65536;  // dynamic + static LDS a workgroup may use
   tk::Tuning tuning;
   bool poisoned = false;
@@ -139,7 +142,16 @@ int eig_need(const tk_tree* t, const StitchLayout& lo);
 // appended to `hits`).  Output buffers from res (may be null when
 // check_outputs is false).
 tk_status make_query_job(tk_tree* t, int64_t ts, int64_t te, int64_t Tb, const tk_result* res, bool check_outputs,
-                         std::vector<Job>& jobs, std::vector<Hit>& hits);
+                         std::vector<Job>& jobs, std::vector<Hit>& hits, bool tail_ok = false);
+// The hits of [ts, te) at snapshot Tb; with tail_ok (Tb the tree's) a range
+// may end in the incomplete block, whose provisional leaf in slot Tb is the
+// last hit (*tail set).  Returns the number of hits needed, or -1 if the
+// range is outside what the call may reach.
+int plan_query_hits(const tk_tree* t, int64_t ts, int64_t te, int64_t Tb, bool tail_ok, Hit* out, int cap,
+                    bool* tail);
+// Tucker-ALS of the incomplete block into slot Tb, zero-padded to the slot's
+// shapes (once per horizon T; tk_tail.hip).
+tk_status provisional_leaf(tk_tree* t);
 // Merge job for node (k, j): Stitch of its two children (Alg. "insert").
 void make_merge_job(tk_tree* t, int k, int64_t j, std::vector<Job>& jobs, std::vector<Hit>& hits);
 

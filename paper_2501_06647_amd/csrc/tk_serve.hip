@@ -428,6 +428,8 @@ tk_status tk_serve_stop(tk_tree* t) {
     (void)hipMemcpy(t->block_buf, s->alane.xbuf.p, size_t(s->rows_staged * t->slice_elems) * 4,
                     hipMemcpyDeviceToDevice);
   t->T = s->T_logical;
+  t->tail_rows = s->failed ? 0 : s->rows_staged;  // the incomplete block's rows, for tail queries
+  t->prov_T = -1;
   const bool failed = s->failed;
   t->server = nullptr;
   server_free(s);

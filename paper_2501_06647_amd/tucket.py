@@ -506,12 +506,29 @@ class Tree:
         return [QueryResult(c, f, res[i], p) for i, (c, f) in enumerate(outputs)]
 
     def query_batch(self, ts, te) -> List[QueryResult]:
-        """tk_query_batch: one synchronous batched call."""
-        b = self.prepare_batch(ts, te)
-        b.run_sync()
-        out = b.results()
-        b.close()
-        return out
+        """tk_query_batch: one synchronous batched call (host Recall and
+        planning every call; a range may end in the incomplete block)."""
+        ts = np.asarray(ts, dtype=np.int64).reshape(-1)
+        te = np.asarray(te, dtype=np.int64).reshape(-1)
+        n = len(ts)
+        p = self.p
+        shapes_all = _query_shapes(self, ts, te)
+        buf, views = self._alloc([s for shp in shapes_all for s in shp])
+        res = (TkResult * max(n, 1))()
+        outputs = []
+        k = 0
+        for i in range(n):
+            core, facs = views[k], views[k + 1:k + 1 + p]
+            k += 1 + p
+            res[i].core = core.data_ptr()
+            for m in range(p):
+                res[i].factor[m] = facs[m].data_ptr()
+            outputs.append((core, facs))
+        a = (c_i64 * max(n, 1))(*ts.tolist())
+        b = (c_i64 * max(n, 1))(*te.tolist())
+        if n:
+            self._check(lib().tk_query_batch(self._h, n, a, b, res), "tk_query_batch")
+        return [QueryResult(c, f, res[i], p) for i, (c, f) in enumerate(outputs)]
 
     # -- launch tuning and serving -----------------------------------------------------
     def tuning(self) -> dict:

@@ -214,3 +214,44 @@ def test_plain_workload_full_size_sampled(torch):
         worst = max(worst, d)
     say("plain: worst query delta %.2e" % worst)
     assert worst <= DELTA
+
+
+def test_tail_queries(torch):
+    """Ranges ending in the incomplete block: tiny data, 63 complete blocks
+    and 3 more slices appended on the device; ranges ending in those slices
+    (some inside them) against the oracle's provisional piece, every other
+    range unchanged; prepared batches refuse the tail; once the block
+    completes the same slot holds the real leaf."""
+    from paper_2501_06647_amd import TuckerError
+    from paper_2501_06647_amd.tucket import TK_ERANGE
+    wl = synth.get("tiny")
+    X = synth.series(wl)
+    Tc = 63 * wl.leaf_len
+    gpu = _gpu_tree(wl, wl.T)
+    gpu.build(X[:Tc + 3])
+    orc = oracle_tree(wl, X, Tc)
+    tail = X[Tc:Tc + 3]
+    worst = 0.0
+    ranges = [(0, Tc + 3), (100, Tc + 1), (Tc - 2, Tc + 2), (Tc, Tc + 3), (Tc + 1, Tc + 3), (Tc + 2, Tc + 3), (5, 200)]
+    res = gpu.query_batch([a for a, _ in ranges], [c for _, c in ranges])
+    for (a, c), r in zip(ranges, res):
+        Go, Uo, info = orc.query(a, c, tail=tail)
+        G, U = to_np(r)
+        assert G.shape == Go.shape, (a, c)
+        d, orth, _, _, _ = compare(X, a, c, G, U, Go, Uo)
+        assert orth <= ORTH, (a, c, orth)
+        worst = max(worst, d)
+    say("tail queries: worst delta %.2e over %d ranges" % (worst, len(ranges)))
+    assert worst <= DELTA
+    with pytest.raises(TuckerError) as e:
+        gpu.prepare_batch([0], [Tc + 2])
+    assert e.value.status == TK_ERANGE
+    # the block completes: slot 63 is the real leaf, stitched as any other
+    gpu.append(X[Tc + 3])
+    full = oracle_tree(wl, X, Tc + 4)
+    for a, c in [(0, Tc + 4), (Tc, Tc + 4), (Tc + 1, Tc + 3)]:
+        r = gpu.query(a, c)
+        Go, Uo, _ = full.query(a, c)
+        G, U = to_np(r)
+        d, orth, _, _, _ = compare(X, a, c, G, U, Go, Uo)
+        assert d <= DELTA and orth <= ORTH, (a, c, d)

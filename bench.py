@@ -31,8 +31,8 @@ HBM_TBPS = 8.0
 # step's launches) scaled by the counters of a 1 GiB reference copy (FETCH
 # reads half the bytes moved, WRITE all of them); valid only for the kernel
 # sources they were taken with.
-TRAFFIC_KERNEL_SHA = "d0a3affeaacb61d3"
-TRAFFIC_BYTES_PER_STEP = {"plain": {"fetch": 1076.5e6, "write": 940.9e6,
+TRAFFIC_KERNEL_SHA = "e1f56f3943b2a678"
+TRAFFIC_BYTES_PER_STEP = {"plain": {"fetch": 1068.3e6, "write": 950.4e6,
                                     "tuning": {"wide_threshold": 32, "wide_threads": 128, "persistent": 0, "graph": 1,
                                                "coarse": 1, "lds_n": 64, "basis_pct": 75, "rest_threads": 256}}}
 KERNEL_SOURCES = ("tk_common.hpp", "tk_device.hpp", "tk_internal.hpp", "tk_kernels.hip")
@@ -274,7 +274,7 @@ def tradeoff_main(args):
 def pscale_main(args):
     """Query latency and throughput against the number of modes on the
     paper's many-mode shapes (every slice 10^6 elements, rank 5 per mode,
-    400 slices, leaf 1): p = 4, 5 and 6; queries of 98, 192 and 384 slices
+    400 slices, leaf 1): p = 4 to 7; queries of 98, 192 and 384 slices
     from seeded random starts, one at a time (latency) and as one prepared
     batch (throughput)."""
     import torch
@@ -285,7 +285,7 @@ def pscale_main(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     rows = []
-    for p in (4, 5, 6):
+    for p in [int(x) for x in args.pscale_p.split(",")]:
         wl = d5(p)
         tree = Tree(wl.dims, wl.node_ranks, wl.leaf_len, wl.theta, wl.max_iter, wl.tol, capacity_T=wl.T)
         gen_s, build_s = 0.0, 0.0
@@ -306,8 +306,19 @@ def pscale_main(args):
               file=sys.stderr, flush=True)
         rng = np.random.default_rng(40 + p)
         tts = rng.integers(0, wl.T - 192 + 1, size=64).astype(np.int64)
-        tuning, _ = tree.autotune(tts, tts + 192, reps=1)
-        print("[pscale] p=%d autotune: %s" % (p, tuning), file=sys.stderr, flush=True)
+        if args.pscale_tuning:
+            tuning = json.loads(args.pscale_tuning)
+            tree.set_tuning(**tuning)
+        elif p in [int(x) for x in args.pscale_tune_p.split(",") if x]:
+            tuning, _ = tree.autotune(tts, tts + 192, reps=1)
+        elif rows:
+            # the grid search costs ~150 batches: at many modes reuse the
+            # tuning chosen for the previous p
+            tuning = rows[-1]["tuning"]
+            tree.set_tuning(**tuning)
+        else:
+            tuning = tree.tuning()
+        print("[pscale] p=%d tuning: %s" % (p, tuning), file=sys.stderr, flush=True)
         for L in (98, 192, 384):
             ts = rng.integers(0, wl.T - L + 1, size=64).astype(np.int64)
             te = ts + L
@@ -316,6 +327,8 @@ def pscale_main(args):
                 t1 = time.perf_counter()
                 tree.query(a, c)
                 lat.append(time.perf_counter() - t1)
+            print("[pscale] p=%d L=%d: 16 single queries, p50 %.2f ms" % (p, L, 1000.0 * float(np.median(lat))),
+                  file=sys.stderr, flush=True)
             b = tree.prepare_batch(ts, te)
             for _ in range(args.warmup):
                 b.run()
@@ -326,11 +339,13 @@ def pscale_main(args):
             torch.cuda.synchronize()
             ms = 1000.0 * (time.perf_counter() - t1) / args.steps
             res = b.results()
+            prof = [b.profile(i) for i in range(len(ts))]
+            phases = {k: round(float(np.mean([pr[k] for pr in prof])), 1) for k in tree.PHASES}
             hits = [len(tree.hitset(int(a), int(c))) for a, c in zip(ts, te)]
             row = {"p": p, "dims": list(wl.dims), "L": L, "tuning": tuning, "latency_p50_ms": 1000.0 * float(np.median(lat)),
                    "latency_p99_ms": 1000.0 * float(np.percentile(lat, 99)), "batch_queries": len(ts),
                    "batch_queries_per_s": len(ts) / (ms / 1000.0), "hits_mean": float(np.mean(hits)),
-                   "sweeps_mean": float(np.mean([r.sweeps for r in res]))}
+                   "sweeps_mean": float(np.mean([r.sweeps for r in res])), "phase_mean_us": phases}
             rows.append(row)
             print("[pscale] %s" % json.dumps(row), file=sys.stderr, flush=True)
             b.close()
@@ -338,7 +353,7 @@ def pscale_main(args):
     out = {"metric": "range-query latency vs number of modes (many-mode shapes, rank 5)",
            "value": rows[-1]["latency_p50_ms"], "unit": "ms", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": False, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "slices of 10^6 elements (100^3, 100^2 x 10^2, 100 x 10^4), 400 slices, leaf 1, "
+           "config": {"workload": "slices of 10^6 elements (100^3, 100^2 x 10^2, 100 x 10^4, 10^6), 400 slices, leaf 1, "
                                   "rank 5, queries of 98/192/384 slices"},
            "rows": rows}
     print(json.dumps(out), flush=True)
@@ -360,7 +375,11 @@ def main():
     ap.add_argument("--aps", type=float, default=1000.0)
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--serve-prefix", type=int, default=4096)
-    ap.add_argument("--pscale", action="store_true", help="latency against the number of modes (p = 4..6)")
+    ap.add_argument("--pscale", action="store_true", help="latency against the number of modes (p = 4..7)")
+    ap.add_argument("--pscale-p", default="4,5,6,7", help="numbers of modes for --pscale")
+    ap.add_argument("--pscale-tune-p", default="4,5,6",
+                    help="numbers of modes autotuned in --pscale (the others reuse the previous tuning)")
+    ap.add_argument("--pscale-tuning", default=None, help="JSON tuning for every p of --pscale")
     ap.add_argument("--tradeoff", action="store_true",
                     help="theta sweep and fixed-block variant: throughput and error per hit-set rule")
     args = ap.parse_args()

@@ -62,7 +62,7 @@ typedef struct tk_tree tk_tree;
 /* Tree configuration.  Hyperparameter defaults of Sec. 8.1: max_iter 20,
  * tol 0.01, theta 0.7. */
 typedef struct {
-  int32_t p;                      /* number of modes, 2..6 (time included)   */
+  int32_t p;                      /* number of modes, 2..7 (time included)   */
   int64_t dims[TK_MAX_MODES];     /* dims[1..p-1] = D_2..D_p; dims[0] unused */
   int32_t ranks[TK_MAX_MODES];    /* target ranks r_1..r_p                   */
   int32_t leaf_len;               /* slices per leaf block, >= 1             */

@@ -112,6 +112,7 @@ int lds_cap(const tk_tree* t) {
 StitchArgs stitch_args(tk_tree* t, int max_iter, double tol) {
   StitchArgs a{};
   a.st = t->dview;
+  a.p = t->p;
   a.max_iter = max_iter;
   a.tol = tol;
   a.merge_max_iter = t->cfg.max_iter;
@@ -465,7 +466,7 @@ tk_status tk_create(const tk_config* cfg, void* hip_stream, tk_tree** out) {
   if (!cfg || !out) return fail(nullptr, TK_EINVAL, "null argument");
   *out = nullptr;
   const int p = cfg->p;
-  if (p < 2 || p > tk::MAXP) return fail(nullptr, TK_EINVAL, "p must be in [2, 6]");
+  if (p < 2 || p > tk::MAXP) return fail(nullptr, TK_EINVAL, "p must be in [2, 7]");
   int64_t slice = 1;
   for (int n = 1; n < p; ++n) {
     if (cfg->dims[n] < 1 || cfg->dims[n] > (1 << 20)) return fail(nullptr, TK_EINVAL, "bad dims");

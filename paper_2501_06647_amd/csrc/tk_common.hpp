@@ -13,7 +13,7 @@
 
 namespace tk {
 
-constexpr int MAXP = 6;      // modes handled by the kernels (time included)
+constexpr int MAXP = 7;      // modes handled by the kernels (time included)
 constexpr int MAXLEV = 48;   // tree levels (2^47 leaf blocks)
 constexpr int MAXHITS = 64;  // hits per query: <= 2(h-1) for trees of height <= 33
 constexpr int EIG_MAXK_HOST = 1024;  // largest eigenproblem a job may need

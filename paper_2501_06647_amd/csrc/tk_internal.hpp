@@ -10,6 +10,7 @@ constexpr int NT_LEAF = 256;   // four wavefronts per leaf job
 
 struct StitchArgs {
   const StoreView* st;
+  int p;               // modes of the tree (selects the kernel instantiation)
   const Job* jobs;
   Hit* hits;           // merge jobs: read; query jobs: written by the kernel's own Recall
   char* ws;

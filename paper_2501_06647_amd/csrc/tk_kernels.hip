@@ -65,21 +65,31 @@ struct PhaseClock {
   }
 };
 
+// PM: the most modes the instantiation handles (its per-mode arrays)
+template <int PM>
 struct StitchShared {
   PhaseClock clk;
   EigCounters ec;
   int64_t recall_stack[RECALL_STACK];
   int32_t kp[MAXHITS];              // temporal rank of each piece after its trim
   int32_t koff[MAXHITS + 1];        // offsets of the pieces in the stacked temporal coordinates
-  int32_t roff[MAXP][MAXHITS + 1];  // offsets of the pieces' columns in C^(n)
-  int32_t q[MAXP];                  // size of the reduced coordinates of mode n
-  int32_t basis[MAXP];              // 1: C^(n) from the Cholesky basis; 0: C^(n) = V~
+  int32_t roff[PM][MAXHITS + 1];    // offsets of the pieces' columns in C^(n)
+  int32_t q[PM];                    // size of the reduced coordinates of mode n
+  int32_t basis[PM];                // 1: C^(n) from the Cholesky basis; 0: C^(n) = V~
   double red[8];
   int redi[4];
 };
 
+// Stitch instantiations: up to four modes (the per-mode arrays and the
+// register budget of the three- and four-way workloads), and up to MAXP
+// modes.  The many-mode one runs small TTM products (at most 8 outputs from
+// at most 8 inputs per fiber, as in rank-5 chains over 5 to 7 modes) one
+// fiber per lane: a 16 x 16 matrix-core tile would be mostly padding.
+constexpr int PM_FEW = 4;
+
+template <int PM>
 __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, const Hit* hits, char* ws, int n_lds,
-                           int lds_doubles, int basis_pct, int max_iter, double tol, bool lowp, StitchShared& sh,
+                           int lds_doubles, int basis_pct, int max_iter, double tol, bool lowp, StitchShared<PM>& sh,
                            double* lds) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int p = st.p;
@@ -135,6 +145,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
   auto ttm = [&](const float* X, int64_t a, int r, int64_t b, const float* A, int64_t as, int64_t bs, int m,
                  float* Y, bool acc) {
     if (lowp) mode_product_bf16(X, a, r, b, A, as, bs, m, Y, acc);
+    else if (PM > PM_FEW && m <= 8 && r <= 8) mode_product_fiber<float, float, float, float, 8>(X, a, r, b, A, as, bs, m, Y, acc);
     else mode_product(X, a, r, b, A, as, bs, m, Y, acc);
   };
   auto gram = [&](const float* X, int64_t a, int q, int64_t b, double* G, int ld) {
@@ -305,7 +316,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     for (int i = 0; i < s; ++i) {
       const int lev = hits[i].level;
       const int r = st.rk[lev][n];
-      int32_t dims[MAXP];
+      int32_t dims[PM];
       dims[0] = sh.kp[i];
       for (int m = 1; m < p; ++m) dims[m] = st.rk[lev][m];
       gram_mode_mfma(core_of(i), prod_range(dims, 0, n), r, prod_range(dims, n + 1, p), S, r);
@@ -324,7 +335,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
   clk.mark(2);
 
   // ---- ALS sweeps (Alg. "stitch") ---------------------------------------------
-  int64_t Rhat[MAXP];
+  int64_t Rhat[PM];
   for (int n = 0; n < p; ++n) {
     Rhat[n] = 1;
     for (int m = 0; m < p; ++m)
@@ -341,7 +352,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     float* M = Fp(lo.M);
     for (int i = 0; i < s; ++i) {
       const int lev = hits[i].level;
-      int32_t dims[MAXP];
+      int32_t dims[PM];
       dims[0] = sh.kp[i];
       for (int m = 1; m < p; ++m) dims[m] = st.rk[lev][m];
       const float* cur = core_of(i);
@@ -371,13 +382,13 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     float* Wst = Fp(lo.WS);
     for (int n = 1; n < p; ++n) {
       const int q = sh.q[n];
-      int32_t kd[MAXP];
+      int32_t kd[PM];
       for (int m = 0; m < p; ++m) kd[m] = rq[m];
       kd[n] = q;
       const int64_t ka = prod_range(kd, 0, n), kb = prod_range(kd, n + 1, p);
       for (int i = 0; i < s; ++i) {
         const int lev = hits[i].level;
-        int32_t dims[MAXP];
+        int32_t dims[PM];
         dims[0] = sh.kp[i];
         for (int m = 1; m < p; ++m) dims[m] = st.rk[lev][m];
         const float* cur = core_of(i);
@@ -508,7 +519,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
                });
     }
     for (int i = 0; i < s; ++i) {
-      int32_t dims[MAXP];
+      int32_t dims[PM];
       dims[0] = sh.kp[i];
       for (int m = 1; m < p; ++m) dims[m] = st.rk[hits[i].level][m];
       mode_product_f64<float>(core_of(i), 1, dims[0], prod_range(dims, 1, p), P0 + int64_t(sh.koff[i]) * rq[0], 1,
@@ -565,10 +576,10 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
 // runs past n_jobs, so every workgroup reaches the exit.
 // Register budget: at most 256 VGPRs, so that two wavefronts share a SIMD
 // (one job's latency hides behind another's).
-template <int NTT>
+template <int NTT, int PM>
 __global__ __launch_bounds__(NTT, 2) void stitch_kernel(StitchArgs args) {
   extern __shared__ double lds[];
-  __shared__ StitchShared sh;
+  __shared__ StitchShared<PM> sh;
   __shared__ Hit qh[MAXHITS];
   __shared__ int next_job;
   __shared__ int n_rec;
@@ -583,6 +594,11 @@ __global__ __launch_bounds__(NTT, 2) void stitch_kernel(StitchArgs args) {
     }
     if (jn >= args.n_jobs) break;
     const Job& job = args.jobs[jn];
+    if (st.p > PM) {  // launched with the wrong instantiation: refuse the job
+      if (threadIdx.x == 0 && job.stats) job.stats[STAT_STATUS] = 3.0;
+      if (!args.queue) break;
+      continue;
+    }
     // the job's hits go to LDS: a query's from its own Recall (published to
     // its slots of args.hits), a merge's two children from args.hits
     if (threadIdx.x == 0) {
@@ -669,7 +685,7 @@ __device__ __forceinline__ const float* project(const float* X, const int32_t* D
                                 const int32_t* rq, float* T1, float* T2, int32_t* dims_out) {
   int32_t dims[MAXP];
   for (int m = 0; m < p; ++m) dims[m] = Dm[m];
-  bool done[MAXP] = {false, false, false, false, false, false};
+  bool done[MAXP] = {};
   const float* cur = X;
   float* bufs[2] = {T1, T2};
   int nb = 0;
@@ -823,23 +839,30 @@ __global__ __launch_bounds__(NT_LEAF, 2) void raw_kernel(RawArgs args) {
 // ------------------------------------------------------------------------------
 // Launchers
 // ------------------------------------------------------------------------------
-hipError_t launch_stitch(const StitchArgs& a, int grid, size_t lds_bytes, int threads, hipStream_t stream) {
-  if (grid <= 0 || a.n_jobs <= 0) return hipSuccess;
-  if (grid > a.n_jobs || (!a.queue && grid != a.n_jobs)) return hipErrorInvalidValue;
+template <int PM>
+static hipError_t launch_stitch_pm(const StitchArgs& a, int grid, size_t lds_bytes, int threads, hipStream_t stream) {
   switch (threads) {
     case 64:
-      hipLaunchKernelGGL(stitch_kernel<64>, dim3(grid), dim3(64), lds_bytes, stream, a);
+      hipLaunchKernelGGL((stitch_kernel<64, PM>), dim3(grid), dim3(64), lds_bytes, stream, a);
       break;
     case 128:
-      hipLaunchKernelGGL(stitch_kernel<128>, dim3(grid), dim3(128), lds_bytes, stream, a);
+      hipLaunchKernelGGL((stitch_kernel<128, PM>), dim3(grid), dim3(128), lds_bytes, stream, a);
       break;
     case 256:
-      hipLaunchKernelGGL(stitch_kernel<256>, dim3(grid), dim3(256), lds_bytes, stream, a);
+      hipLaunchKernelGGL((stitch_kernel<256, PM>), dim3(grid), dim3(256), lds_bytes, stream, a);
       break;
     default:
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_stitch(const StitchArgs& a, int grid, size_t lds_bytes, int threads, hipStream_t stream) {
+  if (grid <= 0 || a.n_jobs <= 0) return hipSuccess;
+  if (grid > a.n_jobs || (!a.queue && grid != a.n_jobs)) return hipErrorInvalidValue;
+  if (a.p < 2 || a.p > MAXP) return hipErrorInvalidValue;
+  return a.p <= PM_FEW ? launch_stitch_pm<PM_FEW>(a, grid, lds_bytes, threads, stream)
+                       : launch_stitch_pm<MAXP>(a, grid, lds_bytes, threads, stream);
 }
 
 hipError_t launch_reset_queue(int* queue, int n, hipStream_t stream) {
@@ -861,9 +884,12 @@ hipError_t launch_leaf(const LeafArgs& a, int n_jobs, size_t lds_bytes, hipStrea
 }
 
 hipError_t set_lds_limits(size_t stitch_bytes, size_t leaf_bytes) {
-  const void* fns[] = {reinterpret_cast<const void*>(stitch_kernel<64>),
-                       reinterpret_cast<const void*>(stitch_kernel<128>),
-                       reinterpret_cast<const void*>(stitch_kernel<256>)};
+  const void* fns[] = {reinterpret_cast<const void*>(stitch_kernel<64, PM_FEW>),
+                       reinterpret_cast<const void*>(stitch_kernel<128, PM_FEW>),
+                       reinterpret_cast<const void*>(stitch_kernel<256, PM_FEW>),
+                       reinterpret_cast<const void*>(stitch_kernel<64, MAXP>),
+                       reinterpret_cast<const void*>(stitch_kernel<128, MAXP>),
+                       reinterpret_cast<const void*>(stitch_kernel<256, MAXP>)};
   for (const void* f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(stitch_bytes));
     if (e != hipSuccess) return e;
@@ -878,9 +904,10 @@ hipError_t set_lds_limits(size_t stitch_bytes, size_t leaf_bytes) {
 int stitch_blocks_per_cu(int threads, size_t lds_bytes) {
   int n = 0;
   hipError_t e = hipErrorInvalidValue;
-  if (threads == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stitch_kernel<64>, 64, lds_bytes);
-  if (threads == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stitch_kernel<128>, 128, lds_bytes);
-  if (threads == 256) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stitch_kernel<256>, 256, lds_bytes);
+  // the many-mode instantiation: its static LDS is the larger
+  if (threads == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stitch_kernel<64, MAXP>, 64, lds_bytes);
+  if (threads == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stitch_kernel<128, MAXP>, 128, lds_bytes);
+  if (threads == 256) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stitch_kernel<256, MAXP>, 256, lds_bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return 1;
@@ -888,7 +915,7 @@ int stitch_blocks_per_cu(int threads, size_t lds_bytes) {
   return n > 0 ? n : 1;
 }
 
-size_t stitch_static_lds() { return sizeof(StitchShared) + sizeof(Hit) * MAXHITS + 64; }
+size_t stitch_static_lds() { return sizeof(StitchShared<MAXP>) + sizeof(Hit) * MAXHITS + 64; }
 size_t leaf_static_lds() { return sizeof(LeafShared) + 64; }
 
 }  // namespace tk

@@ -108,6 +108,7 @@ def test_effective_ranks_match_oracle():
 
 @pytest.mark.parametrize("bad", [
     dict(dims=(), ranks=(4,)),                              # p = 1
+    dict(dims=(2,) * 7, ranks=(2,) * 8),                    # p = 8, above the kernel limit
     dict(dims=(3, 3), ranks=(4, 0, 4)),                     # zero rank
     dict(dims=(3, 3), ranks=(4, 40, 4)),                    # rank above the kernel limit
     dict(dims=(3, 3), ranks=(4, 4, 4), leaf_len=0),

@@ -1,5 +1,5 @@
-"""More modes than the workloads have: p = 5 and p = 6 (the kernels take
-up to six modes), built on the device and queried, against the oracle.
+"""More modes than the workloads have: p = 5, 6 and 7 (the kernels take
+up to seven modes), built on the device and queried, against the oracle.
 
 Bars: every node's relative error within 1e-5 of the oracle's (ratio
 form); queries within 1e-5, the same sweep counts, factor orthonormality
@@ -30,6 +30,7 @@ def torch():
 @pytest.mark.parametrize("dims,ranks,seed", [
     ((6, 5, 4, 3), (3, 3, 2, 2, 2), 2001),
     ((4, 3, 3, 3, 2), (3, 2, 2, 2, 2, 2), 2002),
+    ((3, 3, 2, 2, 2, 2), (3, 2, 2, 2, 2, 2, 2), 2003),
 ])
 def test_many_modes_parity(torch, dims, ranks, seed):
     from paper_2501_06647_amd import Tree

@@ -209,7 +209,7 @@ tk_status tk_batch_wait(tk_batch* b) {
   for (int32_t i = 0; i < b->n; ++i) {
     const double* s = b->hstats.data() + STAT_COUNT * size_t(i);
     if (s[STAT_STATUS] != 0.0)
-      return fail(t, TK_EDEVICE, "stitch kernel: device Recall, workspace or LDS size disagrees with the host plan");
+      return fail(t, TK_EDEVICE, job_status_msg(s[STAT_STATUS]));
     tk_result& r = b->res[i];
     for (int m = 0; m < TK_MAX_MODES; ++m) r.ranks_eff[m] = m < t->p ? b->qjobs[i].rq[m] : 0;
     r.fit = s[STAT_FIT];

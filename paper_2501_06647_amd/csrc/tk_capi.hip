@@ -27,6 +27,11 @@ tk_status fail(tk_tree* t, tk_status st, const std::string& msg) {
   return st;
 }
 
+std::string job_status_msg(double status) {
+  return "stitch kernel: job status " + std::to_string(int(status)) +
+         " (1 device Recall, 2 workspace, 3 LDS or kernel modes) disagrees with the host plan";
+}
+
 tk_status fail_dev(tk_tree* t, hipError_t e, const char* what) {
   std::string m = std::string(what) + ": " + hipGetErrorString(e);
   if (t) {
@@ -750,7 +755,7 @@ tk_status tk_query_batch(tk_tree* t, int32_t n, const int64_t* ts, const int64_t
   for (int32_t i = 0; i < n; ++i) {
     const double* s = hs.data() + STAT_COUNT * size_t(i);
     if (s[STAT_STATUS] != 0.0)
-      return fail(t, TK_EDEVICE, "stitch kernel: device Recall, workspace or LDS size disagrees with the host plan");
+      return fail(t, TK_EDEVICE, job_status_msg(s[STAT_STATUS]));
     for (int m = 0; m < TK_MAX_MODES; ++m) res[i].ranks_eff[m] = m < t->p ? jobs[i].rq[m] : 0;
     res[i].fit = s[STAT_FIT];
     res[i].err_model = s[STAT_ERR];

@@ -122,6 +122,12 @@ struct tk_tree {
 namespace tk {
 
 tk_status fail(tk_tree* t, tk_status st, const std::string& msg);
+// Error text for a stitch job's nonzero STAT_STATUS: 1 the kernel's Recall
+// did not reproduce the planned hit set, 2 the workspace plan was too small,
+// 3 the launch's LDS could not hold the job's eigen vectors or its kernel
+// instantiation holds fewer modes than the tree (the job did nothing in
+// cases 2 and 3).
+std::string job_status_msg(double status);
 tk_status fail_dev(tk_tree* t, hipError_t e, const char* what);
 
 #define TK_HIP(t, call)                                         \

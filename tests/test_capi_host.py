@@ -98,7 +98,7 @@ def test_host_recall_rejects_bad_ranges():
 def test_effective_ranks_match_oracle():
     rng = np.random.default_rng(0)
     for _ in range(500):
-        p = int(rng.integers(2, 6))
+        p = int(rng.integers(2, 8))  # 2..7 modes
         dims = tuple(int(x) for x in rng.integers(1, 40, size=p - 1))
         ranks = tuple(int(x) for x in rng.integers(1, 33, size=p))
         length = int(rng.integers(1, 100))

@@ -198,6 +198,29 @@ def test_stitch_full_rank_pieces_equal_hooi_on_materialised():
         assert np.allclose(G1, G2, atol=1e-9)
 
 
+@pytest.mark.parametrize("shape,ranks", [
+    ((6, 4, 3, 3, 2), (2, 2, 2, 2, 2)),
+    ((6, 3, 3, 2, 2, 2, 2), (2, 2, 2, 2, 2, 2, 2)),
+])
+def test_many_modes_exact_recovery_and_stitch(shape, ranks):
+    """Five and seven modes: exact Tucker data is recovered to rounding, and
+    the stitch of pieces that represent X exactly equals Tucker-ALS on X."""
+    X = synth.small_series(shape, ranks, 0.0, seed=11)
+    G, U, _ = hooi(X, ranks, max_iter=3, tol=0.0)
+    assert relative_error(X, G, U) < 1e-11
+    Xn = synth.small_series(shape, ranks, 0.2, seed=12)
+    pieces = []
+    for a, b in ((0, 2), (2, 6)):
+        Gp, Up, _ = hooi(Xn[a:b], (b - a,) + shape[1:], max_iter=1, tol=0.0)
+        pieces.append(S.Piece(Gp, Up))
+    assert np.allclose(_materialise(pieces), Xn, atol=1e-12)
+    G1, U1, _ = S.stitch(pieces, ranks, max_iter=2, tol=0.0)
+    G2, U2, _ = hooi(Xn, ranks, max_iter=2, tol=0.0)
+    assert np.allclose(tucker_to_tensor(G1, U1), tucker_to_tensor(G2, U2), atol=1e-10)
+    for a, b in zip(U1, U2):
+        assert subspace_sine(a, b, a.shape[1]) < 1e-9
+
+
 def test_stitch_invariants_on_noisy_pieces():
     r = rng(10)
     dims, ranks = (9, 7), (4, 3)

@@ -53,6 +53,23 @@ struct RawArgs {
 // than n_jobs and the queue counter must read 0 at launch (reset_queue).
 hipError_t launch_stitch(const StitchArgs& a, int grid, size_t lds_bytes, int threads, hipStream_t stream);
 hipError_t launch_reset_queue(int* queue, int n, hipStream_t stream);
+
+// Entry points of the stitch kernel's instantiations (block size x mode
+// count: 64/128/256 threads, trees of at most 4 or at most MAXP modes), one
+// translation unit each (tk_stitch_inst.hip).  launch_stitch dispatches to
+// them; occupancy returns 0 when the runtime cannot tell.
+#define TK_STITCH_ENTRIES(NTT, PM)                                                                    \
+  hipError_t stitch_launch_##NTT##_##PM(const StitchArgs& a, int grid, size_t lds_bytes, hipStream_t stream); \
+  hipError_t stitch_set_lds_##NTT##_##PM(size_t bytes);                                              \
+  int stitch_occupancy_##NTT##_##PM(size_t lds_bytes);
+TK_STITCH_ENTRIES(64, 4)
+TK_STITCH_ENTRIES(128, 4)
+TK_STITCH_ENTRIES(256, 4)
+TK_STITCH_ENTRIES(64, 7)
+TK_STITCH_ENTRIES(128, 7)
+TK_STITCH_ENTRIES(256, 7)
+#undef TK_STITCH_ENTRIES
+
 hipError_t launch_leaf(const LeafArgs& a, int n_jobs, size_t lds_bytes, hipStream_t stream);
 // one NT_LEAF workgroup per raw range
 hipError_t launch_raw(const RawArgs& a, int n_jobs, size_t lds_bytes, hipStream_t stream);

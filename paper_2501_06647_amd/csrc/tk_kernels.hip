@@ -1,639 +1,14 @@
-// Stitch and leaf kernels (gfx950).
-//
-// stitch_kernel: one wavefront per job.  A job is a range query (Sec. 6.1:
-// Recall's hits -> partial-hit trims, Eq. "partial-tucker" -> Alg. "stitch")
-// or the merge of two children when a node completes (Alg. "insert").
-//
-// Alg. "stitch" is Tucker-ALS on the concatenation Y~ of the hit pieces,
-// Y~_i = H~_i x_1 V~_i^(1) ... x_p V~_i^(p).  The kernel runs it in exact
-// reduced coordinates:
-//   * temporal mode: the blocks V~_i^(1) are orthonormal, so the leading left
-//     singular vectors of Z^(1) (Eq. "stitch-temp-2") are
-//     blockdiag(V~_i^(1)) P with P those of the small stacked matrix
-//     M = [mat_1(H~_i x_{m>=2} (U^(m)T V~_i^(m)))]_i, and
-//     U^(1)_{[t_{i-1},t_i)}^T V~_i^(1) = P_i^T;
-//   * mode n >= 2: Z^(n) (Eq. "stitch-nontemp-3") lies in the span of
-//     [V~_1^(n) .. V~_s^(n)]; with B an orthonormal basis of that span and
-//     C_i = B^T V~_i^(n), B^T Z^(n) = sum_i C_i mat_n(W_i^(n)) and
-//     U^(n) = B P_n, U^(n)T V~_i^(n) = P_n^T C_i.
-// The leading singular vectors come from the Gram of the small matrix and an
-// FP64 Jacobi eigensolver, warm-started from the previous sweep's basis.
-// Partial hits are trimmed through a pivoted Cholesky factor of the Gram of
-// the sliced rows (an exact orthonormal factorisation, equal to the QR of
-// Eq. "partial-tucker" up to a permutation of the piece's core rows), and the
-// span bases come from a pivoted Cholesky factor of the factors' Gram.
-// Full-size factors are formed once, in FP64, when the result is written.
+// Leaf and raw-range kernels (gfx950) and the launchers of every kernel.
 //
 // leaf_kernel: one workgroup of four wavefronts per leaf block; Tucker-ALS
 // (Sec. 2) of the raw ell x D_2 x ... x D_p block with HOSVD initialisation.
-#include "tk_device.hpp"
-#include "tk_internal.hpp"
+// raw_kernel: the same Tucker-ALS on one whole raw range per workgroup.
+// The stitch kernel lives in tk_stitch.hpp; its instantiations are compiled
+// in tk_stitch_inst.hip and reached through the entry points declared in
+// tk_internal.hpp.
+#include "tk_stitch.hpp"
 
 namespace tk {
-
-__device__ __forceinline__ void wg_copy(float* dst, const float* src, int64_t n) {
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
-}
-
-__device__ __forceinline__ int64_t prod_range(const int32_t* d, int lo, int hi) {
-  int64_t r = 1;
-  for (int m = lo; m < hi; ++m) r *= d[m];
-  return r;
-}
-
-// Phase timer: thread 0 accumulates the 100 MHz wall clock between marks
-// (state in LDS, so it costs no registers over the kernel's lifetime).
-struct PhaseClock {
-  uint64_t last;
-  uint64_t acc[STAT_NPHASE];
-  __device__ __forceinline__ void start() {
-    if (threadIdx.x == 0) {
-      last = wall_clock64();
-      for (int i = 0; i < STAT_NPHASE; ++i) acc[i] = 0;
-    }
-  }
-  __device__ __forceinline__ void mark(int ph) {
-    if (threadIdx.x == 0) {
-      const uint64_t now = wall_clock64();
-      acc[ph] += now - last;
-      last = now;
-    }
-  }
-  __device__ __forceinline__ void store(double* stats) const {
-    if (threadIdx.x == 0 && stats)
-      for (int i = 0; i < STAT_NPHASE; ++i) stats[STAT_PHASE + i] = double(acc[i]) * 0.01;
-  }
-};
-
-// PM: the most modes the instantiation handles (its per-mode arrays)
-template <int PM>
-struct StitchShared {
-  PhaseClock clk;
-  EigCounters ec;
-  int64_t recall_stack[RECALL_STACK];
-  int32_t kp[MAXHITS];              // temporal rank of each piece after its trim
-  int32_t koff[MAXHITS + 1];        // offsets of the pieces in the stacked temporal coordinates
-  int32_t roff[PM][MAXHITS + 1];    // offsets of the pieces' columns in C^(n)
-  int32_t q[PM];                    // size of the reduced coordinates of mode n
-  int32_t basis[PM];                // 1: C^(n) from the Cholesky basis; 0: C^(n) = V~
-  double red[8];
-  int redi[4];
-};
-
-// Stitch instantiations: up to four modes (the per-mode arrays and the
-// register budget of the three- and four-way workloads), and up to MAXP
-// modes.  The many-mode one runs small TTM products (at most 8 outputs from
-// at most 8 inputs per fiber, as in rank-5 chains over 5 to 7 modes) one
-// fiber per lane: a 16 x 16 matrix-core tile would be mostly padding.
-constexpr int PM_FEW = 4;
-
-template <int PM>
-__device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, const Hit* hits, char* ws, int n_lds,
-                           int lds_doubles, int basis_pct, int max_iter, double tol, bool lowp, StitchShared<PM>& sh,
-                           double* lds) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int p = st.p;
-  const int s = job.s;
-  const int32_t* rq = job.rq;
-
-  // One entire hit at the node's own ranks: the range is a stored node;
-  // return it verbatim.
-  bool node_ranks = s == 1 && !hits[0].partial;
-  for (int n = 0; n < p && node_ranks; ++n) node_ranks = rq[n] == st.rk[hits[0].level][n];
-  if (node_ranks) {
-    const Hit h = hits[0];
-    const int lev = h.level;
-    wg_copy(job.out_core, st.core[lev] + h.index * st.core_elems[lev], st.core_elems[lev]);
-    for (int n = 1; n < p; ++n)
-      wg_copy(job.out_fac[n], st.fac[lev][n] + h.index * fac_elems(st, lev, n), fac_elems(st, lev, n));
-    const int64_t row0 = (h.index << lev) * st.ell;
-    wg_copy(job.out_fac[0], st.plane[lev] + row0 * st.rk[lev][0], (st.ell << lev) * st.rk[lev][0]);
-    if (tid == 0 && job.stats) {
-      job.stats[STAT_FIT] = -1.0;
-      job.stats[STAT_ERR] = -1.0;
-      job.stats[STAT_NORM] = -1.0;
-      job.stats[STAT_SWEEPS] = 0.0;
-      job.stats[STAT_CONV] = 1.0;
-      job.stats[STAT_HITS] = 1.0;
-      job.stats[STAT_STATUS] = 0.0;
-    }
-    return;
-  }
-
-  PhaseClock& clk = sh.clk;
-  EigCounters& ec = sh.ec;
-  if (tid == 0) ec.calls = ec.sweeps = ec.jacobi_ticks = ec.tail_ticks = ec.fallbacks = ec.tri_ticks = ec.invit_ticks = 0;
-  clk.start();
-  // the layout record lives at the head of the workspace
-  StitchLayout* lop = reinterpret_cast<StitchLayout*>(ws);
-  if (tid == 0) stitch_layout(st, hits, s, rq, n_lds, lop);
-  __threadfence_block();
-  __syncthreads();
-  const StitchLayout& lo = *lop;
-  if (lo.total > job.ws_bytes) {
-    if (tid == 0 && job.stats) job.stats[STAT_STATUS] = 2.0;
-    return;
-  }
-  const int eneed = stitch_eig_need(lo, st, basis_pct);
-  if (eneed > n_lds && eig_vec_doubles(eneed) > lds_doubles) {  // launched with too little LDS
-    if (tid == 0 && job.stats) job.stats[STAT_STATUS] = 3.0;
-    return;
-  }
-  double* red = sh.red;
-  // the ALS contractions (TTM chains, Z^(n), core update) and their Grams:
-  // FP32 on the matrix cores, or BF16 operands with FP32 accumulation
-  auto ttm = [&](const float* X, int64_t a, int r, int64_t b, const float* A, int64_t as, int64_t bs, int m,
-                 float* Y, bool acc) {
-    if (lowp) mode_product_bf16(X, a, r, b, A, as, bs, m, Y, acc);
-    else if (PM > PM_FEW && m <= 8 && r <= 8) mode_product_fiber<float, float, float, float, 8>(X, a, r, b, A, as, bs, m, Y, acc);
-    else mode_product(X, a, r, b, A, as, bs, m, Y, acc);
-  };
-  auto gram = [&](const float* X, int64_t a, int q, int64_t b, double* G, int ld) {
-    if (lowp) gram_mode_bf16(X, a, q, b, G, ld);
-    else gram_mode_mfma(X, a, q, b, G, ld);
-  };
-  auto Fp = [&](int64_t off) { return reinterpret_cast<float*>(ws + off); };
-  auto Dp = [&](int64_t off) { return reinterpret_cast<double*>(ws + off); };
-  double* TMP = Dp(lo.TMP);
-  // Run f on the eigen/Cholesky buffer (matrix part, vector part): both in
-  // LDS when the problem fits, else the matrix in the job's global buffer and
-  // the vectors in LDS.  Calling f from two branches lets each inlined copy
-  // address its buffers directly (LDS instructions where they are in LDS).
-  auto with_buf = [&](int n, auto&& f) {
-    if (n <= n_lds) f(lds, lds + int64_t(n) * n);
-    else f(Dp(lo.EIG), lds);
-  };
-  // the same for a mode's eigenproblem, which may exceed the planned size
-  // (a rank-deficient basis falls back to D_n): vectors in LDS only when
-  // the launch has room for them
-  auto with_eig_buf = [&](int n, auto&& f) {
-    if (n <= n_lds) f(lds, lds + int64_t(n) * n);
-    else if (eig_vec_doubles(n) <= lds_doubles) f(Dp(lo.EIG), lds);
-    else f(Dp(lo.EIG), Dp(lo.EIG) + int64_t(n) * n);
-  };
-
-  // ---- trims (Eq. "partial-tucker") and |Y~|^2 ------------------------------
-  double ny2 = 0.0;
-  for (int i = 0; i < s; ++i) {
-    const Hit h = hits[i];
-    const int lev = h.level;
-    const int k = st.rk[lev][0];
-    int64_t R = 1;
-    for (int n = 1; n < p; ++n) R *= st.rk[lev][n];
-    const float* H = st.core[lev] + h.index * st.core_elems[lev];
-    if (!h.partial) {
-      if (tid == 0) sh.kp[i] = k;
-      double part = 0.0;
-      for (int64_t e = tid; e < int64_t(k) * R; e += nt) part += double(H[e]) * double(H[e]);
-      ny2 += block_sum(part, red);
-      continue;
-    }
-    // rows [a, a+l) of V^(1) = Q~ R~ through a pivoted Cholesky of their Gram
-    const float* V = st.plane[lev] + ((h.index << lev) * st.ell + h.a) * k;
-    float* Rt = Fp(lo.T1);  // R~, kp x k
-    int kp = 0;
-    with_buf(k, [&](double* Gm, double*) {
-      gram_rows(V, h.l, k, Gm, k, Dp(lo.D1));
-      double* d = Gm + k * k;
-      int* piv = reinterpret_cast<int*>(Gm + k * k + k);
-      kp = pchol(Gm, k, 1e-12, TMP, piv, d, red, sh.redi);
-      pchol_basis<float>(TMP, piv, k, kp, Rt, k, Dp(lo.F[i]), k, Dp(lo.EF[0]));
-    });
-    float* Ht = Fp(lo.Ht[i]);
-    mode_product(H, 1, k, R, Rt, k, 1, kp, Ht, false);
-    double part = 0.0;
-    for (int64_t e = tid; e < int64_t(kp) * R; e += nt) part += double(Ht[e]) * double(Ht[e]);
-    ny2 += block_sum(part, red);
-    if (tid == 0) sh.kp[i] = kp;
-    __syncthreads();
-  }
-  clk.mark(0);
-  if (tid == 0) {
-    sh.koff[0] = 0;
-    for (int i = 0; i < s; ++i) sh.koff[i + 1] = sh.koff[i] + sh.kp[i];
-    for (int n = 1; n < p; ++n) {
-      sh.roff[n][0] = 0;
-      for (int i = 0; i < s; ++i) sh.roff[n][i + 1] = sh.roff[n][i] + st.rk[hits[i].level][n];
-    }
-  }
-  __syncthreads();
-  auto core_of = [&](int i) -> const float* {
-    const Hit& h = hits[i];
-    return h.partial ? Fp(lo.Ht[i]) : st.core[h.level] + h.index * st.core_elems[h.level];
-  };
-  auto fac_of = [&](int i, int n) -> const float* {
-    const Hit& h = hits[i];
-    return st.fac[h.level][n] + h.index * fac_elems(st, h.level, n);
-  };
-  auto A_off = [&](int i, int n) -> int64_t {  // offset of U^(n)T V~_i^(n) = P_n^T C_i, rq_n x r_i^(n)
-    int64_t off = 0;
-    for (int m = 1; m < n; ++m) off += int64_t(rq[m]) * st.rk[hits[i].level][m];
-    return off;
-  };
-  auto hit_of_col = [&](int n, int c) {  // the hit whose mode-n factor holds column c of V_cat
-    int i = 0;
-    while (c >= sh.roff[n][i + 1]) ++i;
-    return i;
-  };
-  auto vcat = [&](int n, int64_t dd, int c) -> float {  // V_cat[dd][c]
-    const int i = hit_of_col(n, c);
-    return fac_of(i, n)[dd * st.rk[hits[i].level][n] + (c - sh.roff[n][i])];
-  };
-
-  // ---- orthonormal bases of the non-temporal spans -----------------------------
-  for (int n = 1; n < p; ++n) {
-    const int sr = lo.sr[n];
-    const int64_t Dn = st.D[n];
-    float* C = Fp(lo.C[n]);  // q x sr, leading dimension sr
-    double* C64 = Dp(lo.C64[n]);
-    int use_basis = 0;
-    if (span_basis(sr, Dn, basis_pct)) {
-      with_buf(sr, [&](double* Gm, double*) {
-        // Gram of V_cat = [V~_1^(n) .. V~_s^(n)] over its D_n rows, FP64 on
-        // the matrix cores, then mirrored so that it is exactly symmetric
-        gemm_f64(sr, sr, int(Dn), [&](int x, int dd) { return vcat(n, dd, x); },
-                 [&](int dd, int y) { return vcat(n, dd, y); }, [&](int x, int y, double v) { Gm[x * sr + y] = v; });
-        for (int e = tid; e < sr * sr; e += nt) {
-          const int x = e / sr, y = e % sr;
-          if (y < x) Gm[e] = Gm[y * sr + x];
-        }
-        __syncthreads();
-        double* d = Gm + sr * sr;
-        int* piv = reinterpret_cast<int*>(Gm + sr * sr + sr);
-        const int q = pchol(Gm, sr, 1e-11, TMP, piv, d, red, sh.redi);
-        if (q >= rq[n]) {
-          use_basis = 1;
-          pchol_basis<double>(TMP, piv, sr, q, C64, sr, Dp(lo.Fn[n]), sr, Dp(lo.EF[n]));
-          for (int e = tid; e < q * sr; e += nt) C[e] = float(C64[e]);
-          if (tid == 0) sh.q[n] = q;
-        }
-      });
-    }
-    if (!use_basis) {
-      for (int64_t e = tid; e < Dn * sr; e += nt) {
-        const int64_t dd = e / sr;
-        const int c = int(e % sr);
-        int i = 0;
-        while (c >= sh.roff[n][i + 1]) ++i;
-        const int r = st.rk[hits[i].level][n];
-        C[e] = fac_of(i, n)[dd * r + (c - sh.roff[n][i])];
-        C64[e] = double(C[e]);
-      }
-      if (tid == 0) sh.q[n] = int32_t(Dn);
-    }
-    if (tid == 0) sh.basis[n] = use_basis;
-    __syncthreads();
-  }
-  clk.mark(1);
-
-  // P_n^T C_i for every piece (mode n >= 1), FP32 copy of P_n
-  auto update_A = [&](int n) {
-    const int q = sh.q[n], sr = lo.sr[n], r_out = rq[n];
-    const double* P = Dp(lo.Pd[n]);
-    const double* C64 = Dp(lo.C64[n]);
-    // [A_1 .. A_s] = P_n^T C^(n) (r_out x sr); A_i is stored r_out x r_i
-    gemm_f64(r_out, sr, q, [&](int c, int dd) { return P[dd * r_out + c]; },
-             [&](int dd, int col) { return C64[int64_t(dd) * sr + col]; },
-             [&](int c, int col, double v) {
-               const int i = hit_of_col(n, col);
-               const int r = st.rk[hits[i].level][n];
-               Fp(lo.A[i])[A_off(i, n) + int64_t(c) * r + (col - sh.roff[n][i])] = float(v);
-             });
-    float* Pf = Fp(lo.Pf[n]);
-    for (int e = tid; e < q * r_out; e += nt) Pf[e] = float(P[e]);
-    __syncthreads();
-  };
-
-  // ---- HOSVD initialisation of U^(2..p) (Gram of Y~ in reduced coordinates)
-  for (int n = 1; n < p; ++n) {
-    const int q = sh.q[n], sr = lo.sr[n];
-    with_eig_buf(q, [&](double* Wm, double* Wv) {
-    for (int e = tid; e < q * q; e += nt) Wm[e] = 0.0;
-    __syncthreads();
-    double* S = Dp(lo.S);
-    double* T = Dp(lo.D1);  // C_i S_i, q x r
-    const double* C64 = Dp(lo.C64[n]);
-    for (int i = 0; i < s; ++i) {
-      const int lev = hits[i].level;
-      const int r = st.rk[lev][n];
-      int32_t dims[PM];
-      dims[0] = sh.kp[i];
-      for (int m = 1; m < p; ++m) dims[m] = st.rk[lev][m];
-      gram_mode_mfma(core_of(i), prod_range(dims, 0, n), r, prod_range(dims, n + 1, p), S, r);
-      const int c0 = sh.roff[n][i];
-      // T = C_i S_i (q x r), then Wm += T C_i^T
-      gemm_f64(q, r, r, [&](int dd, int c) { return C64[int64_t(dd) * sr + c0 + c]; },
-               [&](int c, int j) { return S[c * r + j]; }, [&](int dd, int j, double v) { T[dd * r + j] = v; });
-      gemm_f64(q, q, r, [&](int dd, int j) { return T[dd * r + j]; },
-               [&](int j, int d2) { return C64[int64_t(d2) * sr + c0 + j]; },
-               [&](int dd, int d2, double v) { Wm[dd * q + d2] += v; });
-    }
-    eig_top(Wm, q, rq[n], Dp(lo.Pd[n]), rq[n], red, Dp(lo.EF[n]), TMP, false, &ec, Wv);
-    });
-    update_A(n);
-  }
-  clk.mark(2);
-
-  // ---- ALS sweeps (Alg. "stitch") ---------------------------------------------
-  int64_t Rhat[PM];
-  for (int n = 0; n < p; ++n) {
-    Rhat[n] = 1;
-    for (int m = 0; m < p; ++m)
-      if (m != n) Rhat[n] *= rq[m];
-  }
-  float* T1 = Fp(lo.T1);
-  float* T2 = Fp(lo.T2);
-  float* G = Fp(lo.G);
-  double fit_prev = 0.0, fit = 0.0;
-  int sweeps = 0, conv = 0;
-  double g2 = 0.0;
-  for (int it = 1; it <= max_iter; ++it) {
-    // temporal mode: M = [mat_1(H~_i x_{m>=2} A_i^(m))]_i, P_0 = leading eigvecs of M M^T
-    float* M = Fp(lo.M);
-    for (int i = 0; i < s; ++i) {
-      const int lev = hits[i].level;
-      int32_t dims[PM];
-      dims[0] = sh.kp[i];
-      for (int m = 1; m < p; ++m) dims[m] = st.rk[lev][m];
-      const float* cur = core_of(i);
-      for (int n = 1; n < p; ++n) {
-        float* out = (n == p - 1) ? M + int64_t(sh.koff[i]) * Rhat[0] : ((n & 1) ? T1 : T2);
-        ttm(cur, prod_range(dims, 0, n), dims[n], prod_range(dims, n + 1, p),
-            Fp(lo.A[i]) + A_off(i, n), dims[n], 1, rq[n], out, false);
-        dims[n] = rq[n];
-        cur = out;
-      }
-    }
-    const int sk = sh.koff[s];
-    with_buf(sk, [&](double* Wm, double* Wv) {
-      gram(M, 1, sk, Rhat[0], Wm, sk);
-      clk.mark(3);
-      eig_top(Wm, sk, rq[0], Dp(lo.Pd[0]), rq[0], red, Dp(lo.EF[0]), TMP, it > 1, &ec, Wv);
-    });
-    float* P0f = Fp(lo.Pf[0]);
-    {
-      const double* P0 = Dp(lo.Pd[0]);
-      for (int e = tid; e < sk * rq[0]; e += nt) P0f[e] = float(P0[e]);
-      __syncthreads();
-    }
-    clk.mark(4);
-    // non-temporal modes: K_n = sum_i W_i^(n) x_n C_i, P_n = leading eigvecs of its Gram
-    float* K = Fp(lo.K);
-    float* Wst = Fp(lo.WS);
-    for (int n = 1; n < p; ++n) {
-      const int q = sh.q[n];
-      int32_t kd[PM];
-      for (int m = 0; m < p; ++m) kd[m] = rq[m];
-      kd[n] = q;
-      const int64_t ka = prod_range(kd, 0, n), kb = prod_range(kd, n + 1, p);
-      for (int i = 0; i < s; ++i) {
-        const int lev = hits[i].level;
-        int32_t dims[PM];
-        dims[0] = sh.kp[i];
-        for (int m = 1; m < p; ++m) dims[m] = st.rk[lev][m];
-        const float* cur = core_of(i);
-        float* bufs[2] = {T1, T2};
-        int nb = 0;
-        // x_1 P_i^T : A(c, j) = P0[(koff_i + j) rq_0 + c]
-        ttm(cur, 1, dims[0], prod_range(dims, 1, p), P0f + int64_t(sh.koff[i]) * rq[0], 1, rq[0],
-                     rq[0], bufs[nb], false);
-        dims[0] = rq[0];
-        cur = bufs[nb];
-        nb ^= 1;
-        for (int m = 1; m < p; ++m) {
-          if (m == n) continue;
-          ttm(cur, prod_range(dims, 0, m), dims[m], prod_range(dims, m + 1, p),
-                       Fp(lo.A[i]) + A_off(i, m), dims[m], 1, rq[m], bufs[nb], false);
-          dims[m] = rq[m];
-          cur = bufs[nb];
-          nb ^= 1;
-        }
-        // W_i^(n) into the stack Wst (ka x sr_n x kb) at mode-n rows roff_i
-        const int ri = dims[n];
-        const int64_t rb = int64_t(ri) * kb;
-        const int srn = lo.sr[n];
-        for (int64_t e = tid; e < ka * rb; e += nt) {
-          const int64_t x = e / rb, jy = e - x * rb;
-          Wst[(x * srn + sh.roff[n][i]) * kb + jy] = cur[e];
-        }
-        __syncthreads();
-      }
-      // K_n = sum_i W_i^(n) x_n C_i: one product over the stacked mode
-      ttm(Wst, ka, lo.sr[n], kb, Fp(lo.C[n]), lo.sr[n], 1, q, K, false);
-      with_eig_buf(q, [&](double* Wn, double* Wv) {
-        gram(K, ka, q, kb, Wn, q);
-        clk.mark(5);
-        eig_top(Wn, q, rq[n], Dp(lo.Pd[n]), rq[n], red, Dp(lo.EF[n]), TMP, true, &ec, Wv);
-      });
-      update_A(n);
-      clk.mark(6);
-    }
-    // core update: G = Z^(p) x_p U^(p)T, here K_p x_p P_p^T
-    {
-      const int q = sh.q[p - 1];
-      ttm(K, prod_range(rq, 0, p - 1), q, 1, Fp(lo.Pf[p - 1]), 1, rq[p - 1], rq[p - 1], G, false);
-      const int64_t gel = prod_range(rq, 0, p);
-      double part = 0.0;
-      for (int64_t e = tid; e < gel; e += nt) part += double(G[e]) * double(G[e]);
-      g2 = block_sum(part, red);
-    }
-    fit = ny2 > 0.0 ? 1.0 - sqrt(fmax(0.0, ny2 - g2)) / sqrt(ny2) : 1.0;
-    sweeps = it;
-    clk.mark(5);
-    if (it >= 2 && fabs(fit - fit_prev) < tol) {
-      conv = 1;
-      break;
-    }
-    fit_prev = fit;
-  }
-
-  // ---- write the result ----------------------------------------------------------
-  // (FP64 products on the matrix cores, FP32 stores)
-  // U^(n) = B P_n (= V_cat F_n P_n on the basis route)
-  for (int n = 1; n < p; ++n) {
-    const int64_t Dn = st.D[n];
-    const int r_out = rq[n];
-    const double* P = Dp(lo.Pd[n]);
-    float* out = job.out_fac[n];
-    if (sh.basis[n]) {
-      const int sr = lo.sr[n], q = sh.q[n];
-      const double* Fn = Dp(lo.Fn[n]);
-      double* Fh = Dp(lo.Fh[n]);
-      gemm_f64(sr, r_out, q, [&](int c, int dd) { return Fn[c * sr + dd]; },
-               [&](int dd, int j) { return P[dd * r_out + j]; },
-               [&](int c, int j, double v) { Fh[c * r_out + j] = v; });
-      gemm_f64(int(Dn), r_out, sr, [&](int dd, int c) { return vcat(n, dd, c); },
-               [&](int c, int j) { return Fh[c * r_out + j]; },
-               [&](int dd, int j, double v) { out[int64_t(dd) * r_out + j] = float(v); });
-    } else {
-      for (int64_t e = tid; e < Dn * r_out; e += nt) out[e] = float(P[e]);
-    }
-  }
-  // U^(1) rows: block i = V~_i^(1) P_i, V~_i^(1) = rows F_i on a partial hit
-  {
-    const double* P0 = Dp(lo.Pd[0]);
-    const int r0 = rq[0];
-    int64_t t = 0;
-    for (int i = 0; i < s; ++i) {
-      const Hit h = hits[i];
-      const int lev = h.level;
-      const int k = st.rk[lev][0];
-      const int kp = sh.kp[i];
-      double* F0 = Dp(lo.F0[i]);  // k x r0
-      const double* Pi = P0 + int64_t(sh.koff[i]) * r0;
-      if (h.partial) {
-        const double* Fi = Dp(lo.F[i]);
-        gemm_f64(k, r0, kp, [&](int c, int m) { return Fi[c * k + m]; }, [&](int m, int j) { return Pi[m * r0 + j]; },
-                 [&](int c, int j, double v) { F0[c * r0 + j] = v; });
-      } else {
-        for (int e = tid; e < k * r0; e += nt) F0[e] = Pi[e];
-        __syncthreads();
-      }
-      const float* V = st.plane[lev] + ((h.index << lev) * st.ell + h.a) * k;
-      float* out = job.out_fac[0] + t * r0;
-      gemm_f64(int(h.l), r0, k, [&](int row, int c) { return V[int64_t(row) * k + c]; },
-               [&](int c, int j) { return F0[c * r0 + j]; },
-               [&](int row, int j, double v) { out[int64_t(row) * r0 + j] = float(v); });
-      t += h.l;
-    }
-  }
-  // final core in FP64: G = sum_i H~_i x_1 P_i^T x_{n>=2} (P_n^T C_i), and
-  // the model error |Y~|^2 - |G|^2 from it
-  {
-    const int64_t gel = prod_range(rq, 0, p);
-    double* G64 = Dp(lo.G64);
-    double* D1 = Dp(lo.D1);
-    double* D2 = Dp(lo.D2);
-    const double* P0 = Dp(lo.Pd[0]);
-    // [A64_1 .. A64_s] = P_n^T C^(n) for every mode
-    for (int n = 1; n < p; ++n) {
-      const int q = sh.q[n], sr = lo.sr[n], r_out = rq[n];
-      const double* P = Dp(lo.Pd[n]);
-      const double* C = Dp(lo.C64[n]);
-      gemm_f64(r_out, sr, q, [&](int c, int dd) { return P[dd * r_out + c]; },
-               [&](int dd, int col) { return C[int64_t(dd) * sr + col]; },
-               [&](int c, int col, double v) {
-                 const int i = hit_of_col(n, col);
-                 const int r = st.rk[hits[i].level][n];
-                 Dp(lo.A64[i])[A_off(i, n) + int64_t(c) * r + (col - sh.roff[n][i])] = v;
-               });
-    }
-    for (int i = 0; i < s; ++i) {
-      int32_t dims[PM];
-      dims[0] = sh.kp[i];
-      for (int m = 1; m < p; ++m) dims[m] = st.rk[hits[i].level][m];
-      mode_product_f64<float>(core_of(i), 1, dims[0], prod_range(dims, 1, p), P0 + int64_t(sh.koff[i]) * rq[0], 1,
-                              rq[0], rq[0], D1, false);
-      dims[0] = rq[0];
-      const double* cur = D1;
-      double* bufs[2] = {D2, D1};
-      int nb = 0;
-      for (int n = 1; n < p; ++n) {
-        double* out = (n == p - 1) ? G64 : bufs[nb];
-        mode_product_f64<double>(cur, prod_range(dims, 0, n), dims[n], prod_range(dims, n + 1, p),
-                                 Dp(lo.A64[i]) + A_off(i, n), dims[n], 1, rq[n], out, n == p - 1 && i > 0);
-        dims[n] = rq[n];
-        cur = out;
-        nb ^= 1;
-      }
-    }
-    double part = 0.0;
-    for (int64_t e = tid; e < gel; e += nt) {
-      part += G64[e] * G64[e];
-      job.out_core[e] = float(G64[e]);
-    }
-    g2 = block_sum(part, red);
-  }
-  if (tid == 0 && job.stats) {
-    job.stats[STAT_STATUS] = 0.0;
-    job.stats[STAT_FIT] = fit;
-    job.stats[STAT_ERR] = ny2 > 0.0 ? sqrt(fmax(0.0, ny2 - g2)) / sqrt(ny2) : 0.0;
-    job.stats[STAT_NORM] = sqrt(ny2);
-    job.stats[STAT_SWEEPS] = double(sweeps);
-    job.stats[STAT_CONV] = double(conv);
-    job.stats[STAT_HITS] = double(s);
-  }
-  clk.mark(7);
-  clk.store(job.stats);
-  if (tid == 0 && job.stats) {
-    job.stats[STAT_EIG + 0] = double(ec.calls);
-    job.stats[STAT_EIG + 1] = double(ec.sweeps);
-    job.stats[STAT_EIG + 2] = double(ec.jacobi_ticks) * 0.01;
-    job.stats[STAT_EIG + 3] = double(ec.tail_ticks) * 0.01;
-    job.stats[STAT_EIG_FALLBACK] = double(ec.fallbacks);
-    job.stats[STAT_EIG_TRI] = double(ec.tri_ticks) * 0.01;
-    job.stats[STAT_EIG_INVIT] = double(ec.invit_ticks) * 0.01;
-  }
-}
-
-// One wavefront per job for jobs whose eigenproblems are small; two or four
-// wavefronts for jobs with large ones (more lanes per rotation pair and per
-// contraction shorten their latency, which bounds a batch's completion).
-// A query job first runs Recall (Alg. "recall") on its own range and
-// snapshot, into LDS, and publishes the hits to its slots of args.hits.
-// With args.queue set the launch is persistent: each workgroup takes jobs
-// from the queue counter (heaviest first, as the host sorted them) until it
-// runs past n_jobs, so every workgroup reaches the exit.
-// Register budget: at most 256 VGPRs, so that two wavefronts share a SIMD
-// (one job's latency hides behind another's).
-template <int NTT, int PM>
-__global__ __launch_bounds__(NTT, 2) void stitch_kernel(StitchArgs args) {
-  extern __shared__ double lds[];
-  __shared__ StitchShared<PM> sh;
-  __shared__ Hit qh[MAXHITS];
-  __shared__ int next_job;
-  __shared__ int n_rec;
-  const StoreView& st = *args.st;
-  int jn = blockIdx.x;
-  for (;;) {
-    if (args.queue) {
-      if (threadIdx.x == 0) next_job = atomicAdd(args.queue, 1);
-      __syncthreads();
-      jn = next_job;
-      __syncthreads();
-    }
-    if (jn >= args.n_jobs) break;
-    const Job& job = args.jobs[jn];
-    if (st.p > PM) {  // launched with the wrong instantiation: refuse the job
-      if (threadIdx.x == 0 && job.stats) job.stats[STAT_STATUS] = 3.0;
-      if (!args.queue) break;
-      continue;
-    }
-    // the job's hits go to LDS: a query's from its own Recall (published to
-    // its slots of args.hits), a merge's two children from args.hits
-    if (threadIdx.x == 0) {
-      int n = job.s;
-      if (job.kind == 0) {
-        n = recall_with_stack(job.ts, job.ts + job.L, job.Tb, st.ell, args.theta_num, args.theta_den, qh, MAXHITS,
-                              sh.recall_stack);
-        if (n == job.s)
-          for (int i = 0; i < n; ++i) args.hits[job.hit0 + i] = qh[i];
-      } else {
-        for (int i = 0; i < n && i < MAXHITS; ++i) qh[i] = args.hits[job.hit0 + i];
-      }
-      n_rec = n;
-    }
-    __syncthreads();
-    if (n_rec != job.s) {
-      if (threadIdx.x == 0 && job.stats) {
-        job.stats[STAT_STATUS] = 1.0;
-        job.stats[STAT_HITS] = double(n_rec);
-      }
-      if (!args.queue) break;
-      continue;
-    }
-    const Hit* hits = qh;
-    const uint64_t t_begin = wall_clock64();
-    stitch_one(st, job, hits, args.ws + job.ws_off, args.n_lds, args.lds_doubles, args.basis_pct,
-               job.kind == 1 ? args.merge_max_iter : args.max_iter, job.kind == 1 ? args.merge_tol : args.tol,
-               job.kind == 1 ? args.merge_bf16 != 0 : args.bf16 != 0, sh, lds);
-    if (threadIdx.x == 0 && job.stats) {
-      job.stats[STAT_T0] = double(t_begin);
-      job.stats[STAT_T1] = double(wall_clock64());
-    }
-    if (!args.queue) break;
-  }
-}
 
 __global__ void reset_queue_kernel(int* queue, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) queue[i] = 0;
@@ -839,30 +214,17 @@ __global__ __launch_bounds__(NT_LEAF, 2) void raw_kernel(RawArgs args) {
 // ------------------------------------------------------------------------------
 // Launchers
 // ------------------------------------------------------------------------------
-template <int PM>
-static hipError_t launch_stitch_pm(const StitchArgs& a, int grid, size_t lds_bytes, int threads, hipStream_t stream) {
-  switch (threads) {
-    case 64:
-      hipLaunchKernelGGL((stitch_kernel<64, PM>), dim3(grid), dim3(64), lds_bytes, stream, a);
-      break;
-    case 128:
-      hipLaunchKernelGGL((stitch_kernel<128, PM>), dim3(grid), dim3(128), lds_bytes, stream, a);
-      break;
-    case 256:
-      hipLaunchKernelGGL((stitch_kernel<256, PM>), dim3(grid), dim3(256), lds_bytes, stream, a);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
 hipError_t launch_stitch(const StitchArgs& a, int grid, size_t lds_bytes, int threads, hipStream_t stream) {
   if (grid <= 0 || a.n_jobs <= 0) return hipSuccess;
   if (grid > a.n_jobs || (!a.queue && grid != a.n_jobs)) return hipErrorInvalidValue;
   if (a.p < 2 || a.p > MAXP) return hipErrorInvalidValue;
-  return a.p <= PM_FEW ? launch_stitch_pm<PM_FEW>(a, grid, lds_bytes, threads, stream)
-                       : launch_stitch_pm<MAXP>(a, grid, lds_bytes, threads, stream);
+  const bool few = a.p <= PM_FEW;
+  switch (threads) {
+    case 64: return few ? stitch_launch_64_4(a, grid, lds_bytes, stream) : stitch_launch_64_7(a, grid, lds_bytes, stream);
+    case 128: return few ? stitch_launch_128_4(a, grid, lds_bytes, stream) : stitch_launch_128_7(a, grid, lds_bytes, stream);
+    case 256: return few ? stitch_launch_256_4(a, grid, lds_bytes, stream) : stitch_launch_256_7(a, grid, lds_bytes, stream);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_reset_queue(int* queue, int n, hipStream_t stream) {
@@ -884,14 +246,10 @@ hipError_t launch_leaf(const LeafArgs& a, int n_jobs, size_t lds_bytes, hipStrea
 }
 
 hipError_t set_lds_limits(size_t stitch_bytes, size_t leaf_bytes) {
-  const void* fns[] = {reinterpret_cast<const void*>(stitch_kernel<64, PM_FEW>),
-                       reinterpret_cast<const void*>(stitch_kernel<128, PM_FEW>),
-                       reinterpret_cast<const void*>(stitch_kernel<256, PM_FEW>),
-                       reinterpret_cast<const void*>(stitch_kernel<64, MAXP>),
-                       reinterpret_cast<const void*>(stitch_kernel<128, MAXP>),
-                       reinterpret_cast<const void*>(stitch_kernel<256, MAXP>)};
-  for (const void* f : fns) {
-    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(stitch_bytes));
+  hipError_t (*const fns[])(size_t) = {stitch_set_lds_64_4, stitch_set_lds_128_4, stitch_set_lds_256_4,
+                                       stitch_set_lds_64_7, stitch_set_lds_128_7, stitch_set_lds_256_7};
+  for (auto f : fns) {
+    const hipError_t e = f(stitch_bytes);
     if (e != hipSuccess) return e;
   }
   const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(leaf_kernel),
@@ -902,16 +260,11 @@ hipError_t set_lds_limits(size_t stitch_bytes, size_t leaf_bytes) {
 }
 
 int stitch_blocks_per_cu(int threads, size_t lds_bytes) {
-  int n = 0;
-  hipError_t e = hipErrorInvalidValue;
   // the many-mode instantiation: its static LDS is the larger
-  if (threads == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stitch_kernel<64, MAXP>, 64, lds_bytes);
-  if (threads == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stitch_kernel<128, MAXP>, 128, lds_bytes);
-  if (threads == 256) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stitch_kernel<256, MAXP>, 256, lds_bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return 1;
-  }
+  int n = 0;
+  if (threads == 64) n = stitch_occupancy_64_7(lds_bytes);
+  if (threads == 128) n = stitch_occupancy_128_7(lds_bytes);
+  if (threads == 256) n = stitch_occupancy_256_7(lds_bytes);
   return n > 0 ? n : 1;
 }
 

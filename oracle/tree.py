@@ -90,51 +90,61 @@ class StreamSegmentTree:
             return 1 + max(h(v.left), h(v.right))
         return h(self.root)
 
-    # -- Alg. "append" ---------------------------------------------------------
+    # -- Alg. "append" and Alg. "insert" (Sec. 6.2) ----------------------------
+    # The stream segment tree is a dyadic tree over block indices grown on
+    # demand.  Appending block T (a) doubles the root when T reaches its end
+    # (the new root is a placeholder [0, 2 tau) with the old root on its left),
+    # (b) walks from the root to the slot [T, T+1), creating the missing
+    # placeholders on the way (in that order, which fixes the node ids), (c)
+    # turns the slot into a leaf holding the block's Tucker decomposition, and
+    # (d) finishes, from the bottom up, every node on that path whose range now
+    # ends at T+1: each becomes an intermediate node whose decomposition is
+    # the Stitch of its two children.
     def append(self, block: Optional[np.ndarray]) -> None:
         T = self.T_b
-        if T == 0:
+        if self.root is None:
             self.root = self._new(0, 1)
         elif T == self.root.hi:
-            r = self._new(0, 2 * self.root.hi)
-            r.left = self.root
-            self.root = r
+            grown = self._new(0, 2 * self.root.hi)
+            grown.left = self.root
+            self.root = grown
+        path = [self.root]
+        while path[-1].hi - path[-1].lo > 1:
+            v = path[-1]
+            half = (v.lo + v.hi) // 2
+            side = "left" if T < half else "right"
+            child = getattr(v, side)
+            if child is None:
+                child = self._new(v.lo, half) if side == "left" else self._new(half, v.hi)
+                setattr(v, side, child)
+            path.append(child)
+        leaf = path[-1]
+        assert leaf.lo == T, "the walk must end at the new block's slot"
+        leaf.kind = "L"
+        if block is not None:
+            r = effective_ranks(self.leaf_len, self.dims, self.ranks)
+            G, U, info = hooi(np.asarray(block, dtype=np.float64), r, self.max_iter, self.tol)
+            leaf.H, leaf.V = canonical_signs(G, U)
+            leaf.info = info
         self.merges_last = 0
-        self._insert(self.root, T, block)
+        for v in reversed(path[:-1]):
+            if v.hi != T + 1:
+                break  # nodes above end later; none of them completes now
+            self._complete(v, block is not None)
         self.T_b += 1
         self.merges_total += self.merges_last
 
-    # -- Alg. "insert" ---------------------------------------------------------
-    def _insert(self, v: Node, T: int, block) -> None:
-        if v.lo == T and v.hi == T + 1:
-            v.kind = "L"
-            if block is not None:
-                X = np.asarray(block, dtype=np.float64)
-                r = effective_ranks(self.leaf_len, self.dims, self.ranks)
-                G, U, info = hooi(X, r, self.max_iter, self.tol)
-                v.H, v.V = canonical_signs(G, U)
-                v.info = info
-            return
-        mu = (v.lo + v.hi) // 2
-        if T < mu:
-            if v.left is None:
-                v.left = self._new(v.lo, mu)
-            self._insert(v.left, T, block)
-        else:
-            if v.right is None:
-                v.right = self._new(mu, v.hi)
-            self._insert(v.right, T, block)
-            if v.hi == T + 1:
-                v.kind = "M"
-                self.merges_last += 1
-                if block is not None:
-                    u1, u2 = v.left, v.right
-                    r = effective_ranks((v.hi - v.lo) * self.leaf_len, self.dims, self.ranks)
-                    pieces = [stitch_mod.Piece(u1.H, u1.V), stitch_mod.Piece(u2.H, u2.V)]
-                    G, U, info = stitch_mod.stitch(pieces, r, self.max_iter, self.tol)
-                    v.H, v.V, v.info = G, U, info
+    def _complete(self, v: Node, decompose: bool) -> None:
+        """v's last block has arrived: it becomes intermediate, stitched from
+        its children at the ranks its length admits."""
+        v.kind = "M"
+        self.merges_last += 1
+        if decompose:
+            r = effective_ranks((v.hi - v.lo) * self.leaf_len, self.dims, self.ranks)
+            pieces = [stitch_mod.Piece(v.left.H, v.left.V), stitch_mod.Piece(v.right.H, v.right.V)]
+            v.H, v.V, v.info = stitch_mod.stitch(pieces, r, self.max_iter, self.tol)
 
-    # -- Alg. "recall" ---------------------------------------------------------
+    # -- Alg. "recall" (Sec. 5.1) ---------------------------------------------
     def _accept(self, v: Node, ts: int, te: int) -> bool:
         inter = max(0, min(te, self.tau(v)) - max(ts, self.sigma(v)))
         num, den = self.theta
@@ -142,31 +152,26 @@ class StreamSegmentTree:
 
     def recall(self, ts: int, te: int, _visited: Optional[list] = None) -> List[Tuple[Node, int, int]]:
         """Pruned hit set of [ts, te) in time order: (node, lo, hi) with the
-        clipped range [lo, hi) in slices."""
+        clipped range [lo, hi) in slices.  Starting from the root, a node is
+        taken whole when it is complete and the range covers at least theta of
+        it, or when it is a leaf (nothing below it to refine); any other node
+        hands the search to those of its children that overlap the range,
+        earlier child first."""
         if not (0 <= ts < te <= self.T):
             raise ValueError("range [%d,%d) not inside [0,%d)" % (ts, te, self.T))
         out: List[Node] = []
-
-        def rec(v: Node):
+        todo = [self.root]
+        while todo:
+            v = todo.pop()
             if _visited is not None:
                 _visited.append(v)
-            if v.kind in ("L", "M") and self._accept(v, ts, te):
+            if v.kind == "L" or (v.kind == "M" and self._accept(v, ts, te)):
                 out.append(v)
-                return
-            if v.kind == "L":          # terminal leaf below the threshold
-                out.append(v)
-                return
-            u1, u2 = v.left, v.right
-            if te <= self.tau(u1):
-                rec(u1)
-            elif u2 is not None and ts >= self.sigma(u2):
-                rec(u2)
-            else:
-                assert u2 is not None, "placeholder without right child inside the range"
-                rec(u1)
-                rec(u2)
-
-        rec(self.root)
+                continue
+            kids = [u for u in (v.left, v.right)
+                    if u is not None and max(ts, self.sigma(u)) < min(te, self.tau(u))]
+            assert kids, "a node inside the range without children"
+            todo.extend(reversed(kids))  # the earlier child is popped first
         return [(v, max(ts, self.sigma(v)), min(te, self.tau(v))) for v in out]
 
     def fixed_block_hits(self, ts: int, te: int, level: int) -> List[Tuple[Node, int, int]]:

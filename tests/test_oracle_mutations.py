@@ -104,3 +104,58 @@ def test_mode_product_reference_is_independent():
     U = np.arange(6.0).reshape(2, 3)
     Y = mode_product(X, U, 1)
     assert Y[1, 1, 2] == sum(U[1, j] * X[1, j, 2] for j in range(3))
+
+
+# --- the checkers themselves (oracle/evaluate.py) -----------------------------------
+
+import oracle.evaluate as EV  # noqa: E402
+import test_oracle_evaluate as ev_pins  # noqa: E402
+
+
+def test_sine_projecting_the_wrong_span_is_caught(monkeypatch):
+    def own_span(A, B, k):
+        Qb = np.linalg.qr(np.asarray(B, dtype=np.float64)[:, :k])[0]
+        R = Qb - Qb @ (Qb.T @ Qb)                 # projects B out of its own span
+        return float(np.linalg.norm(R, 2)) if R.size else 0.0
+    monkeypatch.setattr(EV, "subspace_sine", own_span)
+    monkeypatch.setattr(ev_pins, "subspace_sine", own_span)
+    with pytest.raises(AssertionError):
+        ev_pins.test_sine_of_planar_rotation(0.3)
+
+
+def test_sine_smallest_angle_is_caught(monkeypatch):
+    def smallest(A, B, k):
+        Qa = np.linalg.qr(np.asarray(A, dtype=np.float64)[:, :k])[0]
+        Qb = np.linalg.qr(np.asarray(B, dtype=np.float64)[:, :k])[0]
+        s = np.linalg.svd(Qb - Qa @ (Qa.T @ Qb), compute_uv=False)
+        return float(s[-1])                       # the smallest principal angle
+    monkeypatch.setattr(ev_pins, "subspace_sine", smallest)
+    with pytest.raises(AssertionError):
+        ev_pins.test_sine_is_the_largest_angle_of_several()
+
+
+def test_orthonormality_diagonal_only_is_caught(monkeypatch):
+    def diag_only(U):
+        U = np.asarray(U, dtype=np.float64)
+        return float(np.max(np.abs(np.sum(U * U, axis=0) - 1.0)))
+    monkeypatch.setattr(ev_pins, "orthonormality_error", diag_only)
+    with pytest.raises(AssertionError):
+        ev_pins.test_orthonormality_error_of_known_matrices()
+
+
+def test_relative_error_chunk_offset_is_caught(monkeypatch):
+    from oracle.tensor_ops import fro2, mode_product as mp
+
+    def restart_rows(X, G, Us, chunk=4096):
+        num_, den = 0.0, 0.0
+        for t0 in range(0, X.shape[0], chunk):
+            t1 = min(X.shape[0], t0 + chunk)
+            Y = mp(np.asarray(G, dtype=np.float64), np.asarray(Us[0])[:t1 - t0], 0)   # rows from 0
+            for n, U in enumerate(Us[1:], start=1):
+                Y = mp(Y, np.asarray(U), n)
+            num_ += fro2(np.asarray(X[t0:t1]) - Y)
+            den += fro2(X[t0:t1])
+        return float(np.sqrt(num_ / den))
+    monkeypatch.setattr(ev_pins, "relative_error", restart_rows)
+    with pytest.raises(AssertionError):
+        ev_pins.test_relative_error_beyond_one_default_chunk()

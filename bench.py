@@ -359,6 +359,21 @@ def pscale_main(args):
     print(json.dumps(out), flush=True)
 
 
+def copy_calibration_main(args):
+    """A device-to-device copy of a known size (PyTorch's copy kernel), for
+    converting rocprofv3's FETCH_SIZE / WRITE_SIZE counters into bytes: each
+    copy reads and writes args.copy_mib MiB."""
+    import torch
+    n = args.copy_mib * (1 << 20) // 4
+    src = torch.randn(n, device="cuda", dtype=torch.float32)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print("copied 3 x %d MiB" % args.copy_mib, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -382,7 +397,12 @@ def main():
     ap.add_argument("--pscale-tuning", default=None, help="JSON tuning for every p of --pscale")
     ap.add_argument("--tradeoff", action="store_true",
                     help="theta sweep and fixed-block variant: throughput and error per hit-set rule")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only a device copy of --copy-mib MiB (HBM counter calibration under rocprofv3)")
+    ap.add_argument("--copy-mib", type=int, default=1024)
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration_main(args)
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(queries are independent; see DESIGN.md on sharding)", file=sys.stderr)

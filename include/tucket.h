@@ -136,8 +136,12 @@ const char* tk_last_error(const tk_tree* t);
  * (Tucker-ALS, Sec. 2) and the stitches of Alg. "insert" run on the device. */
 tk_status tk_append(tk_tree* t, const float* slice, int on_device);
 
-/* T successive appends of X (T x D_2 x ... x D_p, C-order), executed level
- * by level: all leaves in one launch, then each tree level's merges. */
+/* Build = T successive stream updates (Sec. 3; Alg. "append" applied to
+ * slices 0..T-1, Sec. 6.2): X holds T x D_2 x ... x D_p FP32 values, C-order,
+ * on the host or (on_device) the device.  Executed level by level: all new
+ * leaves in one launch, then each tree level's merges (Alg. "insert"); the
+ * stored nodes are the same as T calls of tk_append.  TK_ENOMEM past
+ * capacity_T; a host X is copied before return. */
 tk_status tk_build(tk_tree* t, const float* X, int64_t T, int on_device);
 
 /* Pruned hit set of [t_s, t_e) in time order (host-side, bit-exact
@@ -146,7 +150,11 @@ tk_status tk_build(tk_tree* t, const float* X, int64_t T, int on_device);
 tk_status tk_hitset(const tk_tree* t, int64_t ts, int64_t te, tk_hit* out,
                     int32_t cap, int32_t* n);
 
-/* Output shape of a query (ranges as tk_query accepts them). */
+/* Output shape of a range query (Sec. 3: the core is r_1 x ... x r_p,
+ * U^(1) is (t_e - t_s) x r_1, U^(n) is D_n x r_n), with the ranks clipped to
+ * what the range admits, the size of its pruned hit set (Alg. "recall") and
+ * its device workspace; ranges as tk_query accepts them (TK_ERANGE
+ * otherwise).  Host-only, no device work. */
 tk_status tk_query_shape(const tk_tree* t, int64_t ts, int64_t te, tk_shape* out);
 
 /* Range query (Sec. 6.1): Recall, partial-hit trims (Eq. "partial-tucker")
@@ -233,7 +241,10 @@ tk_status tk_read_node(tk_tree* t, int32_t level, int64_t index, float* core,
                        float* const* factor);
 /* Set the committed horizon to T slices without computing anything, then
  * load complete nodes with tk_load_node.  Queries are valid once every node
- * they touch is loaded. */
+ * they touch is loaded.  T must be a multiple of leaf_len (a whole number of
+ * leaf blocks; the slices of an incomplete block belong to no node, so a
+ * horizon inside a block could not be continued by later appends): else
+ * TK_EINVAL, before any device work. */
 tk_status tk_restore_begin(tk_tree* t, int64_t T);
 tk_status tk_load_node(tk_tree* t, int32_t level, int64_t index, const float* core,
                        const float* const* factor);

@@ -21,8 +21,13 @@ thread_local std::string g_create_error;
 
 namespace tk {
 
+void set_error(tk_tree* t, const std::string& msg) {
+  std::lock_guard<std::mutex> lk(t->err_mu);
+  t->err = msg;
+}
+
 tk_status fail(tk_tree* t, tk_status st, const std::string& msg) {
-  if (t) t->err = msg;
+  if (t) set_error(t, msg);
   else g_create_error = msg;
   return st;
 }
@@ -36,7 +41,7 @@ tk_status fail_dev(tk_tree* t, hipError_t e, const char* what) {
   std::string m = std::string(what) + ": " + hipGetErrorString(e);
   if (t) {
     t->poisoned = true;
-    t->err = m;
+    set_error(t, m);
   } else {
     g_create_error = m;
   }
@@ -465,7 +470,14 @@ extern "C" {
 
 const char* tk_version(void) { return "0.1.0"; }
 
-const char* tk_last_error(const tk_tree* t) { return t ? t->err.c_str() : g_create_error.c_str(); }
+const char* tk_last_error(const tk_tree* t) {
+  if (!t) return g_create_error.c_str();
+  // a per-thread copy: another thread may replace the tree's text meanwhile
+  thread_local std::string copy;
+  std::lock_guard<std::mutex> lk(t->err_mu);
+  copy = t->err;
+  return copy.c_str();
+}
 
 tk_status tk_create(const tk_config* cfg, void* hip_stream, tk_tree** out) {
   if (!cfg || !out) return fail(nullptr, TK_EINVAL, "null argument");
@@ -1001,6 +1013,9 @@ tk_status tk_read_node(tk_tree* t, int32_t level, int64_t index, float* core, fl
 
 tk_status tk_restore_begin(tk_tree* t, int64_t T) {
   if (!t || T < 0 || T > t->cap_blocks * t->ell) return TK_EINVAL;
+  // the slices of an incomplete block are not part of any node: a horizon
+  // inside a block could not be continued by later appends
+  if (T % t->ell != 0) return fail(t, TK_EINVAL, "restore horizon must end at a leaf block boundary");
   if (t->server) return busy(t);
   if (t->poisoned) return TK_EDEVICE;
   t->T = T;

@@ -269,7 +269,7 @@ struct StitchLayout {
   int64_t Pd[MAXP];           // double D_n x rq_n  ([0]: sk x rq_0)
   int64_t Pf[MAXP];           // float  same
   int64_t Fh[MAXP];           // double sr_n x rq_n
-  int64_t EF[MAXP];           // double eigenbasis kept for warm starts: [0] sk x sk, [n] D_n x D_n
+  int64_t Tinv[MAXP];         // double triangular-inverse scratch of pchol_basis: [0] kmax^2 (trims), [n] sr_n^2 (bases)
   int64_t M;                  // float sk x Rhat_0
   int64_t K;                  // float max_n D_n Rhat_n
   int64_t WS;                 // float max_n sr_n Rhat_n (stacked W_i^(n))
@@ -368,7 +368,7 @@ TK_HD void stitch_layout(const StoreView& st, const Hit* hits, int s, const int3
     Lo->Pd[n] = take(int64_t(Lo->qmax[n]) * rq[n] * 8);
     Lo->Pf[n] = take(int64_t(Lo->qmax[n]) * rq[n] * 4);
     Lo->Fh[n] = take(int64_t(Lo->sr[n]) * rq[n] * 8);
-    Lo->EF[n] = take(int64_t(Lo->qmax[n]) * Lo->qmax[n] * 8);
+    Lo->Tinv[n] = take(int64_t(Lo->sr[n]) * Lo->sr[n] * 8);
     if (Lo->sr[n] > neig) neig = Lo->sr[n];
     if (Lo->qmax[n] > neig) neig = Lo->qmax[n];
     const int64_t kn = int64_t(Lo->qmax[n]) * Rhat[n];
@@ -378,7 +378,7 @@ TK_HD void stitch_layout(const StoreView& st, const Hit* hits, int s, const int3
   Lo->sr[0] = Lo->sk;
   Lo->Pd[0] = take(int64_t(Lo->sk) * rq[0] * 8);
   Lo->Pf[0] = take(int64_t(Lo->sk) * rq[0] * 4);
-  Lo->EF[0] = take(int64_t(Lo->sk) * Lo->sk * 8);
+  Lo->Tinv[0] = take(int64_t(maxk) * maxk * 8);
   Lo->M = take(int64_t(Lo->sk) * Rhat[0] * 4);
   Lo->K = take(kmax * 4);
   int64_t wmax = 0;

@@ -135,30 +135,6 @@ __device__ __forceinline__ void mode_product_fiber(const TX* __restrict__ X, int
   __syncthreads();
 }
 
-template <typename TX, typename TA, typename TY, typename Acc>
-__device__ __forceinline__ void mode_product_t(const TX* __restrict__ X, int64_t a, int r, int64_t b,
-                               const TA* __restrict__ A, int64_t as, int64_t bs, int m,
-                               TY* __restrict__ Y, bool acc) {
-  // fibers live in registers: up to 32 FP32 or 16 FP64 values
-  constexpr int kMax = sizeof(Acc) == 4 ? 32 : 16;
-  if (r <= 8) return mode_product_fiber<TX, TA, TY, Acc, 8>(X, a, r, b, A, as, bs, m, Y, acc);
-  if (r <= 16) return mode_product_fiber<TX, TA, TY, Acc, 16>(X, a, r, b, A, as, bs, m, Y, acc);
-  if (kMax >= 32 && r <= 32) return mode_product_fiber<TX, TA, TY, Acc, kMax>(X, a, r, b, A, as, bs, m, Y, acc);
-  const int64_t total = a * int64_t(m) * b;
-  for (int64_t o = threadIdx.x; o < total; o += blockDim.x) {
-    const int64_t y = o % b;
-    const int64_t t = o / b;
-    const int i = int(t % m);
-    const int64_t x = t / m;
-    const TX* xp = X + x * r * b + y;
-    const TA* ap = A + i * as;
-    Acc s = 0;
-    for (int j = 0; j < r; ++j) s += Acc(ap[j * bs]) * Acc(xp[j * b]);
-    Y[o] = acc ? TY(Acc(Y[o]) + s) : TY(s);
-  }
-  __syncthreads();
-}
-
 typedef float tk_f4 __attribute__((ext_vector_type(4)));
 
 // The same product on the matrix cores, FP32 operands and accumulation: a
@@ -272,57 +248,6 @@ __device__ __forceinline__ void mode_product(const float* __restrict__ X, int64_
                                     const float* __restrict__ A, int64_t as, int64_t bs, int m,
                                     float* __restrict__ Y, bool acc) {
   mode_product_mfma(X, a, r, b, A, as, bs, m, Y, acc);
-}
-
-// Mode Gram G = mat_n(X) mat_n(X)^T (q x q, written as FP64 with leading
-// dimension ld; symmetric) for X viewed as (a, q, b).  Acc is the
-// accumulation type.  Each thread owns a 4 x 4 tile of the upper triangle
-// and streams the fibers through registers.
-template <typename Acc>
-__device__ __forceinline__ void gram_mode(const float* __restrict__ X, int64_t a, int q, int64_t b,
-                          double* __restrict__ G, int ld) {
-  const int nb = (q + 3) / 4;
-  const int ntiles = nb * (nb + 1) / 2;
-  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
-    int bi = 0, rem = t;
-    while (rem >= nb - bi) {
-      rem -= nb - bi;
-      ++bi;
-    }
-    const int bj = bi + rem;
-    Acc s[4][4];
-#pragma unroll
-    for (int ii = 0; ii < 4; ++ii)
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) s[ii][jj] = 0;
-    for (int64_t x = 0; x < a; ++x) {
-      const float* base = X + x * q * b;
-      for (int64_t y = 0; y < b; ++y) {
-        Acc u[4], w[4];
-#pragma unroll
-        for (int ii = 0; ii < 4; ++ii) {
-          const int i = bi * 4 + ii, j = bj * 4 + ii;
-          u[ii] = i < q ? Acc(base[i * b + y]) : Acc(0);
-          w[ii] = j < q ? Acc(base[j * b + y]) : Acc(0);
-        }
-#pragma unroll
-        for (int ii = 0; ii < 4; ++ii)
-#pragma unroll
-          for (int jj = 0; jj < 4; ++jj) s[ii][jj] += u[ii] * w[jj];
-      }
-    }
-#pragma unroll
-    for (int ii = 0; ii < 4; ++ii)
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int i = bi * 4 + ii, j = bj * 4 + jj;
-        if (i < q && j < q) {
-          G[i * ld + j] = double(s[ii][jj]);
-          G[j * ld + i] = double(s[ii][jj]);
-        }
-      }
-  }
-  __syncthreads();
 }
 
 typedef double tk_d4 __attribute__((ext_vector_type(4)));
@@ -780,219 +705,9 @@ __device__ __forceinline__ void pchol_basis(const double* L, const int* piv, int
 // ---------------------------------------------------------------------------
 
 struct EigCounters {  // zeroed by the owner (it may live in LDS)
-  uint64_t calls, sweeps, jacobi_ticks, tail_ticks, fallbacks;
+  uint64_t calls, sweeps, values_ticks, tail_ticks, fallbacks;
   uint64_t tri_ticks, invit_ticks;  // parts of the two above: tridiagonalisation, inverse iteration
 };
-
-// Leading eigenpairs of a symmetric positive semi-definite n x n matrix S by
-// one-sided Jacobi (Hestenes 1958): W (holding S, column c at W + c n) is
-// rotated by plane rotations until its columns are mutually orthogonal,
-// W = S V; then V holds eigenvectors of S and column c of W equals
-// lambda_c v_c.  Pairs are visited in the round-robin order, n/2 disjoint
-// pairs per step, each pair by a group of g <= 16 adjacent lanes that add
-// their partial dot products through DPP quad exchanges (and shuffles beyond
-// four lanes); column norms are carried from rotation to rotation, so a step
-// computes one dot product per pair.
-//
-// Warm start: when warm is set, Ef (n x n, column c at Ef + c n) holds an
-// orthogonal matrix from a previous, nearby problem and the rotations start
-// from W = S Ef, which converges in a few sweeps when Ef is close to an
-// eigenbasis.  When Ef is given it receives all n unit eigenvectors in
-// descending eigenvalue order (orthonormalised, dependent ones completed)
-// for the next warm start.
-//
-// Writes the k leading unit eigenvectors into E (n x k, row-major, lde) in
-// descending eigenvalue order and returns a pointer to the k eigenvalues.
-// W must hold eig_doubles(n) doubles (the scratch follows the matrix; the
-// eigenvalues stay valid until W is reused); tmp: n x n doubles.  When k > n
-// only n eigenpairs exist and the extra columns of E are zero.
-__device__ __forceinline__ const double* eig_top_jacobi(double* W, int n, int k, double* E, int lde, double* red,
-                                                        double* Ef, double* tmp, bool warm, EigCounters* cnt) {
-  __shared__ int s_flag;
-  const uint64_t t_start = wall_clock64();
-  const int tid = threadIdx.x, nt = blockDim.x;
-  double* nrm = W + int64_t(n) * n;
-  double* coef = nrm + n;
-  double* lam = coef + n;
-  int* order = reinterpret_cast<int*>(coef);  // coef is free until the final orthonormalisation
-  if (n <= 0) return lam;
-  double tr = 0.0;
-  for (int i = tid; i < n; i += nt) tr += fabs(W[int64_t(i) * n + i]);
-  tr = block_sum(tr, red);
-  if (warm && Ef) {
-    for (int64_t e = tid; e < int64_t(n) * n; e += nt) tmp[e] = W[e];
-    __syncthreads();
-    for (int64_t e = tid; e < int64_t(n) * n; e += nt) {
-      const int c = int(e / n), r = int(e % n);
-      const double* ec = Ef + int64_t(c) * n;
-      double s = 0.0;
-      for (int j = 0; j < n; ++j) s += tmp[int64_t(j) * n + r] * ec[j];
-      W[e] = s;
-    }
-    __syncthreads();
-  }
-  const int N = n + (n & 1);
-  const int npairs = N / 2;
-  int g = 16;
-  while (g > 1 && npairs * g > nt) g >>= 1;
-  const int groups = nt / g;
-  const double tiny = (1e-17 * tr) * (1e-17 * tr);
-  const double eps = 4e-16 * double(n > 8 ? n : 8);
-  const double eps2 = eps * eps;
-  // squared column norms, refreshed every sweep and updated by each rotation
-  // (a rotation that zeroes w_p . w_q maps |w_p|^2 -> |w_p|^2 - t g and
-  // |w_q|^2 -> |w_q|^2 + t g), so a step needs only the one dot product
-  double* cn = nrm;
-  int sweeps_run = 0;
-  for (int sweep = 0; sweep < 40 && N > 1; ++sweep) {
-    ++sweeps_run;
-    double maxc2 = 0.0;  // largest squared cosine rotated away in this sweep
-    for (int c = tid; c < n; c += nt) {
-      const double* w = W + int64_t(c) * n;
-      double s2 = 0.0;
-      for (int r = 0; r < n; ++r) s2 += w[r] * w[r];
-      cn[c] = s2;
-    }
-    __syncthreads();
-    int rotated = 0;
-    for (int step = 0; step < N - 1; ++step) {
-      for (int base = 0; base < npairs; base += groups) {
-        const int pi = base + tid / g;
-        const int lane = tid % g;
-        int pp = n, qq = n;
-        if (pi < npairs) {
-          if (pi == 0) {
-            pp = N - 1;
-            qq = step;
-          } else {
-            pp = step + pi;
-            if (pp >= N - 1) pp -= N - 1;
-            qq = step - pi;
-            if (qq < 0) qq += N - 1;
-          }
-        }
-        const bool act = pp < n && qq < n;
-        constexpr int RPL = 8;  // rows per lane kept in registers
-        double xr[RPL], yr[RPL];
-        double ga = 0.0, ga2 = 0.0, al = 0.0, be = 0.0;
-        double* wp = W + int64_t(act ? pp : 0) * n;
-        double* wq = W + int64_t(act ? qq : 0) * n;
-        const bool inreg = (n + g - 1) / g <= RPL;
-        if (act) {
-          al = cn[pp];
-          be = cn[qq];
-          if (inreg) {
-#pragma unroll
-            for (int t = 0; t < RPL; ++t) {
-              const int r = lane + t * g;
-              xr[t] = r < n ? wp[r] : 0.0;
-              yr[t] = r < n ? wq[r] : 0.0;
-            }
-#pragma unroll
-            for (int t = 0; t < RPL; t += 2) {
-              ga += xr[t] * yr[t];
-              ga2 += xr[t + 1] * yr[t + 1];
-            }
-            ga += ga2;
-          } else {
-            for (int r = lane; r < n; r += g) ga += wp[r] * wq[r];
-          }
-        }
-        if (g >= 2) ga += quad_swap<0xB1>(ga);
-        if (g >= 4) ga += quad_swap<0x4E>(ga);
-        if (g >= 8) ga += __shfl_xor(ga, 4, 64);
-        if (g >= 16) ga += __shfl_xor(ga, 8, 64);
-        if (act && ga * ga > eps2 * al * be && al * be > tiny * tiny) {
-          maxc2 = fmax(maxc2, ga * ga / (al * be));
-          // t = tan of the rotation angle, the root of t^2 + 2 zeta t - 1 = 0
-          // of smaller magnitude, zeta = (be - al) / (2 ga)
-          const double tau = be - al, rho = 2.0 * ga;
-          const double h2 = tau * tau + rho * rho;
-          const double h = h2 * fast_rsqrt(h2);
-          const double t = (tau >= 0.0 ? rho : -rho) * fast_rcp(fabs(tau) + h);
-          const double c = fast_rsqrt(fma(t, t, 1.0));
-          const double sn = c * t;
-          if (inreg) {
-#pragma unroll
-            for (int tt = 0; tt < RPL; ++tt) {
-              const int r = lane + tt * g;
-              if (r < n) {
-                wp[r] = c * xr[tt] - sn * yr[tt];
-                wq[r] = sn * xr[tt] + c * yr[tt];
-              }
-            }
-          } else {
-            for (int r = lane; r < n; r += g) {
-              const double x = wp[r], y = wq[r];
-              wp[r] = c * x - sn * y;
-              wq[r] = sn * x + c * y;
-            }
-          }
-          if (lane == 0) {
-            cn[pp] = al - t * ga;
-            cn[qq] = be + t * ga;
-          }
-          rotated = 1;
-        }
-      }
-      __syncthreads();
-    }
-    if (!__syncthreads_or(rotated)) break;
-    // quadratic convergence: once every rotated cosine is below sqrt(eps)
-    // the next sweep would leave them below eps, so stop without it
-    double mx = maxc2;
-    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-    if (nt > 64) {
-      if ((tid & 63) == 0) red[tid >> 6] = mx;
-      __syncthreads();
-      for (int w = 0; w < nt / 64; ++w) mx = fmax(mx, red[w]);
-      __syncthreads();
-    }
-    if (mx < eps) break;
-  }
-  const uint64_t t_jac = wall_clock64();
-  // column norms = |lambda|; rank the columns (ties by index)
-  for (int c = tid; c < n; c += nt) {
-    double s = 0.0;
-    const double* w = W + int64_t(c) * n;
-    for (int r = 0; r < n; ++r) s += w[r] * w[r];
-    nrm[c] = sqrt(s);
-  }
-  __syncthreads();
-  for (int c = tid; c < n; c += nt) {
-    int rank = 0;
-    for (int c2 = 0; c2 < n; ++c2)
-      if (nrm[c2] > nrm[c] || (nrm[c2] == nrm[c] && c2 < c)) ++rank;
-    order[rank] = c;
-  }
-  __syncthreads();
-  const int kk = k < n ? k : n;
-  const int nkeep = Ef ? n : kk;
-  double* dst = Ef ? Ef : tmp;
-  for (int64_t e = tid; e < int64_t(n) * nkeep; e += nt) {
-    const int j = int(e / n), r = int(e % n);
-    const int c = order[j];
-    const double s = nrm[c];
-    dst[e] = s > 0.0 ? W[int64_t(c) * n + r] / s : 0.0;
-  }
-  __syncthreads();
-  for (int j = tid; j < kk; j += nt) lam[j] = nrm[order[j]];
-  __syncthreads();
-  orthonormalize(dst, n, nkeep, 1, n, coef, red, &s_flag);
-  for (int64_t e = tid; e < int64_t(n) * k; e += nt) {
-    const int r = int(e / k), j = int(e % k);
-    E[int64_t(r) * lde + j] = j < kk ? dst[int64_t(j) * n + r] : 0.0;
-  }
-  __syncthreads();
-  if (cnt && tid == 0) {
-    cnt->calls += 1;
-    cnt->sweeps += uint64_t(sweeps_run);
-    cnt->jacobi_ticks += t_jac - t_start;
-    cnt->tail_ticks += wall_clock64() - t_jac;
-  }
-  return lam;
-}
-
 
 // Leading eigenpairs of a symmetric n x n matrix S through the tridiagonal
 // route (Golub & Van Loan, Secs. 8.3-8.4; the scheme of LAPACK's
@@ -1008,9 +723,10 @@ __device__ __forceinline__ const double* eig_top_jacobi(double* W, int n, int k,
 //   4. back-transformation by the reflectors, Rayleigh quotients for the
 //      eigenvalues, and a final orthonormality check (CGS2 if needed).
 // The eigenvectors live in W's free upper triangle while k < n / 2 (vector
-// j in rows j and n-2-j), else in tmp.  Same contract as eig_top_jacobi (E:
-// n x k, row stride lde, descending eigenvalues; returns the k
-// eigenvalues), without warm starts.  W holds the n x n matrix, vec the
+// j in rows j and n-2-j), else in tmp.  Writes the k leading unit
+// eigenvectors into E (n x k, row stride lde) in descending eigenvalue order
+// (when k > n the extra columns are zero) and returns the k eigenvalues.
+// W holds the n x n matrix, vec the
 // eig_vec_doubles(n) doubles of vectors and workgroup partials (W + n n when
 // both share one buffer); tmp: 4 n k doubles.  The returned eigenvalues
 // live in vec.
@@ -1494,7 +1210,7 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
   if (cnt && tid == 0) {
     cnt->calls += 1;
     cnt->sweeps += uint64_t(iters + 1);
-    cnt->jacobi_ticks += t_bis - t_start;
+    cnt->values_ticks += t_bis - t_start;
     cnt->tail_ticks += wall_clock64() - t_bis;
     cnt->tri_ticks += t_tri - t_start;
     cnt->invit_ticks += t_inv - t_bis;
@@ -1503,10 +1219,8 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
 }
 
 // The eigensolver the kernels use.
-__device__ __forceinline__ const double* eig_top(double* W, int n, int k, double* E, int lde, double* red, double* Ef,
-                                                 double* tmp, bool warm, EigCounters* cnt, double* vec) {
-  (void)Ef;
-  (void)warm;
+__device__ __forceinline__ const double* eig_top(double* W, int n, int k, double* E, int lde, double* red,
+                                                 double* tmp, EigCounters* cnt, double* vec) {
   return eig_top_tri(W, n, k, E, lde, red, tmp, cnt, vec);
 }
 

@@ -3,6 +3,8 @@
 // serving engine (tk_serve.hip).
 #pragma once
 
+#include <atomic>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -111,8 +113,11 @@ struct tk_tree {
   tk::DevBuf prov_out;                 // its compact decomposition
   int64_t lds_limit = 65536;  // dynamic + static LDS a workgroup may use
   tk::Tuning tuning;
-  bool poisoned = false;
+  std::atomic<bool> poisoned{false};
+  // last error text; written by the caller's threads and the serving
+  // engine's thread, so always under err_mu (set_error / tk_last_error)
   std::string err;
+  mutable std::mutex err_mu;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the last query launches
   std::vector<double> last_stats;           // per-job stats of the last query batch
   bool ev_valid = false;
@@ -122,6 +127,8 @@ struct tk_tree {
 namespace tk {
 
 tk_status fail(tk_tree* t, tk_status st, const std::string& msg);
+// Record msg as the tree's last error (thread-safe).
+void set_error(tk_tree* t, const std::string& msg);
 // Error text for a stitch job's nonzero STAT_STATUS: 1 the kernel's Recall
 // did not reproduce the planned hit set, 2 the workspace plan was too small,
 // 3 the launch's LDS could not hold the job's eigen vectors or its kernel

@@ -37,13 +37,13 @@ __device__ __forceinline__ void leading_left(const float* Y, const int32_t* dims
   if (D <= N) {
     double* Wm = D <= n_lds ? lds : reinterpret_cast<double*>(ws + lo.EIG);
     gram_mode_mfma(Y, a, D, b, Wm, D);
-    eig_top(Wm, D, r, U, r, sh.red, nullptr, TMP, false, nullptr, Wm + int64_t(D) * D);
+    eig_top(Wm, D, r, U, r, sh.red, TMP, nullptr, Wm + int64_t(D) * D);
     return;
   }
   const int Ni = int(N);
   double* Wm = Ni <= n_lds ? lds : reinterpret_cast<double*>(ws + lo.EIG);
   gram_other(Y, a, D, b, Wm, Ni);
-  const double* lam = eig_top(Wm, Ni, r, Vbuf, r, sh.red, nullptr, TMP, false, nullptr, Wm + int64_t(Ni) * Ni);
+  const double* lam = eig_top(Wm, Ni, r, Vbuf, r, sh.red, TMP, nullptr, Wm + int64_t(Ni) * Ni);
   for (int64_t e = tid; e < int64_t(D) * r; e += nt) {
     const int d = int(e / r), j = int(e % r);
     double acc = 0.0;

@@ -259,7 +259,7 @@ tk_status poll_completions(Server* s, bool* progress) {
       const double* st = c.hstats + STAT_COUNT * i;
       int state = REQ_DONE;
       if (st[STAT_STATUS] != 0.0) {
-        t->err = job_status_msg(st[STAT_STATUS]);
+        set_error(t, job_status_msg(st[STAT_STATUS]));
         state = REQ_FAILED;
       }
       tk_result& o = *r->res;

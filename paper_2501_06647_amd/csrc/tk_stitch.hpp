@@ -125,7 +125,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
 
   PhaseClock& clk = sh.clk;
   EigCounters& ec = sh.ec;
-  if (tid == 0) ec.calls = ec.sweeps = ec.jacobi_ticks = ec.tail_ticks = ec.fallbacks = ec.tri_ticks = ec.invit_ticks = 0;
+  if (tid == 0) ec.calls = ec.sweeps = ec.values_ticks = ec.tail_ticks = ec.fallbacks = ec.tri_ticks = ec.invit_ticks = 0;
   clk.start();
   // the layout record lives at the head of the workspace
   StitchLayout* lop = reinterpret_cast<StitchLayout*>(ws);
@@ -200,7 +200,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
       double* d = Gm + k * k;
       int* piv = reinterpret_cast<int*>(Gm + k * k + k);
       kp = pchol(Gm, k, 1e-12, TMP, piv, d, red, sh.redi);
-      pchol_basis<float>(TMP, piv, k, kp, Rt, k, Dp(lo.F[i]), k, Dp(lo.EF[0]));
+      pchol_basis<float>(TMP, piv, k, kp, Rt, k, Dp(lo.F[i]), k, Dp(lo.Tinv[0]));
     });
     float* Ht = Fp(lo.Ht[i]);
     mode_product(H, 1, k, R, Rt, k, 1, kp, Ht, false);
@@ -266,7 +266,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
         const int q = pchol(Gm, sr, 1e-11, TMP, piv, d, red, sh.redi);
         if (q >= rq[n]) {
           use_basis = 1;
-          pchol_basis<double>(TMP, piv, sr, q, C64, sr, Dp(lo.Fn[n]), sr, Dp(lo.EF[n]));
+          pchol_basis<double>(TMP, piv, sr, q, C64, sr, Dp(lo.Fn[n]), sr, Dp(lo.Tinv[n]));
           for (int e = tid; e < q * sr; e += nt) C[e] = float(C64[e]);
           if (tid == 0) sh.q[n] = q;
         }
@@ -331,7 +331,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
                [&](int j, int d2) { return C64[int64_t(d2) * sr + c0 + j]; },
                [&](int dd, int d2, double v) { Wm[dd * q + d2] += v; });
     }
-    eig_top(Wm, q, rq[n], Dp(lo.Pd[n]), rq[n], red, Dp(lo.EF[n]), TMP, false, &ec, Wv);
+    eig_top(Wm, q, rq[n], Dp(lo.Pd[n]), rq[n], red, TMP, &ec, Wv);
     });
     update_A(n);
   }
@@ -371,7 +371,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     with_buf(sk, [&](double* Wm, double* Wv) {
       gram(M, 1, sk, Rhat[0], Wm, sk);
       clk.mark(3);
-      eig_top(Wm, sk, rq[0], Dp(lo.Pd[0]), rq[0], red, Dp(lo.EF[0]), TMP, it > 1, &ec, Wv);
+      eig_top(Wm, sk, rq[0], Dp(lo.Pd[0]), rq[0], red, TMP, &ec, Wv);
     });
     float* P0f = Fp(lo.Pf[0]);
     {
@@ -426,7 +426,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
       with_eig_buf(q, [&](double* Wn, double* Wv) {
         gram(K, ka, q, kb, Wn, q);
         clk.mark(5);
-        eig_top(Wn, q, rq[n], Dp(lo.Pd[n]), rq[n], red, Dp(lo.EF[n]), TMP, true, &ec, Wv);
+        eig_top(Wn, q, rq[n], Dp(lo.Pd[n]), rq[n], red, TMP, &ec, Wv);
       });
       update_A(n);
       clk.mark(6);
@@ -561,7 +561,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
   if (tid == 0 && job.stats) {
     job.stats[STAT_EIG + 0] = double(ec.calls);
     job.stats[STAT_EIG + 1] = double(ec.sweeps);
-    job.stats[STAT_EIG + 2] = double(ec.jacobi_ticks) * 0.01;
+    job.stats[STAT_EIG + 2] = double(ec.values_ticks) * 0.01;
     job.stats[STAT_EIG + 3] = double(ec.tail_ticks) * 0.01;
     job.stats[STAT_EIG_FALLBACK] = double(ec.fallbacks);
     job.stats[STAT_EIG_TRI] = double(ec.tri_ticks) * 0.01;

@@ -122,10 +122,7 @@ class StreamSegmentTree:
         assert leaf.lo == T, "the walk must end at the new block's slot"
         leaf.kind = "L"
         if block is not None:
-            r = effective_ranks(self.leaf_len, self.dims, self.ranks)
-            G, U, info = hooi(np.asarray(block, dtype=np.float64), r, self.max_iter, self.tol)
-            leaf.H, leaf.V = canonical_signs(G, U)
-            leaf.info = info
+            self._decompose_leaf(leaf, block)
         self.merges_last = 0
         for v in reversed(path[:-1]):
             if v.hi != T + 1:
@@ -140,9 +137,20 @@ class StreamSegmentTree:
         v.kind = "M"
         self.merges_last += 1
         if decompose:
-            r = effective_ranks((v.hi - v.lo) * self.leaf_len, self.dims, self.ranks)
-            pieces = [stitch_mod.Piece(v.left.H, v.left.V), stitch_mod.Piece(v.right.H, v.right.V)]
-            v.H, v.V, v.info = stitch_mod.stitch(pieces, r, self.max_iter, self.tol)
+            self._decompose_merge(v)
+
+    def _decompose_leaf(self, leaf: Node, block: np.ndarray) -> None:
+        """A leaf holds the Tucker-ALS decomposition of its raw block."""
+        r = effective_ranks(self.leaf_len, self.dims, self.ranks)
+        G, U, info = hooi(np.asarray(block, dtype=np.float64), r, self.max_iter, self.tol)
+        leaf.H, leaf.V = canonical_signs(G, U)
+        leaf.info = info
+
+    def _decompose_merge(self, v: Node) -> None:
+        """A completed intermediate node holds the Stitch of its two children."""
+        r = effective_ranks((v.hi - v.lo) * self.leaf_len, self.dims, self.ranks)
+        pieces = [stitch_mod.Piece(v.left.H, v.left.V), stitch_mod.Piece(v.right.H, v.right.V)]
+        v.H, v.V, v.info = stitch_mod.stitch(pieces, r, self.max_iter, self.tol)
 
     # -- Alg. "recall" (Sec. 5.1) ---------------------------------------------
     def _accept(self, v: Node, ts: int, te: int) -> bool:
@@ -275,3 +283,69 @@ class StreamSegmentTree:
 
     def complete_nodes(self) -> List[Node]:
         return [v for v in self.nodes if v.kind in ("L", "M")]
+
+
+def node_key(v: Node) -> Tuple[int, int]:
+    """(level, index) of a complete node: level k holds nodes of 2^k blocks,
+    index j covers blocks [j 2^k, (j+1) 2^k)."""
+    k = (v.hi - v.lo).bit_length() - 1
+    return k, v.lo >> k
+
+
+class LazyStreamSegmentTree(StreamSegmentTree):
+    """The same tree with every decomposition made on first use.
+
+    ``append_blocks(n)`` grows the structure only; ``source(t0, t1)`` returns
+    the raw slices [t0, t1).  A node's decomposition depends on nothing but
+    the slices under it (a leaf is Tucker-ALS of its block, an intermediate
+    node the Stitch of its children), so computing it when a query first
+    needs it, from the bottom of its subtree up, gives exactly what the eager
+    tree holds.  ``put(level, index, H, V)`` stores a decomposition computed
+    elsewhere by this package (for example by an eager tree over the same
+    slices); ``ensure`` makes one on demand.
+    """
+
+    def __init__(self, dims, ranks, leaf_len=1, theta=(7, 10), max_iter=20, tol=0.01, source=None):
+        super().__init__(dims, ranks, leaf_len, theta, max_iter, tol)
+        self.source = source
+        self._by_key = {}
+
+    def append_blocks(self, n: int) -> None:
+        for _ in range(int(n)):
+            self.append(None)
+
+    def _index(self):
+        if len(self._by_key) != len(self.nodes):
+            self._by_key = {node_key(v): v for v in self.complete_nodes()}
+        return self._by_key
+
+    def node(self, level: int, index: int) -> Node:
+        return self._index()[(int(level), int(index))]
+
+    def put(self, level: int, index: int, H, V) -> None:
+        v = self.node(level, index)
+        v.H, v.V = H, list(V)
+
+    def ensure(self, v: Node) -> None:
+        if v.H is not None:
+            return
+        if v.kind == "L":
+            ell = self.leaf_len
+            self._decompose_leaf(v, self.source(v.lo * ell, v.hi * ell))
+            return
+        assert v.kind == "M", "only complete nodes hold decompositions"
+        self.ensure(v.left)
+        self.ensure(v.right)
+        self._decompose_merge(v)
+
+    def recall(self, ts, te, _visited=None):
+        hits = super().recall(ts, te, _visited)
+        for v, _, _ in hits:
+            self.ensure(v)
+        return hits
+
+    def fixed_block_hits(self, ts, te, level):
+        hits = super().fixed_block_hits(ts, te, level)
+        for v, _, _ in hits:
+            self.ensure(v)
+        return hits

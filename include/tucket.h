@@ -308,6 +308,15 @@ tk_status tk_batch_profile(const tk_batch* b, int32_t i, double* phase_us);
 tk_status tk_batch_hits(const tk_batch* b, int32_t i, tk_hit* out, int32_t cap, int32_t* n);
 void tk_batch_destroy(tk_batch* b);
 
+/* Limits of tk_autotune's search (defaults: 60 s, cap 3, no progress).
+ * budget_s: no new candidate starts once this many seconds have passed
+ * since the search began (0: no limit); the best so far is kept and the
+ * re-timing stage is skipped.  cap: a candidate whose warm-up execution
+ * already takes more than cap times the best mean so far is not timed
+ * further (0 or 1: never abandon).  progress: one line per candidate on
+ * stderr.  TK_EINVAL for negative or NaN limits. */
+tk_status tk_set_autotune_limits(tk_tree* t, double budget_s, double cap, int32_t progress);
+
 /* Time every candidate tuning (wide_threshold in {32, 48, 64, 96} x
  * wide_threads in {128, 256} x lds_n in {32, 48, 64, 96, 0} (>= the threshold) x
  * persistent in {0, 1} x coarse in {0, 1} at basis_pct 75, rest_threads 0
@@ -316,7 +325,9 @@ void tk_batch_destroy(tk_batch* b);
  * point) on a prepared batch of
  * the given queries (reps timed executions after one warm-up, results into
  * scratch buffers); the eight fastest are timed again with 3 reps
- * executions, and the fastest of those is kept on the tree and reported. */
+ * executions, and the fastest of those is kept on the tree and reported.
+ * The search obeys tk_set_autotune_limits: candidates abandoned after their
+ * warm-up never win, and a spent time budget ends it early. */
 tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* te, int32_t reps,
                       tk_tuning* best, double* best_ms);
 

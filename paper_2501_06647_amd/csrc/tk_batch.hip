@@ -7,10 +7,13 @@
 // Stitch of its queries, the bins forked onto their own streams and joined.
 // tk_batch_run replays the graph on the tree's stream.
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
 #include "tk_host.hpp"
+#include "tk_tune_search.hpp"
 
 using namespace tk;
 
@@ -265,6 +268,14 @@ tk_status tk_batch_hits(const tk_batch* b, int32_t i, tk_hit* out, int32_t cap, 
 
 void tk_batch_destroy(tk_batch* b) { batch_free(b); }
 
+tk_status tk_set_autotune_limits(tk_tree* t, double budget_s, double cap, int32_t progress) {
+  if (!t || !(budget_s >= 0.0) || !(cap >= 0.0)) return fail(t, TK_EINVAL, "bad autotune limits");
+  t->tune_limits.budget_s = budget_s;
+  t->tune_limits.cap = cap;
+  t->tune_limits.progress = progress ? 1 : 0;
+  return TK_OK;
+}
+
 tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* te, int32_t reps, tk_tuning* best,
                       double* best_ms) {
   if (!t || n < 1 || !ts || !te || reps < 1) return fail(t, TK_EINVAL, "bad argument");
@@ -301,26 +312,62 @@ tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* t
   const Tuning saved = t->tuning;
   Tuning bestt = saved;
   double bms = 1e300;
-  // time the tree's current tuning on the sample; false on an error (st set)
+  const auto clock0 = std::chrono::steady_clock::now();
+  auto now_s = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - clock0).count(); };
+  TuneSearch search(t->tune_limits, 0.0);
+  bool abandoned = false;
+  // time the tree's current tuning on the sample: one warm-up execution,
+  // then nrep timed ones unless the warm-up alone rules the candidate out;
+  // false on an error (st set)
   std::vector<std::pair<double, Tuning>> timed;
   auto time_it = [&](int nrep, double* out_ms) {
     tk_batch* b = nullptr;
     st = tk_batch_create(t, n, ts, te, res.data(), &b);
     double sum = 0.0;
+    int done = 0;
+    abandoned = false;
     for (int r = 0; r <= nrep && st == TK_OK; ++r) {
       st = tk_batch_run(b);
       if (st == TK_OK) st = tk_batch_wait(b);
       double ms = 0.0;
       if (st == TK_OK) st = tk_batch_kernel_ms(b, &ms);
-      if (r > 0) sum += ms;  // the first run warms up
+      if (st != TK_OK) break;
+      if (r == 0 && !search.worth_timing(ms)) {
+        abandoned = true;
+        sum = ms;
+        done = 1;
+        break;
+      }
+      if (r > 0) {  // the first run warms up
+        sum += ms;
+        ++done;
+      }
     }
     tk_batch_destroy(b);
-    *out_ms = sum / nrep;
+    *out_ms = done ? sum / done : 0.0;
     return st == TK_OK;
   };
+  auto describe = [&](char* buf, size_t len) {
+    const Tuning& u = t->tuning;
+    std::snprintf(buf, len,
+                  "wide_threshold %d wide_threads %d persistent %d coarse %d lds_n %d basis_pct %d rest_threads %d "
+                  "wide_core %d",
+                  u.wide_threshold, u.wide_threads, u.persistent, u.coarse, u.lds_n, u.basis_pct, u.rest_threads,
+                  u.wide_core);
+  };
+  // false on an error or once the time budget is spent (ok then stays true)
+  bool budget_left = true;
   auto trial = [&]() {
+    if (!search.open(now_s())) {
+      budget_left = false;
+      return false;
+    }
     double ms = 0.0;
     if (!time_it(reps, &ms)) return false;
+    char what[192];
+    describe(what, sizeof(what));
+    search.record(ms, abandoned, what, now_s());
+    if (abandoned) return true;
     timed.push_back({ms, t->tuning});
     if (ms < bms) {
       bms = ms;
@@ -335,7 +382,7 @@ tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* t
   for (int th : thr)
     for (int wt : wth)
       for (int ln : ldsn)
-        for (int pc = 0; pc < 4 && ok; ++pc) {
+        for (int pc = 0; pc < 4 && ok && budget_left; ++pc) {
           if (ln != 0 && ln < th) continue;
           t->tuning = saved;
           t->tuning.wide_threshold = th;
@@ -346,50 +393,68 @@ tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* t
           t->tuning.basis_pct = 75;
           t->tuning.rest_threads = 0;
           t->tuning.wide_core = 0;
-          ok = trial();
+          ok = trial() || (st == TK_OK && !budget_left);
         }
   const int bpct[] = {60, 90, 100};
   Tuning from = bestt;
   for (int bp : bpct) {
-    if (!ok) break;
+    if (!ok || !budget_left) break;
     t->tuning = from;
     t->tuning.basis_pct = bp;
-    ok = trial();
+    ok = trial() || (st == TK_OK && !budget_left);
   }
   const int rth[] = {128, 256};
   from = bestt;
   for (int rt : rth) {
-    if (!ok || rt == from.wide_threads) continue;
+    if (!ok || !budget_left || rt == from.wide_threads) continue;
     t->tuning = from;
     t->tuning.rest_threads = rt;
-    ok = trial();
+    ok = trial() || (st == TK_OK && !budget_left);
   }
   const int wcs[] = {2048, 8192};
   from = bestt;
   for (int wc : wcs) {
-    if (!ok) break;
+    if (!ok || !budget_left) break;
     t->tuning = from;
     t->tuning.wide_core = wc;
-    ok = trial();
+    ok = trial() || (st == TK_OK && !budget_left);
   }
   // single timings pick the luckiest point: the eight fastest are timed
   // again, three times as long, and the best mean wins
-  if (ok && timed.size() > 1) {
+  // (skipped once the budget is spent)
+  if (ok && budget_left && timed.size() > 1) {
     std::stable_sort(timed.begin(), timed.end(),
                      [](const std::pair<double, Tuning>& x, const std::pair<double, Tuning>& y) {
                        return x.first < y.first;
                      });
-    bms = 1e300;
+    const double single_best = bms;
+    double rbest = 1e300;
+    Tuning rt = bestt;
+    bool complete = true;
     for (size_t c = 0; c < timed.size() && c < 8 && ok; ++c) {
+      if (!search.open(now_s())) {
+        complete = false;
+        break;
+      }
       t->tuning = timed[c].second;
       double ms = 0.0;
       ok = time_it(3 * reps, &ms);
-      if (ok && ms < bms) {
-        bms = ms;
-        bestt = timed[c].second;
+      if (ok && !abandoned && ms < rbest) {
+        rbest = ms;
+        rt = timed[c].second;
       }
     }
+    // keep the re-timed winner only when every re-timing ran
+    if (ok && complete && rbest < 1e300) {
+      bms = rbest;
+      bestt = rt;
+    } else {
+      bms = single_best;
+    }
   }
+  if (t->tune_limits.progress)
+    std::fprintf(stderr, "[tk_autotune] %d candidates (%d abandoned after warm-up) in %.1f s%s; best %.3f ms\n",
+                 search.count(), search.abandoned(), now_s(), budget_left ? "" : " (time budget spent)", bms);
   if (!ok) {
     t->tuning = saved;
     release(&outbuf);

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "tk_internal.hpp"
+#include "tk_tune_search.hpp"
 #include "tucket.h"
 
 namespace tk {
@@ -113,6 +114,7 @@ struct tk_tree {
   tk::DevBuf prov_out;                 // its compact decomposition
   int64_t lds_limit = 65536;  // dynamic + static LDS a workgroup may use
   tk::Tuning tuning;
+  tk::TuneLimits tune_limits;  // time budget, abandonment cap and progress output of tk_autotune
   std::atomic<bool> poisoned{false};
   // last error text; written by the caller's threads and the serving
   // engine's thread, so always under err_mu (set_error / tk_last_error)

@@ -109,6 +109,7 @@ SIGNATURES = [
     ("tk_batch_profile", c_i32, [c_vp, c_i32, ctypes.POINTER(c_dbl)]),
     ("tk_batch_hits", c_i32, [c_vp, c_i32, ctypes.POINTER(TkHit), c_i32, ctypes.POINTER(c_i32)]),
     ("tk_batch_destroy", None, [c_vp]),
+    ("tk_set_autotune_limits", c_i32, [c_vp, c_dbl, c_dbl, c_i32]),
     ("tk_autotune", c_i32, [c_vp, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64), c_i32,
                             ctypes.POINTER(TkTuning), ctypes.POINTER(c_dbl)]),
     ("tk_serve_start", c_i32, [c_vp, ctypes.POINTER(TkServeConfig)]),
@@ -542,7 +543,13 @@ class Tree:
         tu = TkTuning(**{k: int(v) for k, v in cur.items()})
         self._check(lib().tk_set_tuning(self._h, ctypes.byref(tu)), "tk_set_tuning")
 
-    def autotune(self, ts, te, reps: int = 2) -> Tuple[dict, float]:
+    def autotune(self, ts, te, reps: int = 2, budget_s: float = 60.0, cap: float = 3.0,
+                 progress: bool = False) -> Tuple[dict, float]:
+        """Search launch tunings on these queries (tk_autotune) within a
+        time budget, abandoning candidates whose warm-up exceeds cap x the
+        best so far; progress: one stderr line per candidate."""
+        self._check(lib().tk_set_autotune_limits(self._h, float(budget_s), float(cap), int(bool(progress))),
+                    "tk_set_autotune_limits")
         ts = np.asarray(ts, dtype=np.int64).reshape(-1)
         te = np.asarray(te, dtype=np.int64).reshape(-1)
         n = len(ts)

@@ -169,6 +169,20 @@ tk_status tk_query_shape(const tk_tree* t, int64_t ts, int64_t te, tk_shape* out
  * batches and served queries end there too (TK_ERANGE). */
 tk_status tk_query(tk_tree* t, int64_t ts, int64_t te, tk_result* res);
 
+/* tk_query for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same Recall, trims and Stitch kernels, with every device buffer the call
+ * needs (hit list, queue counters, statistics, job descriptor, workspace)
+ * taken from one fixed scratch array of 32 MiB per device, held by the
+ * library from its load until the process ends; nothing is allocated or
+ * freed.  The caller passes the output buffers as for tk_query.  The range
+ * must end at or before the last complete block (else TK_ERANGE); a query
+ * whose workspace exceeds the scratch returns TK_ENOMEM before any device
+ * work.  Blocks until the result is written.  Every call on one device
+ * shares that device's scratch (it keeps the last call's contents):
+ * concurrent calls on one device, from any tree or thread, race. */
+tk_status tk_query_noalloc(tk_tree* t, int64_t ts, int64_t te, tk_result* res);
+
 /* n range queries stitched in one device launch (one workgroup per query).
  * Each query's result is identical to what tk_query returns for it. */
 tk_status tk_query_batch(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* te,

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -18,6 +19,46 @@ using tk::StoreView;
 namespace {
 thread_local std::string g_create_error;
 }  // namespace
+
+namespace tk {
+
+// Device scratch of tk_query_noalloc: a file-scope array that every device
+// loading the library holds until the process ends.  Host code never uses
+// its name as an address (on the host it names a stand-in, not device
+// memory): tk_create looks up its address on the tree's device once per
+// device (hipGetSymbolAddress, with that device current), and the entry
+// point passes that address to the kernels like any other buffer.
+constexpr int64_t kNoAllocScratchBytes = int64_t(32) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// The scratch's address on device dev (the current device); nullptr with
+// *err set if it cannot be found.
+char* noalloc_scratch(int dev, hipError_t* err) {
+  *err = hipSuccess;
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace tk
 
 namespace tk {
 
@@ -50,6 +91,7 @@ tk_status fail_dev(tk_tree* t, hipError_t e, const char* what) {
 
 tk_status ensure(tk_tree* t, DevBuf* b, int64_t need, const char* what) {
   if (need <= b->cap) return TK_OK;
+  if (b->fixed) return fail(t, TK_ENOMEM, std::string(what) + ": exceeds the fixed scratch");
   if (b->p) {
     TK_HIP(t, hipDeviceSynchronize());  // the buffer may be in use on any of the tree's streams
     TK_HIP(t, hipFree(b->p));
@@ -66,6 +108,7 @@ tk_status ensure(tk_tree* t, DevBuf* b, int64_t need, const char* what) {
 }
 
 void release(DevBuf* b) {
+  if (b->fixed) return;
   if (b->p) (void)hipFree(b->p);
   b->p = nullptr;
   b->cap = 0;
@@ -606,6 +649,10 @@ tk_status tk_create(const tk_config* cfg, void* hip_stream, tk_tree** out) {
     t->lds_limit = lim;
   }
   if (e == hipSuccess) {
+    step = "hipGetSymbolAddress(no-allocation scratch)";
+    (void)tk::noalloc_scratch(dev, &e);
+  }
+  if (e == hipSuccess) {
     step = "hipStreamSynchronize(create)";
     e = hipStreamSynchronize(t->stream);
   }
@@ -781,6 +828,68 @@ tk_status tk_query_batch(tk_tree* t, int32_t n, const int64_t* ts, const int64_t
 
 tk_status tk_query(tk_tree* t, int64_t ts, int64_t te, tk_result* res) {
   return tk_query_batch(t, 1, &ts, &te, res);
+}
+
+tk_status tk_query_noalloc(tk_tree* t, int64_t ts, int64_t te, tk_result* res) {
+  using namespace tk;
+  if (!t || !res) return fail(t, TK_EINVAL, "bad argument");
+  if (t->server) return busy(t);
+  if (t->poisoned) return TK_EDEVICE;
+  if (!(ts >= 0 && ts < te && te <= t->Tb * t->ell))
+    return fail(t, TK_ERANGE, "query range outside [0, T_c) or empty (no ranges into the incomplete block here)");
+  std::vector<Job> jobs;
+  std::vector<Hit> hits;
+  tk_status st = make_query_job(t, ts, te, t->Tb, res, true, jobs, hits, false);
+  if (st) return st;
+  Plan plan;
+  st = plan_stitch(t, jobs, hits, &plan);
+  if (st) return st;
+  if (plan.groups.size() != 1 || plan.groups[0].jobs.size() != 1) return fail(t, TK_EINVAL, "one query, one job");
+  const Group& gr = plan.groups[0];
+  // scratch layout: hits | queue counters | stats | job descriptor | workspace
+  const int64_t o_hits = 0;
+  const int64_t o_queue = align256(o_hits + int64_t(plan.hits.size() * sizeof(Hit)) + 64);
+  const int64_t o_stats = align256(o_queue + kMaxGroups * 64);
+  const int64_t o_jobs = align256(o_stats + STAT_COUNT * 8);
+  const int64_t o_ws = align256(o_jobs + int64_t(sizeof(Job)));
+  const int64_t ws_cap = kNoAllocScratchBytes - o_ws;
+  if (gr.ws_total + 256 > ws_cap)
+    return fail(t, TK_ENOMEM, "the query's workspace (" + std::to_string(gr.ws_total) +
+                                  " bytes) exceeds the no-allocation scratch (" + std::to_string(ws_cap) + " bytes)");
+  hipError_t e = hipSuccess;
+  char* base = noalloc_scratch(t->device, &e);
+  if (!base) return fail_dev(t, e, "no-allocation scratch address");
+  // a lane whose buffers all lie in the scratch (fixed: never reallocated)
+  Lane lane;
+  lane.stream = t->stream;
+  auto fix = [&](DevBuf* b, int64_t off, int64_t cap) {
+    b->p = base + off;
+    b->cap = cap;
+    b->fixed = true;
+  };
+  fix(&lane.hits, o_hits, o_queue - o_hits);
+  fix(&lane.queue, o_queue, o_stats - o_queue);
+  fix(&lane.stats, o_stats, o_jobs - o_stats);
+  for (int g = 0; g < kMaxGroups; ++g) {
+    fix(&lane.jobs[g], o_jobs, o_ws - o_jobs);
+    fix(&lane.ws[g], o_ws, ws_cap);
+  }
+  double* dstats = reinterpret_cast<double*>(lane.stats.p);
+  plan.groups[0].jobs[0].stats = dstats;
+  st = run_plan(t, &lane, plan, t->q_max_iter, t->q_tol, false);
+  if (st) return st;
+  double hs[STAT_COUNT];
+  TK_HIP(t, hipMemcpyAsync(hs, dstats, sizeof(hs), hipMemcpyDeviceToHost, t->stream));
+  TK_HIP(t, hipStreamSynchronize(t->stream));
+  if (hs[STAT_STATUS] != 0.0) return fail(t, TK_EDEVICE, job_status_msg(hs[STAT_STATUS]));
+  for (int m = 0; m < TK_MAX_MODES; ++m) res->ranks_eff[m] = m < t->p ? jobs[0].rq[m] : 0;
+  res->fit = hs[STAT_FIT];
+  res->err_model = hs[STAT_ERR];
+  res->norm_ytilde = hs[STAT_NORM];
+  res->sweeps = int32_t(hs[STAT_SWEEPS]);
+  res->converged = int32_t(hs[STAT_CONV]);
+  res->n_hits = jobs[0].s;
+  return TK_OK;
 }
 
 tk_status tk_raw_tucker(tk_tree* t, int32_t n, const float* const* X, const int64_t* L, tk_result* res) {

@@ -27,6 +27,7 @@ constexpr size_t kLdsBytes = 160 * 1024;               // LDS per CU on gfx950
 struct DevBuf {
   char* p = nullptr;
   int64_t cap = 0;
+  bool fixed = false;  // memory owned elsewhere (the no-allocation scratch): never reallocated or freed
 };
 
 // Launch tuning of the stitch kernel (tk_tuning).

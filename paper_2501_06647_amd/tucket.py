@@ -82,6 +82,7 @@ SIGNATURES = [
     ("tk_hitset", c_i32, [c_vp, c_i64, c_i64, ctypes.POINTER(TkHit), c_i32, ctypes.POINTER(c_i32)]),
     ("tk_query_shape", c_i32, [c_vp, c_i64, c_i64, ctypes.POINTER(TkShape)]),
     ("tk_query", c_i32, [c_vp, c_i64, c_i64, ctypes.POINTER(TkResult)]),
+    ("tk_query_noalloc", c_i32, [c_vp, c_i64, c_i64, ctypes.POINTER(TkResult)]),
     ("tk_query_batch", c_i32, [c_vp, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
                                ctypes.POINTER(TkResult)]),
     ("tk_set_query_iters", c_i32, [c_vp, c_i32, c_dbl]),
@@ -579,6 +580,23 @@ class Tree:
 
     def query(self, ts: int, te: int) -> QueryResult:
         return self.query_batch([ts], [te])[0]
+
+    def query_noalloc(self, ts: int, te: int, out: Optional[QueryResult] = None) -> QueryResult:
+        """tk_query_noalloc: the library allocates nothing (its fixed device
+        scratch); the outputs are the caller's (``out``'s buffers when
+        given, else new ones)."""
+        if out is None:
+            shp = _query_shapes(self, [ts], [te])[0]
+            _, views = self._alloc(shp)
+            core, facs = views[0], views[1:]
+        else:
+            core, facs = out.core, out.factors
+        res = TkResult()
+        res.core = core.data_ptr()
+        for m in range(self.p):
+            res.factor[m] = facs[m].data_ptr()
+        self._check(lib().tk_query_noalloc(self._h, int(ts), int(te), ctypes.byref(res)), "tk_query_noalloc")
+        return QueryResult(core, list(facs), res, self.p)
 
     def set_query_iters(self, max_iter: int, tol: float):
         self._check(lib().tk_set_query_iters(self._h, max_iter, tol), "tk_set_query_iters")

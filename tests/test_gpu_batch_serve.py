@@ -405,3 +405,77 @@ def test_serving_admission_and_exclusion(torch):
         srv.stop()
     r = gpu.query(0, 8)  # synchronous calls work again
     assert r.n_hits >= 1
+
+
+def _oracle_at(wl, Tc, memo):
+    """An on-demand oracle tree at committed horizon Tc whose nodes come from
+    memo ((level, index) -> (H, V), all built by the oracle from raw data)."""
+    from oracle import pool
+    from oracle.tree import node_key
+    t = pool.lazy_tree(wl, Tc)
+    for v in t.complete_nodes():
+        H, V = memo[node_key(v)]
+        v.H, v.V = H, list(V)
+    return t
+
+
+def test_serving_shape_results_against_oracle(torch):
+    """The serving workload's shape (128 x 128 slices, drifting rank-16
+    model, leaf 1, node ranks 16): a tree of 1024 slices serves 512 more
+    appended one at a time, interleaved with queries of log-uniform lengths
+    inside each query's snapshot, first with FP32 queries, then (a second
+    session) with BF16 queries; merges are FP32 throughout.  Sampled served
+    results are compared with the oracle at their snapshots, the oracle
+    building every node itself from the raw slices."""
+    import math
+    from oracle import pool
+    from oracle.tree import node_key
+    from paper_2501_06647_amd.tucket import TK_BF16
+    wl = synth.get("serving")
+    T0, T1, T2 = 1024, 1280, 1536
+    X = synth.series(wl, 0, T2)
+    gpu = _gpu_tree(wl, T2)
+    gpu.build(X[:T0])
+    rng = np.random.default_rng(23)
+    served = []
+    for prec, t_lo, t_hi in ((None, T0, T1), (TK_BF16, T1, T2)):
+        if prec is not None:
+            gpu.set_query_prec(prec)
+        srv = gpu.serve(max_batch=64)
+        T = t_lo
+        tickets = []
+        for t in range(t_lo, t_hi):
+            srv.submit_append(X[t])
+            T += 1
+            if t % 4 == 0:
+                L = int(min(T, max(1, math.floor(math.exp(rng.uniform(0.0, math.log(T)))))))
+                a = int(rng.integers(0, T - L + 1))
+                tickets.append((srv.submit_query(a, a + L), a, a + L, T))
+        srv.sync()
+        st = srv.stats()
+        say("serving session prec=%s: %s" % (prec, st))
+        assert st["completed"] == st["queries"] + st["appends"]
+        pick = rng.choice(len(tickets), size=min(10, len(tickets)), replace=False)
+        for i in sorted(pick.tolist()):
+            tk, a, c, Tc = tickets[i]
+            r = srv.result(tk)
+            served.append((prec, a, c, Tc, to_np(r)))
+        srv.stop()
+    # the oracle's own nodes over [0, T2)
+    orc = pool.lazy_tree(wl, T2)
+    level = pool.pool_level(wl)
+    pool.fill(orc, wl, level, range(T2 // (wl.leaf_len << level)))
+    for v in orc.complete_nodes():
+        orc.ensure(v)
+    memo = {node_key(v): (v.H, v.V) for v in orc.complete_nodes()}
+    worst = {None: 0.0, TK_BF16: 0.0}
+    for prec, a, c, Tc, (G, U) in served:
+        o = _oracle_at(wl, Tc, memo)
+        Go, Uo, info = o.query(a, c)
+        d, orth, _, eg, _ = compare(X, a, c, G, U, Go, Uo)
+        say("served prec=%s [%d,%d) at T_c=%d hits=%d delta=%.2e orth=%.2e e=%.4e"
+            % (prec, a, c, Tc, len(info["hits"]), d, orth, eg))
+        assert orth <= ORTH
+        worst[prec] = max(worst[prec], d)
+    say("served vs oracle: worst delta FP32 %.2e (bar 1e-5), BF16 %.2e (bar 1e-2)" % (worst[None], worst[TK_BF16]))
+    assert worst[None] <= DELTA and worst[TK_BF16] <= 1e-2

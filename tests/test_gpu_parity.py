@@ -10,13 +10,17 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import compare, level_index, load_store, oracle_tree, round_nodes, say, to_np
+from gpu_helpers import recon_bound, compare, level_index, load_store, oracle_tree, recon_diff, round_nodes, say, to_np, ytilde
 
 pytestmark = pytest.mark.gpu
 
 DELTA = 1e-5
 SINE = 1e-4
 ORTH = 1e-6
+# distance of converged reconstructions, |Y^_gpu - Y^_oracle| / |Y^_oracle|: the
+# FP32 bar of the error ratio applied to the reconstruction itself, plus the
+# Davis-Kahan estimate of what FP32 rounding may move at each mode's rank cut
+RECON = 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -87,7 +91,7 @@ def test_kernel_parity_tiny_converged_subspaces(tiny):
         r = gpu.query(a, b)
         Go, Uo, _ = orc.query(a, b, max_iter=60, tol=0.0)
         G, U = to_np(r)
-        d, orth, sine, _, _ = compare(X, a, b, G, U, Go, Uo, wl.true_ranks, SINE)
+        d, orth, sine, _, _ = compare(X, a, b, G, U, Go, Uo, wl.true_ranks, SINE, Yt=ytilde(orc, a, b))
         assert d <= DELTA and orth <= ORTH and sine <= SINE, (a, b, d, orth, sine)
         worst = max(worst, sine)
     say("tiny converged worst sine %.2e" % worst)
@@ -214,6 +218,26 @@ def test_plain_workload_full_size_sampled(torch):
         worst = max(worst, d)
     say("plain: worst query delta %.2e" % worst)
     assert worst <= DELTA
+    # converged runs (200 sweeps, tolerance 1e-12 on both sides): leading
+    # subspaces and the distance between the two reconstructions
+    gpu.set_query_iters(200, 1e-12)
+    cts, cte = synth.queries(wl, n=64, seed_offset=9)
+    pick = [i for i in range(64) if cte[i] - cts[i] <= 1024][:6]
+    worst_sine, worst_y = 0.0, 0.0
+    for i in pick:
+        a, b = int(cts[i]), int(cte[i])
+        r = gpu.query(a, b)
+        Go, Uo, info = orc.query(a, b, max_iter=200, tol=1e-12)
+        G, U = to_np(r)
+        Yt = ytilde(orc, a, b)
+        d, orth, sine, _, _ = compare(X, a, b, G, U, Go, Uo, wl.true_ranks, SINE, Yt=Yt)
+        dy = recon_diff(G, U, Go, Uo)
+        bound = RECON + recon_bound(Yt, Go, Uo)
+        say("plain converged [%d,%d) sweeps %d/%d delta=%.2e sine=%.2e recon=%.2e (bar %.2e)"
+            % (a, b, r.sweeps, info["sweeps"], d, sine, dy, bound))
+        assert d <= DELTA and orth <= ORTH and sine <= SINE and dy <= bound, (a, b, d, orth, sine, dy, bound)
+        worst_sine, worst_y = max(worst_sine, sine), max(worst_y, dy)
+    say("plain converged: worst sine %.2e, worst reconstruction distance %.2e" % (worst_sine, worst_y))
 
 
 def test_tail_queries(torch):

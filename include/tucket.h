@@ -351,18 +351,24 @@ tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* t
  * After tk_serve_start, queries and appends are submitted from any thread
  * and return a ticket at once; a scheduler thread owned by the tree issues
  * them.  A query sees every append submitted before it (its snapshot T_c),
- * even if that append is still being committed: its launch waits for the
- * commit.  Queries are grouped in three size classes with their own streams;
- * a class admits waiting queries into its next batch, in arrival order,
- * while the batch has job slots (max_batch) and workspace bytes (an equal
- * share of ws_budget_bytes) left.  Appends are committed in groups of up to
- * max_commit_blocks leaf blocks on a stream of their own, concurrently with
- * the query batches.  A query's result is bit-identical to tk_query on a tree
- * holding the same slices (same tuning).  While serving, the synchronous
- * calls that read or change the tree return TK_EBUSY.
+ * even if that append is still being committed: it is admitted once the
+ * commit has completed.  Queries are grouped in three size classes by their
+ * largest eigenproblem.  Each class runs a stitch launch whose workgroups
+ * (at most max_batch: the class's job slots) take admitted queries one at a
+ * time from a job ring in host memory that the device maps; a waiting query
+ * is admitted, in arrival order, as soon as the ring has a free entry
+ * (4 max_batch per class) and the class's workspace (an equal share of
+ * ws_budget_bytes, first fit) has room for it, and it runs beside the
+ * queries already on the device.  A launch ends after 2 ms without work or
+ * 20 ms of age and is relaunched while admitted queries wait.  Appends are
+ * committed in groups of up to max_commit_blocks leaf blocks on a stream of
+ * their own, concurrently with the queries.  A query's result is
+ * bit-identical to tk_query on a tree holding the same slices (same
+ * tuning).  While serving, the synchronous calls that read or change the
+ * tree return TK_EBUSY.
  * ------------------------------------------------------------------------- */
 typedef struct {
-  int32_t max_batch;          /* queries per batch per class; 0: 256          */
+  int32_t max_batch;          /* job slots (concurrent queries) per class; 0: 256 */
   int32_t max_commit_blocks;  /* leaf blocks per append commit; 0: 64         */
   int64_t ws_budget_bytes;    /* query workspace on the device; 0: 1 GiB      */
   int64_t max_queue;          /* unfinished requests before TK_EBUSY; 0: 2^20 */
@@ -373,7 +379,7 @@ typedef struct {
   int64_t completed;          /* finished requests                             */
   int64_t rejected;           /* refused (queue full or over the budget)       */
   int64_t batches, commits;   /* query launches and append commits issued      */
-  int64_t max_batch_seen;     /* largest query batch launched                  */
+  int64_t max_batch_seen;     /* most admitted, unfinished queries of a class  */
   int64_t outstanding;        /* submitted, not finished                       */
   int64_t T_submitted;        /* slices submitted                              */
   int64_t T_committed;        /* slices in committed blocks                    */

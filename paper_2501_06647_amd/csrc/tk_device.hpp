@@ -287,6 +287,56 @@ __device__ __forceinline__ void gemm_f64(int M, int N, int K, FA&& a, FB&& b, FP
   __syncthreads();
 }
 
+// gemm_f64 for many row tiles (M >> N, as when a thin factor's rows stream
+// from HBM): each wavefront takes TB tiles per round and issues the loads of
+// all of them before any product or store, so one memory round trip serves
+// TB tiles.  Same layout and arithmetic order per tile as gemm_f64.
+template <int TB, typename FA, typename FB, typename FP>
+__device__ __forceinline__ void gemm_f64_rows(int M, int N, int K, FA&& a, FB&& b, FP&& put) {
+  const int nw = int(blockDim.x) >> 6, w = int(threadIdx.x) >> 6, l = int(threadIdx.x) & 63;
+  const int lr = l & 15, lk = l >> 4;
+  const int mt = (M + 15) >> 4, ntl = (N + 15) >> 4;
+  const int T = mt * ntl;
+  for (int t0 = w; t0 < T; t0 += TB * nw) {
+    tk_d4 c[TB];
+#pragma unroll
+    for (int g = 0; g < TB; ++g) c[g] = tk_d4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      double av[TB][4], bv[TB][4];
+#pragma unroll
+      for (int g = 0; g < TB; ++g) {
+        const int t = t0 + g * nw;
+        const int I = t % mt, J = t / mt;
+        const int i = I * 16 + lr, j = J * 16 + lr;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + 4 * u + lk;
+          av[g][u] = (t < T && i < M && k < K) ? double(a(i, k)) : 0.0;
+          bv[g][u] = (t < T && j < N && k < K) ? double(b(k, j)) : 0.0;
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < TB; ++g)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (k0 + 4 * u < K) c[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[g][u], bv[g][u], c[g], 0, 0, 0);
+    }
+#pragma unroll
+    for (int g = 0; g < TB; ++g) {
+      const int t = t0 + g * nw;
+      if (t >= T) break;
+      const int I = t % mt, J = t / mt;
+      const int j = J * 16 + lr;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ri = I * 16 + lk + 4 * v;
+        if (ri < M && j < N) put(ri, j, c[g][v]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // Mode product in FP64 on the matrix cores: Y[x][i][y] (+)= sum_j A(i, j)
 // X[x][j][y] (X FP32 or FP64, A and Y FP64), the layout of mode_product_mfma
 // with v_mfma_f64_16x16x4f64 (fibers f = (x, y) as the N dimension).
@@ -482,7 +532,29 @@ __device__ __forceinline__ void gram_rows(const float* __restrict__ V, int64_t l
     for (int ii = 0; ii < 4; ++ii)
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) s[ii][jj] = 0.0;
-    for (int64_t r = sp; r < l; r += nsplit) {
+    // four rows per round, all their loads issued before the products, so
+    // that one memory round trip serves four rows (the rows stream from
+    // HBM); the sums keep the row order
+    int64_t r = sp;
+    for (; r + 3 * int64_t(nsplit) < l; r += 4 * int64_t(nsplit)) {
+      float u[4][4], v[4][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float* row = V + (r + q * int64_t(nsplit)) * k;
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          u[q][ii] = bi * 4 + ii < k ? row[bi * 4 + ii] : 0.0f;
+          v[q][ii] = bj * 4 + ii < k ? row[bj * 4 + ii] : 0.0f;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) s[ii][jj] += double(u[q][ii]) * double(v[q][jj]);
+    }
+    for (; r < l; r += nsplit) {
       const float* row = V + r * k;
       double u[4], v[4];
 #pragma unroll
@@ -731,7 +803,8 @@ struct EigCounters {  // zeroed by the owner (it may live in LDS)
 // both share one buffer); tmp: 4 n k doubles.  The returned eigenvalues
 // live in vec.
 __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, double* E, int lde, double* red,
-                                                     double* tmp, EigCounters* cnt, double* vec) {
+                                                     double* tmp, EigCounters* cnt, double* vec,
+                                                     double* lfree = nullptr, int64_t nfree = 0) {
   __shared__ int s_flag;
   __shared__ int s_busy;
   const uint64_t t_start = wall_clock64();
@@ -796,7 +869,32 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
         double acc = 0.0;
         if (i > 0) {
           const double ur = uo[r], wr = wo[r];
-          for (int c = i + 1 + sp; c < n; c += nsplit) {
+          int c = i + 1 + sp;
+          // four entries per round: every load of the round is issued before
+          // its stores, so one memory round trip serves four entries
+          for (; c + 3 * nsplit < n; c += 4 * nsplit) {
+            double* a0 = W + int64_t(c) * n + r;
+            double* a1 = a0 + int64_t(nsplit) * n;
+            double* a2 = a1 + int64_t(nsplit) * n;
+            double* a3 = a2 + int64_t(nsplit) * n;
+            const double y0 = *a0, y1 = *a1, y2 = *a2, y3 = *a3;
+            const double p0 = uo[c], p1 = uo[c + nsplit], p2 = uo[c + 2 * nsplit], p3 = uo[c + 3 * nsplit];
+            const double q0 = wo[c], q1 = wo[c + nsplit], q2 = wo[c + 2 * nsplit], q3 = wo[c + 3 * nsplit];
+            const double v0 = uc[c], v1 = uc[c + nsplit], v2 = uc[c + 2 * nsplit], v3 = uc[c + 3 * nsplit];
+            const double x0 = y0 - (p0 * wr + q0 * ur);
+            const double x1 = y1 - (p1 * wr + q1 * ur);
+            const double x2 = y2 - (p2 * wr + q2 * ur);
+            const double x3 = y3 - (p3 * wr + q3 * ur);
+            *a0 = x0;
+            *a1 = x1;
+            *a2 = x2;
+            *a3 = x3;
+            acc += x0 * v0;
+            acc += x1 * v1;
+            acc += x2 * v2;
+            acc += x3 * v3;
+          }
+          for (; c < n; c += nsplit) {
             double* a = W + int64_t(c) * n + r;
             const double x = *a - (uo[c] * wr + wo[c] * ur);
             *a = x;
@@ -960,7 +1058,12 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
     int kk;
     __device__ __forceinline__ double& operator()(int j, int r) const { return T[int64_t(r) * kk + j]; }
   };
-  double* U1 = tmp;                    // pivot rows of the LU factors (n x kk each)
+  // pivot rows of the LU factors (n x kk each), and the vectors when they
+  // do not fit in W's free triangle: in LDS when the caller has room there
+  // (lfree, nfree doubles), else in tmp.  Each solve is a serial chain per
+  // lane through these rows, so their latency counts in full.
+  const bool lu_lds = lfree && int64_t(4) * n * kk <= nfree;
+  double* U1 = lu_lds ? lfree : tmp;
   double* U2 = U1 + int64_t(n) * kk;
   double* U3 = U2 + int64_t(n) * kk;
   const double ptiny = 1e-15;  // pivot floor of the scaled problem
@@ -1206,7 +1309,7 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
   }
   };
   if (2 * kk < n) vectors(XinW{W, n});
-  else vectors(XinT{tmp + int64_t(3) * n * kk, kk});
+  else vectors(XinT{U1 + int64_t(3) * n * kk, kk});
   if (cnt && tid == 0) {
     cnt->calls += 1;
     cnt->sweeps += uint64_t(iters + 1);
@@ -1220,8 +1323,9 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
 
 // The eigensolver the kernels use.
 __device__ __forceinline__ const double* eig_top(double* W, int n, int k, double* E, int lde, double* red,
-                                                 double* tmp, EigCounters* cnt, double* vec) {
-  return eig_top_tri(W, n, k, E, lde, red, tmp, cnt, vec);
+                                                 double* tmp, EigCounters* cnt, double* vec,
+                                                 double* lfree = nullptr, int64_t nfree = 0) {
+  return eig_top_tri(W, n, k, E, lde, red, tmp, cnt, vec, lfree, nfree);
 }
 
 }  // namespace tk

@@ -8,6 +8,32 @@ namespace tk {
 constexpr int NT_STITCH = 64;  // one wavefront per stitch job
 constexpr int NT_LEAF = 256;   // four wavefronts per leaf job
 
+// A job ring that the host feeds while a stitch launch runs (serving): the
+// header, the job descriptors, the hits, the statistics and the completion
+// words all live in host memory that the device maps (pinned, coherent).
+// The host writes job q into slot q mod R and then publishes it by raising
+// tail to q + 1; a workgroup claims the next unclaimed job by advancing a
+// counter in device memory, runs it, and writes done[slot] = q + 1 when its
+// outputs and statistics are visible to the host.  A workgroup stops
+// claiming when the host sets stop, when no job has been published for
+// idle_ticks of the device's 100 MHz clock, or once the launch is older
+// than life_ticks, so every launch ends by itself and the host relaunches
+// when jobs are waiting.
+struct RingHdr {
+  int64_t tail;  // jobs published (host)
+  int32_t stop;  // host: claim nothing more
+  int32_t slots; // R
+};
+
+struct StitchRing {
+  RingHdr* hdr;            // device address of the host header
+  const Job* jobs;         // R job descriptors (host memory)
+  int64_t* done;           // R completion words (host memory)
+  int64_t* head;           // jobs claimed (device memory)
+  uint64_t idle_ticks;
+  uint64_t life_ticks;
+};
+
 struct StitchArgs {
   const StoreView* st;
   int p;               // modes of the tree (selects the kernel instantiation)
@@ -27,6 +53,7 @@ struct StitchArgs {
   int bf16;            // query jobs: BF16 operands in the ALS contractions
   int merge_bf16;      // merge jobs: the same
   int64_t theta_num, theta_den;
+  StitchRing ring;     // ring.hdr non-null: jobs come from the host's ring (jobs/n_jobs/queue unused)
 };
 
 struct LeafArgs {

@@ -9,15 +9,19 @@
 //   * a query sees the tree as of its submission (read-your-writes: the
 //     committed horizon T_c of every append submitted before it).  Completed
 //     nodes never change (Alg. "insert" only fills placeholders), so a query
-//     reads a consistent snapshot while later appends add nodes; its launch
-//     waits on the append commits it depends on;
+//     reads a consistent snapshot while later appends add nodes; it is
+//     admitted once the commits it depends on have completed;
 //   * queries are grouped into three size classes by their largest
-//     eigenproblem, each with its own stream and workspace budget.  A class
-//     launches a batch whenever its previous batch has completed and queries
-//     are waiting: it admits them in arrival order while the batch has job
-//     slots and workspace bytes left (queries that arrive while a batch runs
-//     are admitted into the next one), and batches of different classes and
-//     the append commits run on the device at the same time.
+//     eigenproblem.  Each class has a job ring in host memory that the
+//     device maps, and a stitch launch on the class's stream whose
+//     workgroups claim published jobs one at a time as they become free
+//     (a workgroup is a job slot).  A query is admitted, in arrival order, as
+//     soon as its class's ring has a free entry and the class's workspace
+//     has room for it (first fit): it joins the work already running on
+//     the device instead of waiting for a batch to finish.  A launch ends by
+//     itself when its class has been idle for a while, or when it is old
+//     (so the class's hardware queue also serves other work); the scheduler
+//     launches again whenever published jobs are waiting.
 // A query's result depends only on its range and snapshot: the kernel
 // variant is a function of the query's own eigenproblem size, so a query
 // returns the same bits alone and in any mix.
@@ -37,6 +41,8 @@ namespace tk {
 namespace {
 
 constexpr int kClasses = 3;
+constexpr uint64_t kRingIdleTicks = 200000;   // 2 ms of the device's 100 MHz clock
+constexpr uint64_t kRingLifeTicks = 2000000;  // 20 ms
 
 double now_us(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
@@ -57,18 +63,34 @@ struct Request {
   double t_submit = 0, t_launch = 0, t_done = 0;
   int state = REQ_QUEUED;
   int need = 0;  // size of the query's largest eigenproblem
+  int64_t seq = -1, slot = -1, ws_off = -1;  // ring position and workspace of an admitted query
 };
 
 struct ClassLane {
-  Lane lane;
+  Lane lane;  // stream, workspace, ring head counter
   int n_lds = 0;
   int threads = 64;
+  int lds_doubles = 0;
+  int grid = 0;  // job slots: workgroups of the class's launch
   int64_t ws_budget = 0;
   std::deque<Request*> pending;
-  std::vector<Request*> inflight;
-  hipEvent_t done_ev = nullptr;
-  double* hstats = nullptr;  // pinned, max_batch x STAT_COUNT
-  bool busy = false;
+  std::vector<Request*> inflight;  // admitted, not done
+  // the job ring (pinned host memory, mapped on the device)
+  void* host = nullptr;
+  int64_t slots = 0;
+  RingHdr* hdr = nullptr;
+  Job* jobs = nullptr;
+  Hit* hits = nullptr;  // host-planned hit sets (fixed-block queries); Recall writes its own
+  double* stats = nullptr;
+  int64_t* done = nullptr;
+  StitchRing dring{};
+  Hit* dhits = nullptr;
+  double* dstats = nullptr;
+  std::vector<Request*> slot_req;
+  int64_t published = 0;
+  std::vector<std::pair<int64_t, int64_t>> allocs;  // workspace in use: (offset, bytes), by offset
+  hipEvent_t kev = nullptr;
+  bool launched = false;
 };
 
 }  // namespace
@@ -173,63 +195,93 @@ tk_status issue_appends(Server* s) {
   return TK_OK;
 }
 
+// First fit of bytes in the class's workspace; false if no gap is large enough.
+bool ws_alloc(ClassLane& c, int64_t bytes, int64_t* off) {
+  int64_t at = 0;
+  size_t k = 0;
+  for (; k < c.allocs.size(); ++k) {
+    if (c.allocs[k].first - at >= bytes) break;
+    at = align256(c.allocs[k].first + c.allocs[k].second);
+  }
+  if (k == c.allocs.size() && c.ws_budget - at < bytes) return false;
+  c.allocs.insert(c.allocs.begin() + k, {at, bytes});
+  *off = at;
+  return true;
+}
+
+void ws_free(ClassLane& c, int64_t off) {
+  for (size_t k = 0; k < c.allocs.size(); ++k)
+    if (c.allocs[k].first == off) {
+      c.allocs.erase(c.allocs.begin() + k);
+      return;
+    }
+}
+
+bool launch_running(tk_tree* t, ClassLane& c, tk_status* st) {
+  *st = TK_OK;
+  if (!c.launched) return false;
+  const hipError_t e = hipEventQuery(c.kev);
+  if (e == hipErrorNotReady) return true;
+  if (e != hipSuccess) *st = fail_dev(t, e, "query launch");
+  c.launched = false;
+  return false;
+}
+
+// Admit waiting queries of class c into its ring (arrival order) while ring
+// entries and workspace last, and make sure a launch is running while
+// admitted queries are not done.
 tk_status issue_queries(Server* s, ClassLane& c) {
   tk_tree* t = s->t;
-  if (c.busy || c.pending.empty()) return TK_OK;
-  std::vector<Job> jobs;
-  std::vector<Hit> hits;
-  int64_t ws = 0;
-  int64_t Tb_need = 0;
-  int need = 0;
-  while (!c.pending.empty() && int(jobs.size()) < s->cfg.max_batch) {
+  const double tl = now_us(s->t0);
+  int64_t admitted = 0;
+  while (!c.pending.empty()) {
     Request* r = c.pending.front();
-    if (r->Tb > s->Tb_issued) break;  // its appends are not committed yet (later queries neither)
-    if (!jobs.empty() && ws + r->job.ws_bytes > c.ws_budget) break;
+    if (r->Tb > s->Tb_done) break;  // its appends are not committed yet (later queries neither)
+    const int64_t slot = c.published % c.slots;
+    if (c.slot_req[size_t(slot)]) break;  // the ring is full
+    int64_t off = 0;
+    if (!ws_alloc(c, r->job.ws_bytes, &off)) break;  // no room in the workspace yet
     c.pending.pop_front();
     Job jb = r->job;
-    jb.hit0 = int32_t(hits.size());
-    jb.ws_off = ws;
-    jb.stats = reinterpret_cast<double*>(c.lane.stats.p) + STAT_COUNT * int64_t(jobs.size());
-    ws += jb.ws_bytes;
-    hits.insert(hits.end(), r->hits.begin(), r->hits.end());
-    jobs.push_back(jb);
-    c.inflight.push_back(r);
-    if (r->Tb > Tb_need) Tb_need = r->Tb;
-    if (r->need > need) need = r->need;
-  }
-  if (jobs.empty()) return TK_OK;
-  const double tl = now_us(s->t0);
-  for (Request* r : c.inflight) {
+    jb.hit0 = int32_t(slot * MAXHITS);
+    jb.ws_off = off;
+    jb.stats = c.dstats + STAT_COUNT * slot;
+    c.jobs[slot] = jb;
+    std::memcpy(c.hits + slot * MAXHITS, r->hits.data(), size_t(r->job.s) * sizeof(Hit));
+    __atomic_store_n(&c.done[slot], int64_t(0), __ATOMIC_RELAXED);
+    r->seq = c.published;
+    r->slot = slot;
+    r->ws_off = off;
     r->t_launch = tl;
     r->state = REQ_RUNNING;
+    c.slot_req[size_t(slot)] = r;
+    c.inflight.push_back(r);
+    c.published += 1;
+    __atomic_store_n(&c.hdr->tail, c.published, __ATOMIC_RELEASE);  // publish
+    admitted += 1;
   }
-  hipStream_t st_ = c.lane.stream;
-  if (Tb_need > s->Tb_done) TK_HIP(t, hipStreamWaitEvent(st_, s->commit_ev, 0));
-  TK_HIP(t, hipMemcpyAsync(c.lane.jobs[0].p, jobs.data(), jobs.size() * sizeof(Job), hipMemcpyHostToDevice, st_));
+  if (admitted) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (int64_t(c.inflight.size()) > s->stats.max_batch_seen) s->stats.max_batch_seen = int64_t(c.inflight.size());
+  }
+  if (c.inflight.empty()) return TK_OK;
+  tk_status st = TK_OK;
+  if (launch_running(t, c, &st) || st) return st;
+  // every job claimed by an ended launch is done, so the waiting ones need a new launch
   StitchArgs a = stitch_args(t, t->q_max_iter, t->q_tol);
-  TK_HIP(t, hipMemcpyAsync(c.lane.hits.p, hits.data(), hits.size() * sizeof(Hit), hipMemcpyHostToDevice, st_));
-  a.hits = reinterpret_cast<Hit*>(c.lane.hits.p);
-  a.jobs = reinterpret_cast<const Job*>(c.lane.jobs[0].p);
+  a.ring = c.dring;
+  a.hits = c.dhits;
+  a.jobs = nullptr;
   a.ws = c.lane.ws[0].p;
-  a.n_jobs = int(jobs.size());
-  a.n_lds = c.n_lds;
-  a.lds_doubles = int(group_lds_doubles(c.n_lds, need));
-  const size_t lds_bytes = size_t(a.lds_doubles) * 8;
-  int grid = a.n_jobs;
+  a.n_jobs = c.grid;
   a.queue = nullptr;
-  if (t->tuning.persistent) {
-    const int64_t resident = int64_t(stitch_blocks_per_cu(c.threads, lds_bytes)) * t->n_cu;
-    if (resident < grid) grid = int(resident);
-    a.queue = reinterpret_cast<int*>(c.lane.queue.p);
-    TK_HIP(t, launch_reset_queue(a.queue, 1, st_));
-  }
-  TK_HIP(t, launch_stitch(a, grid, lds_bytes, c.threads, st_));
-  TK_HIP(t, hipMemcpyAsync(c.hstats, c.lane.stats.p, jobs.size() * STAT_COUNT * 8, hipMemcpyDeviceToHost, st_));
-  TK_HIP(t, hipEventRecord(c.done_ev, st_));
-  c.busy = true;
+  a.n_lds = c.n_lds;
+  a.lds_doubles = c.lds_doubles;
+  TK_HIP(t, launch_stitch(a, c.grid, size_t(c.lds_doubles) * 8, c.threads, c.lane.stream));
+  TK_HIP(t, hipEventRecord(c.kev, c.lane.stream));
+  c.launched = true;
   std::lock_guard<std::mutex> lk(s->mu);
   s->stats.batches += 1;
-  if (int64_t(jobs.size()) > s->stats.max_batch_seen) s->stats.max_batch_seen = int64_t(jobs.size());
   return TK_OK;
 }
 
@@ -248,15 +300,16 @@ tk_status poll_completions(Server* s, bool* progress) {
     }
   }
   for (ClassLane& c : s->cl) {
-    if (!c.busy) continue;
-    const hipError_t e = hipEventQuery(c.done_ev);
-    if (e == hipErrorNotReady) continue;
-    if (e != hipSuccess) return fail_dev(t, e, "query batch");
-    c.busy = false;
-    *progress = true;
+    if (c.inflight.empty()) continue;
+    size_t keep = 0;
     for (size_t i = 0; i < c.inflight.size(); ++i) {
       Request* r = c.inflight[i];
-      const double* st = c.hstats + STAT_COUNT * i;
+      if (__atomic_load_n(&c.done[r->slot], __ATOMIC_ACQUIRE) != r->seq + 1) {
+        c.inflight[keep++] = r;
+        continue;
+      }
+      *progress = true;
+      const double* st = c.stats + STAT_COUNT * r->slot;
       int state = REQ_DONE;
       if (st[STAT_STATUS] != 0.0) {
         set_error(t, job_status_msg(st[STAT_STATUS]));
@@ -270,9 +323,15 @@ tk_status poll_completions(Server* s, bool* progress) {
       o.sweeps = int32_t(st[STAT_SWEEPS]);
       o.converged = int32_t(st[STAT_CONV]);
       o.n_hits = r->job.s;
+      ws_free(c, r->ws_off);
+      c.slot_req[size_t(r->slot)] = nullptr;
       finish(s, r, state);
     }
-    c.inflight.clear();
+    c.inflight.resize(keep);
+    // a launch that ended with a device error
+    tk_status st = TK_OK;
+    (void)launch_running(t, c, &st);
+    if (st) return st;
   }
   return TK_OK;
 }
@@ -285,7 +344,7 @@ void engine(Server* s) {
       std::unique_lock<std::mutex> lk(s->mu);
       const bool idle = !s->abusy && s->apending.empty() && s->inbox.empty() &&
                         std::all_of(s->cl, s->cl + kClasses, [](const ClassLane& c) {
-                          return !c.busy && c.pending.empty();
+                          return c.inflight.empty() && c.pending.empty();
                         });
       if (idle) {
         if (s->stop) break;
@@ -319,9 +378,10 @@ void engine(Server* s) {
 void server_free(Server* s) {
   lane_destroy(&s->alane);
   for (ClassLane& c : s->cl) {
-    lane_destroy(&c.lane);
-    if (c.done_ev) (void)hipEventDestroy(c.done_ev);
-    if (c.hstats) (void)hipHostFree(c.hstats);
+    if (c.hdr) __atomic_store_n(&c.hdr->stop, 1, __ATOMIC_RELEASE);  // a running launch claims nothing more
+    lane_destroy(&c.lane);  // waits for the class's stream
+    if (c.kev) (void)hipEventDestroy(c.kev);
+    if (c.host) (void)hipHostFree(c.host);
   }
   if (s->aev) (void)hipEventDestroy(s->aev);
   if (s->commit_ev) (void)hipEventDestroy(s->commit_ev);
@@ -391,21 +451,53 @@ tk_status tk_serve_start(tk_tree* t, const tk_serve_config* cfg) {
     const int hi = s->bounds[k];
     cl.threads = hi <= t->tuning.wide_threshold ? NT_STITCH : t->tuning.wide_threads;
     cl.ws_budget = c.ws_budget_bytes / kClasses;
+    // dynamic LDS: every eigenproblem the class admits (the last class: up to
+    // the LDS limit, for the vectors of eigenproblems beyond the cap)
+    cl.lds_doubles = int(k < kClasses - 1 ? eig_doubles(cl.n_lds)
+                                          : (t->lds_limit - int64_t(stitch_static_lds())) / 8);
+    const int per_cu = stitch_blocks_per_cu(cl.threads, size_t(cl.lds_doubles) * 8);
+    cl.grid = std::max(1, std::min(c.max_batch, std::max(1, per_cu) * t->n_cu / 2));
+    cl.slots = int64_t(4) * c.max_batch;
     if ((e = hipStreamCreateWithFlags(&cl.lane.stream, hipStreamNonBlocking)) != hipSuccess)
       return bail(fail_dev(t, e, "serve: class stream"));
     cl.lane.own_stream = true;
-    if ((e = hipEventCreateWithFlags(&cl.done_ev, hipEventDisableTiming)) != hipSuccess)
+    if ((e = hipEventCreateWithFlags(&cl.kev, hipEventDisableTiming)) != hipSuccess)
       return bail(fail_dev(t, e, "serve: class event"));
     if ((st = ensure(t, &cl.lane.ws[0], cl.ws_budget + 256, "serve workspace")) ||
-        (st = ensure(t, &cl.lane.jobs[0], int64_t(c.max_batch) * sizeof(Job), "serve jobs")) ||
-        (st = ensure(t, &cl.lane.hits, int64_t(c.max_batch) * MAXHITS * sizeof(Hit), "serve hits")) ||
-        (st = ensure(t, &cl.lane.stats, int64_t(c.max_batch) * STAT_COUNT * 8, "serve stats")) ||
-        (st = ensure(t, &cl.lane.queue, 64, "serve queue")))
+        (st = ensure(t, &cl.lane.queue, 64, "serve ring head")))
       return bail(st);
-    void* hp = nullptr;
-    if ((e = hipHostMalloc(&hp, size_t(c.max_batch) * STAT_COUNT * 8, hipHostMallocDefault)) != hipSuccess)
-      return bail(fail_dev(t, e, "serve: pinned stats"));
-    cl.hstats = static_cast<double*>(hp);
+    // ring: header | jobs | hits | statistics | completion words (host, mapped)
+    const size_t o_jobs = 256;
+    const size_t o_hits = o_jobs + size_t(align256(cl.slots * int64_t(sizeof(Job))));
+    const size_t o_stats = o_hits + size_t(align256(cl.slots * MAXHITS * int64_t(sizeof(Hit))));
+    const size_t o_done = o_stats + size_t(align256(cl.slots * STAT_COUNT * 8));
+    const size_t bytes = o_done + size_t(cl.slots) * 8;
+    if ((e = hipHostMalloc(&cl.host, bytes, hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)
+      return bail(fail_dev(t, e, "serve: ring memory"));
+    std::memset(cl.host, 0, bytes);
+    void* dp = nullptr;
+    if ((e = hipHostGetDevicePointer(&dp, cl.host, 0)) != hipSuccess)
+      return bail(fail_dev(t, e, "serve: ring device address"));
+    char* h = static_cast<char*>(cl.host);
+    char* d = static_cast<char*>(dp);
+    cl.hdr = reinterpret_cast<RingHdr*>(h);
+    cl.hdr->slots = int32_t(cl.slots);
+    cl.jobs = reinterpret_cast<Job*>(h + o_jobs);
+    cl.hits = reinterpret_cast<Hit*>(h + o_hits);
+    cl.stats = reinterpret_cast<double*>(h + o_stats);
+    cl.done = reinterpret_cast<int64_t*>(h + o_done);
+    cl.dhits = reinterpret_cast<Hit*>(d + o_hits);
+    cl.dstats = reinterpret_cast<double*>(d + o_stats);
+    cl.dring.hdr = reinterpret_cast<RingHdr*>(d);
+    cl.dring.jobs = reinterpret_cast<const Job*>(d + o_jobs);
+    cl.dring.done = reinterpret_cast<int64_t*>(d + o_done);
+    cl.dring.head = reinterpret_cast<int64_t*>(cl.lane.queue.p);
+    cl.dring.idle_ticks = kRingIdleTicks;
+    cl.dring.life_ticks = kRingLifeTicks;
+    cl.slot_req.assign(size_t(cl.slots), nullptr);
+    if ((e = hipMemsetAsync(cl.lane.queue.p, 0, 64, cl.lane.stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(cl.lane.stream)) != hipSuccess)
+      return bail(fail_dev(t, e, "serve: ring head"));
   }
   t->server = s;
   s->th = std::thread(engine, s);

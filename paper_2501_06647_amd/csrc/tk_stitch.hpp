@@ -174,6 +174,29 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     else if (eig_vec_doubles(n) <= lds_doubles) f(Dp(lo.EIG), lds);
     else f(Dp(lo.EIG), Dp(lo.EIG) + int64_t(n) * n);
   };
+  // LDS left free behind an eigen buffer of size n placed by with_buf /
+  // with_eig_buf (the eigensolver keeps its LU rows there when they fit)
+  auto eig_free = [&](int n, double** p) -> int64_t {
+    int64_t used = 0;
+    if (n <= n_lds) used = int64_t(n) * n + eig_vec_doubles(n);
+    else if (eig_vec_doubles(n) <= lds_doubles) used = eig_vec_doubles(n);
+    else used = lds_doubles;
+    *p = lds + used;
+    return lds_doubles - used;
+  };
+
+  // A pivoted Cholesky of an m x m Gram keeps its factor and the triangular
+  // inverse of pchol_basis in LDS when both fit behind what the buffer
+  // already holds (the Gram with its pivot data, or nothing when the Gram
+  // lives in the workspace), else in the workspace: the factorisation's
+  // steps are serial, and each round trip to LDS is far shorter.
+  auto chol_lds_used = [&](int m) -> int64_t { return int64_t(m) * m + m + (m + 1) / 2 + 1; };
+  auto lds_scratch = [&](int64_t used, int m, double** Lx, double** Tx) {
+    if (used + 2 * int64_t(m) * m <= lds_doubles) {
+      *Lx = lds + used;
+      *Tx = lds + used + int64_t(m) * m;
+    }
+  };
 
   // ---- trims (Eq. "partial-tucker") and |Y~|^2 ------------------------------
   double ny2 = 0.0;
@@ -199,8 +222,11 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
       gram_rows(V, h.l, k, Gm, k, Dp(lo.D1));
       double* d = Gm + k * k;
       int* piv = reinterpret_cast<int*>(Gm + k * k + k);
-      kp = pchol(Gm, k, 1e-12, TMP, piv, d, red, sh.redi);
-      pchol_basis<float>(TMP, piv, k, kp, Rt, k, Dp(lo.F[i]), k, Dp(lo.Tinv[0]));
+      double* Lx = TMP;
+      double* Tx = Dp(lo.Tinv[0]);
+      lds_scratch(k <= n_lds ? chol_lds_used(k) : 0, k, &Lx, &Tx);
+      kp = pchol(Gm, k, 1e-12, Lx, piv, d, red, sh.redi);
+      pchol_basis<float>(Lx, piv, k, kp, Rt, k, Dp(lo.F[i]), k, Tx);
     });
     float* Ht = Fp(lo.Ht[i]);
     mode_product(H, 1, k, R, Rt, k, 1, kp, Ht, false);
@@ -263,10 +289,13 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
         __syncthreads();
         double* d = Gm + sr * sr;
         int* piv = reinterpret_cast<int*>(Gm + sr * sr + sr);
-        const int q = pchol(Gm, sr, 1e-11, TMP, piv, d, red, sh.redi);
+        double* Lx = TMP;
+        double* Tx = Dp(lo.Tinv[n]);
+        lds_scratch(sr <= n_lds ? chol_lds_used(sr) : 0, sr, &Lx, &Tx);
+        const int q = pchol(Gm, sr, 1e-11, Lx, piv, d, red, sh.redi);
         if (q >= rq[n]) {
           use_basis = 1;
-          pchol_basis<double>(TMP, piv, sr, q, C64, sr, Dp(lo.Fn[n]), sr, Dp(lo.Tinv[n]));
+          pchol_basis<double>(Lx, piv, sr, q, C64, sr, Dp(lo.Fn[n]), sr, Tx);
           for (int e = tid; e < q * sr; e += nt) C[e] = float(C64[e]);
           if (tid == 0) sh.q[n] = q;
         }
@@ -331,7 +360,9 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
                [&](int j, int d2) { return C64[int64_t(d2) * sr + c0 + j]; },
                [&](int dd, int d2, double v) { Wm[dd * q + d2] += v; });
     }
-    eig_top(Wm, q, rq[n], Dp(lo.Pd[n]), rq[n], red, TMP, &ec, Wv);
+    double* lf = nullptr;
+    const int64_t nf = eig_free(q, &lf);
+    eig_top(Wm, q, rq[n], Dp(lo.Pd[n]), rq[n], red, TMP, &ec, Wv, lf, nf);
     });
     update_A(n);
   }
@@ -371,7 +402,9 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     with_buf(sk, [&](double* Wm, double* Wv) {
       gram(M, 1, sk, Rhat[0], Wm, sk);
       clk.mark(3);
-      eig_top(Wm, sk, rq[0], Dp(lo.Pd[0]), rq[0], red, TMP, &ec, Wv);
+      double* lf = nullptr;
+      const int64_t nf = eig_free(sk, &lf);
+      eig_top(Wm, sk, rq[0], Dp(lo.Pd[0]), rq[0], red, TMP, &ec, Wv, lf, nf);
     });
     float* P0f = Fp(lo.Pf[0]);
     {
@@ -426,7 +459,9 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
       with_eig_buf(q, [&](double* Wn, double* Wv) {
         gram(K, ka, q, kb, Wn, q);
         clk.mark(5);
-        eig_top(Wn, q, rq[n], Dp(lo.Pd[n]), rq[n], red, TMP, &ec, Wv);
+        double* lf = nullptr;
+        const int64_t nf = eig_free(q, &lf);
+        eig_top(Wn, q, rq[n], Dp(lo.Pd[n]), rq[n], red, TMP, &ec, Wv, lf, nf);
       });
       update_A(n);
       clk.mark(6);
@@ -494,9 +529,9 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
       }
       const float* V = st.plane[lev] + ((h.index << lev) * st.ell + h.a) * k;
       float* out = job.out_fac[0] + t * r0;
-      gemm_f64(int(h.l), r0, k, [&](int row, int c) { return V[int64_t(row) * k + c]; },
-               [&](int c, int j) { return F0[c * r0 + j]; },
-               [&](int row, int j, double v) { out[int64_t(row) * r0 + j] = float(v); });
+      gemm_f64_rows<4>(int(h.l), r0, k, [&](int row, int c) { return V[int64_t(row) * k + c]; },
+                       [&](int c, int j) { return F0[c * r0 + j]; },
+                       [&](int row, int j, double v) { out[int64_t(row) * r0 + j] = float(v); });
       t += h.l;
     }
   }
@@ -579,6 +614,28 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
 // runs past n_jobs, so every workgroup reaches the exit.
 // Register budget: at most 256 VGPRs, so that two wavefronts share a SIMD
 // (one job's latency hides behind another's).
+// Claim the next published job of the ring (thread 0): its sequence number,
+// or -1 when the workgroup should stop (stop set, idle too long, launch too
+// old).
+__device__ __forceinline__ int64_t ring_claim(const StitchRing& r, uint64_t t_launch) {
+  const uint64_t t_idle = wall_clock64();
+  for (;;) {
+    const uint64_t now = wall_clock64();
+    if (now - t_launch > r.life_ticks) return -1;
+    const int64_t tail = __hip_atomic_load(&r.hdr->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+    int64_t h = __hip_atomic_load(r.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (h < tail) {
+      if (__hip_atomic_compare_exchange_strong(r.head, &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT))
+        return h;
+      continue;
+    }
+    if (__hip_atomic_load(&r.hdr->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) || now - t_idle > r.idle_ticks)
+      return -1;
+    __builtin_amdgcn_s_sleep(16);
+  }
+}
+
 template <int NTT, int PM>
 __global__ __launch_bounds__(NTT, 2) void stitch_kernel(StitchArgs args) {
   extern __shared__ double lds[];
@@ -586,20 +643,49 @@ __global__ __launch_bounds__(NTT, 2) void stitch_kernel(StitchArgs args) {
   __shared__ Hit qh[MAXHITS];
   __shared__ int next_job;
   __shared__ int n_rec;
+  __shared__ Job rjob;       // the job's descriptor (a ring job's copied from host memory)
+  __shared__ int64_t rseq;
   const StoreView& st = *args.st;
+  const bool ring = args.ring.hdr != nullptr;
+  const uint64_t t_launch = wall_clock64();
   int jn = blockIdx.x;
+  int64_t seq = -1;
   for (;;) {
-    if (args.queue) {
+    if (ring) {
+      if (threadIdx.x == 0) {
+        rseq = ring_claim(args.ring, t_launch);
+        if (rseq >= 0) rjob = args.ring.jobs[rseq % args.ring.hdr->slots];
+      }
+      __syncthreads();
+      seq = rseq;
+      if (seq < 0) break;
+    } else if (args.queue) {
       if (threadIdx.x == 0) next_job = atomicAdd(args.queue, 1);
       __syncthreads();
       jn = next_job;
       __syncthreads();
     }
-    if (jn >= args.n_jobs) break;
-    const Job& job = args.jobs[jn];
+    if (!ring && jn >= args.n_jobs) break;
+    if (!ring) {  // the job's descriptor to LDS, as a ring job's
+      if (threadIdx.x == 0) rjob = args.jobs[jn];
+      __syncthreads();
+    }
+    const Job& job = rjob;
+    // a ring job's statistics and outputs become visible to the host before
+    // its completion word does
+    auto ring_done = [&]() {
+      if (!ring) return;
+      __threadfence_system();
+      __syncthreads();
+      if (threadIdx.x == 0)
+        __hip_atomic_store(&args.ring.done[seq % args.ring.hdr->slots], seq + 1, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+      __syncthreads();  // rjob and rseq are rewritten by the next claim
+    };
     if (st.p > PM) {  // launched with the wrong instantiation: refuse the job
       if (threadIdx.x == 0 && job.stats) job.stats[STAT_STATUS] = 3.0;
-      if (!args.queue) break;
+      ring_done();
+      if (!args.queue && !ring) break;
       continue;
     }
     // the job's hits go to LDS: a query's from its own Recall (published to
@@ -622,7 +708,8 @@ __global__ __launch_bounds__(NTT, 2) void stitch_kernel(StitchArgs args) {
         job.stats[STAT_STATUS] = 1.0;
         job.stats[STAT_HITS] = double(n_rec);
       }
-      if (!args.queue) break;
+      ring_done();
+      if (!args.queue && !ring) break;
       continue;
     }
     const Hit* hits = qh;
@@ -634,7 +721,8 @@ __global__ __launch_bounds__(NTT, 2) void stitch_kernel(StitchArgs args) {
       job.stats[STAT_T0] = double(t_begin);
       job.stats[STAT_T1] = double(wall_clock64());
     }
-    if (!args.queue) break;
+    ring_done();
+    if (!args.queue && !ring) break;
   }
 }
 

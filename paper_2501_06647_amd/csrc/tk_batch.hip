@@ -2,9 +2,10 @@
 //
 // A prepared batch plans a fixed list of range queries once (Recall for the
 // workspace sizes, LDS bins, heaviest-first order), uploads the job
-// descriptors, and captures its launches in a HIP graph: one fused stitch
-// kernel per LDS bin, each running Recall, the partial-hit trims and the
-// Stitch of its queries, the bins forked onto their own streams and joined.
+// descriptors, and captures its launches in a HIP graph: per LDS bin, the
+// trim pass over the long partial hits' rows, then one fused stitch kernel
+// running Recall, the partial-hit trims and the Stitch of its queries, the
+// bins forked onto their own streams and joined.
 // tk_batch_run replays the graph on the tree's stream.
 #include <algorithm>
 #include <chrono>
@@ -23,7 +24,8 @@ struct tk_batch {
   tk_result* res = nullptr;
   std::vector<Job> qjobs;  // in the caller's order (ranks, hit counts)
   Plan plan;
-  DevBuf hits, stats, queue, ws[kMaxGroups], jobs[kMaxGroups];
+  DevBuf hits, stats, queue, ws[kMaxGroups], jobs[kMaxGroups], trims[kMaxGroups];
+  int64_t n_trims[kMaxGroups] = {};  // chunks of the trim pass per group
   hipStream_t cap_stream = nullptr;
   hipStream_t gstream[kMaxGroups] = {};
   hipEvent_t gev[kMaxGroups] = {};
@@ -49,6 +51,7 @@ void batch_free(tk_batch* b) {
   for (int g = 0; g < kMaxGroups; ++g) {
     release(&b->ws[g]);
     release(&b->jobs[g]);
+    release(&b->trims[g]);
     if (b->gstream[g]) (void)hipStreamDestroy(b->gstream[g]);
     if (b->gev[g]) (void)hipEventDestroy(b->gev[g]);
   }
@@ -89,6 +92,8 @@ tk_status issue(tk_batch* b, hipStream_t stream) {
       a.queue = reinterpret_cast<int*>(b->queue.p) + g;
       TK_HIP(t, launch_reset_queue(a.queue, 1, s));
     }
+    if (b->n_trims[g] > 0)  // the trim pass first: row Grams of the long partial hits
+      TK_HIP(t, launch_trim(reinterpret_cast<const TrimChunk*>(b->trims[g].p), b->n_trims[g], s));
     TK_HIP(t, launch_stitch(a, grid, lds_bytes, gr.threads, s));
   }
   for (int sl = 0; sl < kForkStreams && fork; ++sl) {
@@ -130,7 +135,7 @@ tk_status tk_batch_create(tk_tree* t, int32_t n, const int64_t* ts, const int64_
   double* dstats = reinterpret_cast<double*>(b->stats.p);
   std::vector<Job> jobs = b->qjobs;
   for (int32_t i = 0; i < n; ++i) jobs[i].stats = dstats + STAT_COUNT * int64_t(i);
-  st = plan_stitch(t, jobs, hits, &b->plan);
+  st = plan_stitch(t, jobs, hits, &b->plan, true);
   if (st) return bail(st);
   // the kernels run Recall themselves and write the hits; their slots start
   // zeroed (queries on host-planned hits, kind 2, get the plan's)
@@ -159,6 +164,14 @@ tk_status tk_batch_create(tk_tree* t, int32_t n, const int64_t* ts, const int64_
     st = ensure(t, &b->jobs[gr.bin], int64_t(gr.jobs.size() * sizeof(Job)), "batch jobs");
     if (st) return bail(st);
     TK_HIP(t, hipMemcpy(b->jobs[gr.bin].p, gr.jobs.data(), gr.jobs.size() * sizeof(Job), hipMemcpyHostToDevice));
+    std::vector<TrimChunk> trims;
+    trim_chunks_of(t, b->plan, gr, 0, int64_t(gr.jobs.size()), b->ws[gr.bin].p, trims);
+    b->n_trims[gr.bin] = int64_t(trims.size());
+    if (!trims.empty()) {
+      st = ensure(t, &b->trims[gr.bin], int64_t(trims.size() * sizeof(TrimChunk)), "batch trim chunks");
+      if (st) return bail(st);
+      TK_HIP(t, hipMemcpy(b->trims[gr.bin].p, trims.data(), trims.size() * sizeof(TrimChunk), hipMemcpyHostToDevice));
+    }
     if (!b->gstream[gr.slot]) {
       TK_HIP(t, hipStreamCreateWithFlags(&b->gstream[gr.slot], hipStreamNonBlocking));
       TK_HIP(t, hipEventCreateWithFlags(&b->gev[gr.slot], hipEventDisableTiming));

@@ -127,6 +127,7 @@ void lane_destroy(Lane* l) {
   for (int g = 0; g < kMaxGroups; ++g) {
     release(&l->ws[g]);
     release(&l->jobs[g]);
+    release(&l->trims[g]);
     if (l->gstream[g]) (void)hipStreamDestroy(l->gstream[g]);
     if (l->gev[g]) (void)hipEventDestroy(l->gev[g]);
     l->gstream[g] = nullptr;
@@ -248,7 +249,7 @@ void make_merge_job(tk_tree* t, int k, int64_t j, std::vector<Job>& jobs, std::v
   jobs.push_back(jb);
 }
 
-tk_status plan_stitch(tk_tree* t, std::vector<Job>& jobs, std::vector<Hit>& hits, Plan* plan) {
+tk_status plan_stitch(tk_tree* t, std::vector<Job>& jobs, std::vector<Hit>& hits, Plan* plan, bool pretrim) {
   plan->groups.clear();
   plan->n_jobs = int64_t(jobs.size());
   plan->basis_pct = t->tuning.basis_pct;
@@ -302,8 +303,15 @@ tk_status plan_stitch(tk_tree* t, std::vector<Job>& jobs, std::vector<Hit>& hits
     });
     int64_t off = 0;
     for (Job& jb : gr.jobs) {
+      jb.pretrim = 0;
+      if (pretrim && jb.kind != 1) {
+        int64_t rows = 0;
+        for (int i = 0; i < jb.s; ++i)
+          if (hits[size_t(jb.hit0 + i)].partial) rows += hits[size_t(jb.hit0 + i)].l;
+        jb.pretrim = rows >= kPretrimRows ? 1 : 0;
+      }
       StitchLayout lo;
-      stitch_layout(t->view, hits.data() + jb.hit0, jb.s, jb.rq, gr.n_lds, &lo);
+      stitch_layout(t->view, hits.data() + jb.hit0, jb.s, jb.rq, gr.n_lds, &lo, jb.pretrim);
       jb.ws_off = off;
       jb.ws_bytes = lo.total;
       off += lo.total;
@@ -320,10 +328,41 @@ tk_status plan_stitch(tk_tree* t, std::vector<Job>& jobs, std::vector<Hit>& hits
   return TK_OK;
 }
 
+void trim_chunks_of(const tk_tree* t, const Plan& plan, const Group& gr, int64_t i0, int64_t i1, char* ws_base,
+                    std::vector<TrimChunk>& out) {
+  const StoreView& v = t->view;
+  const int64_t base_off = gr.jobs[size_t(i0)].ws_off;
+  for (int64_t j = i0; j < i1; ++j) {
+    const Job& jb = gr.jobs[size_t(j)];
+    if (!jb.pretrim) continue;
+    const Hit* hs = plan.hits.data() + jb.hit0;
+    StitchLayout lo;
+    stitch_layout(v, hs, jb.s, jb.rq, gr.n_lds, &lo, 1);
+    double* tg = reinterpret_cast<double*>(ws_base + (jb.ws_off - base_off) + lo.TG);
+    for (int i = 0; i < jb.s; ++i) {
+      const Hit& h = hs[i];
+      if (!h.partial) continue;
+      const int k = v.rk[h.level][0];
+      const float* V = v.plane[h.level] + ((h.index << h.level) * v.ell + h.a) * k;
+      for (int64_t c = 0; c < trim_chunks(h.l); ++c) {
+        const int64_t r0 = c * TRIM_CHUNK;
+        TrimChunk ch{};
+        ch.V = V + r0 * k;
+        ch.rows = std::min<int64_t>(TRIM_CHUNK, h.l - r0);
+        ch.out = tg;
+        ch.k = k;
+        out.push_back(ch);
+        tg += int64_t(k) * k;
+      }
+    }
+  }
+}
+
 namespace {
 
 // Launch one group (chunked by workspace size) on `stream`.
-tk_status launch_group(tk_tree* t, Lane* lane, Group& gr, const StitchArgs& base, hipStream_t stream) {
+tk_status launch_group(tk_tree* t, Lane* lane, const Plan* plan, Group& gr, const StitchArgs& base,
+                       hipStream_t stream) {
   const int64_t nj = int64_t(gr.jobs.size());
   if (nj == 0) return TK_OK;
   const size_t lds_bytes = size_t(gr.lds_doubles) * 8;
@@ -346,6 +385,15 @@ tk_status launch_group(tk_tree* t, Lane* lane, Group& gr, const StitchArgs& base
     st = ensure(t, djobs, int64_t(chunk.size() * sizeof(Job)), "jobs");
     if (st) return st;
     TK_HIP(t, hipMemcpyAsync(djobs->p, chunk.data(), chunk.size() * sizeof(Job), hipMemcpyHostToDevice, stream));
+    std::vector<TrimChunk> trims;
+    trim_chunks_of(t, *plan, gr, i0, i1, ws->p, trims);
+    if (!trims.empty()) {  // the trim pass: row Grams of the long partial hits
+      st = ensure(t, &lane->trims[gr.bin], int64_t(trims.size() * sizeof(TrimChunk)), "trim chunks");
+      if (st) return st;
+      TK_HIP(t, hipMemcpyAsync(lane->trims[gr.bin].p, trims.data(), trims.size() * sizeof(TrimChunk),
+                               hipMemcpyHostToDevice, stream));
+      TK_HIP(t, launch_trim(reinterpret_cast<const TrimChunk*>(lane->trims[gr.bin].p), int64_t(trims.size()), stream));
+    }
     StitchArgs a = base;
     a.jobs = reinterpret_cast<const Job*>(djobs->p);
     a.ws = ws->p;
@@ -383,7 +431,7 @@ tk_status run_plan(tk_tree* t, Lane* lane, Plan& plan, int max_iter, double tol,
   base.hits = reinterpret_cast<Hit*>(lane->hits.p);
   if (!fork || plan.groups.size() <= 1) {
     for (Group& gr : plan.groups) {
-      st = launch_group(t, lane, gr, base, lane->stream);
+      st = launch_group(t, lane, &plan, gr, base, lane->stream);
       if (st) return st;
     }
     return TK_OK;
@@ -399,7 +447,7 @@ tk_status run_plan(tk_tree* t, Lane* lane, Plan& plan, int max_iter, double tol,
     }
     if (!used[sl]) TK_HIP(t, hipStreamWaitEvent(lane->gstream[sl], lane->fork_ev, 0));
     used[sl] = true;
-    st = launch_group(t, lane, gr, base, lane->gstream[sl]);
+    st = launch_group(t, lane, &plan, gr, base, lane->gstream[sl]);
     if (st) return st;
   }
   // join only after every group is queued (a join between launches would
@@ -467,17 +515,21 @@ tk_status run_leaves(tk_tree* t, Lane* lane, int64_t first_block, int64_t nb, co
 
 }  // namespace
 
-tk_status commit_blocks(tk_tree* t, Lane* lane, int64_t nb, const float* Xdev) {
+tk_status commit_blocks(tk_tree* t, Lane* lane, int64_t nb, const float* Xdev, hipEvent_t* lev_ev, int n_ev) {
   const int64_t b0 = t->Tb, b1 = t->Tb + nb;
   tk_status st = run_leaves(t, lane, b0, nb, Xdev);
   if (st) return st;
+  if (lev_ev && n_ev > 0) TK_HIP(t, hipEventRecord(lev_ev[0], lane->stream));
   const int K = root_level(b1);
   int64_t merges = 0;
   for (int k = 1; k <= K; ++k) {
     // nodes (k, j) with (j+1) 2^k in (b0, b1]
     const int64_t jlo = b0 >> k;
     const int64_t jhi = (b1 >> k) - 1;
-    if (jhi < jlo) continue;
+    if (jhi < jlo) {
+      if (lev_ev && k < n_ev) TK_HIP(t, hipEventRecord(lev_ev[k], lane->stream));
+      continue;
+    }
     std::vector<Job> jobs;
     std::vector<Hit> hits;
     for (int64_t j = jlo; j <= jhi; ++j) make_merge_job(t, k, j, jobs, hits);
@@ -488,6 +540,7 @@ tk_status commit_blocks(tk_tree* t, Lane* lane, int64_t nb, const float* Xdev) {
     // one level's merges share a shape; groups run in order on the lane
     st = run_plan(t, lane, plan, t->cfg.max_iter, t->cfg.tol, false);
     if (st) return st;
+    if (lev_ev && k < n_ev) TK_HIP(t, hipEventRecord(lev_ev[k], lane->stream));
   }
   t->Tb = b1;
   t->merges_total += merges;

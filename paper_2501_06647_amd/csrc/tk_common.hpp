@@ -217,7 +217,7 @@ struct Job {
   int32_t kind;  // 0 query (Recall on the device), 1 merge, 2 query on host-planned hits
   int32_t s;     // hits
   int32_t hit0;  // first hit in the launch's hit array
-  int32_t pad0;
+  int32_t pretrim;  // 1: the trims' row Grams were summed by trim_gram_kernel into the workspace (TG)
   int64_t L;
   int64_t ts;        // query range [ts, ts + L)
   int64_t Tb;        // committed leaf blocks seen by the query
@@ -253,6 +253,22 @@ enum {
   STAT_EIG_TRI = 23, STAT_EIG_INVIT = 24, STAT_COUNT = 26
 };
 
+// Rows of a partial hit's temporal factor per chunk of the trim pass: each
+// chunk's Gram is summed by one workgroup of trim_gram_kernel, and the stitch
+// kernel adds the chunk Grams in chunk order.
+constexpr int64_t TRIM_CHUNK = 1024;
+TK_HD int64_t trim_chunks(int64_t l) { return (l + TRIM_CHUNK - 1) / TRIM_CHUNK; }
+
+// One chunk of the trim pass: the Gram (FP64, both triangles) of rows
+// [0, rows) of V (k floats per row) into out (k x k).
+struct TrimChunk {
+  const float* V;
+  int64_t rows;
+  double* out;
+  int32_t k;
+  int32_t pad;
+};
+
 // ---------------------------------------------------------------------------
 // Workspace layout of a stitch job (bump allocation, 256-byte aligned), used
 // by the host to size the workspace and by the kernel to find its buffers.
@@ -269,7 +285,6 @@ struct StitchLayout {
   int64_t Pd[MAXP];           // double D_n x rq_n  ([0]: sk x rq_0)
   int64_t Pf[MAXP];           // float  same
   int64_t Fh[MAXP];           // double sr_n x rq_n
-  int64_t Tinv[MAXP];         // double triangular-inverse scratch of pchol_basis: [0] kmax^2 (trims), [n] sr_n^2 (bases)
   int64_t M;                  // float sk x Rhat_0
   int64_t K;                  // float max_n D_n Rhat_n
   int64_t WS;                 // float max_n sr_n Rhat_n (stacked W_i^(n))
@@ -278,6 +293,7 @@ struct StitchLayout {
   int64_t S;                  // double 32 x 32 (mode Gram of one core)
   int64_t G;                  // float prod(rq)
   int64_t G64;                // double prod(rq)
+  int64_t TG;                 // double: per partial hit, ceil(l / TRIM_CHUNK) partial k x k Grams (pretrim only)
   int64_t TMP;                // double eig_tmp_doubles(neig) (eigensolver / Cholesky scratch)
   int64_t EIG;                // double eig_doubles(neig) (only when neig > n_lds)
   int64_t total;
@@ -295,8 +311,8 @@ TK_HD int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 // size; the layout reserves that much scratch (in D1).  ntiles <= 36 for
 // ranks <= 32, so ntiles * split <= GRAM_ROWS_TILES.
 constexpr int GRAM_ROWS_TILES = 64;
-TK_HD int gram_rows_split(int ntiles, int nthreads) {
-  const int cap = nthreads < GRAM_ROWS_TILES ? nthreads : GRAM_ROWS_TILES;
+TK_HD int gram_rows_split(int ntiles, int nthreads, int max_parts = GRAM_ROWS_TILES) {
+  const int cap = nthreads < max_parts ? nthreads : max_parts;
   const int s = cap / ntiles;
   return s > 0 ? s : 1;
 }
@@ -318,7 +334,7 @@ TK_HD int64_t eig_tmp_doubles(int64_t n) { return n * (n > 4 * 32 ? n : 4 * 32);
 
 // The layout record itself occupies the head of the job's workspace.
 TK_HD void stitch_layout(const StoreView& st, const Hit* hits, int s, const int32_t* rq,
-                         int n_lds, StitchLayout* Lo) {
+                         int n_lds, StitchLayout* Lo, int pretrim = 0) {
   const int p = st.p;
   int64_t off = align256(int64_t(sizeof(StitchLayout)));
   auto take = [&](int64_t bytes) {
@@ -368,7 +384,6 @@ TK_HD void stitch_layout(const StoreView& st, const Hit* hits, int s, const int3
     Lo->Pd[n] = take(int64_t(Lo->qmax[n]) * rq[n] * 8);
     Lo->Pf[n] = take(int64_t(Lo->qmax[n]) * rq[n] * 4);
     Lo->Fh[n] = take(int64_t(Lo->sr[n]) * rq[n] * 8);
-    Lo->Tinv[n] = take(int64_t(Lo->sr[n]) * Lo->sr[n] * 8);
     if (Lo->sr[n] > neig) neig = Lo->sr[n];
     if (Lo->qmax[n] > neig) neig = Lo->qmax[n];
     const int64_t kn = int64_t(Lo->qmax[n]) * Rhat[n];
@@ -378,7 +393,6 @@ TK_HD void stitch_layout(const StoreView& st, const Hit* hits, int s, const int3
   Lo->sr[0] = Lo->sk;
   Lo->Pd[0] = take(int64_t(Lo->sk) * rq[0] * 8);
   Lo->Pf[0] = take(int64_t(Lo->sk) * rq[0] * 4);
-  Lo->Tinv[0] = take(int64_t(maxk) * maxk * 8);
   Lo->M = take(int64_t(Lo->sk) * Rhat[0] * 4);
   Lo->K = take(kmax * 4);
   int64_t wmax = 0;
@@ -406,6 +420,11 @@ TK_HD void stitch_layout(const StoreView& st, const Hit* hits, int s, const int3
   Lo->G = take(gel * 4);
   Lo->G64 = take(gel * 8);
   Lo->neig = neig;
+  int64_t tg = 0;
+  if (pretrim)
+    for (int i = 0; i < s; ++i)
+      if (hits[i].partial) tg += trim_chunks(hits[i].l) * int64_t(st.rk[hits[i].level][0]) * st.rk[hits[i].level][0];
+  Lo->TG = pretrim ? take(tg * 8) : -1;
   Lo->TMP = take(eig_tmp_doubles(neig) * 8);
   Lo->EIG = neig > n_lds ? take(eig_doubles(neig) * 8) : -1;
   Lo->total = off;

@@ -512,13 +512,13 @@ __device__ __forceinline__ void gram_mode_bf16(const float* __restrict__ X, int6
 // Gram of the rows of a tall, narrow matrix: G = V^T V for V (l x k,
 // row-major), FP64 accumulation, k <= 32.  Threads split the rows; each owns
 // a 4 x 4 tile of G for its share of rows, and the partial tiles are summed
-// through part (ntiles x nsplit x 16 doubles, at most GRAM_ROWS_TILES x 16,
-// for any workgroup size).
+// through part (ntiles x nsplit x 16 doubles, at most max_parts x 16, for
+// any workgroup size).
 __device__ __forceinline__ void gram_rows(const float* __restrict__ V, int64_t l, int k, double* __restrict__ G,
-                                          int ld, double* __restrict__ part) {
+                                          int ld, double* __restrict__ part, int max_parts = GRAM_ROWS_TILES) {
   const int nb = (k + 3) / 4;
   const int ntiles = nb * (nb + 1) / 2;
-  const int nsplit = gram_rows_split(ntiles, int(blockDim.x));
+  const int nsplit = gram_rows_split(ntiles, int(blockDim.x), max_parts);
   for (int w = threadIdx.x; w < ntiles * nsplit; w += blockDim.x) {
     const int t = w % ntiles, sp = w / ntiles;
     int bi = 0, rem = t;
@@ -676,21 +676,22 @@ __device__ __forceinline__ void orthonormalize(double* E, int n, int k, int64_t 
 // Pivoted Cholesky
 // ---------------------------------------------------------------------------
 
-// Pivoted Cholesky of a symmetric positive semi-definite m x m matrix G
-// (row-major, leading dimension m): P^T G P = L L^T with the pivot taken as
-// the largest remaining diagonal (outer-product Cholesky with diagonal
-// pivoting, Golub & Van Loan); it stops when that diagonal is at most tau
-// times the largest initial one.  L: m x m row-major (row i belongs to pivot
-// position i; columns < q hold the factor).  piv: m ints; d: m doubles of
-// scratch.  Returns the rank q.
-__device__ __forceinline__ int pchol(const double* G, int m, double tau, double* L, int* piv, double* d, double* red,
-                     int* redi) {
+// Pivoted Cholesky in place (right-looking, symmetric pivoting by swapping
+// rows and columns; Golub & Van Loan's outer-product form): G (m x m,
+// row-major, symmetric, both triangles valid) is overwritten so that its
+// lower triangle holds L with P^T G P = L L^T (row and column i belong to
+// pivot position i; piv[i] is the original index), the pivot being the
+// largest remaining diagonal; it stops when that diagonal is at most tau
+// times the largest initial one and returns that rank q (columns >= q of L
+// are not a factor).  Every step touches only the trailing block, four
+// entries per round with their loads issued first, so the factorisation
+// stays wherever G is (LDS for the sizes that matter).
+__device__ __forceinline__ int pchol_inplace(double* G, int m, double tau, int* piv, double* red, int* redi) {
   const int tid = threadIdx.x, nt = blockDim.x;
   double dmax0 = 0.0;
   for (int i = tid; i < m; i += nt) {
-    d[i] = G[int64_t(i) * m + i];
     piv[i] = i;
-    dmax0 = fmax(dmax0, d[i]);
+    dmax0 = fmax(dmax0, G[int64_t(i) * m + i]);
   }
   int dummy = 0;
   block_argmax(dmax0, dummy, red, redi);
@@ -700,7 +701,7 @@ __device__ __forceinline__ int pchol(const double* G, int m, double tau, double*
     double bv = -1.0;
     int bi = m;
     for (int i = j + tid; i < m; i += nt) {
-      const double v = d[piv[i]];
+      const double v = G[int64_t(i) * m + i];
       if (v > bv || (v == bv && i < bi)) {
         bv = v;
         bi = i;
@@ -711,29 +712,56 @@ __device__ __forceinline__ int pchol(const double* G, int m, double tau, double*
       q = j;
       break;
     }
-    // move pivot position bi to j, with the rows of L computed so far
-    for (int t = tid; t < j; t += nt) {
-      const double x = L[int64_t(j) * m + t];
-      L[int64_t(j) * m + t] = L[int64_t(bi) * m + t];
-      L[int64_t(bi) * m + t] = x;
+    if (bi != j) {  // rows j and bi (every column), then columns j and bi (every row)
+      for (int c = tid; c < m; c += nt) {
+        const double x = G[int64_t(j) * m + c];
+        G[int64_t(j) * m + c] = G[int64_t(bi) * m + c];
+        G[int64_t(bi) * m + c] = x;
+      }
+      __syncthreads();
+      for (int r = tid; r < m; r += nt) {
+        const double x = G[int64_t(r) * m + j];
+        G[int64_t(r) * m + j] = G[int64_t(r) * m + bi];
+        G[int64_t(r) * m + bi] = x;
+      }
+      if (tid == 0) {
+        const int x = piv[j];
+        piv[j] = piv[bi];
+        piv[bi] = x;
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    if (tid == 0) {
-      const int x = piv[j];
-      piv[j] = piv[bi];
-      piv[bi] = x;
-      L[int64_t(j) * m + j] = sqrt(bv);
-    }
-    __syncthreads();
     const double ljj = sqrt(bv);
-    const int pj = piv[j];
+    const double inv = 1.0 / ljj;
     for (int i = j + 1 + tid; i < m; i += nt) {
-      const int pi = piv[i];
-      double s = G[int64_t(pi) * m + pj];
-      for (int t = 0; t < j; ++t) s -= L[int64_t(i) * m + t] * L[int64_t(j) * m + t];
-      const double l = s / ljj;
-      L[int64_t(i) * m + j] = l;
-      d[pi] -= l * l;
+      const double l = G[int64_t(i) * m + j] * inv;
+      G[int64_t(i) * m + j] = l;
+      G[int64_t(j) * m + i] = l;
+    }
+    if (tid == 0) G[int64_t(j) * m + j] = ljj;
+    __syncthreads();
+    // trailing update G[i][k] -= L[i][j] L[k][j] over the whole block (it stays symmetric)
+    const int mm = m - j - 1;
+    const int tot = mm * mm;
+    int e = tid;
+    for (; e + 3 * nt < tot; e += 4 * nt) {
+      int ii[4], kk[4];
+      double g[4], li[4], lk[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int eu = e + u * nt;
+        ii[u] = j + 1 + eu / mm;
+        kk[u] = j + 1 + eu % mm;
+        g[u] = G[int64_t(ii[u]) * m + kk[u]];
+        li[u] = G[int64_t(ii[u]) * m + j];
+        lk[u] = G[int64_t(kk[u]) * m + j];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) G[int64_t(ii[u]) * m + kk[u]] = g[u] - li[u] * lk[u];
+    }
+    for (; e < tot; e += nt) {
+      const int i = j + 1 + e / mm, k = j + 1 + e % mm;
+      G[int64_t(i) * m + k] -= G[int64_t(i) * m + j] * G[int64_t(k) * m + j];
     }
     __syncthreads();
   }
@@ -741,33 +769,47 @@ __device__ __forceinline__ int pchol(const double* G, int m, double tau, double*
   return q;
 }
 
-// From a pivoted Cholesky factor (L, piv, rank q) of the Gram V^T V of a
-// matrix V with m columns, write the coordinates C (q x m, leading dimension
-// ldc) of V's columns in the orthonormal basis B = V P [L11^{-T}; 0], i.e.
-// C = B^T V = L^T P^T, and F (m x q, leading dimension ldf) with B = V F.
-// Tinv: q x q doubles of scratch (L11^{-1}).
+// From pchol_inplace's result (L in the lower triangle of G, piv, rank q)
+// for the Gram V^T V of a matrix V with m columns: the coordinates C (q x m,
+// leading dimension ldc) of V's columns in the orthonormal basis
+// B = V P [L11^{-T}; 0], C = B^T V = L^T P^T, then F (m x q, leading
+// dimension ldf) with B = V F.  L11^{-1} overwrites L11 in place, column by
+// column from the last (each a triangular product with the columns already
+// inverted, rows in parallel); col: m doubles of scratch.
 template <typename TC>
-__device__ __forceinline__ void pchol_basis(const double* L, const int* piv, int m, int q, TC* C, int ldc, double* F, int ldf,
-                            double* Tinv) {
+__device__ __forceinline__ void pchol_basis_inplace(double* G, const int* piv, int m, int q, TC* C, int ldc, double* F,
+                                                    int ldf, double* col) {
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int e = tid; e < q * m; e += nt) {
     const int j = e / m, c = e % m;
-    C[int64_t(j) * ldc + piv[c]] = TC(c >= j ? L[int64_t(c) * m + j] : 0.0);
-  }
-  // T = L11^{-1} (lower triangular), one column per thread
-  for (int c = tid; c < q; c += nt) {
-    for (int i = 0; i < q; ++i) Tinv[int64_t(i) * q + c] = 0.0;
-    Tinv[int64_t(c) * q + c] = 1.0 / L[int64_t(c) * m + c];
-    for (int i = c + 1; i < q; ++i) {
-      double s = 0.0;
-      for (int t = c; t < i; ++t) s += L[int64_t(i) * m + t] * Tinv[int64_t(t) * q + c];
-      Tinv[int64_t(i) * q + c] = -s / L[int64_t(i) * m + i];
-    }
+    C[int64_t(j) * ldc + piv[c]] = TC(c >= j ? G[int64_t(c) * m + j] : 0.0);
   }
   __syncthreads();
+  for (int j = q - 1; j >= 0; --j) {
+    for (int i = j + tid; i < q; i += nt) col[i] = G[int64_t(i) * m + j];
+    __syncthreads();
+    const double djj = 1.0 / col[j];
+    for (int i = j + 1 + tid; i < q; i += nt) {
+      // T[i][j] = -T[j][j] sum_{t=j+1..i} T[i][t] L[t][j]  (columns > j already hold T)
+      const double* Ti = G + int64_t(i) * m;
+      double acc = 0.0;
+      int t = j + 1;
+      for (; t + 3 <= i; t += 4) {
+        const double a0 = Ti[t], a1 = Ti[t + 1], a2 = Ti[t + 2], a3 = Ti[t + 3];
+        acc += a0 * col[t];
+        acc += a1 * col[t + 1];
+        acc += a2 * col[t + 2];
+        acc += a3 * col[t + 3];
+      }
+      for (; t <= i; ++t) acc += Ti[t] * col[t];
+      G[int64_t(i) * m + j] = -djj * acc;
+    }
+    if (tid == 0) G[int64_t(j) * m + j] = djj;
+    __syncthreads();
+  }
   for (int e = tid; e < m * q; e += nt) {
     const int c = e / q, j = e % q;
-    F[int64_t(piv[c]) * ldf + j] = c < q ? Tinv[int64_t(j) * q + c] : 0.0;
+    F[int64_t(piv[c]) * ldf + j] = (c < q && j >= c) ? G[int64_t(j) * m + c] : 0.0;
   }
   __syncthreads();
 }

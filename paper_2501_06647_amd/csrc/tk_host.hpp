@@ -74,7 +74,7 @@ struct Lane {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   DevBuf hits, stats, queue;
-  DevBuf ws[kMaxGroups], jobs[kMaxGroups];
+  DevBuf ws[kMaxGroups], jobs[kMaxGroups], trims[kMaxGroups];
   DevBuf leaf_ws, leaf_jobs, xbuf;
   hipStream_t gstream[kMaxGroups] = {};
   hipEvent_t gev[kMaxGroups] = {};
@@ -173,7 +173,18 @@ void make_merge_job(tk_tree* t, int k, int64_t j, std::vector<Job>& jobs, std::v
 
 // Group jobs by LDS bin under the tree's tuning, sort each group heaviest
 // first and lay out its workspace.
-tk_status plan_stitch(tk_tree* t, std::vector<Job>& jobs, std::vector<Hit>& hits, Plan* plan);
+// Group and order stitch jobs (see tk_capi.hip).  With pretrim (prepared
+// batches), query jobs whose partial hits hold at least kPretrimRows rows
+// get their trims' row Grams from the trim pass (which the launcher of the
+// plan then runs, trim_chunks_of + launch_trim, before the group's stitch
+// launch); its chunked sums round differently from the stitch kernel's own,
+// so those queries may differ from tk_query in the last bits.
+tk_status plan_stitch(tk_tree* t, std::vector<Job>& jobs, std::vector<Hit>& hits, Plan* plan, bool pretrim = false);
+constexpr int64_t kPretrimRows = 2048;
+// The trim-pass chunks of jobs [i0, i1) of a group whose workspace chunk
+// starts at job i0's offset and lives at ws_base.
+void trim_chunks_of(const tk_tree* t, const Plan& plan, const Group& gr, int64_t i0, int64_t i1, char* ws_base,
+                    std::vector<TrimChunk>& out);
 
 // Issue a plan on a lane: hits and jobs uploaded, groups launched (forked
 // onto group streams when fork is set and there are several groups), the
@@ -183,7 +194,11 @@ tk_status run_plan(tk_tree* t, Lane* lane, Plan& plan, int max_iter, double tol,
 
 // Leaves for blocks [Tb, Tb + nb) from device data, then every merge they
 // complete, level by level, on the lane.  Updates Tb and the merge counts.
-tk_status commit_blocks(tk_tree* t, Lane* lane, int64_t nb, const float* Xdev);
+// Commit nb leaf blocks (leaves, then merges level by level) on the lane's
+// stream.  With lev_ev, event lev_ev[k] is recorded once the nodes of level
+// k are written, for k <= the new root level (and < n_ev).
+tk_status commit_blocks(tk_tree* t, Lane* lane, int64_t nb, const float* Xdev, hipEvent_t* lev_ev = nullptr,
+                        int n_ev = 0);
 
 StitchArgs stitch_args(tk_tree* t, int max_iter, double tol);
 // Output ranks of a query of length len (tk_set_query_ranks, clipped).

@@ -80,6 +80,8 @@ struct RawArgs {
 // than n_jobs and the queue counter must read 0 at launch (reset_queue).
 hipError_t launch_stitch(const StitchArgs& a, int grid, size_t lds_bytes, int threads, hipStream_t stream);
 hipError_t launch_reset_queue(int* queue, int n, hipStream_t stream);
+// the trim pass over n chunks (trim_gram_kernel)
+hipError_t launch_trim(const TrimChunk* chunks, int64_t n, hipStream_t stream);
 
 // Entry points of the stitch kernel's instantiations (block size x mode
 // count: 64/128/256 threads, trees of at most 4 or at most MAXP modes), one

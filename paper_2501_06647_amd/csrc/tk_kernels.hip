@@ -14,6 +14,19 @@ __global__ void reset_queue_kernel(int* queue, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) queue[i] = 0;
 }
 
+// The trim pass: one workgroup per chunk of a partial hit's rows, the
+// chunk's FP64 Gram summed with every thread of the workgroup (a stitch job
+// would stream these rows through one wavefront, a memory round trip per
+// few rows).  The stitch kernel adds a hit's chunk Grams in chunk order.
+constexpr int NT_TRIM = 256;
+__global__ __launch_bounds__(NT_TRIM) void trim_gram_kernel(const TrimChunk* __restrict__ chunks, int64_t n) {
+  __shared__ double part[NT_TRIM * 16];
+  for (int64_t c = blockIdx.x; c < n; c += gridDim.x) {
+    const TrimChunk ch = chunks[c];
+    gram_rows(ch.V, ch.rows, ch.k, ch.out, ch.k, part, NT_TRIM);
+  }
+}
+
 // ------------------------------------------------------------------------------
 // Leaf: Tucker-ALS of one raw block (Sec. 2), HOSVD initialisation.
 // ------------------------------------------------------------------------------
@@ -164,6 +177,65 @@ __device__ __forceinline__ void als_stats(double* stats, const AlsResult& r) {
   }
 }
 
+// A leaf of one slice of a three-way series (leaf length 1): the temporal
+// mode has length one, so its rank is one, the two other ranks are equal
+// (r_2 <= r_1 r_3 and r_3 <= r_1 r_2), and Tucker-ALS on the slice reaches
+// its truncated SVD: U^(2) the leading r left singular vectors of the D_2 x
+// D_3 slice X, U^(3) = X^T U^(2) diag(1/s) (orthonormalised), the core
+// U^(2)T X U^(3) (diagonal up to rounding), U^(1) = [1].  One eigensolve of
+// the smaller Gram instead of the sweeps.  Leaves the results where
+// block_tucker_als leaves them.
+__device__ __forceinline__ AlsResult slice_svd(const float* X, const int32_t* Dm, int r, int n_lds, double* lds,
+                                               char* ws, const LeafLayout& lo, LeafShared& sh) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int D2 = Dm[1], D3 = Dm[2];
+  double part = 0.0;
+  for (int64_t e = tid; e < int64_t(D2) * D3; e += nt) part += double(X[e]) * double(X[e]);
+  const double nx2 = block_sum(part, sh.red);
+  double* Ud1 = reinterpret_cast<double*>(ws + lo.Ud[1]);
+  double* Ud2 = reinterpret_cast<double*>(ws + lo.Ud[2]);
+  float* Uf0 = reinterpret_cast<float*>(ws + lo.Uf[0]);
+  float* Uf1 = reinterpret_cast<float*>(ws + lo.Uf[1]);
+  float* Uf2 = reinterpret_cast<float*>(ws + lo.Uf[2]);
+  float* G = reinterpret_cast<float*>(ws + lo.G);
+  double* TMP = reinterpret_cast<double*>(ws + lo.TMP);
+  // the smaller side's Gram and its leading eigenvectors
+  const bool left = D2 <= D3;
+  const int n = left ? D2 : D3;
+  double* Wm = n <= n_lds ? lds : reinterpret_cast<double*>(ws + lo.EIG);
+  if (left) gram_mode_mfma(X, 1, D2, D3, Wm, D2);
+  else gram_other(X, 1, D2, D3, Wm, D3);
+  double* Us = left ? Ud1 : Ud2;  // from the eigensolver
+  double* Uo = left ? Ud2 : Ud1;  // the other side, X^T U / s or X V / s
+  const int Do = left ? D3 : D2;
+  const double* lam = eig_top(Wm, n, r, Us, r, sh.red, TMP, nullptr, Wm + int64_t(n) * n);
+  double* sv = sh.coef;  // r <= kMaxRank <= 64
+  for (int j = tid; j < r; j += nt) sv[j] = sqrt(fmax(lam[j], 0.0));
+  __syncthreads();
+  // the other side's vectors: Uo[d][j] = sum_c X(., .) Us[c][j] / s_j
+  gemm_f64(Do, r, n,
+           [&](int d, int c) { return left ? double(X[int64_t(c) * D3 + d]) : double(X[int64_t(d) * D3 + c]); },
+           [&](int c, int j) { return Us[int64_t(c) * r + j]; },
+           [&](int d, int j, double v) { Uo[int64_t(d) * r + j] = sv[j] > 0.0 ? v / sv[j] : 0.0; });
+  orthonormalize(Uo, Do, r, r, 1, sh.coef + 32, sh.red, &sh.flag);
+  // core G = U^(2)T X U^(3) (r x r), FP64 sums
+  double* XU3 = TMP;  // D2 x r
+  gemm_f64(D2, r, D3, [&](int i, int c) { return double(X[int64_t(i) * D3 + c]); },
+           [&](int c, int j) { return Ud2[int64_t(c) * r + j]; }, [&](int i, int j, double v) { XU3[int64_t(i) * r + j] = v; });
+  part = 0.0;
+  gemm_f64(r, r, D2, [&](int a, int i) { return Ud1[int64_t(i) * r + a]; },
+           [&](int i, int j) { return XU3[int64_t(i) * r + j]; },
+           [&](int a, int j, double v) { G[a * r + j] = float(v); });
+  for (int e = tid; e < r * r; e += nt) part += double(G[e]) * double(G[e]);
+  const double g2 = block_sum(part, sh.red);
+  for (int64_t e = tid; e < int64_t(D2) * r; e += nt) Uf1[e] = float(Ud1[e]);
+  for (int64_t e = tid; e < int64_t(D3) * r; e += nt) Uf2[e] = float(Ud2[e]);
+  if (tid == 0) Uf0[0] = 1.0f;
+  __syncthreads();
+  const double fit = nx2 > 0.0 ? 1.0 - sqrt(fmax(0.0, nx2 - g2)) / sqrt(nx2) : 1.0;
+  return AlsResult{fit, nx2, g2, 1, 1};
+}
+
 __global__ __launch_bounds__(NT_LEAF, 2) void leaf_kernel(LeafArgs args) {
   extern __shared__ double lds[];
   __shared__ LeafShared sh;
@@ -178,7 +250,9 @@ __global__ __launch_bounds__(NT_LEAF, 2) void leaf_kernel(LeafArgs args) {
   int32_t Dm[MAXP];
   Dm[0] = int32_t(st.ell);
   for (int n = 1; n < p; ++n) Dm[n] = int32_t(st.D[n]);
-  const AlsResult r = block_tucker_als(job.X, Dm, rq, p, 0, args.max_iter, args.tol, args.n_lds, lds, ws, lo, sh);
+  const bool svd = p == 3 && st.ell == 1 && rq[0] == 1 && rq[1] == rq[2];
+  const AlsResult r = svd ? slice_svd(job.X, Dm, rq[1], args.n_lds, lds, ws, lo, sh)
+                          : block_tucker_als(job.X, Dm, rq, p, 0, args.max_iter, args.tol, args.n_lds, lds, ws, lo, sh);
   // store the leaf: core, non-temporal factors, temporal rows
   const int64_t b = job.block;
   const float* G = reinterpret_cast<const float*>(ws + lo.G);
@@ -225,6 +299,13 @@ hipError_t launch_stitch(const StitchArgs& a, int grid, size_t lds_bytes, int th
     case 256: return few ? stitch_launch_256_4(a, grid, lds_bytes, stream) : stitch_launch_256_7(a, grid, lds_bytes, stream);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_trim(const TrimChunk* chunks, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const int64_t grid = n < (int64_t(1) << 20) ? n : (int64_t(1) << 20);
+  hipLaunchKernelGGL(trim_gram_kernel, dim3(unsigned(grid)), dim3(NT_TRIM), 0, stream, chunks, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_reset_queue(int* queue, int n, hipStream_t stream) {

@@ -129,7 +129,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
   clk.start();
   // the layout record lives at the head of the workspace
   StitchLayout* lop = reinterpret_cast<StitchLayout*>(ws);
-  if (tid == 0) stitch_layout(st, hits, s, rq, n_lds, lop);
+  if (tid == 0) stitch_layout(st, hits, s, rq, n_lds, lop, job.pretrim);
   __threadfence_block();
   __syncthreads();
   const StitchLayout& lo = *lop;
@@ -185,21 +185,9 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     return lds_doubles - used;
   };
 
-  // A pivoted Cholesky of an m x m Gram keeps its factor and the triangular
-  // inverse of pchol_basis in LDS when both fit behind what the buffer
-  // already holds (the Gram with its pivot data, or nothing when the Gram
-  // lives in the workspace), else in the workspace: the factorisation's
-  // steps are serial, and each round trip to LDS is far shorter.
-  auto chol_lds_used = [&](int m) -> int64_t { return int64_t(m) * m + m + (m + 1) / 2 + 1; };
-  auto lds_scratch = [&](int64_t used, int m, double** Lx, double** Tx) {
-    if (used + 2 * int64_t(m) * m <= lds_doubles) {
-      *Lx = lds + used;
-      *Tx = lds + used + int64_t(m) * m;
-    }
-  };
-
   // ---- trims (Eq. "partial-tucker") and |Y~|^2 ------------------------------
   double ny2 = 0.0;
+  int64_t tg_off = 0;  // this hit's chunk Grams in TG (pretrim)
   for (int i = 0; i < s; ++i) {
     const Hit h = hits[i];
     const int lev = h.level;
@@ -219,14 +207,23 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     float* Rt = Fp(lo.T1);  // R~, kp x k
     int kp = 0;
     with_buf(k, [&](double* Gm, double*) {
-      gram_rows(V, h.l, k, Gm, k, Dp(lo.D1));
-      double* d = Gm + k * k;
+      if (job.pretrim) {  // the trim pass summed the rows' Gram by chunks: add them in order
+        const double* P = Dp(lo.TG) + tg_off;
+        const int64_t nc = trim_chunks(h.l);
+        for (int e = tid; e < k * k; e += nt) {
+          double acc = 0.0;
+          for (int64_t c = 0; c < nc; ++c) acc += P[c * k * k + e];
+          Gm[e] = acc;
+        }
+        __syncthreads();
+        tg_off += nc * k * k;
+      } else {
+        gram_rows(V, h.l, k, Gm, k, Dp(lo.D1));
+      }
+      double* col = Gm + k * k;
       int* piv = reinterpret_cast<int*>(Gm + k * k + k);
-      double* Lx = TMP;
-      double* Tx = Dp(lo.Tinv[0]);
-      lds_scratch(k <= n_lds ? chol_lds_used(k) : 0, k, &Lx, &Tx);
-      kp = pchol(Gm, k, 1e-12, Lx, piv, d, red, sh.redi);
-      pchol_basis<float>(Lx, piv, k, kp, Rt, k, Dp(lo.F[i]), k, Tx);
+      kp = pchol_inplace(Gm, k, 1e-12, piv, red, sh.redi);
+      pchol_basis_inplace<float>(Gm, piv, k, kp, Rt, k, Dp(lo.F[i]), k, col);
     });
     float* Ht = Fp(lo.Ht[i]);
     mode_product(H, 1, k, R, Rt, k, 1, kp, Ht, false);
@@ -287,15 +284,12 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
           if (y < x) Gm[e] = Gm[y * sr + x];
         }
         __syncthreads();
-        double* d = Gm + sr * sr;
+        double* col = Gm + sr * sr;
         int* piv = reinterpret_cast<int*>(Gm + sr * sr + sr);
-        double* Lx = TMP;
-        double* Tx = Dp(lo.Tinv[n]);
-        lds_scratch(sr <= n_lds ? chol_lds_used(sr) : 0, sr, &Lx, &Tx);
-        const int q = pchol(Gm, sr, 1e-11, Lx, piv, d, red, sh.redi);
+        const int q = pchol_inplace(Gm, sr, 1e-11, piv, red, sh.redi);
         if (q >= rq[n]) {
           use_basis = 1;
-          pchol_basis<double>(Lx, piv, sr, q, C64, sr, Dp(lo.Fn[n]), sr, Tx);
+          pchol_basis_inplace<double>(Gm, piv, sr, q, C64, sr, Dp(lo.Fn[n]), sr, col);
           for (int e = tid; e < q * sr; e += nt) C[e] = float(C64[e]);
           if (tid == 0) sh.q[n] = q;
         }
@@ -615,8 +609,10 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
 // Register budget: at most 256 VGPRs, so that two wavefronts share a SIMD
 // (one job's latency hides behind another's).
 // Claim the next published job of the ring (thread 0): its sequence number,
-// or -1 when the workgroup should stop (stop set, idle too long, launch too
-// old).
+// or -1 when the workgroup should stop: stop set, no job published for
+// idle_ticks, or the launch older than life_ticks (then it ends even with
+// jobs waiting, so that the class's hardware queue also serves the work of
+// other streams; the scheduler relaunches at once).
 __device__ __forceinline__ int64_t ring_claim(const StitchRing& r, uint64_t t_launch) {
   const uint64_t t_idle = wall_clock64();
   for (;;) {

@@ -132,7 +132,7 @@ int main() {
             }
           }
           for (int m = 1; m < st.p; ++m)
-            for (int64_t o : {lo.C[m], lo.C64[m], lo.Pd[m], lo.Pf[m], lo.Fh[m], lo.Tinv[m]}) offs.push_back(o);
+            for (int64_t o : {lo.C[m], lo.C64[m], lo.Pd[m], lo.Pf[m], lo.Fh[m]}) offs.push_back(o);
           for (int64_t o : {lo.Pd[0], lo.Pf[0], lo.M, lo.K, lo.WS, lo.T1, lo.T2, lo.D1, lo.D2, lo.S, lo.G, lo.G64,
                             lo.TMP})
             offs.push_back(o);

@@ -299,14 +299,18 @@ tk_status tk_set_tuning(tk_tree* t, const tk_tuning* in);   /* TK_EINVAL if out 
 
 /* A prepared batch: n range queries planned once at the current committed
  * horizon T_c (the snapshot), job descriptors resident on the device, and
- * (tuning.graph = 1) the launches captured in a HIP graph: per LDS bin one
- * fused stitch kernel that runs Recall (Alg. "recall") on each query's range
- * and snapshot, the partial-hit trims (Eq. "partial-tucker") and the Stitch
- * (Alg. "stitch").  res[0..n-1] are caller-owned and must stay valid until
- * tk_batch_destroy; their core/factor buffers are device buffers sized by
- * tk_query_shape.  Results equal those of tk_query_batch under the same
- * tuning.  Later appends do not change what a batch computes (completed
- * nodes are immutable). */
+ * (tuning.graph = 1) the launches captured in a HIP graph: per LDS bin a
+ * trim pass that sums the row Grams of long partial hits (queries whose
+ * partial hits hold 2048 rows or more) over chunks of 1024 rows with every
+ * thread of many workgroups, then one fused stitch kernel that runs Recall
+ * (Alg. "recall") on each query's range and snapshot, the partial-hit trims
+ * (Eq. "partial-tucker") and the Stitch (Alg. "stitch").  res[0..n-1] are
+ * caller-owned and must stay valid until tk_batch_destroy; their
+ * core/factor buffers are device buffers sized by tk_query_shape.  Results
+ * equal those of tk_query_batch under the same tuning, except for queries
+ * with such long partial hits, whose chunked Gram sums round differently
+ * (last bits; within the parity tolerances).  Later appends do not change
+ * what a batch computes (completed nodes are immutable). */
 typedef struct tk_batch tk_batch;
 tk_status tk_batch_create(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* te,
                           tk_result* res, tk_batch** out);
@@ -351,8 +355,9 @@ tk_status tk_autotune(tk_tree* t, int32_t n, const int64_t* ts, const int64_t* t
  * After tk_serve_start, queries and appends are submitted from any thread
  * and return a ticket at once; a scheduler thread owned by the tree issues
  * them.  A query sees every append submitted before it (its snapshot T_c),
- * even if that append is still being committed: it is admitted once the
- * commit has completed.  Queries are grouped in three size classes by their
+ * even if that append is still being committed: it is admitted once every
+ * node of its hit set has been committed (a query away from the latest
+ * appends does not wait for their commits).  Queries are grouped in three size classes by their
  * largest eigenproblem.  Each class runs a stitch launch whose workgroups
  * (at most max_batch: the class's job slots) take admitted queries one at a
  * time from a job ring in host memory that the device maps; a waiting query

@@ -10,7 +10,10 @@
 //     committed horizon T_c of every append submitted before it).  Completed
 //     nodes never change (Alg. "insert" only fills placeholders), so a query
 //     reads a consistent snapshot while later appends add nodes; it is
-//     admitted once the commits it depends on have completed;
+//     admitted once every node of its hit set (Recall at its snapshot) has
+//     been written (commits record an event per tree level, so a query can
+//     start once the levels it needs are done, before the commit's upper
+//     levels), and a query away from the latest appends never waits;
 //   * queries are grouped into three size classes by their largest
 //     eigenproblem.  Each class has a job ring in host memory that the
 //     device maps, and a stitch launch on the class's stream whose
@@ -19,9 +22,9 @@
 //     soon as its class's ring has a free entry and the class's workspace
 //     has room for it (first fit): it joins the work already running on
 //     the device instead of waiting for a batch to finish.  A launch ends by
-//     itself when its class has been idle for a while, or when it is old
-//     (so the class's hardware queue also serves other work); the scheduler
-//     launches again whenever published jobs are waiting.
+//     itself when its class has been idle for 2 ms, or at 20 ms of age (so
+//     the class's hardware queue also serves other streams' work); the
+//     scheduler launches again whenever published jobs are waiting.
 // A query's result depends only on its range and snapshot: the kernel
 // variant is a function of the query's own eigenproblem size, so a query
 // returns the same bits alone and in any mix.
@@ -41,8 +44,10 @@ namespace tk {
 namespace {
 
 constexpr int kClasses = 3;
-constexpr uint64_t kRingIdleTicks = 200000;   // 2 ms of the device's 100 MHz clock
-constexpr uint64_t kRingLifeTicks = 2000000;  // 20 ms
+constexpr uint64_t kRingIdleTicks = 200000;    // 2 ms of the device's 100 MHz clock
+constexpr uint64_t kRingLifeTicks = 2000000;   // 20 ms: streams outnumber the hardware queues, so a
+                                               // queue that a class's launch holds frees up this often
+                                               // for the append commits queued behind it
 
 double now_us(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
@@ -64,6 +69,7 @@ struct Request {
   int state = REQ_QUEUED;
   int need = 0;  // size of the query's largest eigenproblem
   int64_t seq = -1, slot = -1, ws_off = -1;  // ring position and workspace of an admitted query
+  int64_t Tb_need = 0;  // committed blocks its hit nodes need: max over hits of (index + 1) 2^level
 };
 
 struct ClassLane {
@@ -120,6 +126,13 @@ struct Server {
   int64_t Tb_issued = 0;    // blocks whose commit has been issued
   int64_t Tb_done = 0;      // blocks whose commit has completed
   hipEvent_t commit_ev = nullptr;
+  // per-level progress of the commit in flight: its level-k nodes are
+  // written once lev_ev[k] has passed; Tb_lvl[k] blocks have every node of
+  // levels <= k written (a query waits only for the nodes of its hit set)
+  hipEvent_t lev_ev[MAXLEV] = {};
+  int64_t Tb_lvl[MAXLEV] = {};
+  int lev_count = 0, lev_next = 0;
+  int64_t lev_b1 = 0;
   ClassLane cl[kClasses];
   int bounds[kClasses] = {0, 0, 0};  // class c takes eigenproblems <= bounds[c]
 };
@@ -177,8 +190,12 @@ tk_status issue_appends(Server* s) {
   }
   const int64_t nb = s->rows_staged / ell;
   if (nb > 0) {
-    tk_status st = commit_blocks(t, &s->alane, nb, stage);
+    const int64_t b1 = t->Tb + nb;
+    tk_status st = commit_blocks(t, &s->alane, nb, stage, s->lev_ev, MAXLEV);
     if (st) return st;
+    s->lev_count = root_level(b1) + 1;
+    s->lev_next = 0;
+    s->lev_b1 = b1;
     t->T += nb * ell;
     const int64_t rem = s->rows_staged - nb * ell;
     if (rem > 0)  // keep the partial block's rows at the front (no overlap: rem < ell <= nb ell)
@@ -234,14 +251,29 @@ tk_status issue_queries(Server* s, ClassLane& c) {
   tk_tree* t = s->t;
   const double tl = now_us(s->t0);
   int64_t admitted = 0;
-  while (!c.pending.empty()) {
-    Request* r = c.pending.front();
-    if (r->Tb > s->Tb_done) break;  // its appends are not committed yet (later queries neither)
+  // in arrival order; a query whose hit nodes are not all committed yet
+  // (its range reaches the latest appends) waits without holding back the
+  // queries behind it
+  for (auto it = c.pending.begin(); it != c.pending.end();) {
+    Request* r = *it;
+    bool ready = r->Tb_need <= s->Tb_done;
+    if (!ready) {  // the commit in flight may already have written the levels it needs
+      ready = true;
+      for (const Hit& x : r->hits)
+        if (((x.index + 1) << x.level) > s->Tb_lvl[x.level]) {
+          ready = false;
+          break;
+        }
+    }
+    if (!ready) {
+      ++it;
+      continue;
+    }
     const int64_t slot = c.published % c.slots;
     if (c.slot_req[size_t(slot)]) break;  // the ring is full
     int64_t off = 0;
     if (!ws_alloc(c, r->job.ws_bytes, &off)) break;  // no room in the workspace yet
-    c.pending.pop_front();
+    it = c.pending.erase(it);
     Job jb = r->job;
     jb.hit0 = int32_t(slot * MAXHITS);
     jb.ws_off = off;
@@ -287,11 +319,21 @@ tk_status issue_queries(Server* s, ClassLane& c) {
 
 tk_status poll_completions(Server* s, bool* progress) {
   tk_tree* t = s->t;
+  while (s->lev_next < s->lev_count) {  // levels of the commit in flight, in order
+    const hipError_t e = hipEventQuery(s->lev_ev[s->lev_next]);
+    if (e == hipErrorNotReady) break;
+    if (e != hipSuccess) return fail_dev(t, e, "append commit level");
+    s->Tb_lvl[s->lev_next] = s->lev_b1;
+    s->lev_next += 1;
+    *progress = true;
+  }
   if (s->abusy) {
     const hipError_t e = hipEventQuery(s->aev);
     if (e == hipSuccess) {
       s->abusy = false;
       s->Tb_done = s->Tb_issued;
+      for (int k = 0; k < MAXLEV; ++k) s->Tb_lvl[k] = std::max(s->Tb_lvl[k], s->Tb_done);
+      s->lev_next = s->lev_count;
       for (Request* r : s->ainflight) finish(s, r, REQ_DONE);
       s->ainflight.clear();
       *progress = true;
@@ -385,6 +427,8 @@ void server_free(Server* s) {
   }
   if (s->aev) (void)hipEventDestroy(s->aev);
   if (s->commit_ev) (void)hipEventDestroy(s->commit_ev);
+  for (hipEvent_t ev : s->lev_ev)
+    if (ev) (void)hipEventDestroy(ev);
   for (Request* r : s->reqs) delete r;
   delete s;
 }
@@ -439,6 +483,11 @@ tk_status tk_serve_start(tk_tree* t, const tk_serve_config* cfg) {
   if ((e = hipEventCreateWithFlags(&s->aev, hipEventDisableTiming)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&s->commit_ev, hipEventDisableTiming)) != hipSuccess)
     return bail(fail_dev(t, e, "serve: events"));
+  for (int k = 0; k < MAXLEV; ++k) {
+    if ((e = hipEventCreateWithFlags(&s->lev_ev[k], hipEventDisableTiming)) != hipSuccess)
+      return bail(fail_dev(t, e, "serve: level events"));
+    s->Tb_lvl[k] = t->Tb;
+  }
   // size classes: small and medium narrow jobs, then wide ones
   const int cap = lds_cap(t);
   const int thr = t->tuning.wide_threshold < cap ? t->tuning.wide_threshold : cap;
@@ -571,6 +620,7 @@ tk_status tk_submit_query(tk_tree* t, int64_t ts, int64_t te, tk_result* res, ui
   r->ts = ts;
   r->te = te;
   r->Tb = Tb;
+  for (const Hit& h : r->hits) r->Tb_need = std::max(r->Tb_need, (h.index + 1) << h.level);
   r->res = res;
   r->ticket = uint64_t(s->reqs.size()) + 1;
   r->t_submit = now_us(s->t0);

@@ -24,18 +24,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3     # MI355X dense FP32 (MFMA and packed vector)
+PEAK_BF16_TFLOPS = 2500.0    # MI355X dense BF16 MFMA
 HBM_TBPS = 8.0
 
-# HBM bytes per step of the plain workload's stitch launches, from two
-# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE per dispatch, summed over the
-# step's launches) scaled by the counters of a 1 GiB reference copy (FETCH
-# reads half the bytes moved, WRITE all of them); valid only for the kernel
-# sources they were taken with.
-TRAFFIC_KERNEL_SHA = "e1f56f3943b2a678"
-TRAFFIC_BYTES_PER_STEP = {"plain": {"fetch": 1068.3e6, "write": 950.4e6,
-                                    "tuning": {"wide_threshold": 32, "wide_threads": 128, "persistent": 0, "graph": 1,
-                                               "coarse": 1, "lds_n": 64, "basis_pct": 75, "rest_threads": 256}}}
-KERNEL_SOURCES = ("tk_common.hpp", "tk_device.hpp", "tk_internal.hpp", "tk_kernels.hip")
+# HBM bytes per step of a workload's stitch launches, from two rocprofv3
+# --pmc runs (FETCH_SIZE, WRITE_SIZE per dispatch, summed over the step's
+# launches) scaled by the counters of a reference copy of known size
+# (`--copy-calibration`); keyed by (workload, precision) and valid only for
+# the kernel sources (sha) they were taken with.
+TRAFFIC_BYTES_PER_STEP = {}
+KERNEL_SOURCES = ("tk_common.hpp", "tk_device.hpp", "tk_internal.hpp", "tk_kernels.hip", "tk_stitch.hpp",
+                  "tk_stitch_inst.hip")
 
 
 def kernel_sha():
@@ -90,40 +89,51 @@ def blas_threads():
 
 
 def serve_main(args):
-    """Serving run: a prefix of the stream is built, then slices are appended
-    at a steady rate while range queries arrive as a Poisson process, each
-    over a log-uniform length inside the horizon committed so far; the
-    library's scheduler admits and batches them.  Reports queries/s and
-    p50/p99 latency (submission to completion, host clock)."""
+    """Serving run: a short prefix of the stream is built, then slices are
+    appended at a steady rate while range queries arrive as a Poisson
+    process, each over a log-uniform length inside the horizon committed
+    when it is submitted; the library's scheduler admits them into the
+    running work as job slots and workspace free up.  Reports queries/s and
+    p50/p99 latency (submission to completion, host clock), then the
+    closed-loop append rate (a burst of appends submitted at once)."""
     import torch
     import synth
     from paper_2501_06647_amd import Tree
+    from paper_2501_06647_amd.tucket import TK_BF16, TK_F32
+
+    def say(msg):
+        print("[serve] %s" % msg, file=sys.stderr, flush=True)
 
     wl = synth.get(args.workload)
     torch.cuda.set_device(0)
     rng = np.random.default_rng(wl.query_seed + 77)
     T0 = min(args.serve_prefix, wl.T)
-    n_app = min(int(args.aps * args.serve_seconds), wl.T - T0)
-    X = synth.series(wl, 0, T0 + n_app).astype(np.float32)
+    n_app = min(int(args.aps * args.serve_seconds), wl.T - T0 - args.burst_appends)
+    t0 = time.perf_counter()
+    Xd = _device_series(wl, T0 + n_app + args.burst_appends, torch.device("cuda:0"))
+    say("generated %d slices in %.1f s" % (T0 + n_app + args.burst_appends, time.perf_counter() - t0))
     tree = Tree(wl.dims, wl.node_ranks, wl.leaf_len, wl.theta, wl.max_iter, wl.tol, capacity_T=wl.T)
-    tree.build(X[:T0])
+    tree.build(Xd[:T0])
     torch.cuda.synchronize()
     if not args.no_tune:
         ts, te = synth.queries(wl, T=T0, n=512)
-        print("[serve] autotune: %s" % (tree.autotune(ts, te, reps=1),), file=sys.stderr, flush=True)
+        say("autotune: %s" % (tree.autotune(ts, te, reps=1, budget_s=30.0),))
+    prec = TK_BF16 if args.serve_prec == "bf16" else TK_F32
+    tree.set_query_prec(prec)
     # arrival schedule
     horizon = n_app / args.aps
     q_times = np.cumsum(rng.exponential(1.0 / args.qps, size=int(args.qps * horizon * 1.2) + 16))
     q_times = q_times[q_times < horizon]
     a_times = np.arange(n_app) / args.aps
     events = sorted([(t, 1, i) for i, t in enumerate(a_times)] + [(t, 0, i) for i, t in enumerate(q_times)])
-    print("[serve] prefix %d slices, %d appends at %g/s, %d queries at %g/s over %.1f s"
-          % (T0, n_app, args.aps, len(q_times), args.qps, horizon), file=sys.stderr, flush=True)
-    srv = tree.serve()
+    say("prefix %d slices, %d appends at %g/s, %d queries at %g/s over %.1f s, %s queries, FP32 merges"
+        % (T0, n_app, args.aps, len(q_times), args.qps, horizon, args.serve_prec))
+    srv = tree.serve(max_batch=args.serve_slots)
     ell = wl.leaf_len
     T = T0
     qtickets = []
     open_q = []
+    lat = []
     t_start = time.perf_counter()
     last_print = t_start
     for (tev, kind, i) in events:
@@ -134,40 +144,57 @@ def serve_main(args):
             if tev - now > 2e-4:
                 time.sleep(min(tev - now - 1e-4, 1e-3))
         if kind == 1:
-            srv.submit_append(X[T])
+            srv.submit_append(Xd[T])
             T += 1
         else:
             Tc = (T // ell) * ell
+            if Tc < 1:
+                continue
             L = int(min(Tc, max(1, round(math.exp(rng.uniform(0.0, math.log(Tc)))))))
             a = int(rng.integers(0, Tc - L + 1))
             tk = srv.submit_query(a, a + L)
             qtickets.append(tk)
             open_q.append(tk)
-        # release finished outputs so device memory stays bounded
+        # take finished results so device memory stays bounded
         while open_q and srv.poll(open_q[0]):
-            srv.release(open_q.pop(0))
+            tk = open_q.pop(0)
+            ts_, tl_, td_ = srv.times(tk)
+            lat.append(td_ - ts_)
+            srv.release(tk)
         if time.perf_counter() - last_print > 5.0:
             last_print = time.perf_counter()
-            print("[serve] t=%.1f s T=%d %s" % (last_print - t_start, T, srv.stats()), file=sys.stderr, flush=True)
+            say("t=%.1f s T=%d %s" % (last_print - t_start, T, srv.stats()))
     srv.sync()
     wall = time.perf_counter() - t_start
+    for tk in open_q:
+        ts_, tl_, td_ = srv.times(tk)
+        lat.append(td_ - ts_)
+        srv.release(tk)
     stats = srv.stats()
-    lat = np.array([srv.times(tk) for tk in qtickets])
+    # closed loop: a burst of appends submitted at once, committed as fast as the engine can
+    t1 = time.perf_counter()
+    for k in range(args.burst_appends):
+        srv.submit_append(Xd[T + k])
+    srv.sync()
+    burst_s = time.perf_counter() - t1
+    T += args.burst_appends
     srv.stop()
-    lat_ms = (lat[:, 2] - lat[:, 0]) / 1000.0
+    lat_ms = np.array(lat) / 1000.0
     qps = len(qtickets) / wall
     out = {
         "metric": "serving: range queries/s with p50/p99 latency, appends interleaved",
         "value": qps, "unit": "queries/s", "n_gpus": 1, "steps": len(qtickets), "warmup": 0,
         "ms_per_step": 1000.0 * wall / max(1, len(qtickets)), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": args.serve_prec, "data": "synthetic",
         "config": {"workload": "%s: %s slices, T %d -> %d, node ranks %s, leaf %d; Poisson queries at %g/s "
-                               "(log-uniform lengths in [1, T_c]), appends at %g/s"
+                               "(log-uniform lengths in [1, T_c]), appends at %g/s, %s queries, FP32 merges, "
+                               "%d job slots per class"
                                % (wl.name, "x".join(map(str, wl.dims)), T0, T, wl.node_ranks, wl.leaf_len,
-                                  args.qps, args.aps)},
+                                  args.qps, args.aps, args.serve_prec, args.serve_slots)},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "max": float(lat_ms.max())},
         "appends_per_s": n_app / wall,
+        "closed_loop_appends_per_s": args.burst_appends / burst_s,
         "server": stats,
     }
     print(json.dumps(out), flush=True)
@@ -374,12 +401,309 @@ def copy_calibration_main(args):
     print("copied 3 x %d MiB" % args.copy_mib, flush=True)
 
 
+def cpu_info():
+    """Host cores and CPU model (for the oracle baseline's record)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
+
+
+def _device_series(wl, T, dev, chunk=4096):
+    """The workload's first T slices as one FP32 device tensor, generated in
+    chunks (host memory stays at one chunk)."""
+    import torch
+    import synth
+    Xd = torch.empty((T,) + tuple(wl.dims), dtype=torch.float32, device=dev)
+    for t0 in range(0, T, chunk):
+        t1 = min(T, t0 + chunk)
+        Xd[t0:t1].copy_(torch.from_numpy(synth.series(wl, t0, t1).astype(np.float32)))
+    return Xd
+
+
+def _time_batch(batch, steps, warmup):
+    """Warm-up runs, then `steps` graph replays bracketed by device
+    synchronisation; returns (ms per step on the host clock, mean kernel ms
+    from HIP events on the tree's stream)."""
+    import torch
+    for _ in range(warmup):
+        batch.run()
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.run()
+        kms.append(batch.kernel_ms())
+    torch.cuda.synchronize()
+    return 1000.0 * (time.perf_counter() - t0) / steps, float(np.mean(kms))
+
+
+def _device_latency(batch, n):
+    """Per-query completion latency of one batched step from the kernel's own
+    clock (100 MHz): each query's end time minus the step's first start (all
+    queries are submitted together), and each query's execution time."""
+    prof = [batch.profile(i) for i in range(n)]
+    t_s = np.array([pr["start_us"] for pr in prof])
+    t_e = np.array([pr["end_us"] for pr in prof])
+    done = t_e - t_s.min()
+    run = t_e - t_s
+    return prof, {"completion_p50_ms": float(np.percentile(done, 50)) / 1000.0,
+                  "completion_p99_ms": float(np.percentile(done, 99)) / 1000.0,
+                  "exec_p50_ms": float(np.percentile(run, 50)) / 1000.0,
+                  "exec_p99_ms": float(np.percentile(run, 99)) / 1000.0,
+                  "makespan_ms": float(t_e.max() - t_s.min()) / 1000.0,
+                  "mean_concurrency": float(run.sum() / max(1e-9, t_e.max() - t_s.min()))}
+
+
+def _flops(tree, wl, ts, te, results):
+    D = [0] + list(wl.dims)
+    node_ranks = {k: tree.node_ranks(k) for k in range(40) if (wl.leaf_len << k) <= wl.T}
+    flops = 0.0
+    hits_n = []
+    for i in range(len(ts)):
+        hits = tree.hitset(int(ts[i]), int(te[i]))
+        r = results[i]
+        flops += stitch_flops(tree.p, D, r.ranks, hits, node_ranks, r.sweeps, int(te[i] - ts[i]))
+        hits_n.append(len(hits))
+    return flops, hits_n
+
+
+def _accuracy(tree, wl, prefix, nq, precs, say):
+    """Error of the device results against the FP64 oracle on a fixed sample
+    of queries inside the first `prefix` slices: the oracle builds its own
+    tree over that prefix from the raw data (subtrees in worker processes)
+    and answers the same queries; |e_gpu / e_oracle - 1| per precision, e
+    the relative error against the raw data.  Also times the oracle's
+    queries (the CPU baseline)."""
+    import synth
+    from paper_2501_06647_amd.tucket import TK_F32
+    from oracle import pool
+    from oracle.evaluate import relative_error
+    from threadpoolctl import threadpool_limits
+    ts, te = synth.queries(wl, T=prefix, n=nq, seed_offset=17)
+    out = {"sample": "%d queries of the workload's length distribution inside [0, %d)" % (nq, prefix)}
+    dev = {}
+    for name, prec in precs:
+        tree.set_query_prec(prec)
+        b = tree.prepare_batch(ts, te)
+        b.run()
+        dev[name] = [(r.core.double().cpu().numpy(), [u.double().cpu().numpy() for u in r.factors])
+                     for r in b.results()]
+        b.close()
+    tree.set_query_prec(TK_F32)
+    t0 = time.perf_counter()
+    orc = pool.lazy_tree(wl, prefix)
+    level = pool.pool_level(wl)
+    pool.fill(orc, wl, level, range(prefix // (wl.leaf_len << level)))
+    for v in orc.complete_nodes():
+        orc.ensure(v)
+    build_s = time.perf_counter() - t0
+    say("oracle prefix of %d slices built in %.1f s (%d worker processes)" % (prefix, build_s, pool.workers()))
+    X = synth.series(wl, 0, prefix)
+    deltas = {name: [] for name in dev}
+    errs = {name: [] for name in dev}
+    q_s = 0.0
+    blas = 1
+    with threadpool_limits(1):
+        for i, (a, c) in enumerate(zip(ts.tolist(), te.tolist())):
+            t1 = time.perf_counter()
+            Go, Uo, _ = orc.query(a, c)
+            q_s += time.perf_counter() - t1
+            e_o = relative_error(X[a:c], Go, Uo)
+            for name in dev:
+                G, U = dev[name][i]
+                e_g = relative_error(X[a:c], G, U)
+                deltas[name].append(abs(e_g / e_o - 1.0) if e_o > 0 else e_g)
+                errs[name].append(e_g)
+    for name in dev:
+        out[name] = {"max_err_ratio_delta": float(max(deltas[name])),
+                     "p99_err_ratio_delta": float(np.percentile(deltas[name], 99)),
+                     "median_rel_err": float(np.median(errs[name])),
+                     "gate": 1e-5 if name == "f32" else 1e-2}
+    cpu = {"value": nq / q_s, "unit": "queries/s", "cores": blas, "kind": "oracle",
+           "sample": "FP64 NumPy oracle (one BLAS thread): Recall, QR trims and Stitch with Z^(1) materialised "
+                     "for the %d accuracy queries inside [0, %d) (%.1f s of query time); its tree over that "
+                     "prefix built from the raw slices by %d worker processes in %.1f s (%.1f slices/s)"
+                     % (nq, prefix, q_s, pool.workers(), build_s, prefix / build_s)}
+    cpu.update(cpu_info())
+    return out, cpu
+
+
+def batched_main(args):
+    """The headline: a step answers the workload's whole query list as one
+    prepared batch (HIP graph replay; Recall, trims and Stitch of every query
+    on the device), node store built and resident in HBM; FP32 and BF16
+    contractions; beside it the plain one-query-per-launch FP32 path,
+    streamed appends, accuracy against the oracle and the oracle's speed."""
+    import torch
+    import synth
+    from paper_2501_06647_amd import Tree
+    from paper_2501_06647_amd.tucket import TK_BF16, TK_F32
+
+    def say(msg):
+        print("[bench] %s" % msg, file=sys.stderr, flush=True)
+
+    wl = synth.get(args.workload)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    Xd = _device_series(wl, wl.T, dev)
+    say("generated %s: %d slices of %s in %.1f s" % (wl.name, wl.T, "x".join(map(str, wl.dims)),
+                                                    time.perf_counter() - t0))
+    tree = Tree(wl.dims, wl.node_ranks, wl.leaf_len, wl.theta, wl.max_iter, wl.tol, capacity_T=wl.T)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tree.build(Xd)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    say("built the tree from device-resident slices in %.3f s (%.0f slices/s)" % (build_s, wl.T / build_s))
+
+    # streamed appends: one slice per tk_append call, as a stream arrives
+    app = Tree(wl.dims, wl.node_ranks, wl.leaf_len, wl.theta, wl.max_iter, wl.tol, capacity_T=wl.T)
+    n_app = min(wl.T, args.append_slices)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < n_app:
+        app.append(Xd[done])
+        done += 1
+        if time.perf_counter() - t0 > args.append_seconds:
+            break
+    torch.cuda.synchronize()
+    app_s = time.perf_counter() - t0
+    appends = {"streamed_per_s": done / app_s, "streamed_slices": done,
+               "bulk_build_per_s": wl.T / build_s, "merges_total": app.stats()["merges_total"]}
+    app.close()
+    say("streamed appends: %d slices one per call, %.0f slices/s" % (done, done / app_s))
+
+    ts, te = synth.queries(wl)
+    nq = len(ts)
+    precs = [("f32", TK_F32)] + ([] if args.no_bf16 else [("bf16", TK_BF16)])
+    runs = {}
+    for name, prec in precs:
+        tree.set_query_prec(prec)
+        if args.tuning:
+            tree.set_tuning(**json.loads(args.tuning))
+        elif not args.no_tune:
+            t0 = time.perf_counter()
+            tuning, tune_ms = tree.autotune(ts, te, reps=2)
+            say("%s autotune: %s (%.3f ms per batch) in %.1f s" % (name, tuning, tune_ms, time.perf_counter() - t0))
+        batch = tree.prepare_batch(ts, te)
+        ms, kms = _time_batch(batch, args.steps, args.warmup)
+        batch.run()
+        prof, lat = _device_latency(batch, nq)
+        results = batch.results()
+        flops, hits_n = _flops(tree, wl, ts, te, results)
+        peak = PEAK_FP32_TFLOPS if name == "f32" else PEAK_BF16_TFLOPS
+        achieved = flops / (kms / 1000.0) / 1e12
+        phases = {k: float(np.mean([pr[k] for pr in prof])) for k in tree.PHASES}
+        eig = {k: float(np.mean([pr[k] for pr in prof])) for k in tree.COUNTERS[:4] + tree.COUNTERS[6:]}
+        runs[name] = {"queries_per_s": nq / (ms / 1000.0), "ms_per_step": ms, "kernel_ms": kms,
+                      "tuning": tree.tuning(), "latency": lat,
+                      "sweeps_mean": float(np.mean([r.sweeps for r in results])),
+                      "hits_mean": float(np.mean(hits_n)),
+                      "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                                   "frac": achieved / peak, "gflop_per_launch": flops / 1e9},
+                      "phase_mean_us": phases, "eig_mean": eig}
+        say("%s batched: %.3f ms/step (kernel %.3f ms), %.0f queries/s, %.2f TFLOP/s (%.2f%% of peak); "
+            "latency %s" % (name, ms, kms, nq / (ms / 1000.0), achieved, 100.0 * achieved / peak,
+                             json.dumps({k: round(v, 3) for k, v in lat.items()})))
+        say("%s phase mean us: %s; eigensolver: %s" % (name, json.dumps({k: round(v, 1) for k, v in phases.items()}),
+                                                     json.dumps({k: round(v, 1) for k, v in eig.items()})))
+        runs[name]["_batch"] = batch
+    tree.set_query_prec(TK_F32)
+
+    # the plain GPU path: one FP32 query per launch, no graph
+    plain = None
+    if not args.no_plain:
+        b32 = runs["f32"]["_batch"]
+        idx = list(range(0, nq, max(1, nq // args.plain_queries)))[:args.plain_queries]
+        lat = []
+        for i in idx:
+            t1 = time.perf_counter()
+            b32.run_one(i)
+            lat.append(time.perf_counter() - t1)
+        lat = np.array(lat)
+        plain = {"queries_per_s": float(len(idx) / lat.sum()), "p50_ms": float(1000 * np.percentile(lat, 50)),
+                 "p99_ms": float(1000 * np.percentile(lat, 99)), "launches": len(idx),
+                 "sample": "every %d-th query of the list (host clock per call, launch to completion)"
+                           % max(1, nq // args.plain_queries)}
+        say("plain FP32, one query per launch: %.1f queries/s, p50 %.3f ms, p99 %.3f ms over %d queries"
+            % (plain["queries_per_s"], plain["p50_ms"], plain["p99_ms"], len(idx)))
+    for r in runs.values():
+        r.pop("_batch").close()
+
+    accuracy, cpu = None, None
+    if not args.no_cpu:
+        accuracy, cpu = _accuracy(tree, wl, min(args.acc_prefix, wl.T), args.acc_queries, precs, say)
+        say("accuracy vs oracle: %s" % json.dumps(accuracy))
+
+    head = args.headline if args.headline in runs else "f32"
+    h = runs[head]
+    traffic = None
+    tb = TRAFFIC_BYTES_PER_STEP.get((wl.name, head))
+    if tb and kernel_sha() == tb["sha"]:
+        traffic = tb["fetch"] + tb["write"]
+    roof = dict(h["roofline"])
+    roof.update({"traffic": traffic, "kernel": "stitch_kernel (all LDS-bin launches of the step)",
+                 "kernel_ms": h["kernel_ms"]})
+    out = {
+        "metric": "range queries/sec at fixed rel. error; p50/p99 query latency vs plain GPU path",
+        "value": h["queries_per_s"],
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": h["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head,
+        "data": "synthetic",
+        "config": {"workload": "%s: %s x T=%d FP32 series (%s), true rank %s, noise %.2f, leaf %d, node ranks %s; "
+                               "%d queries per step (%s lengths), theta %d/%d, <=%d sweeps, tol %g; the whole "
+                               "list as one prepared batch (HIP graph), node store resident in HBM"
+                               % (wl.name, "x".join(map(str, wl.dims)), wl.T,
+                                  "drifting factors" if wl.drift else "regime-switched" if wl.regime else "stationary",
+                                  wl.true_ranks, wl.noise, wl.leaf_len, wl.node_ranks, nq, wl.query_kind,
+                                  wl.theta[0], wl.theta[1], wl.max_iter, wl.tol),
+                   "queries_per_step": nq, "headline_precision": head},
+        "latency_ms": {"batched_completion_p50": h["latency"]["completion_p50_ms"],
+                       "batched_completion_p99": h["latency"]["completion_p99_ms"],
+                       "batched_exec_p50": h["latency"]["exec_p50_ms"],
+                       "batched_exec_p99": h["latency"]["exec_p99_ms"],
+                       "plain_p50": plain["p50_ms"] if plain else None,
+                       "plain_p99": plain["p99_ms"] if plain else None},
+        "precisions": runs,
+        "plain_gpu_path": plain,
+        "speedup_vs_plain": {k: r["queries_per_s"] / plain["queries_per_s"] for k, r in runs.items()} if plain else None,
+        "appends": appends,
+        "roofline": roof,
+        "accuracy_vs_oracle": accuracy,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="plain")
+    ap.add_argument("--workload", default="serving")
+    ap.add_argument("--headline", default="f32", help="precision of the headline value: f32 or bf16")
+    ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--append-slices", type=int, default=4096, help="streamed appends timed (one slice per call)")
+    ap.add_argument("--append-seconds", type=float, default=10.0)
+    ap.add_argument("--plain-queries", type=int, default=512, help="queries timed on the plain path")
+    ap.add_argument("--acc-prefix", type=int, default=4096, help="oracle tree horizon for the accuracy sample")
+    ap.add_argument("--acc-queries", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -388,8 +712,11 @@ def main():
     ap.add_argument("--serve", action="store_true", help="serving run instead of the batched benchmark")
     ap.add_argument("--qps", type=float, default=2000.0)
     ap.add_argument("--aps", type=float, default=1000.0)
-    ap.add_argument("--serve-seconds", type=float, default=20.0)
-    ap.add_argument("--serve-prefix", type=int, default=4096)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--serve-prefix", type=int, default=256)
+    ap.add_argument("--serve-prec", default="f32", help="query arithmetic while serving: f32 or bf16")
+    ap.add_argument("--serve-slots", type=int, default=256, help="job slots (concurrent queries) per class")
+    ap.add_argument("--burst-appends", type=int, default=2048, help="closed-loop appends after the serving run")
     ap.add_argument("--pscale", action="store_true", help="latency against the number of modes (p = 4..7)")
     ap.add_argument("--pscale-p", default="4,5,6,7", help="numbers of modes for --pscale")
     ap.add_argument("--pscale-tune-p", default="4,5,6",
@@ -405,7 +732,8 @@ def main():
         return copy_calibration_main(args)
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(queries are independent; see DESIGN.md on sharding)", file=sys.stderr)
+              "(queries are independent: several GPUs would each hold a copy of the node store "
+              "and take a share of the queries)", file=sys.stderr)
         sys.exit(2)
     if args.serve:
         if args.workload == "plain":
@@ -415,194 +743,7 @@ def main():
         return tradeoff_main(args)
     if args.pscale:
         return pscale_main(args)
-
-    import torch
-    import synth
-    from paper_2501_06647_amd import Tree
-
-    wl = synth.get(args.workload)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    X = synth.series(wl)
-    Xd = torch.from_numpy(X.astype(np.float32)).to(dev)
-    tree = Tree(wl.dims, wl.node_ranks, wl.leaf_len, wl.theta, wl.max_iter, wl.tol, capacity_T=wl.T)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    tree.build(Xd)
-    torch.cuda.synchronize()
-    build_s = time.perf_counter() - t0
-    print("[bench] built %s tree: %d slices in %.3f s" % (wl.name, wl.T, build_s), file=sys.stderr, flush=True)
-
-    ts, te = synth.queries(wl)
-    nq = len(ts)
-    tuning, tune_ms = None, None
-    if args.tuning:
-        tree.set_tuning(**json.loads(args.tuning))
-    elif not args.no_tune:
-        t0 = time.perf_counter()
-        tuning, tune_ms = tree.autotune(ts, te, reps=2)
-        print("[bench] autotune: %s (%.3f ms per batch) in %.1f s" % (tuning, tune_ms, time.perf_counter() - t0),
-              file=sys.stderr, flush=True)
-    tuning = tree.tuning()
-    batch = tree.prepare_batch(ts, te)
-    for _ in range(args.warmup):
-        batch.run()
-    torch.cuda.synchronize()
-    kms = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        batch.run()
-        kms.append(batch.kernel_ms())
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = 1000.0 * wall / args.steps
-    qps = nq * args.steps / wall
-    print("[bench] batched (graph): %.3f ms/step, kernel %.3f ms" % (ms_per_step, float(np.mean(kms))),
-          file=sys.stderr, flush=True)
-    # the same queries through tk_query_batch (host Recall and planning every call)
-    sync_steps = max(1, min(3, args.steps))
-    t1 = time.perf_counter()
-    for _ in range(sync_steps):
-        batch.run_sync()
-    torch.cuda.synchronize()
-    sync_ms = 1000.0 * (time.perf_counter() - t1) / sync_steps
-    print("[bench] batched (tk_query_batch): %.3f ms/step" % sync_ms, file=sys.stderr, flush=True)
-    batch.run()
-
-    results = batch.results()
-    D = [0] + list(wl.dims)
-    node_ranks = {k: tree.node_ranks(k) for k in range(40) if (wl.leaf_len << k) <= wl.T}
-    flops = 0.0
-    sweeps = []
-    hit_counts = []
-    for i in range(nq):
-        hits = tree.hitset(int(ts[i]), int(te[i]))
-        res = results[i]
-        flops += stitch_flops(tree.p, D, res.ranks, hits, node_ranks, res.sweeps, int(te[i] - ts[i]))
-        sweeps.append(res.sweeps)
-        hit_counts.append(len(hits))
-    kernel_s = float(np.mean(kms)) / 1000.0
-    achieved = flops / kernel_s / 1e12
-    prof = [batch.profile(i) for i in range(nq)]
-    phase_mean = {k: float(np.mean([pr[k] for pr in prof])) for k in tree.PHASES}
-    tot = np.array([sum(pr[k] for k in tree.PHASES) for pr in prof])
-    counters = {k: float(np.mean([pr[k] for pr in prof])) for k in tree.COUNTERS[:4] + tree.COUNTERS[6:]}
-    t_s = np.array([pr["start_us"] for pr in prof])
-    t_e = np.array([pr["end_us"] for pr in prof])
-    t_base = t_s.min()
-    timeline = {"makespan_us": float(t_e.max() - t_base),
-                "start_offset_us_p50": float(np.median(t_s - t_base)),
-                "start_offset_us_max": float((t_s - t_base).max()),
-                "mean_concurrency": float((t_e - t_s).sum() / max(1e-9, t_e.max() - t_base))}
-    print("[bench] device timeline: %s" % json.dumps({k: round(v, 1) for k, v in timeline.items()}),
-          file=sys.stderr, flush=True)
-    print("[bench] eigensolver per query: %s" % json.dumps({k: round(v, 1) for k, v in counters.items()}),
-          file=sys.stderr, flush=True)
-    slow = int(np.argmax(tot))
-    print("[bench] phase mean us: %s" % json.dumps({k: round(v, 1) for k, v in phase_mean.items()}),
-          file=sys.stderr, flush=True)
-    print("[bench] per-query device us: mean %.1f p50 %.1f max %.1f (query %d, %d hits, L=%d)"
-          % (tot.mean(), np.median(tot), tot.max(), slow, hit_counts[slow], int(te[slow] - ts[slow])),
-          file=sys.stderr, flush=True)
-    slowest = {"query": slow, "hits": hit_counts[slow], "L": int(te[slow] - ts[slow]),
-               "sweeps": int(sweeps[slow]), "ranks": [int(r) for r in results[slow].ranks],
-               "phases_us": {k: float(prof[slow][k]) for k in tree.PHASES},
-               "eig": {k: float(prof[slow][k]) for k in tree.COUNTERS[:4] + tree.COUNTERS[7:]}}
-    print("[bench] slowest query: %s" % json.dumps(slowest), file=sys.stderr, flush=True)
-
-    plain = None
-    if not args.no_plain:
-        lat = []
-        for i in range(nq):
-            t1 = time.perf_counter()
-            batch.run_one(i)
-            lat.append(time.perf_counter() - t1)
-        lat = np.array(lat)
-        plain = {"queries_per_s": float(nq / lat.sum()), "p50_ms": float(1000 * np.percentile(lat, 50)),
-                 "p99_ms": float(1000 * np.percentile(lat, 99)), "launches": nq}
-        print("[bench] plain: %.1f q/s p50 %.3f ms p99 %.3f ms" % (plain["queries_per_s"], plain["p50_ms"],
-                                                                 plain["p99_ms"]), file=sys.stderr, flush=True)
-
-    cpu = None
-    accuracy = None
-    if not args.no_cpu:
-        from oracle.evaluate import relative_error
-        from oracle.tree import StreamSegmentTree
-        t0 = time.perf_counter()
-        orc = StreamSegmentTree(wl.dims, wl.node_ranks, wl.leaf_len, wl.theta, wl.max_iter, wl.tol)
-        for b in range(wl.T // wl.leaf_len):
-            orc.append(X[b * wl.leaf_len:(b + 1) * wl.leaf_len])
-        orc_build_s = time.perf_counter() - t0
-        done, qt, deltas, errs = 0, 0.0, [], []
-        while done < nq and qt < args.cpu_seconds:
-            a, b = int(ts[done]), int(te[done])
-            t1 = time.perf_counter()
-            Go, Uo, _ = orc.query(a, b)
-            qt += time.perf_counter() - t1
-            r = results[done]
-            e_g = relative_error(X[a:b], r.core.double().cpu().numpy(), [u.double().cpu().numpy() for u in r.factors])
-            e_o = relative_error(X[a:b], Go, Uo)
-            deltas.append(abs(e_g / e_o - 1.0) if e_o > 0 else e_g)
-            errs.append(e_g)
-            done += 1
-        cpu = {"value": done / qt, "unit": "queries/s", "cores": blas_threads(), "kind": "oracle",
-               "sample": "FP64 NumPy oracle: tree built over all %d slices (%.1f s, %.0f slices/s), then "
-                         "queries 0..%d of the same query list (Recall, QR trims, Stitch with Z^(1) "
-                         "materialised), %.1f s of query time" % (wl.T, orc_build_s, wl.T / orc_build_s,
-                                                                 done - 1, qt)}
-        accuracy = {"n_checked": done, "max_err_ratio_delta": float(max(deltas)),
-                    "median_rel_err": float(np.median(errs)), "gate": 1e-5}
-
-    traffic, traffic_detail = None, None
-    tb = TRAFFIC_BYTES_PER_STEP.get(wl.name)
-    if tb and kernel_sha() == TRAFFIC_KERNEL_SHA:
-        traffic = tb["fetch"] + tb["write"]
-        traffic_detail = {"fetch_bytes": tb["fetch"], "write_bytes": tb["write"],
-                          "GBps_at_kernel_ms": traffic / kernel_s / 1e9,
-                          "measured_with_tuning": tb["tuning"],
-                          "source": "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE per dispatch, copy-calibrated"}
-    out = {
-        "metric": "range queries/sec at fixed rel. error; p50/p99 query latency vs plain GPU path",
-        "value": qps,
-        "unit": "queries/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "%s: %s x T=%d FP32 series, true rank %s, noise %.2f, leaf %d, node ranks %s, "
-                               "%d queries (%s lengths), theta %d/%d, <=%d sweeps, tol %g"
-                               % (wl.name, "x".join(map(str, wl.dims)), wl.T, wl.true_ranks, wl.noise,
-                                  wl.leaf_len, wl.node_ranks, nq, wl.query_kind, wl.theta[0], wl.theta[1],
-                                  wl.max_iter, wl.tol),
-                   "queries_per_step": nq,
-                   "path": "prepared batch: one HIP graph per step, fused Recall+trims+Stitch kernel per LDS bin",
-                   "tuning": tuning},
-        "sync_batch_ms_per_step": sync_ms,
-        "latency_ms": {"batch_p50": ms_per_step, "batch_p99": ms_per_step,
-                       "plain_p50": plain["p50_ms"] if plain else None,
-                       "plain_p99": plain["p99_ms"] if plain else None},
-        "plain_gpu_path": plain,
-        "speedup_vs_plain": (qps / plain["queries_per_s"]) if plain else None,
-        "appends_per_s": wl.T / build_s,
-        "sweeps_mean": float(np.mean(sweeps)),
-        "device_us_per_query": {"mean": float(tot.mean()), "p50": float(np.median(tot)), "max": float(tot.max()),
-                                "phase_mean": phase_mean, "eig_counters_mean": counters,
-                                "timeline": timeline, "slowest": slowest},
-        "hits_mean": float(np.mean(hit_counts)),
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
-                     "traffic_detail": traffic_detail,
-                     "kernel": "stitch_kernel", "kernel_ms": float(np.mean(kms)),
-                     "gflop_per_launch": flops / 1e9},
-        "accuracy_vs_oracle": accuracy,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
+    return batched_main(args)
 
 
 if __name__ == "__main__":

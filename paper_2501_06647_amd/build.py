@@ -28,10 +28,10 @@ FLAGS = [
 ]
 
 
-def _units():
-    units = [(os.path.join(HERE, s), os.path.join(OBJ_DIR, os.path.basename(s)[:-4] + ".o"), []) for s in SOURCES]
+def _units(src_dir, obj_dir):
+    units = [(os.path.join(src_dir, s), os.path.join(obj_dir, os.path.basename(s)[:-4] + ".o"), []) for s in SOURCES]
     for ntt, pm in STITCH_INSTANCES:
-        units.append((os.path.join(HERE, STITCH_SOURCE), os.path.join(OBJ_DIR, "tk_stitch_%d_%d.o" % (ntt, pm)),
+        units.append((os.path.join(src_dir, STITCH_SOURCE), os.path.join(obj_dir, "tk_stitch_%d_%d.o" % (ntt, pm)),
                       ["-DTK_NTT=%d" % ntt, "-DTK_PM=%d" % pm]))
     return units
 
@@ -42,10 +42,13 @@ def _run(cmd):
     return proc.returncode, lines
 
 
-def build(verbose: bool = False, jobs: int = 0) -> str:
+def build(verbose: bool = False, jobs: int = 0, src_dir: str = HERE, obj_dir: str = OBJ_DIR,
+          out: str = OUT) -> str:
+    """Compile and link; src_dir holds the csrc/ tree (default: this
+    package's), objects go to obj_dir and the library to out."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    os.makedirs(OBJ_DIR, exist_ok=True)
-    units = _units()
+    os.makedirs(obj_dir, exist_ok=True)
+    units = _units(src_dir, obj_dir)
     cmds = [[hipcc] + FLAGS + extra + ["-c", src, "-o", obj] for src, obj, extra in units]
     workers = jobs or min(len(cmds), max(1, min(16, os.cpu_count() or 1)))
     with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
@@ -55,14 +58,14 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
             print(" ".join(cmd), flush=True)
         if rc != 0:
             raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + "\n".join(lines))
-    link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", OUT + ".tmp"] + [o for _, o, _ in units]
+    link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", out + ".tmp"] + [o for _, o, _ in units]
     if verbose:
         print(" ".join(link), flush=True)
     rc, lines = _run(link)
     if rc != 0:
         raise RuntimeError("link failed:\n" + "\n".join(lines))
-    os.replace(OUT + ".tmp", OUT)
-    return OUT
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

@@ -15,7 +15,7 @@ from typing import List, Optional, Sequence, Tuple
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtucket.so")
+LIB_PATH = os.environ.get("TUCKET_LIB") or os.path.join(_HERE, "libtucket.so")
 MAX_MODES = 8
 
 TK_OK, TK_EINVAL, TK_ERANGE, TK_ENOMEM, TK_EDEVICE, TK_EBUSY = range(6)

@@ -31,8 +31,18 @@ HBM_TBPS = 8.0
 # --pmc runs (FETCH_SIZE, WRITE_SIZE per dispatch, summed over the step's
 # launches) scaled by the counters of a reference copy of known size
 # (`--copy-calibration`); keyed by (workload, precision) and valid only for
-# the kernel sources (sha) they were taken with.
+# the kernel sources (sha) and the launch tuning they were taken with.
 TRAFFIC_BYTES_PER_STEP = {}
+
+# Launch tunings of the batched runs (tk_autotune's choices on MI355X for
+# the serving workload's 4096-query list; `--autotune` searches again).
+# The HBM counters above are taken under these.
+TUNINGS = {
+    ("serving", "f32"): {"wide_threshold": 32, "wide_threads": 128, "persistent": 1, "graph": 1, "coarse": 1,
+                         "lds_n": 64, "basis_pct": 75, "rest_threads": 0, "wide_core": 0},
+    ("serving", "bf16"): {"wide_threshold": 32, "wide_threads": 256, "persistent": 1, "graph": 1, "coarse": 1,
+                          "lds_n": 64, "basis_pct": 75, "rest_threads": 0, "wide_core": 0},
+}
 KERNEL_SOURCES = ("tk_common.hpp", "tk_device.hpp", "tk_internal.hpp", "tk_kernels.hip", "tk_stitch.hpp",
                   "tk_stitch_inst.hip")
 
@@ -301,7 +311,7 @@ def tradeoff_main(args):
 def pscale_main(args):
     """Query latency and throughput against the number of modes on the
     paper's many-mode shapes (every slice 10^6 elements, rank 5 per mode,
-    400 slices, leaf 1): p = 4 to 7; queries of 98, 192 and 384 slices
+    400 slices, leaf 1): p = 3 to 7; queries of 98, 192 and 384 slices
     from seeded random starts, one at a time (latency) and as one prepared
     batch (throughput)."""
     import torch
@@ -369,7 +379,8 @@ def pscale_main(args):
             prof = [b.profile(i) for i in range(len(ts))]
             phases = {k: round(float(np.mean([pr[k] for pr in prof])), 1) for k in tree.PHASES}
             hits = [len(tree.hitset(int(a), int(c))) for a, c in zip(ts, te)]
-            row = {"p": p, "dims": list(wl.dims), "L": L, "tuning": tuning, "latency_p50_ms": 1000.0 * float(np.median(lat)),
+            row = {"p": p, "dims": list(wl.dims), "L": L, "tuning": tuning, "build_s": build_s,
+                   "latency_p50_ms": 1000.0 * float(np.median(lat)),
                    "latency_p99_ms": 1000.0 * float(np.percentile(lat, 99)), "batch_queries": len(ts),
                    "batch_queries_per_s": len(ts) / (ms / 1000.0), "hits_mean": float(np.mean(hits)),
                    "sweeps_mean": float(np.mean([r.sweeps for r in res])), "phase_mean_us": phases}
@@ -590,10 +601,12 @@ def batched_main(args):
         tree.set_query_prec(prec)
         if args.tuning:
             tree.set_tuning(**json.loads(args.tuning))
-        elif not args.no_tune:
+        elif args.autotune or (wl.name, name) not in TUNINGS:
             t0 = time.perf_counter()
             tuning, tune_ms = tree.autotune(ts, te, reps=2)
             say("%s autotune: %s (%.3f ms per batch) in %.1f s" % (name, tuning, tune_ms, time.perf_counter() - t0))
+        else:
+            tree.set_tuning(**TUNINGS[(wl.name, name)])
         batch = tree.prepare_batch(ts, te)
         ms, kms = _time_batch(batch, args.steps, args.warmup)
         batch.run()
@@ -648,7 +661,7 @@ def batched_main(args):
     h = runs[head]
     traffic = None
     tb = TRAFFIC_BYTES_PER_STEP.get((wl.name, head))
-    if tb and kernel_sha() == tb["sha"]:
+    if tb and kernel_sha() == tb["sha"] and all(h["tuning"].get(k) == v for k, v in tb["tuning"].items()):
         traffic = tb["fetch"] + tb["write"]
     roof = dict(h["roofline"])
     roof.update({"traffic": traffic, "kernel": "stitch_kernel (all LDS-bin launches of the step)",
@@ -708,7 +721,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--tuning", default=None, help="JSON tuning to use instead of autotuning")
+    ap.add_argument("--tuning", default=None, help="JSON tuning for the batched runs")
+    ap.add_argument("--autotune", action="store_true",
+                    help="search the batched runs' tuning (tk_autotune) instead of the stored one")
     ap.add_argument("--serve", action="store_true", help="serving run instead of the batched benchmark")
     ap.add_argument("--qps", type=float, default=2000.0)
     ap.add_argument("--aps", type=float, default=1000.0)
@@ -717,9 +732,9 @@ def main():
     ap.add_argument("--serve-prec", default="f32", help="query arithmetic while serving: f32 or bf16")
     ap.add_argument("--serve-slots", type=int, default=256, help="job slots (concurrent queries) per class")
     ap.add_argument("--burst-appends", type=int, default=2048, help="closed-loop appends after the serving run")
-    ap.add_argument("--pscale", action="store_true", help="latency against the number of modes (p = 4..7)")
-    ap.add_argument("--pscale-p", default="4,5,6,7", help="numbers of modes for --pscale")
-    ap.add_argument("--pscale-tune-p", default="4,5,6",
+    ap.add_argument("--pscale", action="store_true", help="latency against the number of modes (p = 3..7)")
+    ap.add_argument("--pscale-p", default="3,4,5,6,7", help="numbers of modes for --pscale")
+    ap.add_argument("--pscale-tune-p", default="3,4,5,6",
                     help="numbers of modes autotuned in --pscale (the others reuse the previous tuning)")
     ap.add_argument("--pscale-tuning", default=None, help="JSON tuning for every p of --pscale")
     ap.add_argument("--tradeoff", action="store_true",

@@ -452,6 +452,28 @@ TK_HD int stitch_eig_need(const StitchLayout& lo, const StoreView& st, int pct) 
   return n;
 }
 
+// How a leaf is decomposed.  Tucker-ALS on the raw block in general.  A leaf
+// of one slice of a three-way series has temporal rank one and equal
+// non-temporal ranks, and Tucker-ALS on it reaches the slice's truncated
+// SVD (Eckart-Young), which is computed directly: from one eigensolve of
+// the smaller side's Gram while that side has at most kSliceGramMax rows,
+// else (1000 x 1000 slices, say) by block subspace iteration on that Gram,
+// never formed, with slice_block(n, r) columns.
+enum { LEAF_ALS = 0, LEAF_SLICE_GRAM = 1, LEAF_SLICE_ITER = 2 };
+constexpr int kSliceGramMax = 256;
+constexpr int kSliceIterMaxRank = 24;  // r + 8 <= 32 columns, the eigensolver's vector limit
+constexpr int kSliceIterMax = 300;     // subspace iteration steps (a slice with no spectral gap)
+TK_HD int slice_block(int64_t n, int r) {
+  const int b = r <= 8 ? 16 : 32;
+  return n < b ? int(n) : b;
+}
+TK_HD int leaf_route(const StoreView& st) {
+  const int32_t* rq = st.rk[0];
+  if (!(st.p == 3 && st.ell == 1 && rq[0] == 1 && rq[1] == rq[2])) return LEAF_ALS;
+  const int64_t n = st.D[1] < st.D[2] ? st.D[1] : st.D[2];
+  return n > kSliceGramMax && rq[1] <= kSliceIterMaxRank ? LEAF_SLICE_ITER : LEAF_SLICE_GRAM;
+}
+
 // Workspace of a leaf job.
 struct LeafLayout {
   int64_t Ud[MAXP];  // double D_n x rq_n (D_0 = ell)
@@ -461,8 +483,12 @@ struct LeafLayout {
   int64_t G;         // float prod(rq)
   int64_t TMP;       // double eig_tmp_doubles(neig) (eigensolver scratch)
   int64_t EIG;       // double eig_doubles(neig) when neig > n_lds
+  // subspace iteration (LEAF_SLICE_ITER), doubles: Q, S Q, Q W, S Q W
+  // (n x b each, n the smaller side), X^T Q (m x b), W (b x b)
+  int64_t SQ, SY, SQW, SYW, SZ, SW;
   int64_t total;
   int32_t neig;
+  int32_t route;
 };
 
 TK_HD void leaf_layout(const StoreView& st, int n_lds, LeafLayout* Lo) {
@@ -473,6 +499,33 @@ TK_HD void leaf_layout(const StoreView& st, int n_lds, LeafLayout* Lo) {
     off = align256(off + (bytes > 0 ? bytes : 0));
     return o;
   };
+  Lo->route = leaf_route(st);
+  Lo->SQ = Lo->SY = Lo->SQW = Lo->SYW = Lo->SZ = Lo->SW = -1;
+  if (Lo->route == LEAF_SLICE_ITER) {
+    const int64_t n = st.D[1] < st.D[2] ? st.D[1] : st.D[2];
+    const int64_t m = st.D[1] < st.D[2] ? st.D[2] : st.D[1];
+    const int r = st.rk[0][1];
+    const int b = slice_block(n, r);
+    Lo->Ud[0] = take(8);
+    Lo->Uf[0] = take(4);
+    for (int k = 1; k < 3; ++k) {
+      Lo->Ud[k] = take(st.D[k] * r * 8);
+      Lo->Uf[k] = take(st.D[k] * r * 4);
+    }
+    Lo->T1 = Lo->T2 = Lo->V = -1;
+    Lo->G = take(int64_t(r) * r * 4);
+    Lo->SQ = take(n * b * 8);
+    Lo->SY = take(n * b * 8);
+    Lo->SQW = take(n * b * 8);
+    Lo->SYW = take(n * b * 8);
+    Lo->SZ = take(m * b * 8);
+    Lo->SW = take(int64_t(b) * b * 8);
+    Lo->neig = b;
+    Lo->TMP = take(eig_tmp_doubles(b) * 8);
+    Lo->EIG = b > n_lds ? take(eig_doubles(b) * 8) : -1;
+    Lo->total = off;
+    return;
+  }
   int64_t Dm[MAXP];
   Dm[0] = st.ell;
   for (int n = 1; n < p; ++n) Dm[n] = st.D[n];
@@ -595,6 +648,8 @@ TK_HD void raw_layout(int p, const int32_t* Dm, const int32_t* rq, int n_lds, Le
   Lo->neig = neig;
   Lo->TMP = take(eig_tmp_doubles(neig) * 8);
   Lo->EIG = neig > n_lds ? take(eig_doubles(neig) * 8) : -1;
+  Lo->route = LEAF_ALS;
+  Lo->SQ = Lo->SY = Lo->SQW = Lo->SYW = Lo->SZ = Lo->SW = -1;
   Lo->total = off;
 }
 

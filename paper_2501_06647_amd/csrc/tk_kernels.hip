@@ -177,16 +177,148 @@ __device__ __forceinline__ void als_stats(double* stats, const AlsResult& r) {
   }
 }
 
+// Start vectors of the subspace iteration: Wellons' lowbias32 integer hash
+// of the element index, mapped to [-1, 1).
+__device__ __forceinline__ double start_entry(uint32_t i) {
+  uint32_t x = i + 0x9E3779B9u;
+  x ^= x >> 16;
+  x *= 0x7FEB352Du;
+  x ^= x >> 15;
+  x *= 0x846CA68Bu;
+  x ^= x >> 16;
+  return double(x) * (2.0 / 4294967296.0) - 1.0;
+}
+
+// The columns of E (n x k, element (i, j) at E[i * ld + j]) made orthonormal
+// in place, left to right: Gram-Schmidt twice against the earlier columns.
+// A column left with under 1e-10 of its norm lies in their span and is
+// replaced by the first unit vector that does not, so the span stays
+// k-dimensional (k <= n).  coef: k doubles.
+__device__ __forceinline__ void orth_columns(double* E, int n, int k, int ld, double* coef, double* red) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int nw = nt >> 6, w = tid >> 6, l = tid & 63;
+  int cand = 0;
+  for (int j = 0; j < k; ++j) {
+    double part = 0.0;
+    for (int i = tid; i < n; i += nt) part += E[int64_t(i) * ld + j] * E[int64_t(i) * ld + j];
+    double n0 = sqrt(block_sum(part, red));
+    for (;;) {
+      for (int pass = 0; pass < 2 && j > 0; ++pass) {
+        for (int c = w; c < j; c += nw) {
+          double d = 0.0;
+          for (int i = l; i < n; i += 64) d += E[int64_t(i) * ld + c] * E[int64_t(i) * ld + j];
+          for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+          if (l == 0) coef[c] = d;
+        }
+        __syncthreads();
+        for (int i = tid; i < n; i += nt) {
+          double v = E[int64_t(i) * ld + j];
+          for (int c = 0; c < j; ++c) v -= coef[c] * E[int64_t(i) * ld + c];
+          E[int64_t(i) * ld + j] = v;
+        }
+        __syncthreads();
+      }
+      part = 0.0;
+      for (int i = tid; i < n; i += nt) part += E[int64_t(i) * ld + j] * E[int64_t(i) * ld + j];
+      const double n1 = sqrt(block_sum(part, red));
+      if (n1 > 0.0 && n1 > 1e-10 * n0) {
+        const double inv = 1.0 / n1;
+        for (int i = tid; i < n; i += nt) E[int64_t(i) * ld + j] *= inv;
+        __syncthreads();
+        break;
+      }
+      if (cand >= n) {  // unreachable for k <= n: the unit vectors span everything
+        for (int i = tid; i < n; i += nt) E[int64_t(i) * ld + j] = 0.0;
+        __syncthreads();
+        break;
+      }
+      for (int i = tid; i < n; i += nt) E[int64_t(i) * ld + j] = i == cand ? 1.0 : 0.0;
+      ++cand;
+      n0 = 1.0;
+      __syncthreads();
+    }
+  }
+}
+
+// Leading r eigenpairs of S = A A^T for an n x m matrix A (a(i, c) returns
+// A(i, c) in FP64), S never formed: block subspace iteration with b
+// columns (b >= r + 8) and Rayleigh-Ritz (Golub & Van Loan, Sec. 8.2.4 and
+// 8.1.4).  Each step: Z = A^T Q, Y = A Z = S Q; Q^T S Q = Z^T Z = W Theta W^T;
+// Ritz vectors Q W, residuals S Q w_j - theta_j Q w_j = Y w_j - theta_j Q w_j.
+// It stops once the leading r residuals are at most 1e-12 theta_1 (S's
+// rounding level is near 1e-14 theta_1), or after max_it steps; otherwise
+// Q becomes the orthonormalised Y W.  Writes U (n x r, the Ritz vectors),
+// sv (sqrt(theta_j)), and Uo = A^T U diag(1/sv) (m x r, zero where sv is
+// zero).  Returns the steps taken; *conv tells whether the test passed.
+template <typename FA>
+__device__ __forceinline__ int subspace_top(FA&& a, int n, int m, int r, int b, int max_it, int n_lds, double* lds,
+                                            char* ws, const LeafLayout& lo, LeafShared& sh, double* U, double* Uo,
+                                            double* sv, int* conv) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* Q = reinterpret_cast<double*>(ws + lo.SQ);
+  double* Y = reinterpret_cast<double*>(ws + lo.SY);
+  double* QW = reinterpret_cast<double*>(ws + lo.SQW);
+  double* YW = reinterpret_cast<double*>(ws + lo.SYW);
+  double* Z = reinterpret_cast<double*>(ws + lo.SZ);
+  double* W = reinterpret_cast<double*>(ws + lo.SW);
+  double* TMP = reinterpret_cast<double*>(ws + lo.TMP);
+  double* Bm = b <= n_lds ? lds : reinterpret_cast<double*>(ws + lo.EIG);
+  for (int64_t e = tid; e < int64_t(n) * b; e += nt) Q[e] = start_entry(uint32_t(e));
+  __syncthreads();
+  orth_columns(Q, n, b, b, sh.coef, sh.red);
+  int it = 0;
+  *conv = 0;
+  const double* lam = nullptr;
+  for (;;) {
+    ++it;
+    gemm_f64(m, b, n, [&](int c, int i) { return a(i, c); }, [&](int i, int j) { return Q[int64_t(i) * b + j]; },
+             [&](int c, int j, double v) { Z[int64_t(c) * b + j] = v; });
+    gemm_f64(n, b, m, [&](int i, int c) { return a(i, c); }, [&](int c, int j) { return Z[int64_t(c) * b + j]; },
+             [&](int i, int j, double v) { Y[int64_t(i) * b + j] = v; });
+    gemm_f64(b, b, m, [&](int i, int c) { return Z[int64_t(c) * b + i]; },
+             [&](int c, int j) { return Z[int64_t(c) * b + j]; }, [&](int i, int j, double v) { Bm[i * b + j] = v; });
+    lam = eig_top(Bm, b, b, W, b, sh.red, TMP, nullptr, Bm + b * b);
+    gemm_f64(n, b, b, [&](int i, int c) { return Q[int64_t(i) * b + c]; }, [&](int c, int j) { return W[c * b + j]; },
+             [&](int i, int j, double v) { QW[int64_t(i) * b + j] = v; });
+    gemm_f64(n, b, b, [&](int i, int c) { return Y[int64_t(i) * b + c]; }, [&](int c, int j) { return W[c * b + j]; },
+             [&](int i, int j, double v) { YW[int64_t(i) * b + j] = v; });
+    const double top = fmax(lam[0], 0.0);
+    double worst = 0.0;
+    for (int j = 0; j < r; ++j) {
+      double part = 0.0;
+      for (int i = tid; i < n; i += nt) {
+        const double d = YW[int64_t(i) * b + j] - lam[j] * QW[int64_t(i) * b + j];
+        part += d * d;
+      }
+      worst = fmax(worst, sqrt(block_sum(part, sh.red)));
+    }
+    if (worst <= 1e-12 * top) *conv = 1;
+    if (*conv || it >= max_it) break;
+    for (int64_t e = tid; e < int64_t(n) * b; e += nt) Q[e] = YW[e];
+    __syncthreads();
+    orth_columns(Q, n, b, b, sh.coef, sh.red);
+  }
+  for (int j = tid; j < r; j += nt) sv[j] = sqrt(fmax(lam[j], 0.0));
+  for (int64_t e = tid; e < int64_t(n) * r; e += nt) U[e] = QW[(e / r) * b + e % r];
+  __syncthreads();
+  // A^T (Q W) = Z W
+  gemm_f64(m, r, b, [&](int c, int k) { return Z[int64_t(c) * b + k]; }, [&](int k, int j) { return W[k * b + j]; },
+           [&](int c, int j, double v) { Uo[int64_t(c) * r + j] = sv[j] > 0.0 ? v / sv[j] : 0.0; });
+  return it;
+}
+
 // A leaf of one slice of a three-way series (leaf length 1): the temporal
 // mode has length one, so its rank is one, the two other ranks are equal
 // (r_2 <= r_1 r_3 and r_3 <= r_1 r_2), and Tucker-ALS on the slice reaches
 // its truncated SVD: U^(2) the leading r left singular vectors of the D_2 x
 // D_3 slice X, U^(3) = X^T U^(2) diag(1/s) (orthonormalised), the core
-// U^(2)T X U^(3) (diagonal up to rounding), U^(1) = [1].  One eigensolve of
-// the smaller Gram instead of the sweeps.  Leaves the results where
+// U^(2)T X U^(3) (diagonal up to rounding), U^(1) = [1].  The leading
+// singular vectors of the smaller side come from one eigensolve of its Gram
+// (LEAF_SLICE_GRAM) or from subspace iteration on it (LEAF_SLICE_ITER);
+// the other side's follow from them.  Leaves the results where
 // block_tucker_als leaves them.
-__device__ __forceinline__ AlsResult slice_svd(const float* X, const int32_t* Dm, int r, int n_lds, double* lds,
-                                               char* ws, const LeafLayout& lo, LeafShared& sh) {
+__device__ __forceinline__ AlsResult slice_svd(const float* X, const int32_t* Dm, int r, int max_it, int n_lds,
+                                               double* lds, char* ws, const LeafLayout& lo, LeafShared& sh) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int D2 = Dm[1], D3 = Dm[2];
   double part = 0.0;
@@ -199,33 +331,49 @@ __device__ __forceinline__ AlsResult slice_svd(const float* X, const int32_t* Dm
   float* Uf2 = reinterpret_cast<float*>(ws + lo.Uf[2]);
   float* G = reinterpret_cast<float*>(ws + lo.G);
   double* TMP = reinterpret_cast<double*>(ws + lo.TMP);
-  // the smaller side's Gram and its leading eigenvectors
   const bool left = D2 <= D3;
-  const int n = left ? D2 : D3;
-  double* Wm = n <= n_lds ? lds : reinterpret_cast<double*>(ws + lo.EIG);
-  if (left) gram_mode_mfma(X, 1, D2, D3, Wm, D2);
-  else gram_other(X, 1, D2, D3, Wm, D3);
-  double* Us = left ? Ud1 : Ud2;  // from the eigensolver
-  double* Uo = left ? Ud2 : Ud1;  // the other side, X^T U / s or X V / s
-  const int Do = left ? D3 : D2;
-  const double* lam = eig_top(Wm, n, r, Us, r, sh.red, TMP, nullptr, Wm + int64_t(n) * n);
-  double* sv = sh.coef;  // r <= kMaxRank <= 64
-  for (int j = tid; j < r; j += nt) sv[j] = sqrt(fmax(lam[j], 0.0));
-  __syncthreads();
-  // the other side's vectors: Uo[d][j] = sum_c X(., .) Us[c][j] / s_j
-  gemm_f64(Do, r, n,
-           [&](int d, int c) { return left ? double(X[int64_t(c) * D3 + d]) : double(X[int64_t(d) * D3 + c]); },
-           [&](int c, int j) { return Us[int64_t(c) * r + j]; },
-           [&](int d, int j, double v) { Uo[int64_t(d) * r + j] = sv[j] > 0.0 ? v / sv[j] : 0.0; });
-  orthonormalize(Uo, Do, r, r, 1, sh.coef + 32, sh.red, &sh.flag);
-  // core G = U^(2)T X U^(3) (r x r), FP64 sums
-  double* XU3 = TMP;  // D2 x r
-  gemm_f64(D2, r, D3, [&](int i, int c) { return double(X[int64_t(i) * D3 + c]); },
-           [&](int c, int j) { return Ud2[int64_t(c) * r + j]; }, [&](int i, int j, double v) { XU3[int64_t(i) * r + j] = v; });
+  const int n = left ? D2 : D3;   // the smaller side
+  const int Do = left ? D3 : D2;  // the other side
+  double* Us = left ? Ud1 : Ud2;  // leading singular vectors of the smaller side
+  double* Uo = left ? Ud2 : Ud1;  // the other side's, X^T U / s or X V / s
+  double* sv = sh.coef + 32;      // r <= 32 singular values
+  int steps = 1, conv = 1;
+  double* P;  // n x r scratch for the core
+  if (lo.route == LEAF_SLICE_ITER) {
+    const int b = slice_block(n, r);
+    auto a = [&](int i, int c) {
+      return left ? double(X[int64_t(i) * D3 + c]) : double(X[int64_t(c) * D3 + i]);
+    };
+    steps = subspace_top(a, n, Do, r, b, max_it, n_lds, lds, ws, lo, sh, Us, Uo, sv, &conv);
+    P = reinterpret_cast<double*>(ws + lo.SY);  // n x b >= n x r
+  } else {
+    double* Wm = n <= n_lds ? lds : reinterpret_cast<double*>(ws + lo.EIG);
+    if (left) gram_mode_mfma(X, 1, D2, D3, Wm, D2);
+    else gram_other(X, 1, D2, D3, Wm, D3);
+    const double* lam = eig_top(Wm, n, r, Us, r, sh.red, TMP, nullptr, Wm + int64_t(n) * n);
+    for (int j = tid; j < r; j += nt) sv[j] = sqrt(fmax(lam[j], 0.0));
+    __syncthreads();
+    gemm_f64(Do, r, n,
+             [&](int d, int c) { return left ? double(X[int64_t(c) * D3 + d]) : double(X[int64_t(d) * D3 + c]); },
+             [&](int c, int j) { return Us[int64_t(c) * r + j]; },
+             [&](int d, int j, double v) { Uo[int64_t(d) * r + j] = sv[j] > 0.0 ? v / sv[j] : 0.0; });
+    P = TMP;  // eig_tmp_doubles(n) = n max(n, 128) >= n r
+  }
+  orthonormalize(Uo, Do, r, r, 1, sh.coef, sh.red, &sh.flag);
+  // core G = U^(2)T X U^(3) (r x r) in FP64, through the smaller side's
+  // n x r product
+  if (left) {  // P = X U^(3) (D2 x r), G = U^(2)T P
+    gemm_f64(D2, r, D3, [&](int i, int c) { return double(X[int64_t(i) * D3 + c]); },
+             [&](int c, int j) { return Ud2[int64_t(c) * r + j]; }, [&](int i, int j, double v) { P[int64_t(i) * r + j] = v; });
+    gemm_f64(r, r, D2, [&](int a, int i) { return Ud1[int64_t(i) * r + a]; },
+             [&](int i, int j) { return P[int64_t(i) * r + j]; }, [&](int a, int j, double v) { G[a * r + j] = float(v); });
+  } else {  // P = X^T U^(2) (D3 x r), G = P^T U^(3)
+    gemm_f64(D3, r, D2, [&](int c, int i) { return double(X[int64_t(i) * D3 + c]); },
+             [&](int i, int a) { return Ud1[int64_t(i) * r + a]; }, [&](int c, int a, double v) { P[int64_t(c) * r + a] = v; });
+    gemm_f64(r, r, D3, [&](int a, int c) { return P[int64_t(c) * r + a]; },
+             [&](int c, int j) { return Ud2[int64_t(c) * r + j]; }, [&](int a, int j, double v) { G[a * r + j] = float(v); });
+  }
   part = 0.0;
-  gemm_f64(r, r, D2, [&](int a, int i) { return Ud1[int64_t(i) * r + a]; },
-           [&](int i, int j) { return XU3[int64_t(i) * r + j]; },
-           [&](int a, int j, double v) { G[a * r + j] = float(v); });
   for (int e = tid; e < r * r; e += nt) part += double(G[e]) * double(G[e]);
   const double g2 = block_sum(part, sh.red);
   for (int64_t e = tid; e < int64_t(D2) * r; e += nt) Uf1[e] = float(Ud1[e]);
@@ -233,7 +381,7 @@ __device__ __forceinline__ AlsResult slice_svd(const float* X, const int32_t* Dm
   if (tid == 0) Uf0[0] = 1.0f;
   __syncthreads();
   const double fit = nx2 > 0.0 ? 1.0 - sqrt(fmax(0.0, nx2 - g2)) / sqrt(nx2) : 1.0;
-  return AlsResult{fit, nx2, g2, 1, 1};
+  return AlsResult{fit, nx2, g2, steps, conv};
 }
 
 __global__ __launch_bounds__(NT_LEAF, 2) void leaf_kernel(LeafArgs args) {
@@ -250,8 +398,8 @@ __global__ __launch_bounds__(NT_LEAF, 2) void leaf_kernel(LeafArgs args) {
   int32_t Dm[MAXP];
   Dm[0] = int32_t(st.ell);
   for (int n = 1; n < p; ++n) Dm[n] = int32_t(st.D[n]);
-  const bool svd = p == 3 && st.ell == 1 && rq[0] == 1 && rq[1] == rq[2];
-  const AlsResult r = svd ? slice_svd(job.X, Dm, rq[1], args.n_lds, lds, ws, lo, sh)
+  const bool svd = lo.route != LEAF_ALS;
+  const AlsResult r = svd ? slice_svd(job.X, Dm, rq[1], kSliceIterMax, args.n_lds, lds, ws, lo, sh)
                           : block_tucker_als(job.X, Dm, rq, p, 0, args.max_iter, args.tol, args.n_lds, lds, ws, lo, sh);
   // store the leaf: core, non-temporal factors, temporal rows
   const int64_t b = job.block;

@@ -22,7 +22,8 @@ Recipe (all FP64, NumPy PCG64):
 
 Random draws for slices are made per chunk of CHUNK slices from
 SeedSequence([seed, chunk]), so any time range can be produced without
-generating what precedes it.  FP32 workloads are rounded to FP32 and promoted
+generating what precedes it; the noise of large slices is drawn in chunks
+of fewer slices (at most NOISE_CHUNK_ELEMS elements a chunk).  FP32 workloads are rounded to FP32 and promoted
 back to FP64, so the oracle sees exactly the values the GPU sees.
 """
 
@@ -35,6 +36,7 @@ from typing import Optional, Sequence, Tuple
 import numpy as np
 
 CHUNK = 256
+NOISE_CHUNK_ELEMS = 1 << 24
 
 
 @dataclasses.dataclass(frozen=True)
@@ -97,10 +99,15 @@ D5_SHAPES = {3: (1000, 1000), 4: (100, 100, 100), 5: (100, 100, 10, 10), 6: (100
 
 def d5(p: int, T: int = 400) -> Workload:
     dims = D5_SHAPES[p]
-    return Workload("d5_p%d" % p, dims, T, (5,) * p, 0.05, 1, (5,) * p, 256, "uniform_len", seed=3000 + p)
+    name = "d5_p%d" % p if T == 400 else "d5_p%d_T%d" % (p, T)
+    return Workload(name, dims, T, (5,) * p, 0.05, 1, (5,) * p, 256, "uniform_len", seed=3000 + p)
 
 
 def get(name: str) -> Workload:
+    """A workload by name: the table above, or d5_p<p> / d5_p<p>_T<T>."""
+    if name.startswith("d5_p"):
+        parts = name[4:].split("_T")
+        return d5(int(parts[0]), int(parts[1]) if len(parts) > 1 else 400)
     return WORKLOADS[name]
 
 
@@ -167,13 +174,18 @@ def _expand(G, A, Bs) -> np.ndarray:
     return Y
 
 
+def _noise_chunk(wl: Workload) -> int:
+    return max(1, min(CHUNK, NOISE_CHUNK_ELEMS // math.prod(wl.dims)))
+
+
 def _noise(wl: Workload, t0: int, t1: int) -> np.ndarray:
     out = np.empty((t1 - t0,) + wl.dims)
-    for c in range(t0 // CHUNK, -(-t1 // CHUNK)):
-        lo, hi = max(t0, c * CHUNK), min(t1, (c + 1) * CHUNK)
+    ch = _noise_chunk(wl)
+    for c in range(t0 // ch, -(-t1 // ch)):
+        lo, hi = max(t0, c * ch), min(t1, (c + 1) * ch)
         rng = _rng(wl.seed, 2, c)
-        e = rng.standard_normal((CHUNK,) + wl.dims)
-        out[lo - t0:hi - t0] = e[lo - c * CHUNK:hi - c * CHUNK]
+        e = rng.standard_normal((ch,) + wl.dims)
+        out[lo - t0:hi - t0] = e[lo - c * ch:hi - c * ch]
     return out
 
 

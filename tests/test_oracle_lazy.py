@@ -98,3 +98,16 @@ def test_worker_subtrees_equal_eager():
     G1, U1, _ = eager.query(5, 250)
     G2, U2, _ = lazy.query(5, 250)
     assert np.array_equal(G1, G2) and all(np.array_equal(x, y) for x, y in zip(U1, U2))
+
+
+def test_any_slice_range_of_large_slices_matches_the_whole(monkeypatch):
+    """Large slices draw their noise in chunks of fewer slices; a range cut
+    anywhere equals the same rows of the whole series (what the worker
+    processes and the on-demand tree rely on)."""
+    from synth import workloads
+    monkeypatch.setattr(workloads, "NOISE_CHUNK_ELEMS", 3 * 20 * 20)
+    wl = synth.Workload("chunks", (20, 20), 40, (3, 3, 3), 0.1, 1, (3, 3, 3), 4, "pairs", seed=77)
+    assert workloads._noise_chunk(wl) == 3
+    X = synth.series(wl)
+    for a, b in ((0, 40), (1, 2), (2, 7), (5, 6), (17, 40)):
+        np.testing.assert_array_equal(synth.series(wl, a, b), X[a:b])

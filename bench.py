@@ -426,6 +426,60 @@ def cpu_info():
     return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
 
 
+def raw_main(args):
+    """Tucker-ALS from scratch on long raw ranges of the serving workload's
+    series (128 x 128 slices, ranks 16): the many-workgroup streaming
+    decomposition (tk_raw_tucker_stream) at several lengths, and the
+    one-workgroup-per-range kernel (tk_raw_tucker) on the shortest.  Each
+    pass reads the range once ((p - 1) HOSVD passes, then p per sweep), so
+    the effective read bandwidth is passes x bytes / time, against HBM's."""
+    import torch
+    import synth
+    from paper_2501_06647_amd import Tree
+
+    wl = synth.get(args.workload)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    lens = [int(x) for x in args.raw_lengths.split(",")]
+    T = max(lens)
+    t0 = time.perf_counter()
+    Xd = _device_series(wl, T, dev)
+    print("[raw] generated %d slices in %.1f s" % (T, time.perf_counter() - t0), file=sys.stderr, flush=True)
+    tree = Tree(wl.dims, wl.node_ranks, wl.leaf_len, wl.theta, wl.max_iter, wl.tol, capacity_T=wl.T)
+    slice_bytes = int(np.prod(wl.dims)) * 4
+    p = 1 + len(wl.dims)
+    rows = []
+    for L in lens:
+        r = tree.raw_tucker_stream(Xd, 0, L)  # warm-up (buffers)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):
+            t1 = time.perf_counter()
+            r = tree.raw_tucker_stream(Xd, 0, L)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+        sec = float(np.median(ts))
+        passes = (p - 1) + p * r.sweeps
+        gbs = passes * L * slice_bytes / sec / 1e9
+        row = {"L": L, "ms": 1000 * sec, "sweeps": r.sweeps, "passes": passes, "read_GB_per_s": gbs,
+               "hbm_frac": gbs / (HBM_TBPS * 1000), "err_model": r.err_model}
+        rows.append(row)
+        print("[raw] streaming %s" % json.dumps(row), file=sys.stderr, flush=True)
+    L = min(lens)
+    t1 = time.perf_counter()
+    one = tree.raw_tucker(Xd, np.array([0]), np.array([L]))[0]
+    torch.cuda.synchronize()
+    one_ms = 1000 * (time.perf_counter() - t1)
+    print("[raw] one workgroup per range, L=%d: %.1f ms (%d sweeps)" % (L, one_ms, one.sweeps), file=sys.stderr,
+          flush=True)
+    tree.close()
+    out = {"metric": "Tucker-ALS from scratch on a raw range (streaming, many workgroups)", "unit": "ms",
+           "config": {"workload": "%s: %s slices, ranks %s, <=%d sweeps, tol %g"
+                                  % (wl.name, "x".join(map(str, wl.dims)), wl.node_ranks, wl.max_iter, wl.tol)},
+           "streaming": rows, "one_workgroup": {"L": L, "ms": one_ms, "sweeps": one.sweeps}}
+    print(json.dumps(out), flush=True)
+
+
 def _device_series(wl, T, dev, chunk=4096):
     """The workload's first T slices as one FP32 device tensor, generated in
     chunks (host memory stays at one chunk)."""
@@ -737,6 +791,9 @@ def main():
     ap.add_argument("--pscale-tune-p", default="3,4,5,6",
                     help="numbers of modes autotuned in --pscale (the others reuse the previous tuning)")
     ap.add_argument("--pscale-tuning", default=None, help="JSON tuning for every p of --pscale")
+    ap.add_argument("--raw", action="store_true",
+                    help="Tucker-ALS from scratch on long raw ranges (streaming, many workgroups)")
+    ap.add_argument("--raw-lengths", default="4096,16384,65536", help="range lengths for --raw")
     ap.add_argument("--tradeoff", action="store_true",
                     help="theta sweep and fixed-block variant: throughput and error per hit-set rule")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -754,6 +811,8 @@ def main():
         if args.workload == "plain":
             args.workload = "serving"
         return serve_main(args)
+    if args.raw:
+        return raw_main(args)
     if args.tradeoff:
         return tradeoff_main(args)
     if args.pscale:

@@ -234,6 +234,25 @@ tk_status tk_set_query_ranks(tk_tree* t, const int32_t* ranks);
  * stream.  TK_EINVAL for null buffers or L outside [1, 2^30]. */
 tk_status tk_raw_tucker(tk_tree* t, int32_t n, const float* const* X, const int64_t* L, tk_result* res);
 
+/* Tucker-ALS from scratch on one long raw range with many workgroups: the
+ * same iteration as tk_raw_tucker (Sec. 2's Tucker-ALS, HOSVD init of
+ * U^(2..p), sweeps from the temporal mode, the query sweep cap, tolerance and
+ * output ranks), with each pass over the range split into spans of
+ * consecutive slices, one workgroup per span (at most 512), and the spans'
+ * partial Grams and mode products summed in a fixed order.  Every pass reads
+ * the range once: p passes per sweep, bound by HBM.  X is a DEVICE array of
+ * L slices (L x D_2 x ... x D_p floats, C order) that must stay valid until
+ * the call returns; res is sized by tk_query_shape for length L (core and
+ * factors caller-owned device buffers, written in FP32; the factors also
+ * serve as the passes' FP32 operands).  Synchronous on the tree's stream; the
+ * library keeps its working buffers (about L (R_1 + 2 r_1) 8 bytes plus
+ * 512 spans' partials, R_1 the product of the non-temporal output ranks)
+ * until tk_destroy.  A temporal factor of rank below r_1 (zero singular
+ * values) keeps zero columns instead of being completed to an orthonormal
+ * basis.  TK_EINVAL for null buffers, L outside [1, 2^31), a slice dimension
+ * above 1024 or R_1 above 1024. */
+tk_status tk_raw_tucker_stream(tk_tree* t, const float* X, int64_t L, tk_result* res);
+
 /* Hit sets of later queries: level -1 (default) is Alg. "recall" with the
  * tree's theta; level >= 0 the fixed-block variant of the paper's
  * efficiency-accuracy comparison: every complete node of that level

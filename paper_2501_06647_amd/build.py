@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 OBJ_DIR = os.path.join(HERE, "_build")
-SOURCES = ["csrc/tk_kernels.hip", "csrc/tk_capi.hip", "csrc/tk_batch.hip", "csrc/tk_serve.hip", "csrc/tk_tail.hip"]
+SOURCES = ["csrc/tk_kernels.hip", "csrc/tk_capi.hip", "csrc/tk_batch.hip", "csrc/tk_serve.hip", "csrc/tk_tail.hip", "csrc/tk_stream.hip"]
 STITCH_SOURCE = "csrc/tk_stitch_inst.hip"
 STITCH_INSTANCES = [(64, 4), (128, 4), (256, 4), (64, 7), (128, 7), (256, 7)]
 HEADERS = ["csrc/tk_common.hpp", "csrc/tk_device.hpp", "csrc/tk_internal.hpp", "csrc/tk_host.hpp",

@@ -124,6 +124,7 @@ void lane_destroy(Lane* l) {
   release(&l->leaf_ws);
   release(&l->leaf_jobs);
   release(&l->xbuf);
+  for (DevBuf& b : l->sx) release(&b);
   for (int g = 0; g < kMaxGroups; ++g) {
     release(&l->ws[g]);
     release(&l->jobs[g]);

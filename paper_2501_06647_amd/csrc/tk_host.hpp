@@ -76,6 +76,7 @@ struct Lane {
   DevBuf hits, stats, queue;
   DevBuf ws[kMaxGroups], jobs[kMaxGroups], trims[kMaxGroups];
   DevBuf leaf_ws, leaf_jobs, xbuf;
+  DevBuf sx[6];  // streaming Tucker-ALS: projections, partials, Y, U^(1), small buffers, solver
   hipStream_t gstream[kMaxGroups] = {};
   hipEvent_t gev[kMaxGroups] = {};
   hipEvent_t fork_ev = nullptr;

@@ -75,6 +75,54 @@ struct RawArgs {
   double tol;
 };
 
+// Tucker-ALS on one long raw range with many workgroups (streaming): every
+// pass splits the range into spans of `span` consecutive slices, one
+// workgroup each, and each workgroup writes its own partial result (slot
+// blockIdx.x of `part`, part_elems doubles), summed afterwards in a fixed
+// order.
+struct StreamArgs {
+  const float* X;      // L slices, C order
+  int64_t L;
+  int64_t slice;       // elements per slice
+  int64_t span;        // slices per workgroup (the last takes the rest)
+  int p;
+  int32_t D[MAXP];     // D[1..p-1]
+  int32_t rq[MAXP];    // output ranks
+  int skip;            // mode of the pass (0: temporal)
+  float* Uf[MAXP];     // FP32 factors; Uf[0] is L x r_1, indexed by slice
+  char* ws;            // per-workgroup projection buffers: T1 at 0, T2 at t2_off
+  int64_t ws_per, t2_off;
+  float* Y;            // temporal pass: the L x R_1 projected rows
+  double* part;
+  int64_t part_elems;
+  double* nx2;         // Gram pass of mode 1: ||X||^2 of each span (or null)
+};
+
+// One-workgroup steps between the passes.  op 0: the leading r
+// eigenvectors of the n x n FP64 matrix `gram` into U64 (n x r) and U32,
+// sqrt of the eigenvalues into sv.  op 1: the leading r left singular
+// vectors of mode `mode` of the FP32 tensor Z (dims) into U64 and U32; with
+// core set, also core = Z x_mode U^T (mode the last) and out[0] = ||core||^2.
+// op 2: R^{-1} (r x r, upper) of the Cholesky factor R of the r x r Gram
+// `gram` of U^(1), into U64.
+struct SolveArgs {
+  int op;
+  int p, mode, r;
+  int32_t dims[MAXP];
+  int64_t L;
+  const double* gram;
+  const float* Z;
+  double* U64;
+  float* U32;
+  double* sv;
+  float* core;
+  double* out;
+  double* vbuf;      // op 1: other-side vectors
+  char* ws;          // eigensolver scratch (TMP at tmp_off, matrix at eig_off)
+  int64_t tmp_off, eig_off;
+  int n_lds;
+};
+
 // threads: 64 (one wavefront per job), 128 or 256 (jobs with large
 // eigenproblems).  grid <= n_jobs; with a.queue set the grid may be smaller
 // than n_jobs and the queue counter must read 0 at launch (reset_queue).
@@ -103,6 +151,20 @@ hipError_t launch_leaf(const LeafArgs& a, int n_jobs, size_t lds_bytes, hipStrea
 // one NT_LEAF workgroup per raw range
 hipError_t launch_raw(const RawArgs& a, int n_jobs, size_t lds_bytes, hipStream_t stream);
 hipError_t set_lds_limits(size_t stitch_bytes, size_t leaf_bytes);
+// streaming Tucker-ALS passes: one NT_LEAF workgroup per span
+hipError_t launch_stream_gram(const StreamArgs& a, int64_t n_spans, hipStream_t stream);
+hipError_t launch_stream_project(const StreamArgs& a, int64_t n_spans, hipStream_t stream);
+// U64 rows [span b] = Y rows V diag(1 / sv) (V: R_1 x r), the rows' partial
+// Gram into part
+hipError_t launch_stream_u1(const StreamArgs& a, int64_t n_spans, const double* V, const double* sv, double* U64,
+                            hipStream_t stream);
+// U64 rows <- U64 rows Rinv (Rinv r_1 x r_1 upper triangular), and U32 = U64
+hipError_t launch_stream_u1_fix(const StreamArgs& a, int64_t n_spans, const double* Rinv, double* U64, float* U32,
+                                hipStream_t stream);
+// out = sum over n_parts of part[b][e] (FP64, in b order), into out64 and/or out32
+hipError_t launch_stream_reduce(const double* part, int64_t n_parts, int64_t E, double* out64, float* out32,
+                                hipStream_t stream);
+hipError_t launch_stream_solve(const SolveArgs& a, size_t lds_bytes, hipStream_t stream);
 // workgroups of the stitch kernel with `threads` threads and lds_bytes of
 // dynamic LDS that one CU holds at once
 int stitch_blocks_per_cu(int threads, size_t lds_bytes);

@@ -434,6 +434,202 @@ __global__ __launch_bounds__(NT_LEAF, 2) void raw_kernel(RawArgs args) {
 }
 
 // ------------------------------------------------------------------------------
+// Streaming Tucker-ALS on one long raw range: each pass gives every workgroup
+// a span of consecutive slices, treated as a block of the range; what a
+// pass reduces over time (a Gram, a mode-n product with U^(1)'s rows of the
+// span) is linear in the slices, so the spans' partials sum to the range's.
+// ------------------------------------------------------------------------------
+__device__ __forceinline__ int64_t span_rows(const StreamArgs& a, int64_t t0) {
+  const int64_t t1 = t0 + a.span < a.L ? t0 + a.span : a.L;
+  return t1 - t0;
+}
+
+// Partial Gram of mode a.skip (>= 1) of the span, and with a.nx2 its
+// squared norm.
+__global__ __launch_bounds__(NT_LEAF, 2) void stream_gram_kernel(StreamArgs a) {
+  __shared__ double red[8];
+  const int64_t t0 = int64_t(blockIdx.x) * a.span;
+  const int64_t rows = span_rows(a, t0);
+  const float* Xc = a.X + t0 * a.slice;
+  int32_t Dm[MAXP];
+  Dm[0] = int32_t(rows);
+  for (int m = 1; m < a.p; ++m) Dm[m] = a.D[m];
+  const int n = a.skip;
+  gram_mode_mfma(Xc, prod_range(Dm, 0, n), Dm[n], prod_range(Dm, n + 1, a.p), a.part + int64_t(blockIdx.x) * a.part_elems,
+                 Dm[n]);
+  if (a.nx2) {
+    double part = 0.0;
+    for (int64_t e = threadIdx.x; e < rows * a.slice; e += blockDim.x) part += double(Xc[e]) * double(Xc[e]);
+    part = block_sum(part, red);
+    if (threadIdx.x == 0) a.nx2[blockIdx.x] = part;
+  }
+}
+
+// The span projected on every mode but a.skip.  Temporal pass: its rows of
+// Y = X x_{m>=2} U^(m)T and the partial Gram of those rows (R_1 x R_1).
+// Mode n >= 1: X_span x_1 U^(1)[span]^T x_{m != n} U^(m)T, the span's share
+// of the mode-n product, as FP64 into its partial slot.
+__global__ __launch_bounds__(NT_LEAF, 2) void stream_project_kernel(StreamArgs a) {
+  const int64_t t0 = int64_t(blockIdx.x) * a.span;
+  const int64_t rows = span_rows(a, t0);
+  int32_t Dm[MAXP];
+  Dm[0] = int32_t(rows);
+  for (int m = 1; m < a.p; ++m) Dm[m] = a.D[m];
+  float* Uf[MAXP];
+  for (int m = 0; m < a.p; ++m) Uf[m] = a.Uf[m];
+  Uf[0] = a.Uf[0] + t0 * a.rq[0];
+  char* ws = a.ws + int64_t(blockIdx.x) * a.ws_per;
+  int32_t dims[MAXP];
+  const float* Yc = project(a.X + t0 * a.slice, Dm, a.p, a.skip, Uf, a.rq, reinterpret_cast<float*>(ws),
+                            reinterpret_cast<float*>(ws + a.t2_off), dims);
+  const int64_t E = prod_range(dims, 0, a.p);
+  double* part = a.part + int64_t(blockIdx.x) * a.part_elems;
+  if (a.skip == 0) {
+    const int64_t R1 = E / rows;
+    for (int64_t e = threadIdx.x; e < E; e += blockDim.x) a.Y[t0 * R1 + e] = Yc[e];
+    gram_mode_mfma(Yc, rows, int(R1), 1, part, int(R1));
+  } else {
+    for (int64_t e = threadIdx.x; e < E; e += blockDim.x) part[e] = double(Yc[e]);
+    __syncthreads();
+  }
+}
+
+// U^(1) rows of the span from the temporal pass, Y V diag(1 / s), and the
+// partial Gram of those rows (r_1 x r_1).
+__global__ __launch_bounds__(NT_LEAF, 2) void stream_u1_kernel(StreamArgs a, const double* V, const double* sv,
+                                                                double* U64) {
+  const int64_t t0 = int64_t(blockIdx.x) * a.span;
+  const int64_t rows = span_rows(a, t0);
+  const int r = a.rq[0];
+  int64_t R1 = 1;
+  for (int m = 1; m < a.p; ++m) R1 *= a.rq[m];
+  for (int64_t e = threadIdx.x; e < rows * r; e += blockDim.x) {
+    const int64_t t = t0 + e / r;
+    const int j = int(e % r);
+    const float* y = a.Y + t * R1;
+    double acc = 0.0;
+    for (int64_t c = 0; c < R1; ++c) acc += double(y[c]) * V[c * r + j];
+    U64[t * r + j] = sv[j] > 0.0 ? acc / sv[j] : 0.0;
+  }
+  __syncthreads();
+  double* part = a.part + int64_t(blockIdx.x) * a.part_elems;
+  for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
+    const int i = e / r, j = e % r;
+    double acc = 0.0;
+    for (int64_t t = t0; t < t0 + rows; ++t) acc += U64[t * r + i] * U64[t * r + j];
+    part[e] = acc;
+  }
+}
+
+// U^(1) <- U^(1) R^{-1} (the Cholesky QR step), and its FP32 copy.
+__global__ __launch_bounds__(NT_LEAF, 2) void stream_u1_fix_kernel(StreamArgs a, const double* Rinv, double* U64,
+                                                                    float* U32) {
+  const int64_t t0 = int64_t(blockIdx.x) * a.span;
+  const int64_t rows = span_rows(a, t0);
+  const int r = a.rq[0];
+  __shared__ double row[NT_LEAF / 8][32];
+  // rows in groups that fit: each group's old values are read before any is rewritten
+  const int per = NT_LEAF / 8 < int(rows) ? NT_LEAF / 8 : int(rows);
+  for (int64_t g = 0; g < rows; g += per) {
+    const int n = rows - g < per ? int(rows - g) : per;
+    for (int e = threadIdx.x; e < n * r; e += blockDim.x) row[e / r][e % r] = U64[(t0 + g + e / r) * r + e % r];
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * r; e += blockDim.x) {
+      const int i = e / r, j = e % r;
+      double acc = 0.0;
+      for (int k = 0; k <= j; ++k) acc += row[i][k] * Rinv[k * r + j];
+      U64[(t0 + g + i) * r + j] = acc;
+      U32[(t0 + g + i) * r + j] = float(acc);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void stream_reduce_kernel(const double* part, int64_t n_parts, int64_t E, double* out64, float* out32) {
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < E; e += int64_t(gridDim.x) * blockDim.x) {
+    double s = 0.0;
+    for (int64_t b = 0; b < n_parts; ++b) s += part[b * E + e];
+    if (out64) out64[e] = s;
+    if (out32) out32[e] = float(s);
+  }
+}
+
+__global__ __launch_bounds__(NT_LEAF, 1) void stream_solve_kernel(SolveArgs a) {
+  extern __shared__ double lds[];
+  __shared__ LeafShared sh;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* TMP = reinterpret_cast<double*>(a.ws + a.tmp_off);
+  const int r = a.r;
+  int64_t rows = 0;
+  if (a.op == 0) {
+    const int n = a.dims[0];
+    double* Wm = n <= a.n_lds ? lds : reinterpret_cast<double*>(a.ws + a.eig_off);
+    for (int64_t e = tid; e < int64_t(n) * n; e += nt) Wm[e] = a.gram[e];
+    __syncthreads();
+    const double* lam = eig_top(Wm, n, r, a.U64, r, sh.red, TMP, nullptr, Wm + int64_t(n) * n);
+    for (int j = tid; j < r; j += nt) a.sv[j] = sqrt(fmax(lam[j], 0.0));
+    rows = n;
+  } else if (a.op == 1) {
+    LeafLayout lo;
+    lo.TMP = a.tmp_off;
+    lo.EIG = a.eig_off;
+    leading_left(a.Z, a.dims, a.p, a.mode, r, a.U64, a.vbuf, a.n_lds, lds, a.ws, lo, sh);
+    rows = a.dims[a.mode];
+    if (a.core) {  // the mode is the last: core[i][j] = sum_d Z[i][d] U[d][j]
+      const int D = a.dims[a.mode];
+      const int64_t R = prod_range(a.dims, 0, a.mode);
+      double part = 0.0;
+      for (int64_t e = tid; e < R * r; e += nt) {
+        const int64_t i = e / r;
+        const int j = int(e % r);
+        double acc = 0.0;
+        for (int d = 0; d < D; ++d) acc += double(a.Z[i * D + d]) * a.U64[int64_t(d) * r + j];
+        a.core[e] = float(acc);
+        part += acc * acc;
+      }
+      part = block_sum(part, sh.red);
+      if (tid == 0) a.out[0] = part;
+    }
+  } else {
+    // Cholesky G = R^T R of the r x r Gram of U^(1), then R^{-1} (upper)
+    // into U64; a pivot at or below 1e-13 of the largest diagonal entry
+    // (U^(1) rank-deficient: a zero singular value of the temporal problem)
+    // leaves that column as it is
+    if (tid == 0) {
+      double* R = TMP;
+      double dmax = 0.0;
+      for (int i = 0; i < r; ++i) dmax = fmax(dmax, a.gram[i * r + i]);
+      for (int e = 0; e < r * r; ++e) R[e] = 0.0;
+      for (int j = 0; j < r; ++j) {
+        double d = a.gram[j * r + j];
+        for (int k = 0; k < j; ++k) d -= R[k * r + j] * R[k * r + j];
+        const bool ok = d > 1e-13 * dmax;
+        R[j * r + j] = ok ? sqrt(d) : 1.0;
+        for (int i = j + 1; i < r; ++i) {
+          double v = a.gram[j * r + i];
+          for (int k = 0; k < j; ++k) v -= R[k * r + j] * R[k * r + i];
+          R[j * r + i] = ok ? v / R[j * r + j] : 0.0;
+        }
+      }
+      double* Ri = a.U64;
+      for (int e = 0; e < r * r; ++e) Ri[e] = 0.0;
+      for (int j = 0; j < r; ++j) {  // column j of R^{-1}: back substitution
+        Ri[j * r + j] = 1.0 / R[j * r + j];
+        for (int i = j - 1; i >= 0; --i) {
+          double v = 0.0;
+          for (int k = i + 1; k <= j; ++k) v += R[i * r + k] * Ri[k * r + j];
+          Ri[i * r + j] = -v / R[i * r + i];
+        }
+      }
+    }
+    rows = 0;
+  }
+  __syncthreads();
+  if (a.U32)
+    for (int64_t e = tid; e < rows * r; e += nt) a.U32[e] = float(a.U64[e]);
+}
+
+// ------------------------------------------------------------------------------
 // Launchers
 // ------------------------------------------------------------------------------
 hipError_t launch_stitch(const StitchArgs& a, int grid, size_t lds_bytes, int threads, hipStream_t stream) {
@@ -474,6 +670,45 @@ hipError_t launch_leaf(const LeafArgs& a, int n_jobs, size_t lds_bytes, hipStrea
   return hipGetLastError();
 }
 
+hipError_t launch_stream_gram(const StreamArgs& a, int64_t n_spans, hipStream_t stream) {
+  if (n_spans <= 0 || n_spans > (int64_t(1) << 20) || a.skip < 1 || a.skip >= a.p) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(stream_gram_kernel, dim3(unsigned(n_spans)), dim3(NT_LEAF), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_project(const StreamArgs& a, int64_t n_spans, hipStream_t stream) {
+  if (n_spans <= 0 || n_spans > (int64_t(1) << 20) || a.skip < 0 || a.skip >= a.p) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(stream_project_kernel, dim3(unsigned(n_spans)), dim3(NT_LEAF), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_u1(const StreamArgs& a, int64_t n_spans, const double* V, const double* sv, double* U64,
+                            hipStream_t stream) {
+  if (n_spans <= 0 || n_spans > (int64_t(1) << 20)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(stream_u1_kernel, dim3(unsigned(n_spans)), dim3(NT_LEAF), 0, stream, a, V, sv, U64);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_u1_fix(const StreamArgs& a, int64_t n_spans, const double* Rinv, double* U64, float* U32,
+                                hipStream_t stream) {
+  if (n_spans <= 0 || n_spans > (int64_t(1) << 20) || a.rq[0] > 32) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(stream_u1_fix_kernel, dim3(unsigned(n_spans)), dim3(NT_LEAF), 0, stream, a, Rinv, U64, U32);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_reduce(const double* part, int64_t n_parts, int64_t E, double* out64, float* out32,
+                                hipStream_t stream) {
+  if (E <= 0 || n_parts <= 0) return hipErrorInvalidValue;
+  const int64_t blocks = (E + 255) / 256 < 4096 ? (E + 255) / 256 : 4096;
+  hipLaunchKernelGGL(stream_reduce_kernel, dim3(unsigned(blocks)), dim3(256), 0, stream, part, n_parts, E, out64, out32);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_solve(const SolveArgs& a, size_t lds_bytes, hipStream_t stream) {
+  hipLaunchKernelGGL(stream_solve_kernel, dim3(1), dim3(NT_LEAF), lds_bytes, stream, a);
+  return hipGetLastError();
+}
+
 hipError_t set_lds_limits(size_t stitch_bytes, size_t leaf_bytes) {
   hipError_t (*const fns[])(size_t) = {stitch_set_lds_64_4, stitch_set_lds_128_4, stitch_set_lds_256_4,
                                        stitch_set_lds_64_7, stitch_set_lds_128_7, stitch_set_lds_256_7};
@@ -481,8 +716,11 @@ hipError_t set_lds_limits(size_t stitch_bytes, size_t leaf_bytes) {
     const hipError_t e = f(stitch_bytes);
     if (e != hipSuccess) return e;
   }
-  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(leaf_kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(leaf_bytes));
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(leaf_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(leaf_bytes));
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(stream_solve_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          int(leaf_bytes));
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(raw_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                              int(leaf_bytes));

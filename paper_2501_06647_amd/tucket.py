@@ -100,6 +100,7 @@ SIGNATURES = [
     ("tk_set_query_ranks", c_i32, [c_vp, c_vp]),
     ("tk_set_query_recall", c_i32, [c_vp, c_i32]),
     ("tk_raw_tucker", c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp]),
+    ("tk_raw_tucker_stream", c_i32, [c_vp, c_vp, c_i64, c_vp]),
     ("tk_get_tuning", c_i32, [c_vp, ctypes.POINTER(TkTuning)]),
     ("tk_set_tuning", c_i32, [c_vp, ctypes.POINTER(TkTuning)]),
     ("tk_batch_create", c_i32, [c_vp, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
@@ -506,6 +507,28 @@ class Tree:
         if n:
             self._check(lib().tk_raw_tucker(self._h, n, ptrs, lens, res), "tk_raw_tucker")
         return [QueryResult(c, f, res[i], p) for i, (c, f) in enumerate(outputs)]
+
+    def raw_tucker_stream(self, X, ts, te) -> QueryResult:
+        """tk_raw_tucker_stream: Tucker-ALS from scratch on the range
+        [ts, te) of the series X (on the device, or moved there) with many
+        workgroups per pass."""
+        X = self._device_f32(X)
+        assert tuple(X.shape[1:]) == self.dims
+        ts, te = int(ts), int(te)
+        if not (0 <= ts < te <= X.shape[0]):
+            raise TuckerError(TK_ERANGE, "raw range outside the series")
+        p = self.p
+        shapes = _query_shapes(self, np.array([ts], dtype=np.int64), np.array([te], dtype=np.int64))[0]
+        buf, views = self._alloc(shapes)
+        core, facs = views[0], views[1:1 + p]
+        res = TkResult()
+        res.core = core.data_ptr()
+        for m in range(p):
+            res.factor[m] = facs[m].data_ptr()
+        slice_bytes = int(np.prod(self.dims)) * 4
+        self._check(lib().tk_raw_tucker_stream(self._h, X.data_ptr() + ts * slice_bytes, te - ts, ctypes.byref(res)),
+                    "tk_raw_tucker_stream")
+        return QueryResult(core, facs, res, p)
 
     def query_batch(self, ts, te) -> List[QueryResult]:
         """tk_query_batch: one synchronous batched call (host Recall and

@@ -136,3 +136,12 @@ def test_create_respects_memory_budget():
     h = ctypes.c_void_p(0)
     assert tk.lib().tk_create(ctypes.byref(cfg), None, ctypes.byref(h)) == tk.TK_ENOMEM
     assert b"mem_budget" in tk.lib().tk_last_error(None)
+
+
+def test_raw_tucker_stream_rejects_null_arguments():
+    """Argument checks before any device work: no tree, no data, no result."""
+    res = tk.TkResult()
+    buf = ctypes.c_float(0.0)
+    assert tk.lib().tk_raw_tucker_stream(None, ctypes.byref(buf), 4, ctypes.byref(res)) == tk.TK_EINVAL
+    assert tk.lib().tk_raw_tucker_stream(None, None, 4, ctypes.byref(res)) == tk.TK_EINVAL
+    assert tk.lib().tk_raw_tucker_stream(None, ctypes.byref(buf), 4, None) == tk.TK_EINVAL

@@ -32,7 +32,12 @@ HBM_TBPS = 8.0
 # launches) scaled by the counters of a reference copy of known size
 # (`--copy-calibration`); keyed by (workload, precision) and valid only for
 # the kernel sources (sha) and the launch tuning they were taken with.
-TRAFFIC_BYTES_PER_STEP = {}
+TRAFFIC_BYTES_PER_STEP = {
+    ("serving", "f32"): {"fetch": 10404818828, "write": 10127307584, "sha": "935fc41dd8416443",
+                         "tuning": {"wide_threshold": 32, "wide_threads": 128, "persistent": 1, "graph": 1,
+                                    "coarse": 1, "lds_n": 64, "basis_pct": 75, "rest_threads": 0,
+                                    "wide_core": 0}},
+}
 
 # Launch tunings of the batched runs (tk_autotune's choices on MI355X for
 # the serving workload's 4096-query list; `--autotune` searches again).
@@ -144,6 +149,9 @@ def serve_main(args):
     qtickets = []
     open_q = []
     lat = []
+    lat_T = []       # horizon at each query's submission, in the order of lat
+    q_T = {}
+    atickets = []
     t_start = time.perf_counter()
     last_print = t_start
     for (tev, kind, i) in events:
@@ -154,7 +162,7 @@ def serve_main(args):
             if tev - now > 2e-4:
                 time.sleep(min(tev - now - 1e-4, 1e-3))
         if kind == 1:
-            srv.submit_append(Xd[T])
+            atickets.append(srv.submit_append(Xd[T]))
             T += 1
         else:
             Tc = (T // ell) * ell
@@ -165,11 +173,13 @@ def serve_main(args):
             tk = srv.submit_query(a, a + L)
             qtickets.append(tk)
             open_q.append(tk)
+            q_T[tk] = T
         # take finished results so device memory stays bounded
         while open_q and srv.poll(open_q[0]):
             tk = open_q.pop(0)
             ts_, tl_, td_ = srv.times(tk)
             lat.append(td_ - ts_)
+            lat_T.append(q_T.pop(tk))
             srv.release(tk)
         if time.perf_counter() - last_print > 5.0:
             last_print = time.perf_counter()
@@ -179,6 +189,12 @@ def serve_main(args):
     for tk in open_q:
         ts_, tl_, td_ = srv.times(tk)
         lat.append(td_ - ts_)
+        lat_T.append(q_T.pop(tk))
+        srv.release(tk)
+    a_lat = []
+    for tk in atickets:
+        ts_, tl_, td_ = srv.times(tk)
+        a_lat.append(td_ - ts_)
         srv.release(tk)
     stats = srv.stats()
     # closed loop: a burst of appends submitted at once, committed as fast as the engine can
@@ -190,7 +206,18 @@ def serve_main(args):
     T += args.burst_appends
     srv.stop()
     lat_ms = np.array(lat) / 1000.0
+    lat_T = np.array(lat_T)
+    a_ms = np.array(a_lat) / 1000.0
     qps = len(qtickets) / wall
+    # query latency against the horizon (quarters of the run's T range) and
+    # append latency (submission to commit)
+    edges = np.linspace(T0, T0 + n_app, 5)
+    by_T = []
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        m = (lat_T >= lo) & (lat_T < hi) if hi < edges[-1] else (lat_T >= lo)
+        if m.any():
+            by_T.append({"T": [int(lo), int(hi)], "queries": int(m.sum()),
+                         "p50": float(np.percentile(lat_ms[m], 50)), "p99": float(np.percentile(lat_ms[m], 99))})
     out = {
         "metric": "serving: range queries/s with p50/p99 latency, appends interleaved",
         "value": qps, "unit": "queries/s", "n_gpus": 1, "steps": len(qtickets), "warmup": 0,
@@ -203,6 +230,9 @@ def serve_main(args):
                                   args.qps, args.aps, args.serve_prec, args.serve_slots)},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "max": float(lat_ms.max())},
+        "latency_by_horizon_ms": by_T,
+        "append_latency_ms": {"p50": float(np.percentile(a_ms, 50)), "p99": float(np.percentile(a_ms, 99)),
+                              "max": float(a_ms.max())} if len(a_ms) else None,
         "appends_per_s": n_app / wall,
         "closed_loop_appends_per_s": args.burst_appends / burst_s,
         "server": stats,
@@ -781,7 +811,8 @@ def main():
     ap.add_argument("--serve", action="store_true", help="serving run instead of the batched benchmark")
     ap.add_argument("--qps", type=float, default=2000.0)
     ap.add_argument("--aps", type=float, default=1000.0)
-    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--serve-seconds", type=float, default=63.0,
+                    help="serving run length: at 1000 appends/s from 256 slices the horizon reaches 63256")
     ap.add_argument("--serve-prefix", type=int, default=256)
     ap.add_argument("--serve-prec", default="f32", help="query arithmetic while serving: f32 or bf16")
     ap.add_argument("--serve-slots", type=int, default=256, help="job slots (concurrent queries) per class")

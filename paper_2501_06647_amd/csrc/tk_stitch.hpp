@@ -144,15 +144,21 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
   }
   double* red = sh.red;
   // the ALS contractions (TTM chains, Z^(n), core update) and their Grams:
-  // FP32 on the matrix cores, or BF16 operands with FP32 accumulation
+  // FP32 on the matrix cores, or BF16 operands with FP32 accumulation.  In
+  // the BF16 mode the last mode's chain and the core update keep FP32
+  // operands: the sweep's stop test compares fits through |Y~|^2 - |G|^2,
+  // which cancels to a few per mille of |Y~|^2 at the workloads' fits, so
+  // the BF16 rounding of |G|^2 (~2^-9 relative) would exceed the tolerance
+  // and hold the stop back for extra sweeps.
+  bool lp = lowp;
   auto ttm = [&](const float* X, int64_t a, int r, int64_t b, const float* A, int64_t as, int64_t bs, int m,
                  float* Y, bool acc) {
-    if (lowp) mode_product_bf16(X, a, r, b, A, as, bs, m, Y, acc);
+    if (lp) mode_product_bf16(X, a, r, b, A, as, bs, m, Y, acc);
     else if (PM > PM_FEW && m <= 8 && r <= 8) mode_product_fiber<float, float, float, float, 8>(X, a, r, b, A, as, bs, m, Y, acc);
     else mode_product(X, a, r, b, A, as, bs, m, Y, acc);
   };
   auto gram = [&](const float* X, int64_t a, int q, int64_t b, double* G, int ld) {
-    if (lowp) gram_mode_bf16(X, a, q, b, G, ld);
+    if (lp) gram_mode_bf16(X, a, q, b, G, ld);
     else gram_mode_mfma(X, a, q, b, G, ld);
   };
   auto Fp = [&](int64_t off) { return reinterpret_cast<float*>(ws + off); };
@@ -376,6 +382,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
   int sweeps = 0, conv = 0;
   double g2 = 0.0;
   for (int it = 1; it <= max_iter; ++it) {
+    lp = lowp;
     // temporal mode: M = [mat_1(H~_i x_{m>=2} A_i^(m))]_i, P_0 = leading eigvecs of M M^T
     float* M = Fp(lo.M);
     for (int i = 0; i < s; ++i) {
@@ -411,6 +418,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     float* K = Fp(lo.K);
     float* Wst = Fp(lo.WS);
     for (int n = 1; n < p; ++n) {
+      lp = lowp && n < p - 1;
       const int q = sh.q[n];
       int32_t kd[PM];
       for (int m = 0; m < p; ++m) kd[m] = rq[m];

@@ -45,8 +45,8 @@ TRAFFIC_BYTES_PER_STEP = {
 TUNINGS = {
     ("serving", "f32"): {"wide_threshold": 32, "wide_threads": 128, "persistent": 1, "graph": 1, "coarse": 1,
                          "lds_n": 64, "basis_pct": 75, "rest_threads": 0, "wide_core": 0},
-    ("serving", "bf16"): {"wide_threshold": 32, "wide_threads": 256, "persistent": 1, "graph": 1, "coarse": 1,
-                          "lds_n": 64, "basis_pct": 75, "rest_threads": 0, "wide_core": 0},
+    ("serving", "bf16"): {"wide_threshold": 32, "wide_threads": 128, "persistent": 0, "graph": 1, "coarse": 1,
+                          "lds_n": 48, "basis_pct": 75, "rest_threads": 0, "wide_core": 0},
 }
 KERNEL_SOURCES = ("tk_common.hpp", "tk_device.hpp", "tk_internal.hpp", "tk_kernels.hip", "tk_stitch.hpp",
                   "tk_stitch_inst.hip")

@@ -132,3 +132,15 @@ def test_raw_tucker_stream_batch_workload(torch):
     worst = _check_stream(gpu, wl, X, [(1000, 9000)], wl.node_ranks, wl.max_iter, wl.tol)
     say("streaming Tucker-ALS batch workload, 8000 slices: delta %.2e" % worst)
     assert worst <= DELTA
+
+
+def test_raw_tucker_stream_four_modes(torch):
+    """The precision workload's four-way shape (200 x 24 x 8 slices, ranks
+    (20, 20, 6, 4), R_1 = 480) on 1000 slices against the oracle."""
+    from paper_2501_06647_amd import Tree
+    wl = synth.get("precision")
+    X = synth.series(wl, 0, 1200)
+    gpu = Tree(wl.dims, wl.node_ranks, wl.leaf_len, wl.theta, max_iter=wl.max_iter, tol=wl.tol, capacity_T=wl.T)
+    worst = _check_stream(gpu, wl, X, [(100, 1100), (0, 37)], wl.node_ranks, wl.max_iter, wl.tol)
+    say("streaming Tucker-ALS precision workload: delta %.2e" % worst)
+    assert worst <= DELTA

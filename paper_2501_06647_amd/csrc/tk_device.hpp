@@ -67,37 +67,12 @@ __device__ __forceinline__ void block_argmax(double& v, int& idx, double* red, i
   __syncthreads();
 }
 
-// Exchange a double with the lane whose index differs in bit 0 (CTRL 0xB1)
-// or bit 1 (CTRL 0x4E) inside each group of four lanes (DPP quad_perm).
-template <int CTRL>
-__device__ __forceinline__ double quad_swap(double v) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-
-// 1/x and 1/sqrt(x) for finite x > 0: the hardware approximations refined by
-// two Newton steps each (quadratic convergence to FP64 rounding).
+// 1/x for finite nonzero x: the hardware approximation refined by two
+// Newton steps (quadratic convergence to FP64 rounding).
 __device__ __forceinline__ double fast_rcp(double x) {
   double y = __builtin_amdgcn_rcp(x);
   y = fma(y, fma(-x, y, 1.0), y);
   y = fma(y, fma(-x, y, 1.0), y);
-  return y;
-}
-
-// 1/x for finite nonzero x of either sign.
-__device__ __forceinline__ double fast_rcp_signed(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  y = fma(y, fma(-x, y, 1.0), y);
-  y = fma(y, fma(-x, y, 1.0), y);
-  return y;
-}
-
-__device__ __forceinline__ double fast_rsqrt(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double hx = 0.5 * x;
-  y = y * fma(-hx * y, y, 1.5);
-  y = y * fma(-hx * y, y, 1.5);
   return y;
 }
 
@@ -886,8 +861,8 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
     double beta = alpha, t = 0.0, scale = 0.0;
     if (s2 > 0.0) {
       beta = -copysign(sqrt(alpha * alpha + s2), alpha);
-      t = (beta - alpha) * fast_rcp_signed(beta);
-      scale = fast_rcp_signed(alpha - beta);
+      t = (beta - alpha) * fast_rcp(beta);
+      scale = fast_rcp(alpha - beta);
     }
     for (int c = i + 1 + tid; c < n; c += nt) {
       const double u = c == i + 1 ? 1.0 : Wi[c] * scale;
@@ -1150,7 +1125,7 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
         double nxr;
         if (fabs(w0) >= fabs(c)) {
           if (fabs(w0) < ptiny) w0 = w0 < 0.0 ? -ptiny : ptiny;
-          const double inv = fast_rcp_signed(w0);
+          const double inv = fast_rcp(w0);
           const double l = c * inv;
           U1[o] = inv;  // reciprocal pivot
           U2[o] = w1;
@@ -1160,7 +1135,7 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
           w0 = a1 - l * w1;
           w1 = b1;
         } else {
-          const double inv = fast_rcp_signed(c);
+          const double inv = fast_rcp(c);
           const double l = w0 * inv;
           U1[o] = inv;
           U2[o] = a1;

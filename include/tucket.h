@@ -122,7 +122,9 @@ typedef struct {
   int32_t height;        /* tree height (Thm. "height-T")                     */
 } tk_stats;
 
-/* Create an empty tree.  hip_stream: a hipStream_t (NULL = default stream);
+/* Create an empty tree (the problem statement, Sec. 3: dimensions, target
+ * ranks, leaf length, theta, sweep cap and tolerance, capacity).
+ * hip_stream: a hipStream_t (NULL = default stream);
  * all device work of the tree is ordered on it.  The node store for
  * capacity_T slices is allocated here.  *out is owned by the caller and
  * released with tk_destroy. */
@@ -262,6 +264,11 @@ tk_status tk_raw_tucker_stream(tk_tree* t, const float* X, int64_t L, tk_result*
  * tree does not have, TK_EBUSY while serving. */
 tk_status tk_set_query_recall(tk_tree* t, int32_t level);
 
+/* Counters of the tree (tk_stats above): slices appended, the committed
+ * horizon, blocks, nodes, height, node-store bytes, and the merges of
+ * Alg. "insert" in total and for the last block (one per block amortized,
+ * Prop. "time_complexity_appending").  Host-only; TK_EINVAL for null
+ * arguments. */
 tk_status tk_stats_get(const tk_tree* t, tk_stats* out);
 
 /* Node store access (checkpoint/restore and tests).  A node (level, index)

@@ -444,10 +444,91 @@ __device__ __forceinline__ int64_t span_rows(const StreamArgs& a, int64_t t0) {
   return t1 - t0;
 }
 
+// Mode Gram G = sum over (x, y) of X[x][:][y] X[x][:][y]^T (q x q, FP64
+// sums of exact FP32 products) for X viewed as (a, q, b) with b >= KC or
+// b = 1, and q <= 16 SG_T: the columns stream through LDS in chunks of KC,
+// loaded along the contiguous index (KC consecutive y, or for b = 1 the
+// rows of KC consecutive x), and each wavefront keeps its 16 x 16 output
+// tiles of the upper triangle in registers over all chunks
+// (v_mfma_f64_16x16x4f64; operand layout that of gemm_f64).  Rows are
+// padded by one float against bank conflicts.
+constexpr int SG_KC = 32;  // columns per chunk
+constexpr int SG_T = 8;    // q <= 128
+constexpr int SG_SLOTS = 9;  // tiles per wavefront: 36 upper tiles over four wavefronts
+__device__ __forceinline__ void gram_staged(const float* __restrict__ X, int64_t a, int q, int64_t b, double* G,
+                                            float (*S)[SG_KC + 1]) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int nw = nt >> 6, w = tid >> 6, l = tid & 63;
+  const int lr = l & 15, lk = l >> 4;
+  const int tq = (q + 15) >> 4;
+  const int tiles = tq * (tq + 1) / 2;
+  int TI[SG_SLOTS], TJ[SG_SLOTS];
+  tk_d4 acc[SG_SLOTS];
+#pragma unroll
+  for (int sl = 0; sl < SG_SLOTS; ++sl) {
+    int t = w + sl * nw, I = 0;
+    while (t >= tq - I && I < tq) {  // upper-triangle tile t -> (I, J), I <= J
+      t -= tq - I;
+      ++I;
+    }
+    TI[sl] = I;
+    TJ[sl] = I + t;
+    acc[sl] = tk_d4{0.0, 0.0, 0.0, 0.0};
+  }
+  const bool rows = b == 1;  // chunks of KC consecutive x, each a contiguous row of q
+  const int64_t nx = rows ? (a + SG_KC - 1) / SG_KC : a;
+  for (int64_t x = 0; x < nx; ++x) {
+    for (int64_t y0 = 0; y0 < b; y0 += SG_KC) {
+      __syncthreads();  // the previous chunk is consumed
+      if (rows) {
+        const int64_t x0 = x * SG_KC;
+        for (int e = tid; e < q * SG_KC; e += nt) {
+          const int k = e / q, i = e % q;
+          S[i][k] = x0 + k < a ? X[(x0 + k) * q + i] : 0.f;
+        }
+      } else {
+        for (int e = tid; e < q * SG_KC; e += nt) {
+          const int i = e / SG_KC, k = e % SG_KC;
+          S[i][k] = y0 + k < b ? X[(x * q + i) * b + y0 + k] : 0.f;
+        }
+      }
+      for (int e = q * SG_KC + tid; e < tq * 16 * SG_KC; e += nt) S[e / SG_KC][e % SG_KC] = 0.f;
+      __syncthreads();
+#pragma unroll
+      for (int sl = 0; sl < SG_SLOTS; ++sl) {
+        if (w + sl * nw < tiles) {
+          const int ri = TI[sl] * 16 + lr, rj = TJ[sl] * 16 + lr;
+#pragma unroll
+          for (int kk = 0; kk < SG_KC / 4; ++kk) {
+            const double av = double(S[ri][4 * kk + lk]);
+            const double bv = double(S[rj][4 * kk + lk]);
+            acc[sl] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[sl], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int sl = 0; sl < SG_SLOTS; ++sl) {
+    if (w + sl * nw < tiles) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = TI[sl] * 16 + lk + 4 * v, j = TJ[sl] * 16 + lr;
+        if (i < q && j < q) {
+          G[int64_t(i) * q + j] = acc[sl][v];
+          G[int64_t(j) * q + i] = acc[sl][v];
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // Partial Gram of mode a.skip (>= 1) of the span, and with a.nx2 its
 // squared norm.
 __global__ __launch_bounds__(NT_LEAF, 2) void stream_gram_kernel(StreamArgs a) {
   __shared__ double red[8];
+  __shared__ float S[SG_T * 16][SG_KC + 1];
   const int64_t t0 = int64_t(blockIdx.x) * a.span;
   const int64_t rows = span_rows(a, t0);
   const float* Xc = a.X + t0 * a.slice;
@@ -455,8 +536,12 @@ __global__ __launch_bounds__(NT_LEAF, 2) void stream_gram_kernel(StreamArgs a) {
   Dm[0] = int32_t(rows);
   for (int m = 1; m < a.p; ++m) Dm[m] = a.D[m];
   const int n = a.skip;
-  gram_mode_mfma(Xc, prod_range(Dm, 0, n), Dm[n], prod_range(Dm, n + 1, a.p), a.part + int64_t(blockIdx.x) * a.part_elems,
-                 Dm[n]);
+  const int64_t ga = prod_range(Dm, 0, n), gb = prod_range(Dm, n + 1, a.p);
+  double* G = a.part + int64_t(blockIdx.x) * a.part_elems;
+  if ((gb >= SG_KC || gb == 1) && Dm[n] <= SG_T * 16 && blockDim.x == NT_LEAF)
+    gram_staged(Xc, ga, Dm[n], gb, G, S);
+  else
+    gram_mode_mfma(Xc, ga, Dm[n], gb, G, Dm[n]);
   if (a.nx2) {
     double part = 0.0;
     for (int64_t e = threadIdx.x; e < rows * a.slice; e += blockDim.x) part += double(Xc[e]) * double(Xc[e]);

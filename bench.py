@@ -111,6 +111,13 @@ def serve_main(args):
     running work as job slots and workspace free up.  Reports queries/s and
     p50/p99 latency (submission to completion, host clock), then the
     closed-loop append rate (a burst of appends submitted at once)."""
+    # The serving engine drives five streams (the tree's, the appends', three
+    # query classes); HIP maps streams onto GPU_MAX_HW_QUEUES hardware queues
+    # (4 by default), and an append commit sharing a queue with a class's
+    # running launch waits for it.  --hw-queues (default 8) gives every
+    # stream its own; it must be set before the runtime starts.
+    if args.hw_queues > 0:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     import torch
     import synth
     from paper_2501_06647_amd import Tree
@@ -118,6 +125,8 @@ def serve_main(args):
 
     def say(msg):
         print("[serve] %s" % msg, file=sys.stderr, flush=True)
+
+    say("GPU_MAX_HW_QUEUES=%s" % os.environ.get("GPU_MAX_HW_QUEUES"))
 
     wl = synth.get(args.workload)
     torch.cuda.set_device(0)
@@ -814,6 +823,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=63.0,
                     help="serving run length: at 1000 appends/s from 256 slices the horizon reaches 63256")
     ap.add_argument("--serve-prefix", type=int, default=256)
+    ap.add_argument("--hw-queues", type=int, default=8,
+                    help="GPU_MAX_HW_QUEUES for the serving run (0: leave the environment's)")
     ap.add_argument("--serve-prec", default="f32", help="query arithmetic while serving: f32 or bf16")
     ap.add_argument("--serve-slots", type=int, default=256, help="job slots (concurrent queries) per class")
     ap.add_argument("--burst-appends", type=int, default=2048, help="closed-loop appends after the serving run")

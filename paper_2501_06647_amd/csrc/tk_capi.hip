@@ -538,6 +538,11 @@ tk_status commit_blocks(tk_tree* t, Lane* lane, int64_t nb, const float* Xdev, h
     Plan plan;
     st = plan_stitch(t, jobs, hits, &plan);
     if (st) return st;
+    // a commit's levels run one after another, each as long as its slowest
+    // merge, so a merge's latency sets the commit time: at least two
+    // wavefronts a merge (the thread count stays a function of the job and
+    // the tuning, so appends and builds store the same bits)
+    for (Group& gr : plan.groups) gr.threads = std::max(gr.threads, kMergeThreads);
     // one level's merges share a shape; groups run in order on the lane
     st = run_plan(t, lane, plan, t->cfg.max_iter, t->cfg.tol, false);
     if (st) return st;

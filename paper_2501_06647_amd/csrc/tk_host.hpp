@@ -182,6 +182,7 @@ void make_merge_job(tk_tree* t, int k, int64_t j, std::vector<Job>& jobs, std::v
 // so those queries may differ from tk_query in the last bits.
 tk_status plan_stitch(tk_tree* t, std::vector<Job>& jobs, std::vector<Hit>& hits, Plan* plan, bool pretrim = false);
 constexpr int64_t kPretrimRows = 2048;
+constexpr int kMergeThreads = 128;  // least threads of a merge job (append commits, builds)
 // The trim-pass chunks of jobs [i0, i1) of a group whose workspace chunk
 // starts at job i0's offset and lives at ws_base.
 void trim_chunks_of(const tk_tree* t, const Plan& plan, const Group& gr, int64_t i0, int64_t i1, char* ws_base,

@@ -1,5 +1,6 @@
-"""More modes than the workloads have: p = 5, 6 and 7 (the kernels take
-up to seven modes), built on the device and queried, against the oracle.
+"""Other numbers of modes than the workloads have: p = 2 (a matrix series)
+and p = 5, 6 and 7 (the kernels take two to seven modes), built on the
+device and queried, against the oracle.
 
 Bars: every node's relative error within 1e-5 of the oracle's (ratio
 form); queries within 1e-5, the same sweep counts, factor orthonormality
@@ -28,6 +29,7 @@ def torch():
 
 
 @pytest.mark.parametrize("dims,ranks,seed", [
+    ((30,), (5, 5), 2000),
     ((6, 5, 4, 3), (3, 3, 2, 2, 2), 2001),
     ((4, 3, 3, 3, 2), (3, 2, 2, 2, 2, 2), 2002),
     ((3, 3, 2, 2, 2, 2), (3, 2, 2, 2, 2, 2, 2), 2003),
@@ -71,6 +73,18 @@ def test_many_modes_parity(torch, dims, ranks, seed):
         assert orth <= ORTH and r.sweeps == info["sweeps"], (a, c)
         worst = max(worst, d)
     say("p=%d: raw Tucker-ALS worst delta %.2e" % (len(dims) + 1, worst))
+    assert worst <= DELTA
+    worst = 0.0
+    Xd = torch.from_numpy(X.astype(np.float32)).to("cuda:0")
+    for a, c in [(0, T), (3, 50), (10, 11)]:
+        r = gpu.raw_tucker_stream(Xd, a, c)
+        rq = effective_ranks(c - a, wl.dims, wl.node_ranks)
+        Go, Uo, info = hooi(X[a:c].astype(np.float32).astype(np.float64), rq, wl.max_iter, wl.tol)
+        G, U = to_np(r)
+        d, orth, _, _, _ = compare(X, a, c, G, U, Go, Uo)
+        assert orth <= ORTH and r.sweeps == info["sweeps"], (a, c)
+        worst = max(worst, d)
+    say("p=%d: streaming Tucker-ALS worst delta %.2e" % (len(dims) + 1, worst))
     assert worst <= DELTA
 
 

@@ -101,6 +101,17 @@ def ytilde(orc, ts, te):
     return np.concatenate([reconstruct(pc.H, pc.V) for pc in orc.pieces(ts, te)], axis=0)
 
 
+EXACT = 1e-5  # an oracle error below this is FP32-level: the gate is the device's own error
+
+
+def node_delta(e_g, e_o):
+    """The error-ratio gap |e_gpu / e_oracle - 1|; where the oracle's
+    decomposition is exact to below FP32 resolution (a node whose ranks
+    reach its shape), the ratio has no meaning and the device's own
+    relative error is gated instead."""
+    return abs(e_g / e_o - 1.0) if e_o > EXACT else abs(e_g)
+
+
 def compare(X, ts, te, G, U, Go, Uo, true_ranks=None, sine_tol=None, Yt=None):
     """Error ratio, orthonormality and (with sine_tol) the largest sine
     between the leading subspaces of each mode, over the directions up to
@@ -110,7 +121,7 @@ def compare(X, ts, te, G, U, Go, Uo, true_ranks=None, sine_tol=None, Yt=None):
     sine_tol."""
     e_g = relative_error(X[ts:te], G, U)
     e_o = relative_error(X[ts:te], Go, Uo)
-    delta = abs(e_g / e_o - 1.0) if e_o > 0 else abs(e_g)
+    delta = node_delta(e_g, e_o)
     orth = max(orthonormality_error(u) for u in U)
     sine = 0.0
     if sine_tol is not None:

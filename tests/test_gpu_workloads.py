@@ -28,7 +28,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import recon_bound, compare, oracle_tree, recon_diff, say, to_np, ytilde
+from gpu_helpers import compare, node_delta, oracle_tree, recon_bound, recon_diff, say, to_np, ytilde
 from oracle import pool
 from oracle.evaluate import orthonormality_error, relative_error
 
@@ -204,7 +204,7 @@ def test_precision_shape_small_horizon_both_sides(torch):
         Xi = X[orc.sigma(v):orc.tau(v)]
         e_g = relative_error(Xi, core.astype(np.float64), [f.astype(np.float64) for f in facs])
         e_o = relative_error(Xi, v.H, v.V)
-        worst = max(worst, abs(e_g / e_o - 1.0) if e_o > 0 else e_g)
+        worst = max(worst, node_delta(e_g, e_o))
     say("precision small: worst node delta %.2e over %d nodes" % (worst, len(orc.complete_nodes())))
     assert worst <= DELTA
     ts, te = synth.queries(wl, T=T, n=12)

@@ -206,7 +206,12 @@ tk_status tk_last_query_kernel_ms(const tk_tree* t, double* ms);
  * and end on the device clock in microseconds; then the number of
  * eigensolves whose vectors needed the Gram-Schmidt fallback; then the
  * microseconds of the eigenvalue time spent tridiagonalising and of the
- * eigenvector time spent in inverse iteration.  phase_us has 17 entries. */
+ * eigenvector time spent in inverse iteration (those counters cover the
+ * full solver only); then four for the sweeps' warm-started eigensolves
+ * (subspace iteration from the previous sweep's vectors, kept when a
+ * certificate shows it found the leading subspace): accepted, refused (the
+ * full solver ran after them), their iteration steps, their microseconds.
+ * phase_us has 21 entries. */
 tk_status tk_last_query_profile(const tk_tree* t, int32_t i, double* phase_us);
 
 /* Override the ALS sweep cap and tolerance for later queries (not merges). */

@@ -250,7 +250,7 @@ tk_status tk_batch_kernel_ms(const tk_batch* b, double* ms) {
 tk_status tk_batch_profile(const tk_batch* b, int32_t i, double* phase_us) {
   if (!b || !phase_us || i < 0 || i >= b->n) return TK_EINVAL;
   if (b->hstats.size() != size_t(b->n) * STAT_COUNT) return TK_EINVAL;
-  for (int k = 0; k < STAT_NPHASE + 9; ++k)
+  for (int k = 0; k < PROFILE_COUNT; ++k)
     phase_us[k] = b->hstats[size_t(i) * STAT_COUNT + STAT_PHASE + k] *
                   (k == STAT_NPHASE + 4 || k == STAT_NPHASE + 5 ? 0.01 : 1.0);
   return TK_OK;

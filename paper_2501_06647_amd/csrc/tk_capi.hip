@@ -1057,7 +1057,7 @@ tk_status tk_last_query_profile(const tk_tree* t, int32_t i, double* phase_us) {
   if (!t || !phase_us || i < 0) return TK_EINVAL;
   const int64_t n = int64_t(t->last_stats.size()) / tk::STAT_COUNT;
   if (i >= n) return TK_EINVAL;
-  for (int k = 0; k < tk::STAT_NPHASE + 9; ++k)
+  for (int k = 0; k < tk::PROFILE_COUNT; ++k)
     phase_us[k] = t->last_stats[size_t(i) * tk::STAT_COUNT + tk::STAT_PHASE + k] *
                   (k == tk::STAT_NPHASE + 4 || k == tk::STAT_NPHASE + 5 ? 0.01 : 1.0);
   return TK_OK;

@@ -246,12 +246,18 @@ struct LeafJob {
 // needed the Gram-Schmidt fallback; STAT_EIG.. hold eigensolver calls, bisection steps,
 // and microseconds computing eigenvalues and eigenvectors; STAT_EIG_TRI and
 // STAT_EIG_INVIT the parts of those spent in tridiagonalisation and in
-// inverse iteration.
+// inverse iteration; STAT_EIG_WARM.. the warm-started sweep eigensolves:
+// accepted, refused (the full solver ran after them), their subspace
+// iteration steps and microseconds.
 enum {
   STAT_FIT = 0, STAT_ERR = 1, STAT_NORM = 2, STAT_SWEEPS = 3, STAT_CONV = 4, STAT_HITS = 5, STAT_STATUS = 6,
   STAT_PHASE = 8, STAT_NPHASE = 8, STAT_EIG = 16, STAT_T0 = 20, STAT_T1 = 21, STAT_EIG_FALLBACK = 22,
-  STAT_EIG_TRI = 23, STAT_EIG_INVIT = 24, STAT_COUNT = 26
+  STAT_EIG_TRI = 23, STAT_EIG_INVIT = 24, STAT_EIG_WARM = 25, STAT_EIG_WARM_FAIL = 26, STAT_EIG_WARM_STEPS = 27,
+  STAT_EIG_WARM_US = 28, STAT_COUNT = 29
 };
+// Entries of a query's profile (tk_last_query_profile, tk_batch_profile):
+// STAT_PHASE .. STAT_EIG_WARM_US.
+constexpr int PROFILE_COUNT = STAT_EIG_WARM_US + 1 - STAT_PHASE;
 
 // Rows of a partial hit's temporal factor per chunk of the trim pass: each
 // chunk's Gram is summed by one workgroup of trim_gram_kernel, and the stitch
@@ -322,8 +328,15 @@ TK_HD int gram_rows_split(int ntiles, int nthreads, int max_parts = GRAM_ROWS_TI
 // work vectors, brackets) and 256 doubles of per-thread partial results.
 // The vector part of an eigen buffer (tridiagonal, reflector scalars,
 // eigenvalues, work vectors, brackets, workgroup partials): it can live in
-// LDS when the n x n matrix part does not.
-TK_HD int64_t eig_vec_doubles(int64_t n) { return 8 * n + 256; }
+// LDS when the n x n matrix part does not.  It is at least large enough for
+// the small matrices of a warm-started eigensolve with up to WARM_SMALL_K
+// vectors (eig_top_warm), which use the same place.
+constexpr int64_t WARM_SMALL_K = 16;
+TK_HD int64_t warm_small_doubles(int64_t k) { return 2 * k * k + 2 * k + 4; }
+TK_HD int64_t eig_vec_doubles(int64_t n) {
+  const int64_t v = 8 * n + 256, w = warm_small_doubles(WARM_SMALL_K);
+  return v > w ? v : w;
+}
 TK_HD int64_t eig_doubles(int64_t n) { return n * n + eig_vec_doubles(n); }
 
 // Scratch of the eigensolver besides its buffer (inverse-iteration LU

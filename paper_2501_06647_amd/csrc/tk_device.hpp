@@ -796,6 +796,7 @@ __device__ __forceinline__ void pchol_basis_inplace(double* G, const int* piv, i
 struct EigCounters {  // zeroed by the owner (it may live in LDS)
   uint64_t calls, sweeps, values_ticks, tail_ticks, fallbacks;
   uint64_t tri_ticks, invit_ticks;  // parts of the two above: tridiagonalisation, inverse iteration
+  uint64_t warm, warm_fail, warm_steps, warm_ticks;  // eig_top_warm: accepted, refused, steps, time
 };
 
 // Leading eigenpairs of a symmetric n x n matrix S through the tridiagonal
@@ -1336,6 +1337,312 @@ __device__ __forceinline__ const double* eig_top_tri(double* W, int n, int k, do
     cnt->invit_ticks += t_inv - t_bis;
   }
   return lam;
+}
+
+// ---------------------------------------------------------------------------
+// Warm-started leading eigenvectors
+// ---------------------------------------------------------------------------
+
+// Pair a (0 <= a < m / 2) of round t (0 <= t < m - 1) of a round-robin
+// schedule over m (even) indices: index m - 1 meets t, and for a >= 1 the
+// indices (t + a) and (t - a) modulo m - 1 meet, so every pair meets once
+// per m - 1 rounds and the m / 2 pairs of a round are disjoint.
+__device__ __forceinline__ void robin_pair(int t, int a, int m, int* p, int* q) {
+  int x, y;
+  if (a == 0) {
+    x = t;
+    y = m - 1;
+  } else {
+    x = (t + a) % (m - 1);
+    y = (t - a + (m - 1)) % (m - 1);
+  }
+  *p = x < y ? x : y;
+  *q = x < y ? y : x;
+}
+
+// Rows of Q = Y L^{-T} for the Cholesky factor L of Y^T Y (lower triangle of
+// Lm, k x k; dinv[j] = 1 / L(j, j)): one row per lane, forward substitution
+// column by column so each step's updates are independent; in registers for
+// k <= 16, else in Q's row.
+__device__ __forceinline__ void chol_solve_rows(const double* Y, double* Q, int n, int k, const double* Lm,
+                                                const double* dinv) {
+  constexpr int KM = 16;
+  if (k > KM) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      double* q = Q + int64_t(i) * k;
+      for (int j = 0; j < k; ++j) q[j] = Y[int64_t(i) * k + j];
+      for (int j = 0; j < k; ++j) {
+        const double qj = q[j] * dinv[j];
+        q[j] = qj;
+        for (int t = j + 1; t < k; ++t) q[t] -= qj * Lm[t * k + j];
+      }
+    }
+    __syncthreads();
+    return;
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double y[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) y[j] = j < k ? Y[int64_t(i) * k + j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+      if (j < k) {
+        const double qj = y[j] * dinv[j];
+        y[j] = qj;
+#pragma unroll
+        for (int t = j + 1; t < KM; ++t)
+          if (t < k) y[t] -= qj * Lm[t * k + j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < KM; ++j)
+      if (j < k) Q[int64_t(i) * k + j] = y[j];
+  }
+  __syncthreads();
+}
+
+// Leading k eigenvectors of a symmetric positive semidefinite n x n matrix
+// S (a Gram; row-major, both triangles) from a close start: E (n x k, row
+// stride lde) holds orthonormal vectors of a nearby matrix, here the
+// previous ALS sweep's for the same mode in the same coordinates.
+//   * Block subspace iteration (Golub & Van Loan, Sec. 8.2.4): Y = S Q,
+//     H = Q^T Y and the residual R = Y - Q H; while ||R||_F exceeds 1e-11
+//     max_j H(j, j), Q becomes the Cholesky QR of Y.  From the third step
+//     on, the observed contraction of ||R|| predicts the steps still needed;
+//     a start that cannot converge within kWarmMaxSteps is given up early.
+//   * Rayleigh-Ritz (Sec. 8.1.4): H = W Theta W^T by cyclic Jacobi (Sec.
+//     8.5: the two-by-two symmetric Schur rotation, round-robin pairs, the
+//     m / 2 disjoint rotations of a round applied together, each thread
+//     updating whole 2 x 2 blocks in place), until no off-diagonal entry
+//     exceeds 1e-15 sqrt(|H(p, p) H(q, q)|).
+//   * A certificate that span Q is S's leading invariant subspace: in the
+//     basis [Q, Q_perp], S = [[H, R'^T], [R', C]] with ||R'|| = ||R||, and
+//     C is positive semidefinite, so lambda_max(C) <= min(trace C, ||C||_F)
+//     with trace C = trace S - sum theta and ||C||_F^2 = ||S||_F^2 -
+//     ||H||_F^2 - 2 ||R||_F^2 (rounding margins added).  By Weyl's theorem
+//     S's eigenvalues lie within ||R|| of those of blockdiag(H, C), so
+//     gap = min theta - that bound - 2 ||R|| > 0 makes S's top k the ones
+//     near theta, and the sin-theta theorem bounds the angle between span Q
+//     and the exact leading subspace by ||R|| / gap, required below 1e-8.
+// On success the Ritz vectors Q W, in descending order of theta, replace E
+// and it returns true; otherwise E is untouched and it returns false (the
+// caller then runs the full solver).  S is only read.  qy: 2 n k doubles
+// (Q and Y), sm: warm_small_doubles(k) doubles (the k x k matrices, kept in
+// LDS by the callers), k <= 32, n > k.
+constexpr int kWarmMaxSteps = 8;
+__device__ __forceinline__ bool eig_top_warm(const double* S, int n, int k, double* E, int lde, double* qy,
+                                             double* sm, double* red, EigCounters* cnt) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const uint64_t t_start = wall_clock64();
+  double* Q = qy;
+  double* Y = Q + int64_t(n) * k;
+  double* H = sm;
+  double* W = H + k * k;
+  const int m = (k + 1) & ~1, hp = m / 2;
+  double* cs = W + k * k;                            // c, s, t of each pair of a round
+  int* pos = reinterpret_cast<int*>(cs + 3 * hp);    // output column of each Ritz vector
+  int* flag = pos + k;                               // [1]: an off-diagonal entry left to rotate
+  // |S|_F^2 and trace S for the certificate; Q = E
+  double a2 = 0.0, tr = 0.0;
+  for (int e = tid; e < n * n; e += nt) {
+    const double v = S[e];
+    a2 += v * v;
+    if (e % (n + 1) == 0) tr += v;
+  }
+  const double nS2 = block_sum(a2, red);
+  const double trS = block_sum(tr, red);
+  for (int e = tid; e < n * k; e += nt) Q[e] = E[int64_t(e / k) * lde + e % k];
+  __syncthreads();
+  bool conv = false;
+  double rho = 0.0, rho_prev = 0.0;
+  int it = 0;
+  for (;;) {
+    ++it;
+    gemm_f64(n, k, n, [&](int i, int c) { return S[int64_t(i) * n + c]; },
+             [&](int c, int j) { return Q[int64_t(c) * k + j]; },
+             [&](int i, int j, double v) { Y[int64_t(i) * k + j] = v; });
+    gemm_f64(k, k, n, [&](int i, int c) { return Q[int64_t(c) * k + i]; },
+             [&](int c, int j) { return Y[int64_t(c) * k + j]; }, [&](int i, int j, double v) { H[i * k + j] = v; });
+    double part = 0.0;
+    gemm_f64(n, k, k, [&](int i, int c) { return Q[int64_t(i) * k + c]; }, [&](int c, int j) { return H[c * k + j]; },
+             [&](int i, int j, double v) {
+               const double d = Y[int64_t(i) * k + j] - v;
+               part += d * d;
+             });
+    rho = sqrt(block_sum(part, red));
+    double hmax = 0.0;
+    for (int j = 0; j < k; ++j) hmax = fmax(hmax, H[j * k + j]);
+    __syncthreads();  // H is read; the Cholesky QR overwrites it
+    if (!(hmax > 0.0)) break;
+    if (rho <= 1e-11 * hmax) {
+      conv = true;
+      break;
+    }
+    if (it >= kWarmMaxSteps) break;
+    if (it >= 3) {  // steps still needed at the observed contraction
+      const double f = rho / rho_prev;
+      if (!(f < 0.5) || double(it) + log(1e-11 * hmax / rho) / log(f) > double(kWarmMaxSteps)) break;
+    }
+    rho_prev = rho;
+    // Cholesky QR: H <- Y^T Y = L L^T (lower triangle), Q <- Y L^{-T}
+    gemm_f64(k, k, n, [&](int i, int c) { return Y[int64_t(c) * k + i]; },
+             [&](int c, int j) { return Y[int64_t(c) * k + j]; }, [&](int i, int j, double v) { H[i * k + j] = v; });
+    const double d0 = H[0];
+    bool ok = true;
+    for (int j = 0; j < k; ++j) {
+      const double d = H[j * k + j];
+      if (!(d > 1e-24 * d0)) {  // Y (numerically) rank deficient
+        ok = false;
+        break;
+      }
+      const double ljj = sqrt(d), inv = 1.0 / ljj;
+      __syncthreads();  // every thread has read H(j, j)
+      for (int i = j + 1 + tid; i < k; i += nt) H[i * k + j] *= inv;
+      if (tid == 0) {
+        H[j * k + j] = ljj;
+        cs[j] = inv;
+      }
+      __syncthreads();
+      const int mm = k - j - 1;
+      for (int e = tid; e < mm * mm; e += nt) {
+        const int i = j + 1 + e / mm, l = j + 1 + e % mm;
+        if (l <= i) H[i * k + l] -= H[i * k + j] * H[l * k + j];
+      }
+      __syncthreads();
+    }
+    if (!ok) break;
+    chol_solve_rows(Y, Q, n, k, H, cs);
+  }
+  bool accept = false;
+  if (conv) {
+    // Rayleigh-Ritz: H (symmetrised) = W Theta W^T by cyclic Jacobi
+    for (int e = tid; e < k * k; e += nt) {
+      const int i = e / k, j = e % k;
+      W[e] = i == j ? 1.0 : 0.0;
+      if (j > i) {
+        const double v = 0.5 * (H[e] + H[j * k + i]);
+        H[e] = v;
+        H[j * k + i] = v;
+      }
+    }
+    __syncthreads();
+    // an entry calls for a rotation above 1e-15 of its diagonal's scale
+    // (the relative criterion for positive definite Jacobi)
+    auto rotates = [](double hpq, double hpp, double hqq) {
+      return hpq != 0.0 && fabs(hpq) > 1e-15 * sqrt(fabs(hpp) * fabs(hqq));
+    };
+    // whether some off-diagonal entry still calls for a rotation (flag[1];
+    // the last barrier keeps the next clear behind every reader)
+    auto off_diag = [&]() {
+      if (tid == 0) flag[1] = 0;
+      __syncthreads();
+      for (int e = tid; e < k * k; e += nt) {
+        const int i = e / k, j = e % k;
+        const double v = H[e];
+        if (j > i && rotates(v, H[i * k + i], H[j * k + j])) flag[1] = 1;
+      }
+      __syncthreads();
+      const bool any = flag[1] != 0;
+      __syncthreads();
+      return any;
+    };
+    bool done = !off_diag();
+    for (int sw = 0; sw < 12 && !done; ++sw) {
+      for (int t = 0; t < m - 1; ++t) {
+        for (int a = tid; a < hp; a += nt) {
+          int p, q;
+          robin_pair(t, a, m, &p, &q);
+          double c = 1.0, sn = 0.0, tt = 0.0;
+          if (q < k) {
+            const double hpq = H[p * k + q], hpp = H[p * k + p], hqq = H[q * k + q];
+            if (rotates(hpq, hpp, hqq)) {
+              const double tau = (hqq - hpp) / (2.0 * hpq);
+              tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+              c = 1.0 / sqrt(1.0 + tt * tt);
+              sn = tt * c;
+            }
+          }
+          cs[3 * a] = c;
+          cs[3 * a + 1] = sn;
+          cs[3 * a + 2] = tt;
+        }
+        __syncthreads();
+        // H <- J^T H J, block (pair a rows) x (pair b columns) per thread
+        for (int u = tid; u < hp * hp; u += nt) {
+          const int a = u / hp, b = u % hp;
+          const double ca = cs[3 * a], sa = cs[3 * a + 1], cb = cs[3 * b], sb = cs[3 * b + 1];
+          if (sa == 0.0 && sb == 0.0) continue;
+          int p, q, p2, q2;
+          robin_pair(t, a, m, &p, &q);
+          robin_pair(t, b, m, &p2, &q2);
+          if (a == b) {  // the rotated pair itself: exact diagonal, zero coupling
+            const double tt = cs[3 * a + 2], hpq = H[p * k + q];
+            H[p * k + p] -= tt * hpq;
+            H[q * k + q] += tt * hpq;
+            H[p * k + q] = 0.0;
+            H[q * k + p] = 0.0;
+            continue;
+          }
+          const bool qv = q < k, q2v = q2 < k;
+          const double x00 = H[p * k + p2], x01 = q2v ? H[p * k + q2] : 0.0;
+          const double x10 = qv ? H[q * k + p2] : 0.0, x11 = qv && q2v ? H[q * k + q2] : 0.0;
+          const double r00 = ca * x00 - sa * x10, r01 = ca * x01 - sa * x11;  // J_a^T rows
+          const double r10 = sa * x00 + ca * x10, r11 = sa * x01 + ca * x11;
+          H[p * k + p2] = cb * r00 - sb * r01;  // then J_b columns
+          if (q2v) H[p * k + q2] = sb * r00 + cb * r01;
+          if (qv) H[q * k + p2] = cb * r10 - sb * r11;
+          if (qv && q2v) H[q * k + q2] = sb * r10 + cb * r11;
+        }
+        for (int u = tid; u < k * hp; u += nt) {  // W <- W J
+          const int i = u / hp, b = u % hp;
+          const double cb = cs[3 * b], sb = cs[3 * b + 1];
+          if (sb == 0.0) continue;
+          int p2, q2;
+          robin_pair(t, b, m, &p2, &q2);
+          const double w0 = W[i * k + p2], w1 = W[i * k + q2];
+          W[i * k + p2] = cb * w0 - sb * w1;
+          W[i * k + q2] = sb * w0 + cb * w1;
+        }
+        __syncthreads();
+      }
+      done = !off_diag();
+    }
+    if (done) {
+      double th_min = 0.0, s1 = 0.0, s2 = 0.0;
+      for (int j = 0; j < k; ++j) {
+        const double th = H[j * k + j];
+        th_min = j == 0 ? th : fmin(th_min, th);
+        s1 += th;
+        s2 += th * th;
+      }
+      const double cT = fmax(0.0, trS - s1) + 1e-12 * fabs(trS);
+      const double cF = sqrt(fmax(0.0, nS2 - s2 - 2.0 * rho * rho) + 1e-12 * nS2);
+      const double gap = th_min - fmin(cT, cF) - 2.0 * rho;
+      accept = gap > 0.0 && rho <= 1e-8 * gap;
+    }
+  }
+  if (accept) {
+    for (int j = tid; j < k; j += nt) {  // descending theta, ties by index
+      const double th = H[j * k + j];
+      int r = 0;
+      for (int i = 0; i < k; ++i) {
+        const double o = H[i * k + i];
+        r += (o > th || (o == th && i < j)) ? 1 : 0;
+      }
+      pos[j] = r;
+    }
+    __syncthreads();
+    gemm_f64(n, k, k, [&](int i, int c) { return Q[int64_t(i) * k + c]; }, [&](int c, int j) { return W[c * k + j]; },
+             [&](int i, int j, double v) { E[int64_t(i) * lde + pos[j]] = v; });
+  }
+  if (cnt && tid == 0) {
+    cnt->warm += accept ? 1 : 0;
+    cnt->warm_fail += accept ? 0 : 1;
+    cnt->warm_steps += uint64_t(it);
+    cnt->warm_ticks += wall_clock64() - t_start;
+  }
+  __syncthreads();
+  return accept;
 }
 
 // The eigensolver the kernels use.

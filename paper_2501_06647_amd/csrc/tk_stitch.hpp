@@ -79,6 +79,7 @@ struct StitchShared {
   int32_t roff[PM][MAXHITS + 1];    // offsets of the pieces' columns in C^(n)
   int32_t q[PM];                    // size of the reduced coordinates of mode n
   int32_t basis[PM];                // 1: C^(n) from the Cholesky basis; 0: C^(n) = V~
+  int32_t warm[PM];                 // 1: mode n's sweep eigensolve may start from its last vectors
   double red[8];
   int redi[4];
 };
@@ -125,7 +126,10 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
 
   PhaseClock& clk = sh.clk;
   EigCounters& ec = sh.ec;
-  if (tid == 0) ec.calls = ec.sweeps = ec.values_ticks = ec.tail_ticks = ec.fallbacks = ec.tri_ticks = ec.invit_ticks = 0;
+  if (tid == 0) {
+    ec.calls = ec.sweeps = ec.values_ticks = ec.tail_ticks = ec.fallbacks = ec.tri_ticks = ec.invit_ticks = 0;
+    ec.warm = ec.warm_fail = ec.warm_steps = ec.warm_ticks = 0;
+  }
   clk.start();
   // the layout record lives at the head of the workspace
   StitchLayout* lop = reinterpret_cast<StitchLayout*>(ws);
@@ -189,6 +193,33 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     else used = lds_doubles;
     *p = lds + used;
     return lds_doubles - used;
+  };
+  // A sweep's eigensolve for mode `mode` (Gram n x n in Wm, vector buffer
+  // Wv, as with_buf / with_eig_buf placed them): the k leading eigenvectors
+  // into P_mode.  The Gram changes little from sweep to sweep, so the
+  // previous sweep's vectors start a subspace iteration that is kept when
+  // its certificate holds (eig_top_warm); otherwise, and for the rest of
+  // the job once a start has failed, the full solver runs.  The iteration's
+  // k x k matrices go to the LDS behind the Gram (the eigensolver's vector
+  // part, sized for them up to WARM_SMALL_K), its two n x k blocks behind
+  // those when they fit, else to TMP.
+  auto sweep_eig = [&](int mode, double* Wm, double* Wv, int n, int k) {
+    double* E = Dp(lo.Pd[mode]);
+    if (sh.warm[mode] && n > k && k <= 32) {
+      const int64_t used = n <= n_lds ? int64_t(n) * n : 0;
+      const int64_t nsm = warm_small_doubles(k), nqy = 2 * int64_t(n) * k;
+      if (lds_doubles - used >= nsm) {
+        double* sm = lds + used;
+        double* qy = lds_doubles - used - nsm >= nqy ? sm + nsm : (nqy <= eig_tmp_doubles(n) ? TMP : nullptr);
+        if (qy) {
+          if (eig_top_warm(Wm, n, k, E, k, qy, sm, red, &ec)) return;
+          if (tid == 0) sh.warm[mode] = 0;
+        }
+      }
+    }
+    double* lf = nullptr;
+    const int64_t nf = eig_free(n, &lf);
+    eig_top(Wm, n, k, E, k, red, TMP, &ec, Wv, lf, nf);
   };
 
   // ---- trims (Eq. "partial-tucker") and |Y~|^2 ------------------------------
@@ -366,6 +397,8 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     });
     update_A(n);
   }
+  if (tid == 0)
+    for (int n = 0; n < p; ++n) sh.warm[n] = n > 0;  // P_0 exists after the first sweep
   clk.mark(2);
 
   // ---- ALS sweeps (Alg. "stitch") ---------------------------------------------
@@ -403,10 +436,9 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     with_buf(sk, [&](double* Wm, double* Wv) {
       gram(M, 1, sk, Rhat[0], Wm, sk);
       clk.mark(3);
-      double* lf = nullptr;
-      const int64_t nf = eig_free(sk, &lf);
-      eig_top(Wm, sk, rq[0], Dp(lo.Pd[0]), rq[0], red, TMP, &ec, Wv, lf, nf);
+      sweep_eig(0, Wm, Wv, sk, rq[0]);
     });
+    if (tid == 0 && it == 1) sh.warm[0] = 1;
     float* P0f = Fp(lo.Pf[0]);
     {
       const double* P0 = Dp(lo.Pd[0]);
@@ -461,9 +493,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
       with_eig_buf(q, [&](double* Wn, double* Wv) {
         gram(K, ka, q, kb, Wn, q);
         clk.mark(5);
-        double* lf = nullptr;
-        const int64_t nf = eig_free(q, &lf);
-        eig_top(Wn, q, rq[n], Dp(lo.Pd[n]), rq[n], red, TMP, &ec, Wv, lf, nf);
+        sweep_eig(n, Wn, Wv, q, rq[n]);
       });
       update_A(n);
       clk.mark(6);
@@ -603,6 +633,10 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     job.stats[STAT_EIG_FALLBACK] = double(ec.fallbacks);
     job.stats[STAT_EIG_TRI] = double(ec.tri_ticks) * 0.01;
     job.stats[STAT_EIG_INVIT] = double(ec.invit_ticks) * 0.01;
+    job.stats[STAT_EIG_WARM] = double(ec.warm);
+    job.stats[STAT_EIG_WARM_FAIL] = double(ec.warm_fail);
+    job.stats[STAT_EIG_WARM_STEPS] = double(ec.warm_steps);
+    job.stats[STAT_EIG_WARM_US] = double(ec.warm_ticks) * 0.01;
   }
 }
 

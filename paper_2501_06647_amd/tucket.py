@@ -286,7 +286,7 @@ class PreparedBatch:
         return ms.value
 
     def profile(self, i: int) -> dict:
-        out = (c_dbl * 17)()
+        out = (c_dbl * len(Tree.PHASES + Tree.COUNTERS))()
         self.tree._check(lib().tk_batch_profile(self._h, i, out), "tk_batch_profile")
         return dict(zip(Tree.PHASES + Tree.COUNTERS, list(out)))
 
@@ -589,10 +589,11 @@ class Tree:
 
     PHASES = ("trim", "basis", "init", "t_ttm_gram", "t_eig", "n_ttm_gram", "n_eig", "final")
     COUNTERS = ("eig_calls", "eig_bisect_steps", "eig_values_us", "eig_vectors_us", "start_us", "end_us",
-                "eig_fallbacks", "eig_tridiag_us", "eig_invit_us")
+                "eig_fallbacks", "eig_tridiag_us", "eig_invit_us", "eig_warm", "eig_warm_refused",
+                "eig_warm_steps", "eig_warm_us")
 
     def last_profile(self, i: int) -> dict:
-        out = (c_dbl * 17)()
+        out = (c_dbl * len(Tree.PHASES + Tree.COUNTERS))()
         self._check(lib().tk_last_query_profile(self._h, i, out), "tk_last_query_profile")
         return dict(zip(self.PHASES + self.COUNTERS, list(out)))
 

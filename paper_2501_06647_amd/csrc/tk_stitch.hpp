@@ -194,12 +194,13 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     *p = lds + used;
     return lds_doubles - used;
   };
-  // A sweep's eigensolve for mode `mode` (Gram n x n in Wm, vector buffer
-  // Wv, as with_buf / with_eig_buf placed them): the k leading eigenvectors
-  // into P_mode.  The Gram changes little from sweep to sweep, so the
-  // previous sweep's vectors start a subspace iteration that is kept when
-  // its certificate holds (eig_top_warm); otherwise, and for the rest of
-  // the job once a start has failed, the full solver runs.  The iteration's
+  // An eigensolve for mode `mode` (Gram n x n in Wm, vector buffer Wv, as
+  // with_buf / with_eig_buf placed them): the k leading eigenvectors into
+  // P_mode.  The Gram changes little from sweep to sweep, so the previous
+  // sweep's vectors (or a start written there) begin a subspace iteration
+  // that is kept when its certificate holds (eig_top_warm); otherwise, and
+  // for the rest of the job's sweeps once a start has failed, the full
+  // solver runs.  The iteration's
   // k x k matrices go to the LDS behind the Gram (the eigensolver's vector
   // part, sized for them up to WARM_SMALL_K), its two n x k blocks behind
   // those when they fit, else to TMP.
@@ -367,9 +368,28 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     __syncthreads();
   };
 
+  // The longest hit carries most of Y~: its own leading vectors start the
+  // subspace iterations that have no previous sweep (its mode-n factor's
+  // coordinates for the HOSVD initialisation, its rows of the stacked
+  // temporal coordinates for the first temporal solve); the certificate of
+  // eig_top_warm decides as for any start.
+  int dom = 0;
+  for (int i = 1; i < s; ++i)
+    if (hits[i].l > hits[dom].l) dom = i;
+
   // ---- HOSVD initialisation of U^(2..p) (Gram of Y~ in reduced coordinates)
   for (int n = 1; n < p; ++n) {
     const int q = sh.q[n], sr = lo.sr[n];
+    {
+      const int rd = st.rk[hits[dom].level][n], c0 = sh.roff[n][dom];
+      const int r = rq[n];
+      const double* C64 = Dp(lo.C64[n]);
+      double* P = Dp(lo.Pd[n]);
+      if (rd >= r)
+        for (int e = tid; e < q * r; e += nt) P[e] = C64[int64_t(e / r) * sr + c0 + e % r];
+      if (tid == 0) sh.warm[n] = rd >= r;
+      __syncthreads();
+    }
     with_eig_buf(q, [&](double* Wm, double* Wv) {
     for (int e = tid; e < q * q; e += nt) Wm[e] = 0.0;
     __syncthreads();
@@ -391,14 +411,20 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
                [&](int j, int d2) { return C64[int64_t(d2) * sr + c0 + j]; },
                [&](int dd, int d2, double v) { Wm[dd * q + d2] += v; });
     }
-    double* lf = nullptr;
-    const int64_t nf = eig_free(q, &lf);
-    eig_top(Wm, q, rq[n], Dp(lo.Pd[n]), rq[n], red, TMP, &ec, Wv, lf, nf);
+    sweep_eig(n, Wm, Wv, q, rq[n]);
     });
     update_A(n);
   }
-  if (tid == 0)
-    for (int n = 0; n < p; ++n) sh.warm[n] = n > 0;  // P_0 exists after the first sweep
+  {
+    const int r0 = rq[0], k0 = sh.kp[dom], o0 = sh.koff[dom];
+    const int sk = sh.koff[s];
+    double* P0 = Dp(lo.Pd[0]);
+    if (k0 >= r0)
+      for (int e = tid; e < sk * r0; e += nt) P0[e] = (e / r0 - o0 == e % r0) ? 1.0 : 0.0;
+    if (tid == 0)
+      for (int n = 0; n < p; ++n) sh.warm[n] = n > 0 || k0 >= r0;
+    __syncthreads();
+  }
   clk.mark(2);
 
   // ---- ALS sweeps (Alg. "stitch") ---------------------------------------------

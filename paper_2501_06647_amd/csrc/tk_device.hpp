@@ -113,53 +113,73 @@ __device__ __forceinline__ void mode_product_fiber(const TX* __restrict__ X, int
 typedef float tk_f4 __attribute__((ext_vector_type(4)));
 
 // The same product on the matrix cores, FP32 operands and accumulation: a
-// GEMM with M = m outputs, K = r, and N = a b fibers f = (x, y).  Each
-// wavefront takes 16 x 16 output tiles (16 outputs of 16 fibers) and runs
-// v_mfma_f32_16x16x4f32 over K in steps of 4: lane l supplies A(16 I + l %
-// 16, 4 c + l / 16) and X at fiber 16 J + l % 16, index 4 c + l / 16, and
-// holds Y rows 16 I + 4 (l / 16) + v of fiber 16 J + l % 16.  Y must not
-// overlap X; with acc the tile is added to Y.
+// GEMM with M = m outputs, K = r, and N = a b fibers f = (x, y), in 16 x 16
+// output tiles (16 outputs of 16 fibers) with v_mfma_f32_16x16x4f32 over K
+// in steps of 4: lane l supplies A(16 I + l % 16, 4 c + l / 16) and X at
+// fiber 16 J + l % 16, index 4 c + l / 16, and holds Y rows 16 I + 4 (l /
+// 16) + v of fiber 16 J + l % 16.  A wavefront takes TB fiber tiles of one
+// row tile at a time and issues the loads of all of them (four K steps per
+// round) before their MFMAs: the operands come from HBM or L2, so one
+// memory round trip serves TB tiles.  Each tile's K steps run in order, as
+// with one tile at a time.  Y must not overlap X; with acc the tile is
+// added to Y.
 __device__ __forceinline__ void mode_product_mfma(const float* __restrict__ X, int64_t a, int r, int64_t b,
                                                   const float* __restrict__ A, int64_t as, int64_t bs, int m,
                                                   float* __restrict__ Y, bool acc) {
+  constexpr int TB = 4;
   const int nw = int(blockDim.x) >> 6, w = int(threadIdx.x) >> 6, l = int(threadIdx.x) & 63;
   const int lr = l & 15, lk = l >> 4;
   const int64_t F = a * b;
   const int mt = (m + 15) >> 4;
-  const int64_t ntiles = int64_t(mt) * ((F + 15) >> 4);
-  for (int64_t t = w; t < ntiles; t += nw) {
+  const int64_t ngr = (((F + 15) >> 4) + TB - 1) / TB;
+  for (int64_t t = w; t < int64_t(mt) * ngr; t += nw) {
     const int I = int(t % mt);
-    const int64_t f = (t / mt) * 16 + lr;
+    const int64_t g = t / mt;
     // out-of-range rows, fibers and indices read a valid element, masked to 0
-    const float fm = f < F ? 1.f : 0.f;
-    const int64_t fc = f < F ? f : F - 1;
-    const int64_t x = fc / b, y = fc % b;
     const int ia = I * 16 + lr;
     const float im = ia < m ? 1.f : 0.f;
     const int64_t ic = ia < m ? ia : m - 1;
-    tk_f4 c = {0.f, 0.f, 0.f, 0.f};
-    // eight K steps per round: all loads issued before the MFMAs that use them
-    for (int k0 = 0; k0 < r; k0 += 32) {
-      float av[8], bv[8];
+    int64_t xo[TB];
+    float fm[TB];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int j = k0 + 4 * u + lk;
+    for (int u = 0; u < TB; ++u) {
+      const int64_t f = (g * TB + u) * 16 + lr;
+      fm[u] = f < F ? 1.f : 0.f;
+      const int64_t fc = f < F ? f : F - 1;
+      xo[u] = (fc / b) * r * b + fc % b;
+    }
+    tk_f4 c[TB];
+#pragma unroll
+    for (int u = 0; u < TB; ++u) c[u] = tk_f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < r; k0 += 16) {
+      float av[4], bv[TB][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = k0 + 4 * q + lk;
         const float jm = j < r ? 1.f : 0.f;
         const int64_t jc = j < r ? j : r - 1;
-        av[u] = A[ic * as + jc * bs] * (im * jm);
-        bv[u] = X[(x * r + jc) * b + y] * (fm * jm);
+        av[q] = A[ic * as + jc * bs] * (im * jm);
+#pragma unroll
+        for (int u = 0; u < TB; ++u) bv[u][q] = X[xo[u] + jc * b] * (fm[u] * jm);
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (k0 + 4 * u < r) c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[u], c, 0, 0, 0);
-    }
-    if (f < F) {
+      for (int u = 0; u < TB; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = I * 16 + 4 * lk + v;
-        if (i < m) {
-          const int64_t o = (x * m + i) * b + y;
-          Y[o] = acc ? Y[o] + c[v] : c[v];
+        for (int q = 0; q < 4; ++q)
+          if (k0 + 4 * q < r) c[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], bv[u][q], c[u], 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < TB; ++u) {
+      const int64_t f = (g * TB + u) * 16 + lr;
+      if (f < F) {
+        const int64_t x = f / b, y = f % b;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = I * 16 + 4 * lk + v;
+          if (i < m) {
+            const int64_t o = (x * m + i) * b + y;
+            Y[o] = acc ? Y[o] + c[u][v] : c[u][v];
+          }
         }
       }
     }
@@ -365,9 +385,77 @@ __device__ __forceinline__ void mode_product_f64(const TX* __restrict__ X, int64
 // them with v_mfma_f64_16x16x4f64 over the a b columns, four per step: lane
 // l supplies row 16 I + l % 16 (and 16 J + l % 16) of column 4 c + l / 16,
 // and holds G[16 I + l / 16 + 4 v][16 J + l % 16] for v < 4.  The FP32
-// products are exact in FP64 and the sums are FP64.
+// products are exact in FP64 and the sums are FP64.  For q <= 48 a
+// wavefront loads the column block of every row tile once per round (four
+// columns) and feeds all its tiles from those registers (gram_mode_panel),
+// so a round costs one memory round trip whatever the tile count; each
+// tile's column steps run in the same order either way.
+template <int NB>
+__device__ __forceinline__ void gram_mode_panel(const float* __restrict__ X, int64_t a, int q, int64_t b,
+                                                double* __restrict__ G, int ld) {
+  constexpr int NT = NB * (NB + 1) / 2;
+  const int nw = int(blockDim.x) >> 6, w = int(threadIdx.x) >> 6, l = int(threadIdx.x) & 63;
+  const int lr = l & 15, lk = l >> 4;
+  const int64_t N = a * b;
+  tk_d4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = tk_d4{0.0, 0.0, 0.0, 0.0};
+  int64_t x = lk / b, y = lk % b;
+  const int64_t xs = 4 / b, ys = 4 % b;
+  for (int64_t k0 = 0; k0 < N; k0 += 16) {
+    float v[NB][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool in = k0 + 4 * u + lk < N;
+      const float* col = X + x * q * b + y;
+#pragma unroll
+      for (int bi = 0; bi < NB; ++bi) {
+        const int row = bi * 16 + lr;
+        v[bi][u] = (in && row < q) ? col[int64_t(row) * b] : 0.f;
+      }
+      x += xs;
+      y += ys;
+      if (y >= b) {
+        y -= b;
+        ++x;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (k0 + 4 * u >= N) break;
+      int t = 0;
+#pragma unroll
+      for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+        for (int bj = bi; bj < NB; ++bj, ++t)
+          if (t % nw == w)
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(double(v[bi][u]), double(v[bj][u]), acc[t], 0, 0, 0);
+    }
+  }
+  int t = 0;
+#pragma unroll
+  for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+    for (int bj = bi; bj < NB; ++bj, ++t) {
+      if (t % nw != w) continue;
+      const int cj = bj * 16 + lr;
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) {
+        const int ri = bi * 16 + lk + 4 * vv;
+        if (ri < q && cj < q) {
+          G[int64_t(ri) * ld + cj] = acc[t][vv];
+          G[int64_t(cj) * ld + ri] = acc[t][vv];
+        }
+      }
+    }
+  __syncthreads();
+}
+
 __device__ __forceinline__ void gram_mode_mfma(const float* __restrict__ X, int64_t a, int q, int64_t b,
                                                double* __restrict__ G, int ld) {
+  if (q <= 16) return gram_mode_panel<1>(X, a, q, b, G, ld);
+  if (q <= 32) return gram_mode_panel<2>(X, a, q, b, G, ld);
+  if (q <= 48) return gram_mode_panel<3>(X, a, q, b, G, ld);
   const int nw = int(blockDim.x) >> 6, w = int(threadIdx.x) >> 6, l = int(threadIdx.x) & 63;
   const int nb = (q + 15) >> 4;
   const int ntiles = nb * (nb + 1) / 2;

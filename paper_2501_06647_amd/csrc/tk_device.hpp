@@ -334,44 +334,60 @@ __device__ __forceinline__ void gemm_f64_rows(int M, int N, int K, FA&& a, FB&& 
 
 // Mode product in FP64 on the matrix cores: Y[x][i][y] (+)= sum_j A(i, j)
 // X[x][j][y] (X FP32 or FP64, A and Y FP64), the layout of mode_product_mfma
-// with v_mfma_f64_16x16x4f64 (fibers f = (x, y) as the N dimension).
+// with v_mfma_f64_16x16x4f64 (fibers f = (x, y) as the N dimension), four
+// fiber tiles per memory round as there.
 template <typename TX>
 __device__ __forceinline__ void mode_product_f64(const TX* __restrict__ X, int64_t a, int r, int64_t b,
                                                  const double* __restrict__ A, int64_t as, int64_t bs, int m,
                                                  double* __restrict__ Y, bool acc) {
+  constexpr int TB = 4;
   const int nw = int(blockDim.x) >> 6, w = int(threadIdx.x) >> 6, l = int(threadIdx.x) & 63;
   const int lr = l & 15, lk = l >> 4;
   const int64_t F = a * b;
   const int mt = (m + 15) >> 4;
-  const int64_t ntiles = int64_t(mt) * ((F + 15) >> 4);
-  for (int64_t t = w; t < ntiles; t += nw) {
+  const int64_t ngr = (((F + 15) >> 4) + TB - 1) / TB;
+  for (int64_t t = w; t < int64_t(mt) * ngr; t += nw) {
     const int I = int(t % mt);
-    const int64_t fo = (t / mt) * 16;  // first fiber of the tile
-    const int64_t f = fo + lr;         // this lane's fiber (B operand column)
-    const bool fv = f < F;
-    const int64_t x = fv ? f / b : 0, y = fv ? f % b : 0;
+    const int64_t g = t / mt;
     const int ia = I * 16 + lr;
     const bool iav = ia < m;
-    tk_d4 c = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < r; k0 += 16) {
-      double av[4], bv[4];
+    int64_t xo[TB];
+    bool fv[TB];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int j = k0 + 4 * u + lk;
-        av[u] = (iav && j < r) ? A[int64_t(ia) * as + int64_t(j) * bs] : 0.0;
-        bv[u] = (fv && j < r) ? double(X[(x * r + j) * b + y]) : 0.0;
+    for (int u = 0; u < TB; ++u) {
+      const int64_t f = (g * TB + u) * 16 + lr;
+      fv[u] = f < F;
+      xo[u] = fv[u] ? (f / b) * r * b + f % b : 0;
+    }
+    tk_d4 c[TB];
+#pragma unroll
+    for (int u = 0; u < TB; ++u) c[u] = tk_d4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < r; k0 += 16) {
+      double av[4], bv[TB][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = k0 + 4 * q + lk;
+        av[q] = (iav && j < r) ? A[int64_t(ia) * as + int64_t(j) * bs] : 0.0;
+#pragma unroll
+        for (int u = 0; u < TB; ++u) bv[u][q] = (fv[u] && j < r) ? double(X[xo[u] + int64_t(j) * b]) : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (k0 + 4 * u < r) c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], c, 0, 0, 0);
+      for (int u = 0; u < TB; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (k0 + 4 * q < r) c[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[u][q], c[u], 0, 0, 0);
     }
-    if (fv) {
+#pragma unroll
+    for (int u = 0; u < TB; ++u) {
+      if (!fv[u]) continue;
+      const int64_t f = (g * TB + u) * 16 + lr;
+      const int64_t x = f / b, y = f % b;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = I * 16 + lk + 4 * v;
         if (i < m) {
           const int64_t o = (x * m + i) * b + y;
-          Y[o] = acc ? Y[o] + c[v] : c[v];
+          Y[o] = acc ? Y[o] + c[u][v] : c[u][v];
         }
       }
     }

@@ -558,9 +558,9 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
       gemm_f64(sr, r_out, q, [&](int c, int dd) { return Fn[c * sr + dd]; },
                [&](int dd, int j) { return P[dd * r_out + j]; },
                [&](int c, int j, double v) { Fh[c * r_out + j] = v; });
-      gemm_f64(int(Dn), r_out, sr, [&](int dd, int c) { return vcat(n, dd, c); },
-               [&](int c, int j) { return Fh[c * r_out + j]; },
-               [&](int dd, int j, double v) { out[int64_t(dd) * r_out + j] = float(v); });
+      gemm_f64_rows<4>(int(Dn), r_out, sr, [&](int dd, int c) { return vcat(n, dd, c); },
+                       [&](int c, int j) { return Fh[c * r_out + j]; },
+                       [&](int dd, int j, double v) { out[int64_t(dd) * r_out + j] = float(v); });
     } else {
       for (int64_t e = tid; e < Dn * r_out; e += nt) out[e] = float(P[e]);
     }

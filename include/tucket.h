@@ -210,8 +210,9 @@ tk_status tk_last_query_kernel_ms(const tk_tree* t, double* ms);
  * full solver only); then four for the sweeps' warm-started eigensolves
  * (subspace iteration from the previous sweep's vectors, kept when a
  * certificate shows it found the leading subspace): accepted, refused (the
- * full solver ran after them), their iteration steps, their microseconds.
- * phase_us has 21 entries. */
+ * full solver ran after them), their iteration steps, their microseconds;
+ * then the part of those microseconds spent in their Rayleigh-Ritz step.
+ * phase_us has 22 entries. */
 tk_status tk_last_query_profile(const tk_tree* t, int32_t i, double* phase_us);
 
 /* Override the ALS sweep cap and tolerance for later queries (not merges). */

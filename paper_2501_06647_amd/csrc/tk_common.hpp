@@ -248,16 +248,17 @@ struct LeafJob {
 // STAT_EIG_INVIT the parts of those spent in tridiagonalisation and in
 // inverse iteration; STAT_EIG_WARM.. the warm-started sweep eigensolves:
 // accepted, refused (the full solver ran after them), their subspace
-// iteration steps and microseconds.
+// iteration steps and microseconds, and the part of those microseconds
+// spent in the Rayleigh-Ritz step and the certificate.
 enum {
   STAT_FIT = 0, STAT_ERR = 1, STAT_NORM = 2, STAT_SWEEPS = 3, STAT_CONV = 4, STAT_HITS = 5, STAT_STATUS = 6,
   STAT_PHASE = 8, STAT_NPHASE = 8, STAT_EIG = 16, STAT_T0 = 20, STAT_T1 = 21, STAT_EIG_FALLBACK = 22,
   STAT_EIG_TRI = 23, STAT_EIG_INVIT = 24, STAT_EIG_WARM = 25, STAT_EIG_WARM_FAIL = 26, STAT_EIG_WARM_STEPS = 27,
-  STAT_EIG_WARM_US = 28, STAT_COUNT = 29
+  STAT_EIG_WARM_US = 28, STAT_EIG_WARM_RR_US = 29, STAT_COUNT = 30
 };
 // Entries of a query's profile (tk_last_query_profile, tk_batch_profile):
-// STAT_PHASE .. STAT_EIG_WARM_US.
-constexpr int PROFILE_COUNT = STAT_EIG_WARM_US + 1 - STAT_PHASE;
+// STAT_PHASE .. STAT_EIG_WARM_RR_US.
+constexpr int PROFILE_COUNT = STAT_EIG_WARM_RR_US + 1 - STAT_PHASE;
 
 // Rows of a partial hit's temporal factor per chunk of the trim pass: each
 // chunk's Gram is summed by one workgroup of trim_gram_kernel, and the stitch

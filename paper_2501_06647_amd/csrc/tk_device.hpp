@@ -43,6 +43,19 @@ __device__ __forceinline__ double block_sum_once(double v, double* buf) {
 }
 
 // Largest v over the workgroup with its index (smallest index on ties).
+// The largest of the workgroup's values, returned to every thread.
+__device__ __forceinline__ double block_max(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  if (blockDim.x <= 64) return v;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double m = red[0];
+  for (int w = 1; w < int(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
+  __syncthreads();
+  return m;
+}
+
 __device__ __forceinline__ void block_argmax(double& v, int& idx, double* red, int* redi) {
   for (int o = 32; o > 0; o >>= 1) {
     const double ov = __shfl_xor(v, o, 64);
@@ -439,6 +452,67 @@ __device__ __forceinline__ void gram_mode_panel(const float* __restrict__ X, int
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       if (k0 + 4 * u >= N) break;
+      int t = 0;
+#pragma unroll
+      for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+        for (int bj = bi; bj < NB; ++bj, ++t)
+          if (t % nw == w)
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(double(v[bi][u]), double(v[bj][u]), acc[t], 0, 0, 0);
+    }
+  }
+  int t = 0;
+#pragma unroll
+  for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+    for (int bj = bi; bj < NB; ++bj, ++t) {
+      if (t % nw != w) continue;
+      const int cj = bj * 16 + lr;
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) {
+        const int ri = bi * 16 + lk + 4 * vv;
+        if (ri < q && cj < q) {
+          G[int64_t(ri) * ld + cj] = acc[t][vv];
+          G[int64_t(cj) * ld + ri] = acc[t][vv];
+        }
+      }
+    }
+  __syncthreads();
+}
+
+// G = V^T V (q x q, FP64, leading dimension ld, both triangles) for a
+// matrix V of D rows whose column c < q <= 16 NB is the strided FP32 vector
+// p_c[d s_c], d < D (col(c, &p_c, &s_c) names it): gram_mode_panel's scheme
+// with the D rows summed, each lane's column pointers fixed for the call.
+// The column steps run in the order of gemm_f64 over the same operands.
+template <int NB, typename FC>
+__device__ __forceinline__ void gram_cols_panel(int D, int q, FC&& col, double* __restrict__ G, int ld) {
+  constexpr int NT = NB * (NB + 1) / 2;
+  const int nw = int(blockDim.x) >> 6, w = int(threadIdx.x) >> 6, l = int(threadIdx.x) & 63;
+  const int lr = l & 15, lk = l >> 4;
+  const float* cp[NB];
+  int64_t cs[NB];
+#pragma unroll
+  for (int bi = 0; bi < NB; ++bi) {
+    const int c = bi * 16 + lr;
+    cp[bi] = nullptr;
+    cs[bi] = 0;
+    if (c < q) col(c, &cp[bi], &cs[bi]);
+  }
+  tk_d4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = tk_d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < D; k0 += 16) {
+    float v[NB][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int d = k0 + 4 * u + lk;
+#pragma unroll
+      for (int bi = 0; bi < NB; ++bi) v[bi][u] = (d < D && cp[bi]) ? cp[bi][int64_t(d) * cs[bi]] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (k0 + 4 * u >= D) break;
       int t = 0;
 #pragma unroll
       for (int bi = 0; bi < NB; ++bi)
@@ -901,6 +975,7 @@ struct EigCounters {  // zeroed by the owner (it may live in LDS)
   uint64_t calls, sweeps, values_ticks, tail_ticks, fallbacks;
   uint64_t tri_ticks, invit_ticks;  // parts of the two above: tridiagonalisation, inverse iteration
   uint64_t warm, warm_fail, warm_steps, warm_ticks;  // eig_top_warm: accepted, refused, steps, time
+  uint64_t warm_rr_ticks;                            // the part of warm_ticks in Rayleigh-Ritz
 };
 
 // Leading eigenpairs of a symmetric n x n matrix S through the tridiagonal
@@ -1510,8 +1585,10 @@ __device__ __forceinline__ void chol_solve_rows(const double* Y, double* Q, int 
 // stride lde) holds orthonormal vectors of a nearby matrix, here the
 // previous ALS sweep's for the same mode in the same coordinates.
 //   * Block subspace iteration (Golub & Van Loan, Sec. 8.2.4): Y = S Q,
-//     H = Q^T Y and the residual R = Y - Q H; while ||R||_F exceeds 1e-11
-//     max_j H(j, j), Q becomes the Cholesky QR of Y.  From the third step
+//     H = Q^T Y and the residual R = Y - Q H; until ||R||_F is at most
+//     1e-11 max_j H(j, j), or the certificate below holds already with a
+//     Gershgorin lower bound for min theta, Q becomes the Cholesky QR of Y.
+//     From the third step
 //     on, the observed contraction of ||R|| predicts the steps still needed;
 //     a start that cannot converge within kWarmMaxSteps is given up early.
 //   * Rayleigh-Ritz (Sec. 8.1.4): H = W Theta W^T by cyclic Jacobi (Sec.
@@ -1576,9 +1653,32 @@ __device__ __forceinline__ bool eig_top_warm(const double* S, int n, int k, doub
     rho = sqrt(block_sum(part, red));
     double hmax = 0.0;
     for (int j = 0; j < k; ++j) hmax = fmax(hmax, H[j * k + j]);
+    // Once near convergence, the certificate below with Gershgorin's lower
+    // bound for the smallest eigenvalue of H (symmetrised) in place of the
+    // exact one: when it already holds, this step's Q is final.
+    bool cert = false;
+    if (hmax > 0.0 && rho <= 1e-6 * hmax) {
+      double nlb = -1e300, trp = 0.0, h2p = 0.0;
+      for (int i = tid; i < k; i += nt) {
+        double off = 0.0;
+        for (int j = 0; j < k; ++j) {
+          const double hs = 0.5 * (H[i * k + j] + H[j * k + i]);
+          h2p += hs * hs;
+          if (j != i) off += fabs(hs);
+        }
+        trp += H[i * k + i];
+        nlb = fmax(nlb, off - H[i * k + i]);
+      }
+      const double lb = -block_max(nlb, red);
+      const double trH = block_sum(trp, red), nH2 = block_sum(h2p, red);
+      const double cT = fmax(0.0, trS - trH) + 1e-12 * fabs(trS);
+      const double cF = sqrt(fmax(0.0, nS2 - nH2 - 2.0 * rho * rho) + 1e-12 * nS2);
+      const double gap = lb - fmin(cT, cF) - 2.0 * rho;
+      cert = gap > 0.0 && rho <= 1e-8 * gap;
+    }
     __syncthreads();  // H is read; the Cholesky QR overwrites it
     if (!(hmax > 0.0)) break;
-    if (rho <= 1e-11 * hmax) {
+    if (cert || rho <= 1e-11 * hmax) {
       conv = true;
       break;
     }
@@ -1618,6 +1718,7 @@ __device__ __forceinline__ bool eig_top_warm(const double* S, int n, int k, doub
     chol_solve_rows(Y, Q, n, k, H, cs);
   }
   bool accept = false;
+  const uint64_t t_rr = wall_clock64();
   if (conv) {
     // Rayleigh-Ritz: H (symmetrised) = W Theta W^T by cyclic Jacobi
     for (int e = tid; e < k * k; e += nt) {
@@ -1743,7 +1844,9 @@ __device__ __forceinline__ bool eig_top_warm(const double* S, int n, int k, doub
     cnt->warm += accept ? 1 : 0;
     cnt->warm_fail += accept ? 0 : 1;
     cnt->warm_steps += uint64_t(it);
-    cnt->warm_ticks += wall_clock64() - t_start;
+    const uint64_t t_end = wall_clock64();
+    cnt->warm_ticks += t_end - t_start;
+    cnt->warm_rr_ticks += t_end - t_rr;
   }
   __syncthreads();
   return accept;

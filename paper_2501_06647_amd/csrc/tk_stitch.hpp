@@ -128,7 +128,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
   EigCounters& ec = sh.ec;
   if (tid == 0) {
     ec.calls = ec.sweeps = ec.values_ticks = ec.tail_ticks = ec.fallbacks = ec.tri_ticks = ec.invit_ticks = 0;
-    ec.warm = ec.warm_fail = ec.warm_steps = ec.warm_ticks = 0;
+    ec.warm = ec.warm_fail = ec.warm_steps = ec.warm_ticks = ec.warm_rr_ticks = 0;
   }
   clk.start();
   // the layout record lives at the head of the workspace
@@ -314,14 +314,24 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     if (span_basis(sr, Dn, basis_pct)) {
       with_buf(sr, [&](double* Gm, double*) {
         // Gram of V_cat = [V~_1^(n) .. V~_s^(n)] over its D_n rows, FP64 on
-        // the matrix cores, then mirrored so that it is exactly symmetric
-        gemm_f64(sr, sr, int(Dn), [&](int x, int dd) { return vcat(n, dd, x); },
-                 [&](int dd, int y) { return vcat(n, dd, y); }, [&](int x, int y, double v) { Gm[x * sr + y] = v; });
-        for (int e = tid; e < sr * sr; e += nt) {
-          const int x = e / sr, y = e % sr;
-          if (y < x) Gm[e] = Gm[y * sr + x];
+        // the matrix cores, exactly symmetric (the upper triangle mirrored)
+        auto vcol = [&](int c, const float** ptr, int64_t* stride) {
+          const int i = hit_of_col(n, c);
+          *stride = st.rk[hits[i].level][n];
+          *ptr = fac_of(i, n) + (c - sh.roff[n][i]);
+        };
+        if (sr <= 16) gram_cols_panel<1>(int(Dn), sr, vcol, Gm, sr);
+        else if (sr <= 32) gram_cols_panel<2>(int(Dn), sr, vcol, Gm, sr);
+        else if (sr <= 48) gram_cols_panel<3>(int(Dn), sr, vcol, Gm, sr);
+        else {
+          gemm_f64(sr, sr, int(Dn), [&](int x, int dd) { return vcat(n, dd, x); },
+                   [&](int dd, int y) { return vcat(n, dd, y); }, [&](int x, int y, double v) { Gm[x * sr + y] = v; });
+          for (int e = tid; e < sr * sr; e += nt) {
+            const int x = e / sr, y = e % sr;
+            if (y < x) Gm[e] = Gm[y * sr + x];
+          }
+          __syncthreads();
         }
-        __syncthreads();
         double* col = Gm + sr * sr;
         int* piv = reinterpret_cast<int*>(Gm + sr * sr + sr);
         const int q = pchol_inplace(Gm, sr, 1e-11, piv, red, sh.redi);
@@ -663,6 +673,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     job.stats[STAT_EIG_WARM_FAIL] = double(ec.warm_fail);
     job.stats[STAT_EIG_WARM_STEPS] = double(ec.warm_steps);
     job.stats[STAT_EIG_WARM_US] = double(ec.warm_ticks) * 0.01;
+    job.stats[STAT_EIG_WARM_RR_US] = double(ec.warm_rr_ticks) * 0.01;
   }
 }
 

@@ -590,7 +590,7 @@ class Tree:
     PHASES = ("trim", "basis", "init", "t_ttm_gram", "t_eig", "n_ttm_gram", "n_eig", "final")
     COUNTERS = ("eig_calls", "eig_bisect_steps", "eig_values_us", "eig_vectors_us", "start_us", "end_us",
                 "eig_fallbacks", "eig_tridiag_us", "eig_invit_us", "eig_warm", "eig_warm_refused",
-                "eig_warm_steps", "eig_warm_us")
+                "eig_warm_steps", "eig_warm_us", "eig_warm_rr_us")
 
     def last_profile(self, i: int) -> dict:
         out = (c_dbl * len(Tree.PHASES + Tree.COUNTERS))()

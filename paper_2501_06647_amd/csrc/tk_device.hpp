@@ -1589,13 +1589,15 @@ __device__ __forceinline__ void chol_solve_rows(const double* Y, double* Q, int 
 //     1e-11 max_j H(j, j), or the certificate below holds already with a
 //     Gershgorin lower bound for min theta, Q becomes the Cholesky QR of Y.
 //     From the third step
-//     on, the observed contraction of ||R|| predicts the steps still needed;
-//     a start that cannot converge within kWarmMaxSteps is given up early.
+//     on, the observed contraction of ||R|| predicts the steps still needed
+//     to reach 1e-8 of the smallest diagonal entry of H (the certificate's
+//     level) or 1e-11 of the largest; a start that cannot converge within
+//     kWarmMaxSteps is given up early.
 //   * Rayleigh-Ritz (Sec. 8.1.4): H = W Theta W^T by cyclic Jacobi (Sec.
 //     8.5: the two-by-two symmetric Schur rotation, round-robin pairs, the
 //     m / 2 disjoint rotations of a round applied together, each thread
 //     updating whole 2 x 2 blocks in place), until no off-diagonal entry
-//     exceeds 1e-15 sqrt(|H(p, p) H(q, q)|).
+//     exceeds 1e-12 sqrt(|H(p, p) H(q, q)|).
 //   * A certificate that span Q is S's leading invariant subspace: in the
 //     basis [Q, Q_perp], S = [[H, R'^T], [R', C]] with ||R'|| = ||R||, and
 //     C is positive semidefinite, so lambda_max(C) <= min(trace C, ||C||_F)
@@ -1610,7 +1612,7 @@ __device__ __forceinline__ void chol_solve_rows(const double* Y, double* Q, int 
 // caller then runs the full solver).  S is only read.  qy: 2 n k doubles
 // (Q and Y), sm: warm_small_doubles(k) doubles (the k x k matrices, kept in
 // LDS by the callers), k <= 32, n > k.
-constexpr int kWarmMaxSteps = 8;
+constexpr int kWarmMaxSteps = 10;
 __device__ __forceinline__ bool eig_top_warm(const double* S, int n, int k, double* E, int lde, double* qy,
                                              double* sm, double* red, EigCounters* cnt) {
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -1651,8 +1653,11 @@ __device__ __forceinline__ bool eig_top_warm(const double* S, int n, int k, doub
                part += d * d;
              });
     rho = sqrt(block_sum(part, red));
-    double hmax = 0.0;
-    for (int j = 0; j < k; ++j) hmax = fmax(hmax, H[j * k + j]);
+    double hmax = 0.0, hmin = H[0];
+    for (int j = 0; j < k; ++j) {
+      hmax = fmax(hmax, H[j * k + j]);
+      hmin = fmin(hmin, H[j * k + j]);
+    }
     // Once near convergence, the certificate below with Gershgorin's lower
     // bound for the smallest eigenvalue of H (symmetrised) in place of the
     // exact one: when it already holds, this step's Q is final.
@@ -1683,9 +1688,10 @@ __device__ __forceinline__ bool eig_top_warm(const double* S, int n, int k, doub
       break;
     }
     if (it >= kWarmMaxSteps) break;
-    if (it >= 3) {  // steps still needed at the observed contraction
+    if (it >= 3) {  // steps still needed at the observed contraction (to the certificate's level)
       const double f = rho / rho_prev;
-      if (!(f < 0.5) || double(it) + log(1e-11 * hmax / rho) / log(f) > double(kWarmMaxSteps)) break;
+      const double target = fmax(1e-11 * hmax, 1e-8 * hmin);
+      if (!(f < 0.5) || double(it) + log(target / rho) / log(f) > double(kWarmMaxSteps)) break;
     }
     rho_prev = rho;
     // Cholesky QR: H <- Y^T Y = L L^T (lower triangle), Q <- Y L^{-T}
@@ -1731,10 +1737,11 @@ __device__ __forceinline__ bool eig_top_warm(const double* S, int n, int k, doub
       }
     }
     __syncthreads();
-    // an entry calls for a rotation above 1e-15 of its diagonal's scale
-    // (the relative criterion for positive definite Jacobi)
+    // an entry calls for a rotation above 1e-12 of its diagonal's scale
+    // (the relative criterion for positive definite Jacobi; the Ritz
+    // vectors only order the basis, the subspace is fixed already)
     auto rotates = [](double hpq, double hpp, double hqq) {
-      return hpq != 0.0 && fabs(hpq) > 1e-15 * sqrt(fabs(hpp) * fabs(hqq));
+      return hpq != 0.0 && fabs(hpq) > 1e-12 * sqrt(fabs(hpp) * fabs(hqq));
     };
     // whether some off-diagonal entry still calls for a rotation (flag[1];
     // the last barrier keeps the next clear behind every reader)

@@ -295,6 +295,50 @@ __device__ __forceinline__ void gemm_f64(int M, int N, int K, FA&& a, FB&& b, FP
   __syncthreads();
 }
 
+// C = A B for a tall A (M x K, FP32 entries a(i, k)) and a small B (K x N,
+// K <= 16, N <= 16, FP64 entries b(k, j)) on the FP64 matrix cores: B's
+// fragment is loaded once, then each wavefront streams TB row tiles per
+// round, their loads issued before any product or store.  Same layout and
+// arithmetic order per tile as gemm_f64.
+template <int TB, typename FA, typename FB, typename FP>
+__device__ __forceinline__ void gemm_f64_tall(int M, int N, int K, FA&& a, FB&& b, FP&& put) {
+  const int nw = int(blockDim.x) >> 6, w = int(threadIdx.x) >> 6, l = int(threadIdx.x) & 63;
+  const int lr = l & 15, lk = l >> 4;
+  const int mt = (M + 15) >> 4;
+  double bv[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int k = 4 * u + lk;
+    bv[u] = (lr < N && k < K) ? double(b(k, lr)) : 0.0;
+  }
+  for (int t0 = w; t0 < mt; t0 += TB * nw) {
+    float av[TB][4];
+#pragma unroll
+    for (int g = 0; g < TB; ++g) {
+      const int i = (t0 + g * nw) * 16 + lr;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = 4 * u + lk;
+        av[g][u] = (i < M && k < K) ? a(i, k) : 0.f;
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < TB; ++g) {
+      tk_d4 c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (4 * u < K) c = __builtin_amdgcn_mfma_f64_16x16x4f64(double(av[g][u]), bv[u], c, 0, 0, 0);
+      const int I = t0 + g * nw;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ri = I * 16 + lk + 4 * v;
+        if (I < mt && ri < M && lr < N) put(ri, lr, c[v]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // gemm_f64 for many row tiles (M >> N, as when a thin factor's rows stream
 // from HBM): each wavefront takes TB tiles per round and issues the loads of
 // all of them before any product or store, so one memory round trip serves

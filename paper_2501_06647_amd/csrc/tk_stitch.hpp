@@ -597,9 +597,14 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
       }
       const float* V = st.plane[lev] + ((h.index << lev) * st.ell + h.a) * k;
       float* out = job.out_fac[0] + t * r0;
-      gemm_f64_rows<4>(int(h.l), r0, k, [&](int row, int c) { return V[int64_t(row) * k + c]; },
-                       [&](int c, int j) { return F0[c * r0 + j]; },
-                       [&](int row, int j, double v) { out[int64_t(row) * r0 + j] = float(v); });
+      if (k <= 16 && r0 <= 16)
+        gemm_f64_tall<8>(int(h.l), r0, k, [&](int row, int c) { return V[int64_t(row) * k + c]; },
+                         [&](int c, int j) { return F0[c * r0 + j]; },
+                         [&](int row, int j, double v) { out[int64_t(row) * r0 + j] = float(v); });
+      else
+        gemm_f64_rows<4>(int(h.l), r0, k, [&](int row, int c) { return V[int64_t(row) * k + c]; },
+                         [&](int c, int j) { return F0[c * r0 + j]; },
+                         [&](int row, int j, double v) { out[int64_t(row) * r0 + j] = float(v); });
       t += h.l;
     }
   }

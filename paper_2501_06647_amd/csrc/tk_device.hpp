@@ -210,40 +210,56 @@ typedef __bf16 tk_b8 __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ void mode_product_bf16(const float* __restrict__ X, int64_t a, int r, int64_t b,
                                                   const float* __restrict__ A, int64_t as, int64_t bs, int m,
                                                   float* __restrict__ Y, bool acc) {
+  constexpr int TB = 4;  // fiber tiles per memory round, as in mode_product_mfma
   const int nw = int(blockDim.x) >> 6, w = int(threadIdx.x) >> 6, l = int(threadIdx.x) & 63;
   const int lr = l & 15, lk = l >> 4;
   const int64_t F = a * b;
   const int mt = (m + 15) >> 4;
-  const int64_t ntiles = int64_t(mt) * ((F + 15) >> 4);
-  for (int64_t t = w; t < ntiles; t += nw) {
+  const int64_t ngr = (((F + 15) >> 4) + TB - 1) / TB;
+  for (int64_t t = w; t < int64_t(mt) * ngr; t += nw) {
     const int I = int(t % mt);
-    const int64_t f = (t / mt) * 16 + lr;
-    const float fm = f < F ? 1.f : 0.f;
-    const int64_t fc = f < F ? f : F - 1;
-    const int64_t x = fc / b, y = fc % b;
+    const int64_t g = t / mt;
     const int ia = I * 16 + lr;
     const float im = ia < m ? 1.f : 0.f;
     const int64_t ic = ia < m ? ia : m - 1;
-    tk_f4 c = {0.f, 0.f, 0.f, 0.f};
+    int64_t xo[TB];
+    float fm[TB];
+#pragma unroll
+    for (int u = 0; u < TB; ++u) {
+      const int64_t f = (g * TB + u) * 16 + lr;
+      fm[u] = f < F ? 1.f : 0.f;
+      const int64_t fc = f < F ? f : F - 1;
+      xo[u] = (fc / b) * r * b + fc % b;
+    }
+    tk_f4 c[TB];
+#pragma unroll
+    for (int u = 0; u < TB; ++u) c[u] = tk_f4{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < r; k0 += 32) {
-      tk_b8 av, bv;
+      tk_b8 av, bv[TB];
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
         const int j = k0 + 8 * lk + v;
         const float jm = j < r ? 1.f : 0.f;
         const int64_t jc = j < r ? j : r - 1;
         av[v] = (__bf16)(A[ic * as + jc * bs] * (im * jm));
-        bv[v] = (__bf16)(X[(x * r + jc) * b + y] * (fm * jm));
-      }
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
-    }
-    if (f < F) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = I * 16 + 4 * lk + v;
-        if (i < m) {
-          const int64_t o = (x * m + i) * b + y;
-          Y[o] = acc ? Y[o] + c[v] : c[v];
+        for (int u = 0; u < TB; ++u) bv[u][v] = (__bf16)(X[xo[u] + jc * b] * (fm[u] * jm));
+      }
+#pragma unroll
+      for (int u = 0; u < TB; ++u) c[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[u], c[u], 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < TB; ++u) {
+      const int64_t f = (g * TB + u) * 16 + lr;
+      if (f < F) {
+        const int64_t x = f / b, y = f % b;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = I * 16 + 4 * lk + v;
+          if (i < m) {
+            const int64_t o = (x * m + i) * b + y;
+            Y[o] = acc ? Y[o] + c[u][v] : c[u][v];
+          }
         }
       }
     }
@@ -649,8 +665,81 @@ __device__ __forceinline__ void gram_mode_mfma(const float* __restrict__ X, int6
 // (v_mfma_f32_16x16x32_bf16, 32 columns per step; lane l supplies rows
 // 16 I + l % 16 and 16 J + l % 16 of columns 32 c + 8 (l / 16) + v), stored
 // as FP64 like gram_mode_mfma.
+// gram_mode_bf16 for q <= 16 NB: each round loads the 32-column block of
+// every row tile once and feeds all the wavefront's tiles of the upper
+// triangle from those registers (same per-tile arithmetic).
+template <int NB>
+__device__ __forceinline__ void gram_mode_bf16_panel(const float* __restrict__ X, int64_t a, int q, int64_t b,
+                                                     double* __restrict__ G, int ld) {
+  constexpr int NT = NB * (NB + 1) / 2;
+  const int nw = int(blockDim.x) >> 6, w = int(threadIdx.x) >> 6, l = int(threadIdx.x) & 63;
+  const int64_t N = a * b;
+  const int lr = l & 15, lk = l >> 4;
+  int64_t ro[NB];
+  float rm[NB];
+#pragma unroll
+  for (int bi = 0; bi < NB; ++bi) {
+    const int i = bi * 16 + lr;
+    rm[bi] = i < q ? 1.f : 0.f;
+    ro[bi] = int64_t(i < q ? i : q - 1) * b;
+  }
+  tk_f4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = tk_f4{0.f, 0.f, 0.f, 0.f};
+  int64_t x = (8 * lk) / b, y = (8 * lk) % b;
+  const int64_t xs = 32 / b, ys = 32 % b;
+  for (int64_t k0 = 0; k0 < N; k0 += 32) {
+    tk_b8 v[NB];
+    int64_t xv = x, yv = y;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const bool kin = k0 + 8 * lk + e < N;
+      const float* col = X + (kin ? xv * q * b + yv : 0);
+      const float km = kin ? 1.f : 0.f;
+#pragma unroll
+      for (int bi = 0; bi < NB; ++bi) v[bi][e] = (__bf16)(col[ro[bi]] * (rm[bi] * km));
+      if (++yv == b) {
+        yv = 0;
+        ++xv;
+      }
+    }
+    int t = 0;
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+      for (int bj = bi; bj < NB; ++bj, ++t)
+        if (t % nw == w) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(v[bi], v[bj], acc[t], 0, 0, 0);
+    x += xs;
+    y += ys;
+    if (y >= b) {
+      y -= b;
+      ++x;
+    }
+  }
+  int t = 0;
+#pragma unroll
+  for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+    for (int bj = bi; bj < NB; ++bj, ++t) {
+      if (t % nw != w) continue;
+      const int cj = bj * 16 + lr;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int ri = bi * 16 + 4 * lk + e;
+        if (ri < q && cj < q) {
+          G[int64_t(ri) * ld + cj] = double(acc[t][e]);
+          G[int64_t(cj) * ld + ri] = double(acc[t][e]);
+        }
+      }
+    }
+  __syncthreads();
+}
+
 __device__ __forceinline__ void gram_mode_bf16(const float* __restrict__ X, int64_t a, int q, int64_t b,
                                                double* __restrict__ G, int ld) {
+  if (q <= 16) return gram_mode_bf16_panel<1>(X, a, q, b, G, ld);
+  if (q <= 32) return gram_mode_bf16_panel<2>(X, a, q, b, G, ld);
+  if (q <= 48) return gram_mode_bf16_panel<3>(X, a, q, b, G, ld);
   const int nw = int(blockDim.x) >> 6, w = int(threadIdx.x) >> 6, l = int(threadIdx.x) & 63;
   const int nb = (q + 15) >> 4;
   const int ntiles = nb * (nb + 1) / 2;

@@ -206,18 +206,27 @@ def test_plain_workload_full_size_sampled(torch):
     orc = oracle_tree(wl, X, wl.T)
     ts, te = synth.queries(wl, n=24)
     worst = 0.0
+    refused = accepted = 0
     for a, b in zip(ts.tolist(), te.tolist()):
         say("plain query", a, b)
         assert [(h["node_id"], h["lo"], h["hi"]) for h in gpu.hitset(a, b)] == \
             [(v.id, lo, hi) for v, lo, hi in orc.recall(a, b)]
         r = gpu.query(a, b)
+        pr = gpu.last_profile(0)
+        refused += pr["eig_warm_refused"]
+        accepted += pr["eig_warm"]
         Go, Uo, _ = orc.query(a, b)
         G, U = to_np(r)
         d, orth, _, eg, eo = compare(X, a, b, G, U, Go, Uo)
         assert orth <= ORTH
         worst = max(worst, d)
-    say("plain: worst query delta %.2e" % worst)
+    say("plain: worst query delta %.2e; warm-started eigensolves %d accepted, %d refused"
+        % (worst, accepted, refused))
     assert worst <= DELTA
+    # node ranks (10) above the data's rank (8): no gap after the 10th
+    # eigenvalue, so the certificate must refuse the subspace iterations
+    # (the full solver then gives the results compared above)
+    assert refused > 0
     # converged runs (200 sweeps, tolerance 1e-12 on both sides): leading
     # subspaces and the distance between the two reconstructions
     gpu.set_query_iters(200, 1e-12)

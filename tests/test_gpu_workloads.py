@@ -72,7 +72,10 @@ def _prefix_samples(ts, te, hits_of, prefix):
     return sorted(idx)
 
 
-def _full_size(name, torch, bf16=False):
+def _full_size(name, torch, bf16=False, expect_warm=False):
+    """expect_warm: the workload's node ranks equal its data's rank (a
+    spectral gap after them), so sampled queries must take certified
+    warm-started eigensolves: their parity below covers that path."""
     from paper_2501_06647_amd.tucket import TK_BF16, TK_F32
     wl = synth.get(name)
     T, ell = wl.T, wl.leaf_len
@@ -100,6 +103,13 @@ def _full_size(name, torch, bf16=False):
         b.run()
         say("%s prec=%d: batch of %d queries, kernel %.1f ms" % (name, prec, len(all_ts), b.kernel_ms()))
         res = b.results()
+        if prec == TK_F32:
+            prof = [b.profile(i) for i in sample]
+            warm = sum(pr["eig_warm"] for pr in prof)
+            say("%s: sampled queries took %d certified warm-started eigensolves, %d refused, %d full"
+                % (name, warm, sum(pr["eig_warm_refused"] for pr in prof), sum(pr["eig_calls"] for pr in prof)))
+            if expect_warm:
+                assert warm > 0, "no warm-started eigensolve on a workload with a spectral gap"
         dev[prec] = {i: (to_np(res[i]), res[i].sweeps,
                          [(h["node_id"], h["lo"], h["hi"]) for h in b.device_hits(i)]) for i in sample}
         b.close()
@@ -182,7 +192,7 @@ def test_precision_workload_full_size_fp32_and_bf16(torch):
 
 @pytest.mark.timeout(900)
 def test_serving_shape_full_size(torch):
-    _full_size("serving", torch)
+    _full_size("serving", torch, expect_warm=True)
 
 
 def test_precision_shape_small_horizon_both_sides(torch):

@@ -1714,18 +1714,17 @@ __device__ __forceinline__ void chol_solve_rows(const double* Y, double* Q, int 
 }
 
 // Leading k eigenvectors of a symmetric positive semidefinite n x n matrix
-// S (a Gram; row-major, both triangles) from a close start: E (n x k, row
-// stride lde) holds orthonormal vectors of a nearby matrix, here the
-// previous ALS sweep's for the same mode in the same coordinates.
+// S (a Gram; row-major, both triangles) from a start: E (n x k, row stride
+// lde) holds orthonormal vectors close to them (the previous ALS sweep's
+// for the same mode in the same coordinates, or a hit's own vectors).
 //   * Block subspace iteration (Golub & Van Loan, Sec. 8.2.4): Y = S Q,
 //     H = Q^T Y and the residual R = Y - Q H; until ||R||_F is at most
 //     1e-11 max_j H(j, j), or the certificate below holds already with a
 //     Gershgorin lower bound for min theta, Q becomes the Cholesky QR of Y.
-//     From the third step
-//     on, the observed contraction of ||R|| predicts the steps still needed
-//     to reach 1e-8 of the smallest diagonal entry of H (the certificate's
-//     level) or 1e-11 of the largest; a start that cannot converge within
-//     kWarmMaxSteps is given up early.
+//     From the third step on, the observed contraction of ||R|| predicts
+//     the steps still needed to reach 1e-8 of the smallest diagonal entry
+//     of H (the certificate's level) or 1e-11 of the largest; a start that
+//     cannot converge within kWarmMaxSteps is given up early.
 //   * Rayleigh-Ritz (Sec. 8.1.4): H = W Theta W^T by cyclic Jacobi (Sec.
 //     8.5: the two-by-two symmetric Schur rotation, round-robin pairs, the
 //     m / 2 disjoint rotations of a round applied together, each thread

@@ -802,7 +802,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="serving")
+    ap.add_argument("--workload", default=None,
+                    help="workload name (default: serving; plain for --tradeoff, whose from-scratch "
+                         "baseline decomposes every raw range in one workgroup)")
     ap.add_argument("--headline", default="f32", help="precision of the headline value: f32 or bf16")
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--append-slices", type=int, default=4096, help="streamed appends timed (one slice per call)")
@@ -849,14 +851,14 @@ def main():
               "(queries are independent: several GPUs would each hold a copy of the node store "
               "and take a share of the queries)", file=sys.stderr)
         sys.exit(2)
+    if args.tradeoff:
+        args.workload = args.workload or "plain"
+        return tradeoff_main(args)
+    args.workload = args.workload or "serving"
     if args.serve:
-        if args.workload == "plain":
-            args.workload = "serving"
         return serve_main(args)
     if args.raw:
         return raw_main(args)
-    if args.tradeoff:
-        return tradeoff_main(args)
     if args.pscale:
         return pscale_main(args)
     return batched_main(args)

@@ -1740,13 +1740,15 @@ __device__ __forceinline__ void chol_solve_rows(const double* Y, double* Q, int 
 //     near theta, and the sin-theta theorem bounds the angle between span Q
 //     and the exact leading subspace by ||R|| / gap, required below 1e-8.
 // On success the Ritz vectors Q W, in descending order of theta, replace E
-// and it returns true; otherwise E is untouched and it returns false (the
-// caller then runs the full solver).  S is only read.  qy: 2 n k doubles
+// and it returns 1; otherwise E is untouched and it returns 0, or -1 when
+// the refusal shows no gap after the k-th eigenvalue (a residual that
+// contracts by less than half a step, or a converged subspace that fails
+// the certificate): the caller then runs the full solver.  S is only read.  qy: 2 n k doubles
 // (Q and Y), sm: warm_small_doubles(k) doubles (the k x k matrices, kept in
 // LDS by the callers), k <= 32, n > k.
 constexpr int kWarmMaxSteps = 10;
-__device__ __forceinline__ bool eig_top_warm(const double* S, int n, int k, double* E, int lde, double* qy,
-                                             double* sm, double* red, EigCounters* cnt) {
+__device__ __forceinline__ int eig_top_warm(const double* S, int n, int k, double* E, int lde, double* qy,
+                                            double* sm, double* red, EigCounters* cnt) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const uint64_t t_start = wall_clock64();
   double* Q = qy;
@@ -1768,7 +1770,7 @@ __device__ __forceinline__ bool eig_top_warm(const double* S, int n, int k, doub
   const double trS = block_sum(tr, red);
   for (int e = tid; e < n * k; e += nt) Q[e] = E[int64_t(e / k) * lde + e % k];
   __syncthreads();
-  bool conv = false;
+  bool conv = false, nogap = false;
   double rho = 0.0, rho_prev = 0.0;
   int it = 0;
   for (;;) {
@@ -1823,7 +1825,8 @@ __device__ __forceinline__ bool eig_top_warm(const double* S, int n, int k, doub
     if (it >= 3) {  // steps still needed at the observed contraction (to the certificate's level)
       const double f = rho / rho_prev;
       const double target = fmax(1e-11 * hmax, 1e-8 * hmin);
-      if (!(f < 0.5) || double(it) + log(target / rho) / log(f) > double(kWarmMaxSteps)) break;
+      nogap = !(f < 0.5);
+      if (nogap || double(it) + log(target / rho) / log(f) > double(kWarmMaxSteps)) break;
     }
     rho_prev = rho;
     // Cholesky QR: H <- Y^T Y = L L^T (lower triangle), Q <- Y L^{-T}
@@ -1963,6 +1966,7 @@ __device__ __forceinline__ bool eig_top_warm(const double* S, int n, int k, doub
       const double cF = sqrt(fmax(0.0, nS2 - s2 - 2.0 * rho * rho) + 1e-12 * nS2);
       const double gap = th_min - fmin(cT, cF) - 2.0 * rho;
       accept = gap > 0.0 && rho <= 1e-8 * gap;
+      nogap = !accept;
     }
   }
   if (accept) {
@@ -1988,7 +1992,7 @@ __device__ __forceinline__ bool eig_top_warm(const double* S, int n, int k, doub
     cnt->warm_rr_ticks += t_end - t_rr;
   }
   __syncthreads();
-  return accept;
+  return accept ? 1 : (nogap ? -1 : 0);
 }
 
 // The eigensolver the kernels use.

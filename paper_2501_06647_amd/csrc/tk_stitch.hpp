@@ -79,7 +79,9 @@ struct StitchShared {
   int32_t roff[PM][MAXHITS + 1];    // offsets of the pieces' columns in C^(n)
   int32_t q[PM];                    // size of the reduced coordinates of mode n
   int32_t basis[PM];                // 1: C^(n) from the Cholesky basis; 0: C^(n) = V~
-  int32_t warm[PM];                 // 1: mode n's sweep eigensolve may start from its last vectors
+  int32_t warm[PM];                 // 1: mode n's next eigensolve starts from the vectors in P_n;
+                                    // 2, 3: it runs in full, later sweeps' may start warm again
+                                    // (2: no start written, 3: a start failed); 0: all in full
   double red[8];
   int redi[4];
 };
@@ -200,21 +202,27 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
   // sweep's vectors (or a start written there) begin a subspace iteration
   // that is kept when its certificate holds (eig_top_warm); otherwise, and
   // for the rest of the job's sweeps once a start has failed, the full
-  // solver runs.  The iteration's
+  // solver runs.  A start refused for lack of a gap after the k-th
+  // eigenvalue (node ranks above the data's rank: no start converges)
+  // rules out the mode's later starts in the job; one refused otherwise
+  // (a start too far off) only its starts until the next sweep begins
+  // afresh (after the HOSVD initialisation, after the first temporal
+  // solve).  The iteration's
   // k x k matrices go to the LDS behind the Gram (the eigensolver's vector
   // part, sized for them up to WARM_SMALL_K), its two n x k blocks behind
   // those when they fit, else to TMP.
   auto sweep_eig = [&](int mode, double* Wm, double* Wv, int n, int k) {
     double* E = Dp(lo.Pd[mode]);
-    if (sh.warm[mode] && n > k && k <= 32) {
+    if (sh.warm[mode] == 1 && n > k && k <= 32) {
       const int64_t used = n <= n_lds ? int64_t(n) * n : 0;
       const int64_t nsm = warm_small_doubles(k), nqy = 2 * int64_t(n) * k;
       if (lds_doubles - used >= nsm) {
         double* sm = lds + used;
         double* qy = lds_doubles - used - nsm >= nqy ? sm + nsm : (nqy <= eig_tmp_doubles(n) ? TMP : nullptr);
         if (qy) {
-          if (eig_top_warm(Wm, n, k, E, k, qy, sm, red, &ec)) return;
-          if (tid == 0) sh.warm[mode] = 0;
+          const int got = eig_top_warm(Wm, n, k, E, k, qy, sm, red, &ec);
+          if (got > 0) return;
+          if (tid == 0) sh.warm[mode] = got < 0 ? 0 : 3;
         }
       }
     }
@@ -397,7 +405,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
       double* P = Dp(lo.Pd[n]);
       if (rd >= r)
         for (int e = tid; e < q * r; e += nt) P[e] = C64[int64_t(e / r) * sr + c0 + e % r];
-      if (tid == 0) sh.warm[n] = rd >= r;
+      if (tid == 0) sh.warm[n] = rd >= r ? 1 : 2;
       __syncthreads();
     }
     with_eig_buf(q, [&](double* Wm, double* Wv) {
@@ -432,7 +440,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
     if (k0 >= r0)
       for (int e = tid; e < sk * r0; e += nt) P0[e] = (e / r0 - o0 == e % r0) ? 1.0 : 0.0;
     if (tid == 0)
-      for (int n = 0; n < p; ++n) sh.warm[n] = n > 0 || k0 >= r0;
+      for (int n = 0; n < p; ++n) sh.warm[n] = n > 0 ? int(sh.warm[n] != 0) : (k0 >= r0 ? 1 : 2);
     __syncthreads();
   }
   clk.mark(2);
@@ -474,7 +482,7 @@ __device__ __forceinline__ void stitch_one(const StoreView& st, const Job& job, 
       clk.mark(3);
       sweep_eig(0, Wm, Wv, sk, rq[0]);
     });
-    if (tid == 0 && it == 1) sh.warm[0] = 1;
+    if (tid == 0 && it == 1) sh.warm[0] = sh.warm[0] != 0;
     float* P0f = Fp(lo.Pf[0]);
     {
       const double* P0 = Dp(lo.Pd[0]);

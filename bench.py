@@ -33,7 +33,7 @@ HBM_TBPS = 8.0
 # (`--copy-calibration`); keyed by (workload, precision) and valid only for
 # the kernel sources (sha) and the launch tuning they were taken with.
 TRAFFIC_BYTES_PER_STEP = {
-    ("serving", "f32"): {"fetch": 12625136241, "write": 8706373856, "sha": "baae522e18228e56",
+    ("serving", "f32"): {"fetch": 12600994186, "write": 8685448800, "sha": "6e52f1886517641b",
                          "tuning": {"wide_threshold": 32, "wide_threads": 128, "persistent": 1, "graph": 1,
                                     "coarse": 1, "lds_n": 64, "basis_pct": 75, "rest_threads": 0,
                                     "wide_core": 0}},
